@@ -177,21 +177,22 @@ def column_spectra(window: np.ndarray, lblock: int, ntap: int, nblock: int) -> n
 
 
 def wiener_gain(W: np.ndarray, phi: float, normalise: bool = True,
-                trunc: float = 1e-12) -> np.ndarray:
+                trunc: float = 1e-12, tapsum: np.ndarray | None = None) -> np.ndarray:
     """Gain G applied to F d_n so that xhat_n = F^dagger[G F d_n].
 
     G = H / conj(W) with the Wiener weights of Section 4.1,
     H = |W|^2 (1 + phi^2) / (|W|^2 + phi^2), i.e. G = W (1+phi^2)/(|W|^2+phi^2).
     normalise=False drops the (1+phi^2) factor (Appendix B calls it optional).
-    phi = 0 is the plain division of Section 3.1, with eigenvalues at or below
-    trunc * max|W| set to zero (READING: the pseudo-inverse truncation that
+    phi = 0 is the plain division of Section 3.1; eigenvalues at rounding level,
+    |W| <= trunc * sum_r |h[rN+n]| (tapsum, per column; the largest |W| a column
+    can reach), are set to zero (READING: the pseudo-inverse truncation that
     Section 4.2.2 uses for the toy model).
     """
     W = np.asarray(W, dtype=np.complex128)
     a2 = np.abs(W) ** 2
     if phi == 0.0:
-        thr = trunc * np.abs(W).max()
-        ok = np.abs(W) > thr
+        bound = np.abs(W).max() if tapsum is None else np.broadcast_to(tapsum, W.shape)
+        ok = np.abs(W) > trunc * bound
         G = np.zeros_like(W)
         G[ok] = 1.0 / np.conj(W[ok])
         return G
@@ -207,7 +208,8 @@ def column_inverse(d: np.ndarray, window: np.ndarray, lblock: int, ntap: int,
     d = np.asarray(d, dtype=np.float64)
     b = d.shape[0]
     W = column_spectra(window, lblock, ntap, b)
-    G = wiener_gain(W, phi, normalise)
+    tapsum = np.sum(np.abs(np.asarray(window, dtype=np.float64).reshape(ntap, lblock)), axis=0)
+    G = wiener_gain(W, phi, normalise, tapsum=tapsum[None, :])
     D = np.fft.fft(d, axis=0)
     return np.fft.ifft(G * D, axis=0).real
 
