@@ -1,0 +1,138 @@
+/*
+ * ipfb.h - C ABI of libipfb, the MI355X (gfx950) implementation of the
+ * circulant inverse polyphase filter bank and up-channelization of
+ * Fay et al., "Inverting and Up-channelizing Critically-Sampled Polyphase
+ * Filter Banks".
+ *
+ * Problem statement (Section 2.3 and Section 3): a real timestream x of
+ * nblock frames of lblock samples, stored frame-major (x[j*lblock + n]), is
+ * channelised by the PFB y = F S W x with an ntap-tap window h of length
+ * ntap*lblock; spectrum j uses frames j..j+ntap-1, wrapping circularly (the
+ * circulant model of Section 3.1), so there are nblock spectra of
+ * lblock/2+1 channels, stored [nblock][lblock/2+1] as interleaved (re, im).
+ *
+ * Conventions common to every call:
+ *  - Every data pointer is a device pointer owned by the caller unless the
+ *    argument says "host". The library never frees caller memory.
+ *  - stream is a hipStream_t (NULL = the default stream). Calls enqueue work
+ *    and return without synchronising. A plan must not be used from two
+ *    streams at once: it owns one workspace.
+ *  - Arguments are validated before anything is enqueued; on failure the call
+ *    returns a negative status, writes no output, and ipfb_last_error()
+ *    returns a message (per thread).
+ *  - Real arrays are float (IPFB_F32 plans) or double (IPFB_F64 plans);
+ *    complex arrays are pairs of the same type.
+ *  - Lengths: lblock and nblock are powers of two with lblock >= 4,
+ *    nblock >= 4. Inverse: lblock <= 32768 (F32) / 16384 (F64) and
+ *    nblock <= 32768 (F32) / 16384 (F64). Forward PFB / up-channelization:
+ *    lblock up to 2^20.
+ */
+#ifndef IPFB_H
+#define IPFB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  IPFB_OK = 0,
+  IPFB_EINVAL = -1,       /* bad argument (NULL pointer, size, mismatched plan) */
+  IPFB_EUNSUPPORTED = -2, /* valid problem outside the supported shapes */
+  IPFB_ENOMEM = -3,       /* device allocation failed */
+  IPFB_EHIP = -4          /* HIP runtime or launch error */
+} ipfb_status;
+
+typedef enum { IPFB_F32 = 0, IPFB_F64 = 1 } ipfb_prec;
+
+/* Spectrum formats accepted by the inverse.
+ * IPFB_IN_C4: one byte per complex value, real part in the high nibble and
+ *   imaginary part in the low nibble, each 4-bit two's complement in -7..7
+ *   (Section 4.3's 15-level quantiser), with a per-channel float scale s_k:
+ *   the spectrum is q / s_k.
+ * IPFB_IN_CF32 / IPFB_IN_CF64: interleaved float / double complex. */
+typedef enum { IPFB_IN_C4 = 0, IPFB_IN_CF32 = 2, IPFB_IN_CF64 = 3 } ipfb_infmt;
+
+typedef struct ipfb_plan_s* ipfb_plan;
+
+/* Message for the last failed call on this thread ("" if none). */
+const char* ipfb_last_error(void);
+
+/* Version string of the library. */
+const char* ipfb_version(void);
+
+/* Host helper: the sinc x Hamming window of Section 2.2 (Hamming taper with
+ * numpy's cos(2 pi m/(M-1)) normalisation, Appendix A):
+ *   out[m] = sinc((m - M/2)/lblock) * (0.54 - 0.46 cos(2 pi m/(M-1))),
+ * M = ntap*lblock. out is a host array of M doubles. */
+int ipfb_window_sinc_hamming(double* out, int ntap, int lblock);
+
+/* Create a plan for frames of lblock samples, ntap taps, nblock frames.
+ * window: host, ntap*lblock doubles, copied (the taps of Section 2.3's
+ * reshaped [ntap, lblock] window). prec: IPFB_F32 or IPFB_F64.
+ * The plan allocates its tables and workspace on the current device. */
+int ipfb_plan_create(ipfb_plan* out, int lblock, int ntap, const double* window, int64_t nblock, int prec);
+int ipfb_plan_destroy(ipfb_plan plan);
+/* Device bytes the plan holds (tables + workspace). */
+int ipfb_plan_workspace_size(ipfb_plan plan, size_t* bytes);
+
+/* Forward PFB (Section 2.2 polyphase equation, Section 2.3 y = F S W x),
+ * circular: y_j[k] = sum_n e^{-2 pi i nk/N} sum_r h[rN+n] x[((j+r) mod b)N + n].
+ * x: [nblock*lblock] real. y: [nblock][lblock/2+1] complex. */
+int pfb_forward(ipfb_plan plan, const void* x, void* y, void* stream);
+
+/* Adjoint of pfb_forward under the real inner product on x and Re<.,.> on
+ * the half spectrum (the transpose of S W and of the half-spectrum DFT):
+ *   z_j[n] = Re sum_{k=0}^{N/2} y_jk e^{2 pi i nk/N},
+ *   x[iN+n] = sum_r h[rN+n] z_{(i-r) mod b}[n].
+ * y: [nblock][lblock/2+1] complex, x: [nblock*lblock] real.
+ * lblock <= 32768 (F32) / 16384 (F64). */
+int pfb_adjoint(ipfb_plan plan, const void* y, void* x, void* stream);
+
+/* Circulant Wiener inverse PFB (Section 3.1 decorrelation equation, Section
+ * 4.1 Wiener weights): d_j = inverse real FFT of spectrum j (Section 3), then
+ * per column n, x_n = F^dagger[ G_n F d_n ] with
+ *   W_n(f) = sum_r h[rN+n] e^{-2 pi i r f / nblock},
+ *   G_n = W_n (1+phi^2) / (|W_n|^2 + phi^2).
+ * phi = 0 gives the plain division 1/conj(W_n), with eigenvalues at rounding
+ * level (|W| <= 1e-12 sum_r |h[rN+n]|) truncated to zero.
+ * spec: [nblock][lblock/2+1] in format infmt. chan_scale: device float
+ * [lblock/2+1] for IPFB_IN_C4, ignored (may be NULL) otherwise.
+ * x_out: [nblock*lblock] real, time order. The imaginary parts of the DC and
+ * Nyquist channels are ignored. */
+int ipfb_wiener(ipfb_plan plan, int infmt, const void* spec, const float* chan_scale, double phi,
+                void* x_out, void* stream);
+
+/* As ipfb_wiener, with normalise = 0 dropping the (1+phi^2) factor (Appendix B
+ * calls it optional). */
+int ipfb_wiener_ex(ipfb_plan plan, int infmt, const void* spec, const float* chan_scale, double phi,
+                   int normalise, void* x_out, void* stream);
+
+/* Up-channelization (Section 4.3): the forward PFB re-applied with the fine
+ * plan's longer frame lblock_f (= u * lblock) and its window, circular over
+ * nblock_f = S / lblock_f frames.
+ * x: [nblock_f*lblock_f] real (the inverse's output). y_fine:
+ * [nblock_f][lblock_f/2+1] complex. autospec: NULL, or device double
+ * [lblock_f/2+1] receiving A(f) = (1/nblock_f) sum_j |Y_j(f)|^2
+ * (Section 4.1's autospectrum), summed in a fixed order. */
+int upchannelize(ipfb_plan fine, const void* x, void* y_fine, double* autospec, void* stream);
+
+/* Autospectrum alone: autospec[k] = (1/nspec) sum_j |y_jk|^2 (double). */
+int ipfb_autospectrum(ipfb_plan plan, const void* y, double* autospec, void* stream);
+
+/* Input synthesis (Section 4.3 quantiser): per-channel scale
+ * s_k = float(levels_rms / sigma_k), sigma_k = sqrt(mean_j |y_jk|^2 / 2)
+ * (1 for a channel with no power), then q = clip(rint(s_k y), -7, 7) on real
+ * and imaginary parts, packed as IPFB_IN_C4. y: the plan's complex spectra
+ * [nblock][lblock/2+1]; packed: uint8 [nblock][lblock/2+1]; scales: float
+ * [lblock/2+1]. */
+int ipfb_quantize_c4(ipfb_plan plan, const void* y, double levels_rms, uint8_t* packed, float* scales,
+                     void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IPFB_H */

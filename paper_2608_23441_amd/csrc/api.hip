@@ -1,0 +1,349 @@
+// C ABI of libipfb: plans, argument validation, and the enqueue of the HIP
+// kernels that make up each call. No computation happens on the host besides
+// the window helper and the twiddle tables built once per plan.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ipfb.h"
+#include "launch.hpp"
+
+using namespace ipfb;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return status;
+}
+
+int ok() {
+  g_err.clear();
+  return IPFB_OK;
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(int64_t v) {
+  int l = 0;
+  while ((int64_t(1) << l) < v) ++l;
+  return l;
+}
+
+// Fault injection for tests of the error paths: IPFB_FAULT_INJECT=alloc makes
+// device allocations fail, =launch makes kernel enqueues report an error.
+bool inject(const char* what) {
+  const char* v = getenv("IPFB_FAULT_INJECT");
+  return v && strcmp(v, what) == 0;
+}
+
+// e^{-2 pi i m / L}, m < L, in double, exact at multiples of L/4.
+std::vector<double> twiddles(int64_t L) {
+  std::vector<double> t(2 * L);
+  for (int64_t m = 0; m < L; ++m) {
+    double c, s;
+    if ((4 * m) % L == 0) {
+      const int q = (int)((4 * m) / L);
+      const double cs[4] = {1.0, 0.0, -1.0, 0.0};
+      const double sn[4] = {0.0, 1.0, 0.0, -1.0};
+      c = cs[q];
+      s = sn[q];
+    } else {
+      const long double a = 2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)L;
+      c = (double)cosl(a);
+      s = (double)sinl(a);
+    }
+    t[2 * m] = c;
+    t[2 * m + 1] = -s;
+  }
+  return t;
+}
+
+}  // namespace
+
+struct ipfb_plan_s {
+  int lblock = 0, ntap = 0, prec = 0, log2n = 0, log2b = -1;
+  int64_t nblock = 0;
+  int dev = 0;
+  bool row_lds = false;  // frame fits the LDS-resident row kernels
+  bool col_lds = false;  // nblock is a supported column length
+  double* win64 = nullptr;
+  void* winT = nullptr;
+  void* twN = nullptr;
+  void* twB = nullptr;
+  double* twB64 = nullptr;
+  void* work = nullptr;  // d (inverse) or z (adjoint): nblock*lblock reals
+  void* tmp = nullptr;   // four-step intermediate of long frames: nblock*lblock/2 complex
+  double* part = nullptr;
+  int jchunk = 1, nchunks = 1;
+  size_t bytes = 0;
+};
+
+namespace {
+
+size_t esize(int prec) { return prec == IPFB_F32 ? sizeof(float) : sizeof(double); }
+
+int dev_alloc(ipfb_plan p, void** ptr, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (inject("alloc")) return fail(IPFB_ENOMEM, "device allocation of %zu bytes failed (injected)", bytes);
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? IPFB_ENOMEM : IPFB_EHIP, "hipMalloc(%zu): %s", bytes,
+                hipGetErrorString(e));
+  }
+  p->bytes += bytes;
+  return IPFB_OK;
+}
+
+int upload(void* dst, const void* src, size_t bytes) {
+  hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(IPFB_EHIP, "hipMemcpy: %s", hipGetErrorString(e));
+  return IPFB_OK;
+}
+
+int upload_table(ipfb_plan p, const std::vector<double>& t, int prec, void** dst) {
+  const size_t n = t.size();
+  int st = dev_alloc(p, dst, n * esize(prec));
+  if (st) return st;
+  if (prec == IPFB_F64) return upload(*dst, t.data(), n * sizeof(double));
+  std::vector<float> f(n);
+  for (size_t i = 0; i < n; ++i) f[i] = (float)t[i];
+  return upload(*dst, f.data(), n * sizeof(float));
+}
+
+void free_plan(ipfb_plan p) {
+  void* ptrs[] = {p->win64, p->winT, p->twN, p->twB, p->twB64, p->work, p->tmp, p->part};
+  for (void* q : ptrs)
+    if (q) hipFree(q);
+  delete p;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) hipSetDevice(prev);
+  }
+};
+
+int launched(hipError_t e, const char* what) {
+  if (inject("launch")) e = hipErrorLaunchFailure;
+  if (e != hipSuccess) {
+    hipGetLastError();
+    return fail(IPFB_EHIP, "%s: %s", what, hipGetErrorString(e));
+  }
+  return ok();
+}
+
+int max_log2_row(int prec) { return prec == IPFB_F32 ? kMaxLog2RowF32 : kMaxLog2RowF64; }
+int max_log2_col(int prec) { return prec == IPFB_F32 ? kMaxLog2ColF32 : kMaxLog2ColF64; }
+
+int check_plan(ipfb_plan p) {
+  if (!p) return fail(IPFB_EINVAL, "plan is NULL");
+  return IPFB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ipfb_last_error(void) { return g_err.c_str(); }
+
+const char* ipfb_version(void) { return "ipfb-mi355x 0.1 (gfx950)"; }
+
+int ipfb_window_sinc_hamming(double* out, int ntap, int lblock) {
+  if (!out) return fail(IPFB_EINVAL, "window output is NULL");
+  if (ntap < 1 || lblock < 1) return fail(IPFB_EINVAL, "ntap and lblock must be >= 1");
+  const int64_t M = (int64_t)ntap * lblock;
+  const long double pi = 3.14159265358979323846264338327950288L;
+  for (int64_t m = 0; m < M; ++m) {
+    const long double t = ((long double)m - (long double)M / 2.0L) / (long double)lblock;
+    const long double sinc = (t == 0.0L) ? 1.0L : sinl(pi * t) / (pi * t);
+    const long double taper = (M > 1) ? 0.54L - 0.46L * cosl(2.0L * pi * (long double)m / (long double)(M - 1)) : 1.0L;
+    out[m] = (double)(sinc * taper);
+  }
+  return ok();
+}
+
+int ipfb_plan_create(ipfb_plan* out, int lblock, int ntap, const double* window, int64_t nblock, int prec) {
+  if (!out) return fail(IPFB_EINVAL, "plan output pointer is NULL");
+  *out = nullptr;
+  if (!window) return fail(IPFB_EINVAL, "window is NULL");
+  if (prec != IPFB_F32 && prec != IPFB_F64) return fail(IPFB_EINVAL, "prec must be IPFB_F32 or IPFB_F64");
+  if (!is_pow2(lblock) || lblock < 4) return fail(IPFB_EINVAL, "lblock must be a power of two >= 4 (got %d)", lblock);
+  if (lblock > (1 << 20)) return fail(IPFB_EUNSUPPORTED, "lblock > 2^20 is not supported");
+  if (ntap < 1) return fail(IPFB_EINVAL, "ntap must be >= 1 (got %d)", ntap);
+  if (nblock < 1) return fail(IPFB_EINVAL, "nblock must be >= 1");
+  if (nblock > (int64_t(1) << 31) / 1) return fail(IPFB_EUNSUPPORTED, "nblock too large");
+  if ((int64_t)lblock * nblock > (int64_t(1) << 40)) return fail(IPFB_EUNSUPPORTED, "timestream too long");
+
+  ipfb_plan p = new ipfb_plan_s();
+  p->lblock = lblock;
+  p->ntap = ntap;
+  p->prec = prec;
+  p->nblock = nblock;
+  p->log2n = ilog2(lblock);
+  p->row_lds = p->log2n <= max_log2_row(prec);
+  if (is_pow2(nblock) && nblock >= 4 && ilog2(nblock) <= max_log2_col(prec)) {
+    p->col_lds = true;
+    p->log2b = ilog2(nblock);
+  }
+  if (hipGetDevice(&p->dev) != hipSuccess) {
+    hipGetLastError();
+    delete p;
+    return fail(IPFB_EHIP, "no HIP device available");
+  }
+  const int64_t M = (int64_t)ntap * lblock;
+  int st = dev_alloc(p, (void**)&p->win64, M * sizeof(double));
+  if (!st) st = upload(p->win64, window, M * sizeof(double));
+  if (!st) st = dev_alloc(p, &p->winT, M * esize(prec));
+  if (!st) {
+    if (prec == IPFB_F64) st = upload(p->winT, window, M * sizeof(double));
+    else {
+      std::vector<float> w(M);
+      for (int64_t i = 0; i < M; ++i) w[i] = (float)window[i];
+      st = upload(p->winT, w.data(), M * sizeof(float));
+    }
+  }
+  if (!st) st = upload_table(p, twiddles(lblock), prec, &p->twN);
+  if (!st && p->col_lds) {
+    std::vector<double> tb = twiddles(nblock);
+    st = upload_table(p, tb, prec, &p->twB);
+    if (!st) st = upload_table(p, tb, IPFB_F64, (void**)&p->twB64);
+  }
+  const size_t frames_bytes = (size_t)nblock * lblock * esize(prec);
+  if (!st && p->row_lds) st = dev_alloc(p, &p->work, frames_bytes);
+  if (!st && !p->row_lds) st = dev_alloc(p, &p->tmp, frames_bytes);
+  if (!st) {
+    p->nchunks = (int)(nblock < 16 ? nblock : 16);
+    p->jchunk = (int)((nblock + p->nchunks - 1) / p->nchunks);
+    p->nchunks = (int)((nblock + p->jchunk - 1) / p->jchunk);
+    st = dev_alloc(p, (void**)&p->part, (size_t)p->nchunks * (lblock / 2 + 1) * sizeof(double));
+  }
+  if (st) {
+    std::string keep = g_err;
+    free_plan(p);
+    g_err = keep;
+    return st;
+  }
+  *out = p;
+  return ok();
+}
+
+int ipfb_plan_destroy(ipfb_plan plan) {
+  if (!plan) return fail(IPFB_EINVAL, "plan is NULL");
+  DeviceGuard g(plan->dev);
+  free_plan(plan);
+  return ok();
+}
+
+int ipfb_plan_workspace_size(ipfb_plan plan, size_t* bytes) {
+  if (check_plan(plan)) return IPFB_EINVAL;
+  if (!bytes) return fail(IPFB_EINVAL, "bytes is NULL");
+  *bytes = plan->bytes;
+  return ok();
+}
+
+int pfb_forward(ipfb_plan p, const void* x, void* y, void* stream) {
+  if (check_plan(p)) return IPFB_EINVAL;
+  if (!x || !y) return fail(IPFB_EINVAL, "x and y must be non-NULL device pointers");
+  DeviceGuard g(p->dev);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  if (p->row_lds)
+    e = launch_pfb_fwd_small(p->prec, p->log2n, x, y, p->nblock, p->ntap, p->winT, p->twN, st);
+  else
+    e = launch_pfb_fwd_large(p->prec, p->log2n, x, y, p->nblock, p->ntap, p->winT, p->twN, p->tmp, st);
+  return launched(e, "pfb_forward");
+}
+
+int pfb_adjoint(ipfb_plan p, const void* y, void* x, void* stream) {
+  if (check_plan(p)) return IPFB_EINVAL;
+  if (!x || !y) return fail(IPFB_EINVAL, "x and y must be non-NULL device pointers");
+  if (!p->row_lds) return fail(IPFB_EUNSUPPORTED, "pfb_adjoint supports lblock <= 2^%d", max_log2_row(p->prec));
+  DeviceGuard g(p->dev);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_row_irfft(p->prec, p->log2n, IN_ADJ, y, nullptr, p->work, p->nblock, p->twN, st);
+  if (e == hipSuccess) e = launch_adjoint_gather(p->prec, p->work, x, p->nblock, p->lblock, p->ntap, p->winT, st);
+  return launched(e, "pfb_adjoint");
+}
+
+int ipfb_wiener_ex(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, double phi, int normalise,
+                   void* x_out, void* stream) {
+  if (check_plan(p)) return IPFB_EINVAL;
+  if (!spec || !x_out) return fail(IPFB_EINVAL, "spec and x_out must be non-NULL device pointers");
+  if (infmt != IPFB_IN_C4 && infmt != IPFB_IN_CF32 && infmt != IPFB_IN_CF64)
+    return fail(IPFB_EINVAL, "unknown input format %d", infmt);
+  if (infmt == IPFB_IN_C4 && !chan_scale) return fail(IPFB_EINVAL, "chan_scale is required for IPFB_IN_C4");
+  if (!(phi >= 0.0) || !std::isfinite(phi)) return fail(IPFB_EINVAL, "phi must be finite and >= 0");
+  if (!p->row_lds)
+    return fail(IPFB_EUNSUPPORTED, "ipfb_wiener supports lblock <= 2^%d for this precision", max_log2_row(p->prec));
+  if (!p->col_lds)
+    return fail(IPFB_EUNSUPPORTED, "ipfb_wiener needs nblock a power of two in [4, 2^%d] (got %lld)",
+                max_log2_col(p->prec), (long long)p->nblock);
+  DeviceGuard g(p->dev);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_row_irfft(p->prec, p->log2n, infmt, spec, chan_scale, p->work, p->nblock, p->twN, st);
+  if (e == hipSuccess)
+    e = launch_col_wiener(p->prec, p->log2b, p->work, x_out, p->lblock, p->ntap, p->win64, phi, normalise, p->twB,
+                          p->twB64, st);
+  return launched(e, "ipfb_wiener");
+}
+
+int ipfb_wiener(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, double phi, void* x_out,
+                void* stream) {
+  return ipfb_wiener_ex(p, infmt, spec, chan_scale, phi, 1, x_out, stream);
+}
+
+int ipfb_autospectrum(ipfb_plan p, const void* y, double* autospec, void* stream) {
+  if (check_plan(p)) return IPFB_EINVAL;
+  if (!y || !autospec) return fail(IPFB_EINVAL, "y and autospec must be non-NULL device pointers");
+  DeviceGuard g(p->dev);
+  hipStream_t st = (hipStream_t)stream;
+  const int K = p->lblock / 2 + 1;
+  hipError_t e = launch_power_partial(p->prec, y, p->nblock, K, p->jchunk, p->part, st);
+  if (e == hipSuccess) e = launch_power_final(p->part, p->nchunks, K, 1.0 / (double)p->nblock, autospec, st);
+  return launched(e, "ipfb_autospectrum");
+}
+
+int upchannelize(ipfb_plan fine, const void* x, void* y_fine, double* autospec, void* stream) {
+  int s = pfb_forward(fine, x, y_fine, stream);
+  if (s) return s;
+  if (autospec) return ipfb_autospectrum(fine, y_fine, autospec, stream);
+  return ok();
+}
+
+int ipfb_quantize_c4(ipfb_plan p, const void* y, double levels_rms, uint8_t* packed, float* scales, void* stream) {
+  if (check_plan(p)) return IPFB_EINVAL;
+  if (!y || !packed || !scales) return fail(IPFB_EINVAL, "y, packed and scales must be non-NULL device pointers");
+  if (!(levels_rms > 0.0)) return fail(IPFB_EINVAL, "levels_rms must be > 0");
+  DeviceGuard g(p->dev);
+  hipStream_t st = (hipStream_t)stream;
+  const int K = p->lblock / 2 + 1;
+  // halfpow_k = mean_j |y_jk|^2 / 2 lands in the last row of the partials
+  double* halfpow = p->part;  // reuse: final sums overwrite chunk 0 after the partial pass
+  hipError_t e = launch_power_partial(p->prec, y, p->nblock, K, p->jchunk, p->part, st);
+  if (e == hipSuccess) e = launch_power_final(p->part, p->nchunks, K, 0.5 / (double)p->nblock, halfpow, st);
+  if (e == hipSuccess) e = launch_scales(halfpow, K, levels_rms, scales, st);
+  if (e == hipSuccess) e = launch_quantize(p->prec, y, p->nblock, K, scales, packed, st);
+  return launched(e, "ipfb_quantize_c4");
+}
+
+}  // extern "C"

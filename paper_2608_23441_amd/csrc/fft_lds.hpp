@@ -1,0 +1,215 @@
+// LDS-resident Stockham FFTs for gfx950 (wave64), used by every kernel of the
+// circulant inverse PFB: the N-point row transforms that undo F, the b-point
+// column transforms of the circulant decorrelation (Section 3.1), and the
+// transforms of the forward PFB used for up-channelization (Section 2.2).
+//
+// A workgroup transforms C independent complex sequences of length L (a power
+// of two) that sit in LDS at stride LS. Each pass loads all of a thread's
+// butterfly inputs into registers, waits at a barrier, and writes the radix-R
+// outputs in autosort (Stockham) order, so no bit reversal is ever needed.
+// Twiddles come from a precomputed table of exp(-2 pi i m / LT) (computed in
+// double precision on the host and rounded once for the float form).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace ipfb {
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T a, T b) { cx<T> r; r.x = a; r.y = b; return r; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return mk<T>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return mk<T>(a.x, -a.y); }
+template <typename T>
+__device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+// multiply by DIR*i  (DIR = -1: forward transform kernel e^{-i...}; +1 inverse)
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) {
+  if constexpr (DIR < 0) return mk<T>(a.y, -a.x);
+  else return mk<T>(-a.y, a.x);
+}
+
+// ---- small DFT codelets, in registers ------------------------------------
+template <int DIR, typename T>
+__device__ __forceinline__ void dft2(cx<T>* v) {
+  cx<T> a = v[0];
+  v[0] = a + v[1];
+  v[1] = a - v[1];
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+  cx<T> y0 = a0 + a2, y1 = a0 - a2, y2 = a1 + a3, y3 = mul_i<DIR>(a1 - a3);
+  a0 = y0 + y2;
+  a2 = y0 - y2;
+  a1 = y1 + y3;
+  a3 = y1 - y3;
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft4v(cx<T>* v) { dft4<DIR>(v[0], v[1], v[2], v[3]); }
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+  const T h = T(0.70710678118654752440084436210485);
+  cx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  cx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4<DIR>(e0, e1, e2, e3);
+  dft4<DIR>(o0, o1, o2, o3);
+  // w8^1 = (h, DIR*h), w8^2 = DIR*i, w8^3 = (-h, DIR*h)
+  o1 = mk<T>(h * (o1.x - T(DIR) * o1.y), h * (o1.y + T(DIR) * o1.x));
+  o2 = mul_i<DIR>(o2);
+  o3 = mk<T>(-h * (o3.x + T(DIR) * o3.y), h * (T(DIR) * o3.x - o3.y));
+  v[0] = e0 + o0; v[4] = e0 - o0;
+  v[1] = e1 + o1; v[5] = e1 - o1;
+  v[2] = e2 + o2; v[6] = e2 - o2;
+  v[3] = e3 + o3; v[7] = e3 - o3;
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> rot16(cx<T> a, int m) {
+  // a * exp(DIR * 2 pi i m / 16), m in {1,2,3,4,6,9}
+  const T c1 = T(0.92387953251128675612818318939679);
+  const T s1 = T(0.38268343236508977172845998403040);
+  const T h = T(0.70710678118654752440084436210485);
+  T c, s;
+  switch (m) {
+    case 1: c = c1; s = s1; break;
+    case 2: c = h; s = h; break;
+    case 3: c = s1; s = c1; break;
+    case 4: c = 0; s = 1; break;
+    case 6: c = -h; s = h; break;
+    default: c = -c1; s = -s1; break;  // m = 9: angle 202.5 deg
+  }
+  s *= T(DIR);
+  return mk<T>(a.x * c - a.y * s, a.x * s + a.y * c);
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft16(cx<T>* v) {
+  // X[k1 + 4 k2] = sum_{n2} w4^{n2 k2} w16^{n2 k1} sum_{n1} a[4 n1 + n2] w4^{n1 k1}
+  cx<T> b[16];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    cx<T> a0 = v[n2], a1 = v[n2 + 4], a2 = v[n2 + 8], a3 = v[n2 + 12];
+    dft4<DIR>(a0, a1, a2, a3);
+    b[n2 * 4 + 0] = a0;
+    b[n2 * 4 + 1] = (n2 == 0) ? a1 : rot16<DIR>(a1, n2);
+    b[n2 * 4 + 2] = (n2 == 0) ? a2 : rot16<DIR>(a2, 2 * n2);
+    b[n2 * 4 + 3] = (n2 == 0) ? a3 : rot16<DIR>(a3, 3 * n2);
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cx<T> a0 = b[k1], a1 = b[4 + k1], a2 = b[8 + k1], a3 = b[12 + k1];
+    dft4<DIR>(a0, a1, a2, a3);
+    v[k1] = a0;
+    v[k1 + 4] = a1;
+    v[k1 + 8] = a2;
+    v[k1 + 12] = a3;
+  }
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dftR(cx<T>* v) {
+  if constexpr (R == 2) dft2<DIR>(v);
+  else if constexpr (R == 4) dft4v<DIR>(v);
+  else if constexpr (R == 8) dft8<DIR>(v);
+  else dft16<DIR>(v);
+}
+
+__host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
+
+// ---- one Stockham pass ------------------------------------------------------
+// s: C sequences of length L at stride LS. Ns: product of radices already done.
+// tw: table of exp(-2 pi i m / LT) with LT = L * twmul.
+template <typename T, int L, int R, int NT, int C, int DIR>
+__device__ __forceinline__ void stockham_pass(cx<T>* s, int LS, int Ns, const cx<T>* __restrict__ tw,
+                                              int twmul) {
+  constexpr int LR = L / R;
+  constexpr int NB = C * LR;
+  constexpr int BPT = (NB + NT - 1) / NT;
+  const int tid = threadIdx.x;
+  cx<T> v[BPT][R];
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    const int g = tid + i * NT;
+    if ((NB % NT == 0) || g < NB) {
+      const int c = g / LR, j = g % LR;
+      const cx<T>* src = s + c * LS + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = src[r * LR];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    const int g = tid + i * NT;
+    if ((NB % NT == 0) || g < NB) {
+      const int c = g / LR, j = g % LR;
+      const int k = j & (Ns - 1);
+      if (Ns > 1) {
+        const int step = (L / (Ns * R)) * twmul;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cx<T> w = tw[r * k * step];
+          v[i][r] = (DIR < 0) ? cmul(v[i][r], w) : cmulc(v[i][r], w);
+        }
+      }
+      dftR<R, DIR>(v[i]);
+      cx<T>* dst = s + c * LS + (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * Ns] = v[i][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Radix schedule: P passes of at most RMAXLOG bits each, bits spread evenly.
+template <typename T, int L, int NT, int C, int DIR, int RMAXLOG, int PASS, int NSLOG>
+__device__ __forceinline__ void stockham_rec(cx<T>* s, int LS, const cx<T>* __restrict__ tw, int twmul) {
+  constexpr int E = ilog2c(L);
+  constexpr int P = (E + RMAXLOG - 1) / RMAXLOG;
+  if constexpr (PASS < P) {
+    constexpr int bits = E / P + ((PASS < E % P) ? 1 : 0);
+    constexpr int R = 1 << bits;
+    stockham_pass<T, L, R, NT, C, DIR>(s, LS, 1 << NSLOG, tw, twmul);
+    stockham_rec<T, L, NT, C, DIR, RMAXLOG, PASS + 1, NSLOG + bits>(s, LS, tw, twmul);
+  }
+}
+
+// Full unnormalised transform, exp(DIR * 2 pi i jk / L). Ends with a barrier.
+template <typename T, int L, int NT, int C, int DIR>
+__device__ __forceinline__ void lds_fft(cx<T>* s, int LS, const cx<T>* __restrict__ tw, int twmul) {
+  if constexpr (L > 1) {
+    constexpr int EPT = (L * C) / NT;  // elements per thread
+    constexpr int RM = EPT >= 16 ? 4 : (EPT >= 8 ? 3 : (EPT >= 4 ? 2 : 1));
+    stockham_rec<T, L, NT, C, DIR, RM, 0, 0>(s, LS, tw, twmul);
+  }
+}
+
+// Workgroup index remapping so that logically adjacent workgroups share an
+// XCD (gfx950 dispatches workgroups round-robin over its 8 XCDs, each with
+// its own L2): adjacent column groups then meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int xcd = bid & 7, slot = bid >> 3;
+  return (xcd < r) ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+}
+
+}  // namespace ipfb

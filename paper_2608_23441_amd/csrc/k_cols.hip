@@ -1,0 +1,171 @@
+// Column stage of the circulant inverse PFB (Section 3.1, the decorrelation
+// x_n = F^dagger[ F d_n / (F w_n)^* ], with the Wiener weights of Section 4.1):
+// for every sub-filter path n, a b-point FFT down column n of d, a pointwise
+// FP64 gain, and the inverse FFT, written back in time order.
+//
+// One workgroup owns C adjacent columns. A real column of b samples becomes a
+// b/2-point complex sequence z[m] = d[2m][n] + i d[2m+1][n]; after the forward
+// FFT, the pass that separates the real spectrum X[k], applies the gain and
+// re-packs for the inverse touches the pair (k, b/2-k) in one thread, in
+// double precision. The gain is computed on the fly from the p taps of the
+// column,  W_n(f) = sum_r h[rN+n] e^{-2 pi i r f / b},
+//          G = W (1+phi^2) / (|W|^2 + phi^2) / b,
+// so no N x b table ever touches HBM. Workgroups that own neighbouring columns
+// are placed on the same XCD so the strided rows they share meet in one L2.
+#include "fft_lds.hpp"
+#include "launch.hpp"
+
+namespace ipfb {
+
+template <typename T, int LOG2B>
+struct ColCfg {
+  static constexpr int H = 1 << (LOG2B - 1);
+  static constexpr int BYTES = H * (int)sizeof(cx<T>);
+  static constexpr int C0 = 131072 / BYTES;
+  static constexpr int C = C0 < 1 ? 1 : (C0 > 16 ? 16 : C0);  // columns per workgroup
+  static constexpr int LS = H + (C > 1 ? 1 : 0);              // padded LDS stride
+  static constexpr int EPT = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int NT0 = (H * C) / EPT;
+  static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 1024 ? 1024 : NT0);
+};
+
+struct GainArgs {
+  const double* win;  // [ntap][lblock], FP64
+  int lblock, ntap;
+  double phi2;        // phi^2
+  double gnorm;       // (1 + phi^2) / b  (or 1/b without the normalisation)
+  int naive;          // phi == 0: 1/conj(W), truncated
+};
+
+// G_n(f) for f in [0, b); twB64[m] = e^{-2 pi i m / b}.
+template <int B>
+__device__ __forceinline__ cx<double> wiener_gain(const GainArgs& ga, int n, int f,
+                                                  const cx<double>* __restrict__ twB64) {
+  double wr = 0.0, wi = 0.0, wabs = 0.0;
+  for (int r = 0; r < ga.ntap; ++r) {
+    const double h = ga.win[(int64_t)r * ga.lblock + n];
+    const cx<double> e = twB64[(int)(((int64_t)r * f) & (B - 1))];
+    wr += h * e.x;
+    wi += h * e.y;
+    wabs += fabs(h);
+  }
+  const double a2 = wr * wr + wi * wi;
+  if (ga.naive) {
+    // plain division by conj(W); eigenvalues at rounding level are dropped
+    if (sqrt(a2) <= 1e-12 * wabs) return mk<double>(0.0, 0.0);
+    const double s = 1.0 / (a2 * (double)B);
+    return mk<double>(wr * s, wi * s);
+  }
+  const double s = ga.gnorm / (a2 + ga.phi2);
+  return mk<double>(wr * s, wi * s);
+}
+
+template <typename T, int LOG2B>
+__global__ __launch_bounds__((ColCfg<T, LOG2B>::NT)) void k_col_wiener(
+    const T* __restrict__ d, T* __restrict__ xo, int nwg, GainArgs ga, const cx<T>* __restrict__ twB,
+    const cx<double>* __restrict__ twB64) {
+  using Cfg = ColCfg<T, LOG2B>;
+  constexpr int B = 1 << LOG2B, H = Cfg::H, C = Cfg::C, LS = Cfg::LS, NT = Cfg::NT;
+  constexpr int HP = H / 2 + 1;
+  __shared__ cx<T> s[C * LS];
+  T* sf = reinterpret_cast<T*>(s);
+  const int tid = threadIdx.x;
+  const int N = ga.lblock;
+  const int n0 = xcd_remap(blockIdx.x, nwg) * C;
+
+  // gather the C columns: C consecutive floats per frame
+  for (int e = tid; e < B * C; e += NT) {
+    const int row = e / C, c = e % C;
+    const int n = n0 + c;
+    T v = T(0);
+    if (n < N) v = d[(int64_t)row * N + n];
+    sf[2 * (c * LS + (row >> 1)) + (row & 1)] = v;
+  }
+  __syncthreads();
+  lds_fft<T, H, NT, C, -1>(s, LS, twB, 2);
+
+  // split the packed spectrum, apply the gain, re-pack for the inverse
+  for (int e = tid; e < C * HP; e += NT) {
+    const int c = e / HP, k = e % HP;
+    const int n = n0 + c;
+    if (n >= N) continue;
+    cx<T>* col = s + c * LS;
+    if (k == 0) {
+      const cx<T> z0 = col[0];
+      const double x0 = (double)z0.x + (double)z0.y;  // X[0]
+      const double xh = (double)z0.x - (double)z0.y;  // X[b/2]
+      const double y0 = wiener_gain<B>(ga, n, 0, twB64).x * x0;
+      const double yh = wiener_gain<B>(ga, n, H, twB64).x * xh;
+      col[0] = mk<T>(T(y0 + yh), T(y0 - yh));
+      continue;
+    }
+    const int km = H - k;
+    const cx<T> zk = col[k], zm = col[km];
+    const cx<double> Zk = mk<double>(zk.x, zk.y), Zm = mk<double>(zm.x, zm.y);
+    const cx<double> ek = twB64[k];          // e^{-2 pi i k / b}
+    const cx<double> A = Zk + conj(Zm);
+    const cx<double> Bd = Zk - conj(Zm);
+    const cx<double> eB = cmul(ek, Bd);
+    // X[k] = A/2 - i e B/2 ;  X[H-k] = conj(A)/2 - i conj(e B)/2
+    const cx<double> Xk = mk<double>(0.5 * (A.x + eB.y), 0.5 * (A.y - eB.x));
+    const cx<double> Xm = mk<double>(0.5 * (A.x - eB.y), 0.5 * (-A.y - eB.x));
+    const cx<double> Yk = cmul(wiener_gain<B>(ga, n, k, twB64), Xk);
+    const cx<double> Ym = cmul(wiener_gain<B>(ga, n, km, twB64), Xm);
+    // Z'[k] = P + i conj(e) Q ;  Z'[H-k] = conj(P) + i e conj(Q)
+    const cx<double> P = Yk + conj(Ym);
+    const cx<double> Q = Yk - conj(Ym);
+    const cx<double> t1 = cmulc(Q, ek);            // conj(e) Q
+    const cx<double> t2 = cmul(ek, conj(Q));       // e conj(Q)
+    col[k] = mk<T>(T(P.x - t1.y), T(P.y + t1.x));
+    if (km != k) col[km] = mk<T>(T(P.x - t2.y), T(-P.y + t2.x));
+  }
+  __syncthreads();
+  lds_fft<T, H, NT, C, +1>(s, LS, twB, 2);
+
+  for (int e = tid; e < B * C; e += NT) {
+    const int row = e / C, c = e % C;
+    const int n = n0 + c;
+    if (n < N) xo[(int64_t)row * N + n] = sf[2 * (c * LS + (row >> 1)) + (row & 1)];
+  }
+}
+
+template <typename T, int LOG2B>
+static hipError_t launch_col_t(const void* d, void* xo, const GainArgs& ga, const void* twB,
+                               const double* twB64, hipStream_t st) {
+  using Cfg = ColCfg<T, LOG2B>;
+  const int nwg = (ga.lblock + Cfg::C - 1) / Cfg::C;
+  k_col_wiener<T, LOG2B><<<dim3(nwg), dim3(Cfg::NT), 0, st>>>(
+      (const T*)d, (T*)xo, nwg, ga, (const cx<T>*)twB, (const cx<double>*)twB64);
+  return hipGetLastError();
+}
+
+#define COL_CASE(T, L) \
+  case L: return launch_col_t<T, L>(d, xo, ga, twB, twB64, st);
+
+hipError_t launch_col_wiener(int prec, int log2b, const void* d, void* xo, int lblock, int ntap,
+                             const double* win64, double phi, int normalise, const void* twB,
+                             const double* twB64, hipStream_t st) {
+  GainArgs ga;
+  ga.win = win64;
+  ga.lblock = lblock;
+  ga.ntap = ntap;
+  ga.phi2 = phi * phi;
+  ga.naive = (phi == 0.0);
+  ga.gnorm = (normalise ? (1.0 + phi * phi) : 1.0) / (double)(1LL << log2b);
+  if (prec == F32) {
+    switch (log2b) {
+      COL_CASE(float, 2) COL_CASE(float, 3) COL_CASE(float, 4) COL_CASE(float, 5) COL_CASE(float, 6)
+      COL_CASE(float, 7) COL_CASE(float, 8) COL_CASE(float, 9) COL_CASE(float, 10) COL_CASE(float, 11)
+      COL_CASE(float, 12) COL_CASE(float, 13) COL_CASE(float, 14) COL_CASE(float, 15)
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (log2b) {
+    COL_CASE(double, 2) COL_CASE(double, 3) COL_CASE(double, 4) COL_CASE(double, 5) COL_CASE(double, 6)
+    COL_CASE(double, 7) COL_CASE(double, 8) COL_CASE(double, 9) COL_CASE(double, 10) COL_CASE(double, 11)
+    COL_CASE(double, 12) COL_CASE(double, 13) COL_CASE(double, 14)
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ipfb

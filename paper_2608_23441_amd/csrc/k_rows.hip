@@ -1,0 +1,158 @@
+// Row stage of the circulant inverse PFB (Section 3: an N-point inverse FFT
+// per spectrum undoes F; Appendix C: the first of the three FFT stages).
+//
+// One workgroup inverts C spectra. The N-point inverse real FFT runs as an
+// N/2-point complex inverse FFT on
+//   Z[k] = (Y[k] + conj Y[N/2-k]) + i e^{+2 pi i k/N} (Y[k] - conj Y[N/2-k]),
+// whose output z[m] holds the real samples 2m (real part) and 2m+1 (imaginary
+// part). Dequantisation of the 4-bit input and the 1/N normalisation are
+// folded into Y, so the spectra are read once, straight from HBM, and the
+// frame is written once as contiguous float2/double2.
+#include "fft_lds.hpp"
+#include "launch.hpp"
+
+namespace ipfb {
+
+template <typename T, int FMT>
+__device__ __forceinline__ cx<T> load_spec(const void* __restrict__ in, const float* __restrict__ sc,
+                                           int64_t idx, int k, int N) {
+  if constexpr (FMT == IN_C4) {
+    const signed char b = reinterpret_cast<const signed char*>(in)[idx];
+    const int re = b >> 4;                            // high nibble, sign-extended
+    const int im = (signed char)(b << 4) >> 4;        // low nibble, sign-extended
+    const T f = T(1.0 / ((double)sc[k] * (double)N));
+    return mk<T>(T(re) * f, T(im) * f);
+  } else if constexpr (FMT == IN_CF32) {
+    const cx<float> v = reinterpret_cast<const cx<float>*>(in)[idx];
+    const T f = T(1.0 / (double)N);
+    return mk<T>(T(v.x) * f, T(v.y) * f);
+  } else if constexpr (FMT == IN_CF64) {
+    const cx<double> v = reinterpret_cast<const cx<double>*>(in)[idx];
+    const double f = 1.0 / (double)N;
+    return mk<T>(T(v.x * f), T(v.y * f));
+  } else {  // IN_ADJ: (N/2) irfft(c y) with c_0 = c_{N/2} = 2
+    const cx<T> v = reinterpret_cast<const cx<T>*>(in)[idx];
+    const T f = (k == 0 || k == N / 2) ? T(1) : T(0.5);
+    return mk<T>(v.x * f, v.y * f);
+  }
+}
+
+template <typename T, int LOG2N>
+struct RowCfg {
+  static constexpr int H = 1 << (LOG2N - 1);
+  static constexpr int C = H >= 1024 ? 1 : 1024 / H;  // frames per workgroup
+  static constexpr int EPT = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int NT0 = (H * C) / EPT;
+  static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 1024 ? 1024 : NT0);
+};
+
+template <typename T, int LOG2N, int FMT>
+__global__ __launch_bounds__((RowCfg<T, LOG2N>::NT)) void k_row_irfft(
+    const void* __restrict__ in, const float* __restrict__ sc, T* __restrict__ out, int64_t nrows,
+    const cx<T>* __restrict__ twN) {
+  using Cfg = RowCfg<T, LOG2N>;
+  constexpr int N = 1 << LOG2N, H = Cfg::H, C = Cfg::C, NT = Cfg::NT;
+  __shared__ cx<T> s[C * H];
+  const int tid = threadIdx.x;
+  const int64_t row0 = (int64_t)blockIdx.x * C;
+  for (int e = tid; e < C * H; e += NT) {
+    const int c = e / H, k = e % H;
+    const int64_t row = row0 + c;
+    cx<T> z = mk<T>(T(0), T(0));
+    if (row < nrows) {
+      const int64_t base = row * (H + 1);
+      cx<T> yk = load_spec<T, FMT>(in, sc, base + k, k, N);
+      cx<T> ym = load_spec<T, FMT>(in, sc, base + (H - k), H - k, N);
+      if (k == 0) {  // DC and Nyquist imaginary parts carry nothing for a real frame
+        yk.y = T(0);
+        ym.y = T(0);
+      }
+      const cx<T> a = yk + conj(ym);
+      const cx<T> bdiff = yk - conj(ym);
+      const cx<T> w = conj(twN[k]);  // e^{+2 pi i k / N}
+      const cx<T> t = cmul(w, bdiff);
+      z = mk<T>(a.x - t.y, a.y + t.x);  // a + i t
+    }
+    s[c * H + k] = z;
+  }
+  __syncthreads();
+  lds_fft<T, H, NT, C, +1>(s, H, twN, 2);
+  for (int e = tid; e < C * H; e += NT) {
+    const int c = e / H, m = e % H;
+    const int64_t row = row0 + c;
+    if (row < nrows) reinterpret_cast<cx<T>*>(out + row * N)[m] = s[c * H + m];
+  }
+}
+
+template <typename T, int LOG2N>
+static hipError_t launch_row_t(int fmt, const void* in, const float* sc, void* out, int64_t nrows,
+                               const void* twN, hipStream_t st) {
+  using Cfg = RowCfg<T, LOG2N>;
+  const int64_t grid = (nrows + Cfg::C - 1) / Cfg::C;
+  if (grid == 0) return hipSuccess;
+  const cx<T>* tw = reinterpret_cast<const cx<T>*>(twN);
+  T* o = reinterpret_cast<T*>(out);
+  switch (fmt) {
+    case IN_C4: k_row_irfft<T, LOG2N, IN_C4><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(in, sc, o, nrows, tw); break;
+    case IN_CF32: k_row_irfft<T, LOG2N, IN_CF32><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(in, sc, o, nrows, tw); break;
+    case IN_CF64: k_row_irfft<T, LOG2N, IN_CF64><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(in, sc, o, nrows, tw); break;
+    default: k_row_irfft<T, LOG2N, IN_ADJ><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(in, sc, o, nrows, tw); break;
+  }
+  return hipGetLastError();
+}
+
+#define ROW_CASE(T, L) \
+  case L: return launch_row_t<T, L>(fmt, in, chan_scale, out, nrows, twN, st);
+
+hipError_t launch_row_irfft(int prec, int log2n, int fmt, const void* in, const float* chan_scale,
+                            void* out, int64_t nrows, const void* twN, hipStream_t st) {
+  if (prec == F32) {
+    switch (log2n) {
+      ROW_CASE(float, 2) ROW_CASE(float, 3) ROW_CASE(float, 4) ROW_CASE(float, 5) ROW_CASE(float, 6)
+      ROW_CASE(float, 7) ROW_CASE(float, 8) ROW_CASE(float, 9) ROW_CASE(float, 10) ROW_CASE(float, 11)
+      ROW_CASE(float, 12) ROW_CASE(float, 13) ROW_CASE(float, 14) ROW_CASE(float, 15)
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (log2n) {
+    ROW_CASE(double, 2) ROW_CASE(double, 3) ROW_CASE(double, 4) ROW_CASE(double, 5) ROW_CASE(double, 6)
+    ROW_CASE(double, 7) ROW_CASE(double, 8) ROW_CASE(double, 9) ROW_CASE(double, 10) ROW_CASE(double, 11)
+    ROW_CASE(double, 12) ROW_CASE(double, 13) ROW_CASE(double, 14)
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Transpose of the sliding multiply-and-sum (needed by the adjoint):
+// x[i][n] = sum_{r<p} h[rN+n] z[(i-r) mod b][n]. Contiguous along n.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adjoint_gather(const T* __restrict__ z, T* __restrict__ x,
+                                                        int64_t nblock, int lblock, int ntap, int nchunk,
+                                                        const T* __restrict__ win) {
+  const int64_t i = blockIdx.x / nchunk;
+  const int n = (blockIdx.x % nchunk) * 256 + threadIdx.x;
+  if (n >= lblock) return;
+  T acc = T(0);
+  for (int r = 0; r < ntap; ++r) {
+    int64_t src = (i - r) % nblock;
+    if (src < 0) src += nblock;
+    acc += win[(int64_t)r * lblock + n] * z[src * lblock + n];
+  }
+  x[i * lblock + n] = acc;
+}
+
+hipError_t launch_adjoint_gather(int prec, const void* z, void* x, int64_t nblock, int lblock, int ntap,
+                                 const void* winT, hipStream_t st) {
+  if (nblock == 0) return hipSuccess;
+  const int nchunk = (lblock + 255) / 256;
+  const dim3 grid((unsigned)(nblock * nchunk));
+  if (prec == F32)
+    k_adjoint_gather<float><<<grid, 256, 0, st>>>((const float*)z, (float*)x, nblock, lblock, ntap, nchunk,
+                                                  (const float*)winT);
+  else
+    k_adjoint_gather<double><<<grid, 256, 0, st>>>((const double*)z, (double*)x, nblock, lblock, ntap,
+                                                   nchunk, (const double*)winT);
+  return hipGetLastError();
+}
+
+}  // namespace ipfb

@@ -1,0 +1,54 @@
+// Internal launcher declarations shared by the kernel translation units and
+// the C-ABI layer. Every launcher returns hipSuccess or the launch error.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ipfb {
+
+enum Prec { F32 = 0, F64 = 1 };
+// Input spectrum formats of the inverse (match the public header).
+enum InFmt { IN_C4 = 0, IN_CF32 = 2, IN_CF64 = 3, IN_ADJ = 100 };
+
+// Largest power-of-two lengths each LDS-resident kernel accepts.
+constexpr int kMaxLog2RowF32 = 15;  // N real = 2^15 -> 16384 complex, 128 KiB
+constexpr int kMaxLog2RowF64 = 14;
+constexpr int kMaxLog2ColF32 = 15;
+constexpr int kMaxLog2ColF64 = 14;
+
+// Row stage: d_j = inverse real FFT of spectrum j, times per-channel factors.
+// fmt IN_C4: packed 4-bit, factor 1/(s_k N); IN_CF32/IN_CF64: factor 1/N;
+// IN_ADJ: complex in the plan precision, factor c_k/2 (transpose of the
+// half-spectrum DFT).
+hipError_t launch_row_irfft(int prec, int log2n, int fmt, const void* in, const float* chan_scale,
+                            void* out, int64_t nrows, const void* twN, hipStream_t st);
+
+// Column stage: per column n, x_n = F^-1[ G_n F d_n ] with the FP64 gain.
+hipError_t launch_col_wiener(int prec, int log2b, const void* d, void* xo, int lblock, int ntap,
+                             const double* win64, double phi, int normalise, const void* twB,
+                             const double* twB64, hipStream_t st);
+
+// Forward PFB with LDS-resident rows (N <= 2^kMaxLog2Row*).
+hipError_t launch_pfb_fwd_small(int prec, int log2n, const void* x, void* y, int64_t nblock, int ntap,
+                                const void* winT, const void* twN, hipStream_t st);
+
+// Forward PFB for long frames: four-step over H = N/2 = R1 * R2.
+hipError_t launch_pfb_fwd_large(int prec, int log2n, const void* x, void* y, int64_t nblock, int ntap,
+                                const void* winT, const void* twN, void* tmp, hipStream_t st);
+
+// x[i][n] = sum_r h[rN+n] z[(i-r) mod b][n]
+hipError_t launch_adjoint_gather(int prec, const void* z, void* x, int64_t nblock, int lblock, int ntap,
+                                 const void* winT, hipStream_t st);
+
+// part[c][k] = sum_{j in chunk c} |y_jk|^2 (FP64), nchunks = ceil(nspec / jchunk).
+hipError_t launch_power_partial(int prec, const void* y, int64_t nspec, int nchan, int jchunk,
+                                double* part, hipStream_t st);
+// out[k] = mult * sum_c part[c][k]
+hipError_t launch_power_final(const double* part, int nchunks, int nchan, double mult, double* out,
+                              hipStream_t st);
+// s_k = float(levels / sqrt(pw_k)), where pw_k = mean power / 2 is given.
+hipError_t launch_scales(const double* halfpow, int nchan, double levels, float* scales, hipStream_t st);
+hipError_t launch_quantize(int prec, const void* y, int64_t nspec, int nchan, const float* scales,
+                           uint8_t* packed, hipStream_t st);
+
+}  // namespace ipfb

@@ -1,0 +1,228 @@
+"""Thin Python binding of libipfb (ctypes). Argument marshalling only: every
+step of the computation runs in the HIP kernels behind the C ABI.
+
+Tensors are torch tensors on the GPU (torch provides device memory and
+streams). Real arrays are float32 for F32 plans and float64 for F64 plans;
+complex arrays are complex64 / complex128 (interleaved re, im).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libipfb.so")
+
+F32, F64 = 0, 1
+IN_C4, IN_CF32, IN_CF64 = 0, 2, 3
+OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = 0, -1, -2, -3, -4
+
+# Symbols the C ABI exports (include/ipfb.h).
+EXPORTS = (
+    "ipfb_last_error", "ipfb_version", "ipfb_window_sinc_hamming", "ipfb_plan_create",
+    "ipfb_plan_destroy", "ipfb_plan_workspace_size", "pfb_forward", "pfb_adjoint", "ipfb_wiener",
+    "ipfb_wiener_ex", "upchannelize", "ipfb_autospectrum", "ipfb_quantize_c4",
+)
+
+
+class IpfbError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"ipfb status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libipfb.so from the package directory; fails loudly if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libipfb.so not built at {LIB_PATH}; run __graft_entry__.build() "
+                              "(or python paper_2608_23441_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+        L.ipfb_last_error.restype = ctypes.c_char_p
+        L.ipfb_version.restype = ctypes.c_char_p
+        L.ipfb_window_sinc_hamming.argtypes = [vp, i32, i32]
+        L.ipfb_plan_create.argtypes = [ctypes.POINTER(vp), i32, i32, vp, i64, i32]
+        L.ipfb_plan_destroy.argtypes = [vp]
+        L.ipfb_plan_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.pfb_forward.argtypes = [vp, vp, vp, vp]
+        L.pfb_adjoint.argtypes = [vp, vp, vp, vp]
+        L.ipfb_wiener.argtypes = [vp, i32, vp, vp, dbl, vp, vp]
+        L.ipfb_wiener_ex.argtypes = [vp, i32, vp, vp, dbl, i32, vp, vp]
+        L.upchannelize.argtypes = [vp, vp, vp, vp, vp]
+        L.ipfb_autospectrum.argtypes = [vp, vp, vp, vp]
+        L.ipfb_quantize_c4.argtypes = [vp, vp, dbl, vp, vp, vp]
+        for name in EXPORTS:
+            getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
+        L.ipfb_last_error.restype = ctypes.c_char_p
+        L.ipfb_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != OK:
+        raise IpfbError(status, lib().ipfb_last_error().decode())
+
+
+def window_sinc_hamming(ntap: int, lblock: int) -> np.ndarray:
+    """The library's sinc x Hamming window (host, float64 [ntap*lblock])."""
+    out = np.empty(ntap * lblock, dtype=np.float64)
+    _check(lib().ipfb_window_sinc_hamming(out.ctypes.data, int(ntap), int(lblock)))
+    return out
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, name):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A plan for frames of `lblock` samples, `ntap` taps and `nblock` frames."""
+
+    def __init__(self, lblock: int, ntap: int, window, nblock: int, prec: int = F32):
+        self.lblock, self.ntap, self.nblock, self.prec = int(lblock), int(ntap), int(nblock), int(prec)
+        w = np.ascontiguousarray(np.asarray(window, dtype=np.float64))
+        if w.size != self.lblock * self.ntap:
+            raise ValueError("window must have ntap*lblock taps")
+        h = ctypes.c_void_p()
+        _check(lib().ipfb_plan_create(ctypes.byref(h), self.lblock, self.ntap, w.ctypes.data,
+                                      self.nblock, self.prec))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def nchan(self):
+        return self.lblock // 2 + 1
+
+    @property
+    def real_dtype(self):
+        import torch
+        return torch.float32 if self.prec == F32 else torch.float64
+
+    @property
+    def complex_dtype(self):
+        import torch
+        return torch.complex64 if self.prec == F32 else torch.complex128
+
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().ipfb_plan_workspace_size(self._h, ctypes.byref(b)))
+        return b.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ipfb_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- shape checks (marshalling) --
+    def _real(self, t, name):
+        if t.dtype != self.real_dtype or t.numel() != self.nblock * self.lblock:
+            raise ValueError(f"{name}: expected {self.real_dtype} with {self.nblock * self.lblock} elements")
+        return _ptr(t, name)
+
+    def _cplx(self, t, name):
+        if t.dtype != self.complex_dtype or t.numel() != self.nblock * self.nchan:
+            raise ValueError(f"{name}: expected {self.complex_dtype} with {self.nblock * self.nchan} elements")
+        return _ptr(t, name)
+
+
+def _empty(shape, dtype):
+    import torch
+    return torch.empty(shape, dtype=dtype, device="cuda")
+
+
+def pfb_forward(plan: Plan, x, y=None, stream=None):
+    if y is None:
+        y = _empty((plan.nblock, plan.nchan), plan.complex_dtype)
+    _check(lib().pfb_forward(plan.handle, plan._real(x, "x"), plan._cplx(y, "y"), _stream(stream)))
+    return y
+
+
+def pfb_adjoint(plan: Plan, y, x=None, stream=None):
+    if x is None:
+        x = _empty((plan.nblock * plan.lblock,), plan.real_dtype)
+    _check(lib().pfb_adjoint(plan.handle, plan._cplx(y, "y"), plan._real(x, "x"), _stream(stream)))
+    return x
+
+
+def ipfb_wiener(plan: Plan, spec, chan_scale=None, phi: float = 0.1, x_out=None, normalise: bool = True,
+                stream=None):
+    """spec: uint8 [nblock, nchan] (4-bit packed, needs chan_scale float32 [nchan]),
+    complex64 or complex128 [nblock, nchan]."""
+    import torch
+    if spec.dtype == torch.uint8:
+        fmt = IN_C4
+        if chan_scale is None or chan_scale.dtype != torch.float32 or chan_scale.numel() != plan.nchan:
+            raise ValueError("chan_scale: float32 [nchan] is required for packed 4-bit spectra")
+    elif spec.dtype == torch.complex64:
+        fmt = IN_CF32
+    elif spec.dtype == torch.complex128:
+        fmt = IN_CF64
+    else:
+        raise ValueError("spec must be uint8 (packed 4-bit), complex64 or complex128")
+    if spec.numel() != plan.nblock * plan.nchan:
+        raise ValueError("spec must hold nblock * (lblock/2+1) values")
+    if x_out is None:
+        x_out = _empty((plan.nblock * plan.lblock,), plan.real_dtype)
+    _check(lib().ipfb_wiener_ex(plan.handle, fmt, _ptr(spec, "spec"), _ptr(chan_scale, "chan_scale"),
+                                float(phi), int(bool(normalise)), plan._real(x_out, "x_out"),
+                                _stream(stream)))
+    return x_out
+
+
+def upchannelize(fine: Plan, x, y_fine=None, autospec=None, want_autospec: bool = True, stream=None):
+    import torch
+    if y_fine is None:
+        y_fine = _empty((fine.nblock, fine.nchan), fine.complex_dtype)
+    if autospec is None and want_autospec:
+        autospec = _empty((fine.nchan,), torch.float64)
+    if autospec is not None and (autospec.dtype != torch.float64 or autospec.numel() != fine.nchan):
+        raise ValueError("autospec: float64 [nchan]")
+    _check(lib().upchannelize(fine.handle, fine._real(x, "x"), fine._cplx(y_fine, "y_fine"),
+                              _ptr(autospec, "autospec"), _stream(stream)))
+    return y_fine, autospec
+
+
+def autospectrum(plan: Plan, y, out=None, stream=None):
+    import torch
+    if out is None:
+        out = _empty((plan.nchan,), torch.float64)
+    _check(lib().ipfb_autospectrum(plan.handle, plan._cplx(y, "y"), _ptr(out, "out"), _stream(stream)))
+    return out
+
+
+def quantize_c4(plan: Plan, y, levels_rms: float = 2.5, stream=None):
+    import torch
+    packed = _empty((plan.nblock, plan.nchan), torch.uint8)
+    scales = _empty((plan.nchan,), torch.float32)
+    _check(lib().ipfb_quantize_c4(plan.handle, plan._cplx(y, "y"), float(levels_rms), _ptr(packed, "packed"),
+                                  _ptr(scales, "scales"), _stream(stream)))
+    return packed, scales

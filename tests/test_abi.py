@@ -1,0 +1,78 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, validates arguments before touching the device, and its host
+window helper matches the oracle's window."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import ipfb_oracle as O
+from paper_2608_23441_amd import ipfb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "ipfb.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\*?\s+\*?(\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_header_symbol():
+    L = ipfb.lib()
+    names = _header_functions()
+    assert "ipfb_wiener" in names and "pfb_adjoint" in names and "upchannelize" in names
+    for n in names:
+        assert hasattr(L, n), f"missing export {n}"
+    assert set(ipfb.EXPORTS) <= set(names)
+    assert b"gfx950" in L.ipfb_version()
+
+
+def test_window_helper_matches_oracle():
+    for ntap, lblock in [(4, 64), (4, 2048), (3, 32), (1, 16)]:
+        w = ipfb.window_sinc_hamming(ntap, lblock)
+        assert np.abs(w - O.window_sinc_hamming(ntap, lblock)).max() < 1e-15
+
+
+def _create(lblock, ntap, window, nblock, prec):
+    h = ctypes.c_void_p()
+    w = np.ascontiguousarray(window, dtype=np.float64)
+    st = ipfb.lib().ipfb_plan_create(ctypes.byref(h), lblock, ntap,
+                                     w.ctypes.data if w.size else None, nblock, prec)
+    return st, h
+
+
+@pytest.mark.parametrize("lblock,ntap,nblock,prec", [
+    (3, 4, 16, 0),       # not a power of two
+    (2, 4, 16, 0),       # too short
+    (64, 0, 16, 0),      # no taps
+    (64, 4, 0, 0),       # no frames
+    (64, 4, 16, 7),      # bad precision
+])
+def test_plan_create_rejects_bad_arguments(lblock, ntap, nblock, prec):
+    st, h = _create(lblock, ntap, np.ones(max(1, lblock * max(ntap, 1))), nblock, prec)
+    assert st == ipfb.EINVAL
+    assert not h.value
+    assert len(ipfb.lib().ipfb_last_error()) > 0
+
+
+def test_plan_create_rejects_null_window_and_huge_frames():
+    h = ctypes.c_void_p()
+    assert ipfb.lib().ipfb_plan_create(ctypes.byref(h), 64, 4, None, 16, 0) == ipfb.EINVAL
+    st, _ = _create(1 << 21, 1, np.ones(1), 4, 0)
+    assert st == ipfb.EUNSUPPORTED
+
+
+def test_calls_reject_null_plan_and_pointers():
+    L = ipfb.lib()
+    assert L.pfb_forward(None, None, None, None) == ipfb.EINVAL
+    assert L.pfb_adjoint(None, None, None, None) == ipfb.EINVAL
+    assert L.ipfb_wiener(None, 0, None, None, 0.1, None, None) == ipfb.EINVAL
+    assert L.upchannelize(None, None, None, None, None) == ipfb.EINVAL
+    assert L.ipfb_autospectrum(None, None, None, None) == ipfb.EINVAL
+    assert L.ipfb_quantize_c4(None, None, 2.5, None, None, None) == ipfb.EINVAL
+    assert L.ipfb_plan_destroy(None) == ipfb.EINVAL
+    assert L.ipfb_window_sinc_hamming(None, 4, 16) == ipfb.EINVAL
