@@ -1,0 +1,273 @@
+#!/usr/bin/env python3
+"""Throughput of the circulant inverse PFB + up-channelization on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input already
+resident in HBM: dequantise the 4-bit spectra, row inverse FFTs, column
+Wiener decorrelation (inverse PFB), then the forward PFB at a 64x longer frame
+(up-channelization) and its autospectrum.
+
+Workload (production size): white Gaussian noise (sigma = 1) plus 5 narrow
+tones (amplitude 0.1), lblock = 4096, ntap = 4, sinc x Hamming window,
+nblock = 16384 (2^26 samples), channelised by the library's forward PFB in
+FP64 and quantised to 4 bits per component (per-channel RMS = 2.5 levels);
+Wiener phi = 0.1; up-channelize x64: lblock' = 262144, ntap' = 4,
+nblock' = 256. The headline is the FP32 form; the FP64 form is timed beside it.
+
+Prints one JSON line. Only the `cpu_baseline` leg touches the CPU oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "reconstructed samples/s + HBM GB/s, FP32 vs FP64 form at ≤1e-5 rel RMS"
+HBM_PEAK_GBPS = 8000.0
+
+# Algorithmic bytes per launch, by kernel: what each kernel must read and
+# write across its own boundary (per reconstructed sample, FP32):
+#  ipfb_rows          : 1 B per 4-bit complex value ((N/2+1)/N per sample) + 4 B d write
+#  ipfb_transpose_in  : 4 B d read + 4 B d_T write
+#  ipfb_cols          : 4 B d_T read + 4 B x_T write
+#  ipfb_transpose_out : 4 B x_T read + 4 B xhat write
+#  pfb_fwd_long       : pass 1 reads xhat (4 B) and writes the packed row
+#                       (4 B); pass 2 reads it (4 B) and writes the fine
+#                       spectra (4 B)
+#  autospec_final     : the per-chunk power sums
+# The step is priced separately at the method's compulsory traffic (see
+# step_bytes), independent of this kernel split.
+
+
+def kernel_bytes(name, N, b, Nf, bf, esz):
+    S = N * b
+    K = Nf // 2 + 1
+    if name == "ipfb_rows":
+        return b * (N // 2 + 1) * 1 + (N // 2 + 1) * 4 + S * esz
+    if name in ("ipfb_transpose_in", "ipfb_cols", "ipfb_transpose_out"):
+        return 2 * S * esz
+    if name == "pfb_fwd_long":
+        return S * esz + 4 * Nf * esz + 2 * S * esz + bf * K * 2 * esz
+    if name == "autospec_final":
+        return 8 * ((bf + 1) // 2 + 15) // 16 * K * 8 + K * 8
+    return None
+
+
+def step_bytes(N, b, Nf, bf, esz):
+    """Compulsory HBM bytes of one step: packed input + scales, d written and
+    read once, xhat written, xhat read by the fine PFB, fine window, fine
+    spectra written."""
+    S = N * b
+    return (b * (N // 2 + 1) + 4 * (N // 2 + 1) + 2 * S * esz + S * esz + S * esz + 4 * Nf * esz
+            + bf * (Nf // 2 + 1) * 2 * esz)
+
+
+def source_digest():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2608_23441_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, valid only if
+    the kernel sources are unchanged since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        t = json.load(open(p))
+    except Exception:
+        return None
+    if t.get("source_digest") != source_digest():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+def make_inputs(torch, ipfb, inputs, N, p, b, seed, ntones, tone_seed, amp, levels):
+    """Synthetic 4-bit spectra made on the GPU by the library's own FP64
+    forward PFB and quantiser (input synthesis, not timed)."""
+    x = inputs.timestream_with_tones(N * b, seed, ntones, tone_seed, amp)
+    w = ipfb.window_sinc_hamming(p, N)
+    plan64 = ipfb.Plan(N, p, w, b, ipfb.F64)
+    xd = torch.from_numpy(x).cuda()
+    y = ipfb.pfb_forward(plan64, xd)
+    packed, scales = ipfb.quantize_c4(plan64, y, levels)
+    torch.cuda.synchronize()
+    del xd, y
+    plan64.close()
+    return x, w, packed, scales
+
+
+def time_steps(torch, step, steps, warmup):
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(N, p, Nf, phi, frames, seed):
+    """The FP64 numpy oracle on a bounded sample of the same workload: the
+    same steps (dequantise, row inverse, column Wiener inverse, x64
+    up-channelize with autospectrum) over `frames` frames."""
+    import numpy as np
+
+    from oracle import ipfb_oracle as O
+    from paper_2608_23441_amd import inputs as I
+
+    S = N * frames
+    x = I.timestream_with_tones(S, seed, 5, 102, 0.1)
+    w = O.window_sinc_hamming(p, N)
+    y = O.pfb_forward(x, w, N, p)
+    s = O.channel_scales(y, 2.5)
+    qr, qi = O.quantize(y, s)
+    packed = O.pack_c4(qr, qi)
+    wf = O.window_sinc_hamming(4, Nf)
+    t0 = time.perf_counter()
+    xh = O.ipfb_wiener(packed, s, w, N, p, phi)
+    Y = O.upchannelize(xh, Nf, 4, wf)
+    O.autospectrum(Y)
+    dt = time.perf_counter() - t0
+    threads = 1  # numpy's pocketfft and elementwise kernels run on one thread
+    return {"value": S / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"lblock={N}, ntap={p}, nblock={frames} ({S} samples, "
+                      f"{S / (N * 16384):.3f} of the workload), phi={phi}, x{Nf // N} up-channelize "
+                      f"(lblock'={Nf}, nblock'={S // Nf}) with autospectrum; FP64 numpy oracle, "
+                      f"{dt:.1f} s on {os.cpu_count()} visible host cores",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip timing the FP64 form")
+    ap.add_argument("--cpu-frames", type=int, default=16384)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(streams and columns shard without communication; see the design notes).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2608_23441_amd import inputs, ipfb
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    N, p, b, u, phi = 4096, 4, 16384, 64, 0.1
+    Nf = N * u
+    bf = (N * b) // Nf
+    S = N * b
+
+    _, w, packed, scales = make_inputs(torch, ipfb, inputs, N, p, b, 2, 5, 102, 0.1, 2.5)
+    wf = ipfb.window_sinc_hamming(4, Nf)
+
+    results = {}
+    outputs = {}
+    kernels = ["ipfb_rows", "ipfb_transpose_in", "ipfb_cols", "ipfb_transpose_out", "pfb_fwd_long",
+               "autospec_final"]
+    forms = [("f32", ipfb.F32)] + ([] if args.no_fp64 else [("f64", ipfb.F64)])
+    for tag, prec in forms:
+        coarse = ipfb.Plan(N, p, w, b, prec)
+        fine = ipfb.Plan(Nf, 4, wf, bf, prec)
+        xh = torch.empty(S, dtype=coarse.real_dtype, device="cuda")
+        Y = torch.empty((bf, Nf // 2 + 1), dtype=fine.complex_dtype, device="cuda")
+        A = torch.empty(Nf // 2 + 1, dtype=torch.float64, device="cuda")
+
+        def step():
+            ipfb.ipfb_wiener(coarse, packed, scales, phi, x_out=xh)
+            ipfb.upchannelize(fine, xh, Y, A)
+
+        steps = args.steps if tag == "f32" else max(5, args.steps // 2)
+        ipfb.profile_reset()
+        ipfb.profile_enable(True)
+        sec = time_steps(torch, step, steps, args.warmup)
+        ipfb.profile_enable(False)
+        per_kernel = {}
+        for k in kernels:
+            ms, n = ipfb.profile_query(k)
+            if n:
+                per_kernel[k] = {"avg_us": 1e3 * ms / n, "launches": n}
+        ipfb.profile_reset()
+        esz = 4 if tag == "f32" else 8
+        results[tag] = {"sec_per_step": sec, "per_kernel": per_kernel, "esz": esz, "steps": steps}
+        outputs[tag] = (xh, Y, A)
+        del coarse, fine
+
+    # FP32 form against the FP64 form on the same ints (both parity-tested
+    # against the oracle elsewhere)
+    agree = None
+    if "f64" in outputs:
+        x32, Y32, A32 = outputs["f32"]
+        x64, Y64, A64 = outputs["f64"]
+        ex = float(torch.linalg.vector_norm(x32.double() - x64) / torch.linalg.vector_norm(x64))
+        eY = float(torch.linalg.vector_norm(Y32.to(torch.complex128) - Y64) / torch.linalg.vector_norm(Y64))
+        eA = float(torch.max(torch.abs(A32 - A64) / A64))
+        agree = {"timestream_rel_rms": ex, "fine_spectra_rel_rms": eY, "autospec_max_rel": eA}
+
+    r32 = results["f32"]
+    sec = r32["sec_per_step"]
+    pk = r32["per_kernel"]
+    dom = max(pk, key=lambda k: pk[k]["avg_us"])
+    alg = kernel_bytes(dom, N, b, Nf, bf, 4)
+    achieved = alg / (pk[dom]["avg_us"] * 1e-6) / 1e9
+    sb32 = step_bytes(N, b, Nf, bf, 4)
+    out = {
+        "metric": METRIC,
+        "value": S / sec,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": r32["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "production: white noise + 5 tones, 4-bit spectra, Wiener inverse PFB, "
+                               "x64 up-channelize with autospectrum",
+                   "lblock": N, "ntap": p, "nblock": b, "samples": S, "phi": phi,
+                   "lblock_fine": Nf, "nblock_fine": bf, "window": "sinc x Hamming"},
+        "hbm_GBps": sb32 / sec / 1e9,
+        "hbm_roofline_frac": sb32 / sec / 1e9 / HBM_PEAK_GBPS,
+        "step_bytes": sb32,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": load_traffic(dom),
+                     "alg_bytes_per_launch": alg, "avg_us": pk[dom]["avg_us"]},
+        "per_kernel_us": {k: round(v["avg_us"], 2) for k, v in pk.items()},
+        "per_kernel_GBps": {k: round(kernel_bytes(k, N, b, Nf, bf, 4) / (v["avg_us"] * 1e-6) / 1e9, 1)
+                            for k, v in pk.items() if kernel_bytes(k, N, b, Nf, bf, 4)},
+    }
+    if "f64" in results:
+        r64 = results["f64"]
+        sb64 = step_bytes(N, b, Nf, bf, 8)
+        out["fp64_form"] = {"value": S / r64["sec_per_step"], "unit": "samples/s",
+                            "ms_per_step": r64["sec_per_step"] * 1e3,
+                            "hbm_GBps": sb64 / r64["sec_per_step"] / 1e9,
+                            "per_kernel_us": {k: round(v["avg_us"], 2) for k, v in r64["per_kernel"].items()}}
+        out["fp32_vs_fp64"] = agree
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(N, p, Nf, phi, args.cpu_frames, 2)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -131,6 +131,17 @@ int ipfb_autospectrum(ipfb_plan plan, const void* y, double* autospec, void* str
 int ipfb_quantize_c4(ipfb_plan plan, const void* y, double levels_rms, uint8_t* packed, float* scales,
                      void* stream);
 
+/* Instrumentation: per-kernel timing with HIP events recorded on the
+ * launching stream around every kernel the library enqueues (names:
+ * "ipfb_rows", "ipfb_cols", "pfb_fwd", "pfb_fwd_A", "pfb_fwd_B",
+ * "adj_rows", "adj_gather", "autospec_partial", "autospec_final").
+ * ipfb_profile_enable(1) starts recording (process-wide); ipfb_profile_query
+ * waits for the recorded events and returns the summed milliseconds and
+ * launch count for one name; ipfb_profile_reset drops all records. */
+int ipfb_profile_enable(int on);
+int ipfb_profile_reset(void);
+int ipfb_profile_query(const char* name, double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

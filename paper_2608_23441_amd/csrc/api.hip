@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -83,11 +84,15 @@ struct ipfb_plan_s {
   void* winT = nullptr;
   void* twN = nullptr;
   void* twB = nullptr;
+  void* twS = nullptr;   // long frames: small tables for the two passes
   double* twB64 = nullptr;
   void* work = nullptr;  // d (inverse) or z (adjoint): nblock*lblock reals
+  void* work2 = nullptr; // transposed frame matrix for the column stage
   void* tmp = nullptr;   // four-step intermediate of long frames: nblock*lblock/2 complex
   double* part = nullptr;
+  void* fac = nullptr;   // per-channel dequantisation factors 1/(s_k N)
   int jchunk = 1, nchunks = 1;
+  int qchunk = 1, nqchunks = 1;  // long frames: frame pairs per power-sum chunk
   size_t bytes = 0;
 };
 
@@ -126,7 +131,7 @@ int upload_table(ipfb_plan p, const std::vector<double>& t, int prec, void** dst
 }
 
 void free_plan(ipfb_plan p) {
-  void* ptrs[] = {p->win64, p->winT, p->twN, p->twB, p->twB64, p->work, p->tmp, p->part};
+  void* ptrs[] = {p->win64, p->winT, p->twN, p->twB, p->twB64, p->work, p->work2, p->tmp, p->part, p->fac, p->twS};
   for (void* q : ptrs)
     if (q) hipFree(q);
   delete p;
@@ -151,6 +156,53 @@ int launched(hipError_t e, const char* what) {
   }
   return ok();
 }
+
+// ---- per-kernel timing with HIP events on the launching stream ---------------
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::mutex g_pm;
+bool g_prof = false;
+std::vector<ProfRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t ev_get() {
+  std::lock_guard<std::mutex> lk(g_pm);
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+struct ProfScope {
+  const char* name;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  ProfScope(const char* n, hipStream_t s) : name(n), st(s) {
+    bool on;
+    {
+      std::lock_guard<std::mutex> lk(g_pm);
+      on = g_prof;
+    }
+    if (on && (a = ev_get())) hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = ev_get();
+    if (!b) return;
+    hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_pm);
+    g_recs.push_back({name, a, b});
+  }
+};
 
 int max_log2_row(int prec) { return prec == IPFB_F32 ? kMaxLog2RowF32 : kMaxLog2RowF64; }
 int max_log2_col(int prec) { return prec == IPFB_F32 ? kMaxLog2ColF32 : kMaxLog2ColF64; }
@@ -230,12 +282,33 @@ int ipfb_plan_create(ipfb_plan* out, int lblock, int ntap, const double* window,
   }
   const size_t frames_bytes = (size_t)nblock * lblock * esize(prec);
   if (!st && p->row_lds) st = dev_alloc(p, &p->work, frames_bytes);
-  if (!st && !p->row_lds) st = dev_alloc(p, &p->tmp, frames_bytes);
+  if (!st && p->row_lds && p->col_lds) st = dev_alloc(p, &p->work2, frames_bytes);
+  if (!st && p->row_lds) st = dev_alloc(p, &p->fac, (size_t)(lblock / 2 + 1) * esize(prec));
+  if (!st && !p->row_lds) st = dev_alloc(p, &p->tmp, (size_t)(nblock + 1) * lblock * esize(prec));
+  if (!st && !p->row_lds) {
+    const int l1 = (p->log2n + 1) / 2, l2 = p->log2n / 2;
+    const int64_t P1 = int64_t(1) << l1, P2 = int64_t(1) << l2, nhi = lblock / 512;
+    std::vector<double> t1 = twiddles(P1), t2 = twiddles(P2), tl = twiddles(lblock);
+    std::vector<double> all;
+    all.insert(all.end(), t1.begin(), t1.end());
+    all.insert(all.end(), t2.begin(), t2.end());
+    all.insert(all.end(), tl.begin(), tl.begin() + 2 * 512);
+    for (int64_t m = 0; m < nhi; ++m) {
+      all.push_back(tl[2 * (512 * m)]);
+      all.push_back(tl[2 * (512 * m) + 1]);
+    }
+    st = upload_table(p, all, prec, &p->twS);
+  }
   if (!st) {
+    // deterministic two-stage power sums: at most 16 chunks of spectra
     p->nchunks = (int)(nblock < 16 ? nblock : 16);
     p->jchunk = (int)((nblock + p->nchunks - 1) / p->nchunks);
     p->nchunks = (int)((nblock + p->jchunk - 1) / p->jchunk);
-    st = dev_alloc(p, (void**)&p->part, (size_t)p->nchunks * (lblock / 2 + 1) * sizeof(double));
+    const int64_t nq = (nblock + 1) / 2;  // long frames: chunks of frame pairs
+    p->qchunk = (int)((nq + 31) / 32);  // up to 32 chunks: enough workgroups for the second pass
+    p->nqchunks = (int)((nq + p->qchunk - 1) / p->qchunk);
+    const int nrows = p->nchunks > p->nqchunks ? p->nchunks : p->nqchunks;
+    st = dev_alloc(p, (void**)&p->part, (size_t)nrows * (lblock / 2 + 1) * sizeof(double));
   }
   if (st) {
     std::string keep = g_err;
@@ -267,10 +340,14 @@ int pfb_forward(ipfb_plan p, const void* x, void* y, void* stream) {
   DeviceGuard g(p->dev);
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;
-  if (p->row_lds)
+  if (p->row_lds) {
+    ProfScope ps("pfb_fwd", st);
     e = launch_pfb_fwd_small(p->prec, p->log2n, x, y, p->nblock, p->ntap, p->winT, p->twN, st);
-  else
-    e = launch_pfb_fwd_large(p->prec, p->log2n, x, y, p->nblock, p->ntap, p->winT, p->twN, p->tmp, st);
+  } else {
+    ProfScope ps("pfb_fwd_long", st);
+    e = launch_pfb_fwd_large(p->prec, p->log2n, x, y, p->nblock, p->ntap, p->winT, p->twS, p->tmp, p->qchunk,
+                             nullptr, st);
+  }
   return launched(e, "pfb_forward");
 }
 
@@ -280,8 +357,15 @@ int pfb_adjoint(ipfb_plan p, const void* y, void* x, void* stream) {
   if (!p->row_lds) return fail(IPFB_EUNSUPPORTED, "pfb_adjoint supports lblock <= 2^%d", max_log2_row(p->prec));
   DeviceGuard g(p->dev);
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_row_irfft(p->prec, p->log2n, IN_ADJ, y, nullptr, p->work, p->nblock, p->twN, st);
-  if (e == hipSuccess) e = launch_adjoint_gather(p->prec, p->work, x, p->nblock, p->lblock, p->ntap, p->winT, st);
+  hipError_t e;
+  {
+    ProfScope ps("adj_rows", st);
+    e = launch_row_irfft(p->prec, p->log2n, IN_ADJ, y, nullptr, p->work, p->nblock, p->twN, st);
+  }
+  if (e == hipSuccess) {
+    ProfScope ps("adj_gather", st);
+    e = launch_adjoint_gather(p->prec, p->work, x, p->nblock, p->lblock, p->ntap, p->winT, st);
+  }
   return launched(e, "pfb_adjoint");
 }
 
@@ -300,10 +384,27 @@ int ipfb_wiener_ex(ipfb_plan p, int infmt, const void* spec, const float* chan_s
                 max_log2_col(p->prec), (long long)p->nblock);
   DeviceGuard g(p->dev);
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e = launch_row_irfft(p->prec, p->log2n, infmt, spec, chan_scale, p->work, p->nblock, p->twN, st);
-  if (e == hipSuccess)
-    e = launch_col_wiener(p->prec, p->log2b, p->work, x_out, p->lblock, p->ntap, p->win64, phi, normalise, p->twB,
+  hipError_t e;
+  {
+    ProfScope ps("ipfb_rows", st);
+    if (infmt == IPFB_IN_C4) e = launch_dequant_factors(p->prec, chan_scale, p->lblock / 2 + 1, p->lblock, p->fac, st);
+    else e = hipSuccess;
+    if (e == hipSuccess)
+      e = launch_row_irfft(p->prec, p->log2n, infmt, spec, p->fac, p->work, p->nblock, p->twN, st);
+  }
+  if (e == hipSuccess) {  // d [b][N] -> d_T [N][b]
+    ProfScope ps("ipfb_transpose_in", st);
+    e = launch_transpose(p->prec, p->work, p->work2, p->nblock, p->lblock, st);
+  }
+  if (e == hipSuccess) {  // d_T -> x_T, both [N][b]
+    ProfScope ps("ipfb_cols", st);
+    e = launch_col_wiener(p->prec, p->log2b, p->work2, p->work, p->lblock, p->ntap, p->win64, phi, normalise, p->twB,
                           p->twB64, st);
+  }
+  if (e == hipSuccess) {  // x_T [N][b] -> x [b][N]
+    ProfScope ps("ipfb_transpose_out", st);
+    e = launch_transpose(p->prec, p->work, x_out, p->lblock, p->nblock, st);
+  }
   return launched(e, "ipfb_wiener");
 }
 
@@ -318,12 +419,37 @@ int ipfb_autospectrum(ipfb_plan p, const void* y, double* autospec, void* stream
   DeviceGuard g(p->dev);
   hipStream_t st = (hipStream_t)stream;
   const int K = p->lblock / 2 + 1;
-  hipError_t e = launch_power_partial(p->prec, y, p->nblock, K, p->jchunk, p->part, st);
-  if (e == hipSuccess) e = launch_power_final(p->part, p->nchunks, K, 1.0 / (double)p->nblock, autospec, st);
+  hipError_t e;
+  {
+    ProfScope ps("autospec_partial", st);
+    e = launch_power_partial(p->prec, y, p->nblock, K, p->jchunk, p->part, st);
+  }
+  if (e == hipSuccess) {
+    ProfScope ps("autospec_final", st);
+    e = launch_power_final(p->part, p->nchunks, K, 1.0 / (double)p->nblock, autospec, st);
+  }
   return launched(e, "ipfb_autospectrum");
 }
 
 int upchannelize(ipfb_plan fine, const void* x, void* y_fine, double* autospec, void* stream) {
+  if (check_plan(fine)) return IPFB_EINVAL;
+  if (!fine->row_lds && autospec && x && y_fine) {
+    // long frames: the power sums ride along in the second FFT pass
+    DeviceGuard g(fine->dev);
+    hipStream_t st = (hipStream_t)stream;
+    const int K = fine->lblock / 2 + 1;
+    hipError_t e;
+    {
+      ProfScope ps("pfb_fwd_long", st);
+      e = launch_pfb_fwd_large(fine->prec, fine->log2n, x, y_fine, fine->nblock, fine->ntap, fine->winT, fine->twS,
+                               fine->tmp, fine->qchunk, fine->part, st);
+    }
+    if (e == hipSuccess) {
+      ProfScope ps("autospec_final", st);
+      e = launch_power_final(fine->part, fine->nqchunks, K, 1.0 / (double)fine->nblock, autospec, st);
+    }
+    return launched(e, "upchannelize");
+  }
   int s = pfb_forward(fine, x, y_fine, stream);
   if (s) return s;
   if (autospec) return ipfb_autospectrum(fine, y_fine, autospec, stream);
@@ -344,6 +470,41 @@ int ipfb_quantize_c4(ipfb_plan p, const void* y, double levels_rms, uint8_t* pac
   if (e == hipSuccess) e = launch_scales(halfpow, K, levels_rms, scales, st);
   if (e == hipSuccess) e = launch_quantize(p->prec, y, p->nblock, K, scales, packed, st);
   return launched(e, "ipfb_quantize_c4");
+}
+
+int ipfb_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_pm);
+  g_prof = (on != 0);
+  return IPFB_OK;
+}
+
+int ipfb_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(g_pm);
+  for (auto& r : g_recs) {
+    hipEventSynchronize(r.b);
+    g_pool.push_back(r.a);
+    g_pool.push_back(r.b);
+  }
+  g_recs.clear();
+  return IPFB_OK;
+}
+
+int ipfb_profile_query(const char* name, double* total_ms, int64_t* launches) {
+  if (!name || !total_ms || !launches) return fail(IPFB_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(g_pm);
+  double tot = 0.0;
+  int64_t n = 0;
+  for (auto& r : g_recs) {
+    if (strcmp(r.name, name) != 0) continue;
+    if (hipEventSynchronize(r.b) != hipSuccess) return fail(IPFB_EHIP, "hipEventSynchronize failed");
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return fail(IPFB_EHIP, "hipEventElapsedTime failed");
+    tot += ms;
+    ++n;
+  }
+  *total_ms = tot;
+  *launches = n;
+  return ok();
 }
 
 }  // extern "C"

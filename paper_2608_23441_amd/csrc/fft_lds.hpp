@@ -135,8 +135,16 @@ __device__ __forceinline__ void dftR(cx<T>* v) {
 
 __host__ __device__ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
 
+// LDS index of element i of a sequence: one padding slot after every 16
+// elements, so the stride-R writes of the early Stockham passes (and the
+// stride-16 writes of radix-16) spread over the banks instead of piling onto
+// one. A sequence of length L therefore occupies lds_len(L) slots.
+__device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lds_len(int L) { return L + (L >> 4) + 1; }
+
 // ---- one Stockham pass ------------------------------------------------------
-// s: C sequences of length L at stride LS. Ns: product of radices already done.
+// s: C sequences of length L at stride LS (>= lds_len(L)), element i of a
+// sequence at pidx(i). Ns: product of radices already done.
 // tw: table of exp(-2 pi i m / LT) with LT = L * twmul.
 template <typename T, int L, int R, int NT, int C, int DIR>
 __device__ __forceinline__ void stockham_pass(cx<T>* s, int LS, int Ns, const cx<T>* __restrict__ tw,
@@ -151,9 +159,9 @@ __device__ __forceinline__ void stockham_pass(cx<T>* s, int LS, int Ns, const cx
     const int g = tid + i * NT;
     if ((NB % NT == 0) || g < NB) {
       const int c = g / LR, j = g % LR;
-      const cx<T>* src = s + c * LS + j;
+      const cx<T>* src = s + c * LS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = src[r * LR];
+      for (int r = 0; r < R; ++r) v[i][r] = src[pidx(j + r * LR)];
     }
   }
   __syncthreads();
@@ -164,17 +172,28 @@ __device__ __forceinline__ void stockham_pass(cx<T>* s, int LS, int Ns, const cx
       const int c = g / LR, j = g % LR;
       const int k = j & (Ns - 1);
       if (Ns > 1) {
+        // w^{rk} for r = 1..R-1 from the table entries for r = 1, 2, 4, 8
+        // (power-of-two multiples of k): at most three products per twiddle
         const int step = (L / (Ns * R)) * twmul;
+        cx<T> w[R];
+        w[1] = tw[k * step];
+        if constexpr (R > 2) w[2] = tw[2 * k * step];
+        if constexpr (R > 4) w[4] = tw[4 * k * step];
+        if constexpr (R > 8) w[8] = tw[8 * k * step];
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          cx<T> w = tw[r * k * step];
-          v[i][r] = (DIR < 0) ? cmul(v[i][r], w) : cmulc(v[i][r], w);
+        for (int r = 3; r < R; ++r) {
+          if ((r & (r - 1)) == 0) continue;
+          const int hi = 1 << (31 - __builtin_clz(r));  // highest power of two in r
+          w[r] = cmul(w[r - hi], w[hi]);
         }
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[i][r] = (DIR < 0) ? cmul(v[i][r], w[r]) : cmulc(v[i][r], w[r]);
       }
       dftR<R, DIR>(v[i]);
-      cx<T>* dst = s + c * LS + (j - k) * R + k;
+      cx<T>* dst = s + c * LS;
+      const int base = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * Ns] = v[i][r];
+      for (int r = 0; r < R; ++r) dst[pidx(base + r * Ns)] = v[i][r];
     }
   }
   __syncthreads();

@@ -3,15 +3,17 @@
 // for every sub-filter path n, a b-point FFT down column n of d, a pointwise
 // FP64 gain, and the inverse FFT, written back in time order.
 //
-// One workgroup owns C adjacent columns. A real column of b samples becomes a
-// b/2-point complex sequence z[m] = d[2m][n] + i d[2m+1][n]; after the forward
+// The frame matrix arrives transposed (d_T[n][j], each column contiguous, from
+// a tiled transpose of the row stage's output) and the result leaves the same
+// way (x_T[n][j]); every global access is a contiguous run. One workgroup owns
+// C columns. A real column of b samples becomes a b/2-point complex sequence
+// z[m] = d_T[n][2m] + i d_T[n][2m+1]; after the forward
 // FFT, the pass that separates the real spectrum X[k], applies the gain and
 // re-packs for the inverse touches the pair (k, b/2-k) in one thread, in
 // double precision. The gain is computed on the fly from the p taps of the
 // column,  W_n(f) = sum_r h[rN+n] e^{-2 pi i r f / b},
 //          G = W (1+phi^2) / (|W|^2 + phi^2) / b,
-// so no N x b table ever touches HBM. Workgroups that own neighbouring columns
-// are placed on the same XCD so the strided rows they share meet in one L2.
+// so no N x b table ever touches HBM.
 #include "fft_lds.hpp"
 #include "launch.hpp"
 
@@ -21,12 +23,16 @@ template <typename T, int LOG2B>
 struct ColCfg {
   static constexpr int H = 1 << (LOG2B - 1);
   static constexpr int BYTES = H * (int)sizeof(cx<T>);
-  static constexpr int C0 = 131072 / BYTES;
+  static constexpr int C0 = 65536 / BYTES;  // 64 KiB of data: two workgroups per CU
   static constexpr int C = C0 < 1 ? 1 : (C0 > 16 ? 16 : C0);  // columns per workgroup
-  static constexpr int LS = H + (C > 1 ? 1 : 0);              // padded LDS stride
+  static constexpr int LS = lds_len(H);                       // padded LDS stride
   static constexpr int EPT = sizeof(T) == 4 ? 16 : 8;
   static constexpr int NT0 = (H * C) / EPT;
   static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 1024 ? 1024 : NT0);
+  // waves per SIMD to keep: two workgroups per CU when their LDS allows it
+  static constexpr int LDSB = C * LS * (int)sizeof(cx<T>);
+  static constexpr int WPE0 = (LDSB <= 81920 ? 2 : 1) * (NT / 64) / 4;
+  static constexpr int WPE = WPE0 < 1 ? 1 : WPE0;
 };
 
 struct GainArgs {
@@ -41,13 +47,16 @@ struct GainArgs {
 template <int B>
 __device__ __forceinline__ cx<double> wiener_gain(const GainArgs& ga, int n, int f,
                                                   const cx<double>* __restrict__ twB64) {
+  // e^{-2 pi i r f / b} as successive powers of the table entry for f
+  const cx<double> t1 = twB64[f & (B - 1)];
+  cx<double> e = mk<double>(1.0, 0.0);
   double wr = 0.0, wi = 0.0, wabs = 0.0;
   for (int r = 0; r < ga.ntap; ++r) {
     const double h = ga.win[(int64_t)r * ga.lblock + n];
-    const cx<double> e = twB64[(int)(((int64_t)r * f) & (B - 1))];
     wr += h * e.x;
     wi += h * e.y;
     wabs += fabs(h);
+    e = cmul(e, t1);
   }
   const double a2 = wr * wr + wi * wi;
   if (ga.naive) {
@@ -61,25 +70,24 @@ __device__ __forceinline__ cx<double> wiener_gain(const GainArgs& ga, int n, int
 }
 
 template <typename T, int LOG2B>
-__global__ __launch_bounds__((ColCfg<T, LOG2B>::NT)) void k_col_wiener(
-    const T* __restrict__ d, T* __restrict__ xo, int nwg, GainArgs ga, const cx<T>* __restrict__ twB,
+__global__ __launch_bounds__((ColCfg<T, LOG2B>::NT), (ColCfg<T, LOG2B>::WPE)) void k_col_wiener(
+    const T* __restrict__ dT, T* __restrict__ xT, GainArgs ga, const cx<T>* __restrict__ twB,
     const cx<double>* __restrict__ twB64) {
   using Cfg = ColCfg<T, LOG2B>;
   constexpr int B = 1 << LOG2B, H = Cfg::H, C = Cfg::C, LS = Cfg::LS, NT = Cfg::NT;
   constexpr int HP = H / 2 + 1;
   __shared__ cx<T> s[C * LS];
-  T* sf = reinterpret_cast<T*>(s);
   const int tid = threadIdx.x;
   const int N = ga.lblock;
-  const int n0 = xcd_remap(blockIdx.x, nwg) * C;
+  const int n0 = blockIdx.x * C;
 
-  // gather the C columns: C consecutive floats per frame
-  for (int e = tid; e < B * C; e += NT) {
-    const int row = e / C, c = e % C;
+  // C contiguous columns: z[m] = (d_T[n][2m], d_T[n][2m+1])
+  for (int e = tid; e < H * C; e += NT) {
+    const int c = e / H, m = e % H;
     const int n = n0 + c;
-    T v = T(0);
-    if (n < N) v = d[(int64_t)row * N + n];
-    sf[2 * (c * LS + (row >> 1)) + (row & 1)] = v;
+    cx<T> v = mk<T>(T(0), T(0));
+    if (n < N) v = reinterpret_cast<const cx<T>*>(dT + (int64_t)n * B)[m];
+    s[c * LS + pidx(m)] = v;
   }
   __syncthreads();
   lds_fft<T, H, NT, C, -1>(s, LS, twB, 2);
@@ -91,7 +99,7 @@ __global__ __launch_bounds__((ColCfg<T, LOG2B>::NT)) void k_col_wiener(
     if (n >= N) continue;
     cx<T>* col = s + c * LS;
     if (k == 0) {
-      const cx<T> z0 = col[0];
+      const cx<T> z0 = col[0];  // pidx(0) == 0
       const double x0 = (double)z0.x + (double)z0.y;  // X[0]
       const double xh = (double)z0.x - (double)z0.y;  // X[b/2]
       const double y0 = wiener_gain<B>(ga, n, 0, twB64).x * x0;
@@ -100,7 +108,7 @@ __global__ __launch_bounds__((ColCfg<T, LOG2B>::NT)) void k_col_wiener(
       continue;
     }
     const int km = H - k;
-    const cx<T> zk = col[k], zm = col[km];
+    const cx<T> zk = col[pidx(k)], zm = col[pidx(km)];
     const cx<double> Zk = mk<double>(zk.x, zk.y), Zm = mk<double>(zm.x, zm.y);
     const cx<double> ek = twB64[k];          // e^{-2 pi i k / b}
     const cx<double> A = Zk + conj(Zm);
@@ -116,16 +124,16 @@ __global__ __launch_bounds__((ColCfg<T, LOG2B>::NT)) void k_col_wiener(
     const cx<double> Q = Yk - conj(Ym);
     const cx<double> t1 = cmulc(Q, ek);            // conj(e) Q
     const cx<double> t2 = cmul(ek, conj(Q));       // e conj(Q)
-    col[k] = mk<T>(T(P.x - t1.y), T(P.y + t1.x));
-    if (km != k) col[km] = mk<T>(T(P.x - t2.y), T(-P.y + t2.x));
+    col[pidx(k)] = mk<T>(T(P.x - t1.y), T(P.y + t1.x));
+    if (km != k) col[pidx(km)] = mk<T>(T(P.x - t2.y), T(-P.y + t2.x));
   }
   __syncthreads();
   lds_fft<T, H, NT, C, +1>(s, LS, twB, 2);
 
-  for (int e = tid; e < B * C; e += NT) {
-    const int row = e / C, c = e % C;
+  for (int e = tid; e < H * C; e += NT) {
+    const int c = e / H, m = e % H;
     const int n = n0 + c;
-    if (n < N) xo[(int64_t)row * N + n] = sf[2 * (c * LS + (row >> 1)) + (row & 1)];
+    if (n < N) reinterpret_cast<cx<T>*>(xT + (int64_t)n * B)[m] = s[c * LS + pidx(m)];
   }
 }
 
@@ -135,7 +143,7 @@ static hipError_t launch_col_t(const void* d, void* xo, const GainArgs& ga, cons
   using Cfg = ColCfg<T, LOG2B>;
   const int nwg = (ga.lblock + Cfg::C - 1) / Cfg::C;
   k_col_wiener<T, LOG2B><<<dim3(nwg), dim3(Cfg::NT), 0, st>>>(
-      (const T*)d, (T*)xo, nwg, ga, (const cx<T>*)twB, (const cx<double>*)twB64);
+      (const T*)d, (T*)xo, ga, (const cx<T>*)twB, (const cx<double>*)twB64);
   return hipGetLastError();
 }
 

@@ -13,14 +13,15 @@
 
 namespace ipfb {
 
+// fac[k] = 1/(s_k N) for the 4-bit format (computed once per call in FP64)
 template <typename T, int FMT>
-__device__ __forceinline__ cx<T> load_spec(const void* __restrict__ in, const float* __restrict__ sc,
+__device__ __forceinline__ cx<T> load_spec(const void* __restrict__ in, const T* __restrict__ fac,
                                            int64_t idx, int k, int N) {
   if constexpr (FMT == IN_C4) {
     const signed char b = reinterpret_cast<const signed char*>(in)[idx];
     const int re = b >> 4;                            // high nibble, sign-extended
     const int im = (signed char)(b << 4) >> 4;        // low nibble, sign-extended
-    const T f = T(1.0 / ((double)sc[k] * (double)N));
+    const T f = fac[k];
     return mk<T>(T(re) * f, T(im) * f);
   } else if constexpr (FMT == IN_CF32) {
     const cx<float> v = reinterpret_cast<const cx<float>*>(in)[idx];
@@ -48,11 +49,12 @@ struct RowCfg {
 
 template <typename T, int LOG2N, int FMT>
 __global__ __launch_bounds__((RowCfg<T, LOG2N>::NT)) void k_row_irfft(
-    const void* __restrict__ in, const float* __restrict__ sc, T* __restrict__ out, int64_t nrows,
+    const void* __restrict__ in, const T* __restrict__ sc, T* __restrict__ out, int64_t nrows,
     const cx<T>* __restrict__ twN) {
   using Cfg = RowCfg<T, LOG2N>;
   constexpr int N = 1 << LOG2N, H = Cfg::H, C = Cfg::C, NT = Cfg::NT;
-  __shared__ cx<T> s[C * H];
+  constexpr int LS = lds_len(H);
+  __shared__ cx<T> s[C * LS];
   const int tid = threadIdx.x;
   const int64_t row0 = (int64_t)blockIdx.x * C;
   for (int e = tid; e < C * H; e += NT) {
@@ -73,25 +75,26 @@ __global__ __launch_bounds__((RowCfg<T, LOG2N>::NT)) void k_row_irfft(
       const cx<T> t = cmul(w, bdiff);
       z = mk<T>(a.x - t.y, a.y + t.x);  // a + i t
     }
-    s[c * H + k] = z;
+    s[c * LS + pidx(k)] = z;
   }
   __syncthreads();
-  lds_fft<T, H, NT, C, +1>(s, H, twN, 2);
+  lds_fft<T, H, NT, C, +1>(s, LS, twN, 2);
   for (int e = tid; e < C * H; e += NT) {
     const int c = e / H, m = e % H;
     const int64_t row = row0 + c;
-    if (row < nrows) reinterpret_cast<cx<T>*>(out + row * N)[m] = s[c * H + m];
+    if (row < nrows) reinterpret_cast<cx<T>*>(out + row * N)[m] = s[c * LS + pidx(m)];
   }
 }
 
 template <typename T, int LOG2N>
-static hipError_t launch_row_t(int fmt, const void* in, const float* sc, void* out, int64_t nrows,
+static hipError_t launch_row_t(int fmt, const void* in, const void* fac, void* out, int64_t nrows,
                                const void* twN, hipStream_t st) {
   using Cfg = RowCfg<T, LOG2N>;
   const int64_t grid = (nrows + Cfg::C - 1) / Cfg::C;
   if (grid == 0) return hipSuccess;
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(twN);
   T* o = reinterpret_cast<T*>(out);
+  const T* sc = reinterpret_cast<const T*>(fac);
   switch (fmt) {
     case IN_C4: k_row_irfft<T, LOG2N, IN_C4><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(in, sc, o, nrows, tw); break;
     case IN_CF32: k_row_irfft<T, LOG2N, IN_CF32><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(in, sc, o, nrows, tw); break;
@@ -102,9 +105,9 @@ static hipError_t launch_row_t(int fmt, const void* in, const float* sc, void* o
 }
 
 #define ROW_CASE(T, L) \
-  case L: return launch_row_t<T, L>(fmt, in, chan_scale, out, nrows, twN, st);
+  case L: return launch_row_t<T, L>(fmt, in, fac, out, nrows, twN, st);
 
-hipError_t launch_row_irfft(int prec, int log2n, int fmt, const void* in, const float* chan_scale,
+hipError_t launch_row_irfft(int prec, int log2n, int fmt, const void* in, const void* fac,
                             void* out, int64_t nrows, const void* twN, hipStream_t st) {
   if (prec == F32) {
     switch (log2n) {
@@ -120,6 +123,24 @@ hipError_t launch_row_irfft(int prec, int log2n, int fmt, const void* in, const 
     ROW_CASE(double, 12) ROW_CASE(double, 13) ROW_CASE(double, 14)
     default: return hipErrorInvalidValue;
   }
+}
+
+// fac[k] = 1 / (s_k N) in double, stored in the plan precision
+template <typename T>
+__global__ __launch_bounds__(256) void k_dequant_factors(const float* __restrict__ sc, int nchan, int N,
+                                                         T* __restrict__ fac) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k < nchan) fac[k] = T(1.0 / ((double)sc[k] * (double)N));
+}
+
+hipError_t launch_dequant_factors(int prec, const float* chan_scale, int nchan, int N, void* fac,
+                                  hipStream_t st) {
+  const int grid = (nchan + 255) / 256;
+  if (prec == F32)
+    k_dequant_factors<float><<<grid, 256, 0, st>>>(chan_scale, nchan, N, (float*)fac);
+  else
+    k_dequant_factors<double><<<grid, 256, 0, st>>>(chan_scale, nchan, N, (double*)fac);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -17,13 +17,16 @@ constexpr int kMaxLog2ColF32 = 15;
 constexpr int kMaxLog2ColF64 = 14;
 
 // Row stage: d_j = inverse real FFT of spectrum j, times per-channel factors.
-// fmt IN_C4: packed 4-bit, factor 1/(s_k N); IN_CF32/IN_CF64: factor 1/N;
-// IN_ADJ: complex in the plan precision, factor c_k/2 (transpose of the
-// half-spectrum DFT).
-hipError_t launch_row_irfft(int prec, int log2n, int fmt, const void* in, const float* chan_scale,
+// fmt IN_C4: packed 4-bit, factor fac[k] = 1/(s_k N) (plan precision, from
+// launch_dequant_factors); IN_CF32/IN_CF64: factor 1/N; IN_ADJ: complex in the
+// plan precision, factor c_k/2 (transpose of the half-spectrum DFT).
+hipError_t launch_row_irfft(int prec, int log2n, int fmt, const void* in, const void* fac,
                             void* out, int64_t nrows, const void* twN, hipStream_t st);
+hipError_t launch_dequant_factors(int prec, const float* chan_scale, int nchan, int N, void* fac,
+                                  hipStream_t st);
 
-// Column stage: per column n, x_n = F^-1[ G_n F d_n ] with the FP64 gain.
+// Column stage on the transposed frame matrix: per column n (contiguous in
+// d_T[n][0..b)), x_T[n] = F^-1[ G_n F d_T[n] ] with the FP64 gain.
 hipError_t launch_col_wiener(int prec, int log2b, const void* d, void* xo, int lblock, int ntap,
                              const double* win64, double phi, int normalise, const void* twB,
                              const double* twB64, hipStream_t st);
@@ -32,9 +35,18 @@ hipError_t launch_col_wiener(int prec, int log2b, const void* d, void* xo, int l
 hipError_t launch_pfb_fwd_small(int prec, int log2n, const void* x, void* y, int64_t nblock, int ntap,
                                 const void* winT, const void* twN, hipStream_t st);
 
-// Forward PFB for long frames: four-step over H = N/2 = R1 * R2.
+// Forward PFB for long frames (2^15 <= N <= 2^20): two frames per complex
+// N-point FFT, N = P1 * P2 (P1 = 2^ceil(log2 N / 2)), in two passes through
+// tmp ((nblock+1)/2 * N complex). part: NULL, or [ceil(nq / qchunk)][N/2+1] doubles receiving
+// per-chunk sums of |Y_jk|^2 (nq = (nblock+1)/2 frame pairs).
+// twS: small tables [P1 | P2 | 512 | L/512] of e^{-2 pi i m/P1}, e^{-2 pi i m/P2},
+// e^{-2 pi i m/L} (m < 512) and e^{-2 pi i 512 m/L}.
 hipError_t launch_pfb_fwd_large(int prec, int log2n, const void* x, void* y, int64_t nblock, int ntap,
-                                const void* winT, const void* twN, void* tmp, hipStream_t st);
+                                const void* winT, const void* twS, void* tmp, int qchunk, double* part,
+                                hipStream_t st);
+
+// out[c][r] = in[r][c] for an in[rows][cols] matrix (64 x 64 LDS tiles)
+hipError_t launch_transpose(int prec, const void* in, void* out, int64_t rows, int64_t cols, hipStream_t st);
 
 // x[i][n] = sum_r h[rN+n] z[(i-r) mod b][n]
 hipError_t launch_adjoint_gather(int prec, const void* z, void* x, int64_t nblock, int lblock, int ntap,

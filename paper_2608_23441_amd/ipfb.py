@@ -24,6 +24,7 @@ EXPORTS = (
     "ipfb_last_error", "ipfb_version", "ipfb_window_sinc_hamming", "ipfb_plan_create",
     "ipfb_plan_destroy", "ipfb_plan_workspace_size", "pfb_forward", "pfb_adjoint", "ipfb_wiener",
     "ipfb_wiener_ex", "upchannelize", "ipfb_autospectrum", "ipfb_quantize_c4",
+    "ipfb_profile_enable", "ipfb_profile_reset", "ipfb_profile_query",
 )
 
 
@@ -58,6 +59,9 @@ def lib():
         L.upchannelize.argtypes = [vp, vp, vp, vp, vp]
         L.ipfb_autospectrum.argtypes = [vp, vp, vp, vp]
         L.ipfb_quantize_c4.argtypes = [vp, vp, dbl, vp, vp, vp]
+        L.ipfb_profile_enable.argtypes = [i32]
+        L.ipfb_profile_reset.argtypes = []
+        L.ipfb_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype or ctypes.c_int
         L.ipfb_last_error.restype = ctypes.c_char_p
@@ -226,3 +230,19 @@ def quantize_c4(plan: Plan, y, levels_rms: float = 2.5, stream=None):
     _check(lib().ipfb_quantize_c4(plan.handle, plan._cplx(y, "y"), float(levels_rms), _ptr(packed, "packed"),
                                   _ptr(scales, "scales"), _stream(stream)))
     return packed, scales
+
+
+def profile_enable(on: bool = True):
+    _check(lib().ipfb_profile_enable(int(bool(on))))
+
+
+def profile_reset():
+    _check(lib().ipfb_profile_reset())
+
+
+def profile_query(name: str):
+    """(total milliseconds, launches) recorded for one kernel name."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib().ipfb_profile_query(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
