@@ -119,6 +119,27 @@ int ipfb_wiener_ex(ipfb_plan plan, int infmt, const void* spec, const float* cha
  * (Section 4.1's autospectrum), summed in a fixed order. */
 int upchannelize(ipfb_plan fine, const void* x, void* y_fine, double* autospec, void* stream);
 
+/* Maximum-likelihood reconstruction with a time-domain prior (Section 4.2,
+ * the chi^2 with prior term): minimise |d - A x|^2 + lambda |D (x - prior)|^2
+ * where d are the frames after the N-point inverse FFT of spec (Section 4.2:
+ * A = S W once F is undone, circular), D = diag(mask), by preconditioned
+ * conjugate gradient on (A^T A + lambda D) x = A^T d + lambda D prior
+ * (the CG method the paper cites), with the preconditioner
+ * F^dagger diag(1/(|W_n|^2 + phi_precond^2)) F per column.
+ * spec/chan_scale/infmt as for ipfb_wiener. mask: device uint8 [S] in time
+ * order (S = nblock*lblock), nonzero where the timestream sample is saved.
+ * prior: device [S] real (plan precision), read where mask != 0.
+ * x_init: NULL to start from the Wiener solution with phi_x0 (the paper's
+ * initial guess), else a device [S] real starting point. Runs exactly iters
+ * iterations (no early exit; an exactly converged system stops moving).
+ * x_out: device [S] real, time order. resid_norms: NULL or device double
+ * [iters+1] receiving |r_k|_2 (FP64 sums). Vectors are FP32 for F32 plans,
+ * dot products and norms FP64. The first call on a plan allocates the
+ * workspace (8 vectors of S reals); later calls allocate nothing. */
+int ipfb_ml_cg(ipfb_plan plan, int infmt, const void* spec, const float* chan_scale, const uint8_t* mask,
+               const void* prior, double lambda, double phi_x0, double phi_precond, int iters,
+               const void* x_init, void* x_out, double* resid_norms, void* stream);
+
 /* Autospectrum alone: autospec[k] = (1/nspec) sum_j |y_jk|^2 (double). */
 int ipfb_autospectrum(ipfb_plan plan, const void* y, double* autospec, void* stream);
 
@@ -132,9 +153,10 @@ int ipfb_quantize_c4(ipfb_plan plan, const void* y, double levels_rms, uint8_t* 
                      void* stream);
 
 /* Instrumentation: per-kernel timing with HIP events recorded on the
- * launching stream around every kernel the library enqueues (names:
- * "ipfb_rows", "ipfb_cols", "pfb_fwd", "pfb_fwd_A", "pfb_fwd_B",
- * "adj_rows", "adj_gather", "autospec_partial", "autospec_final").
+ * launching stream around every kernel group the library enqueues (names:
+ * "ipfb_rows", "ipfb_transpose_in", "ipfb_cols", "ipfb_transpose_out",
+ * "pfb_fwd", "pfb_fwd_long", "adj_rows", "adj_gather", "autospec_partial",
+ * "autospec_final", "cg_setup", "cg_iter", "cg_out").
  * ipfb_profile_enable(1) starts recording (process-wide); ipfb_profile_query
  * waits for the recorded events and returns the summed milliseconds and
  * launch count for one name; ipfb_profile_reset drops all records. */

@@ -91,6 +91,12 @@ struct ipfb_plan_s {
   void* tmp = nullptr;   // four-step intermediate of long frames: nblock*lblock/2 complex
   double* part = nullptr;
   void* fac = nullptr;   // per-channel dequantisation factors 1/(s_k N)
+  // maximum-likelihood CG workspace (allocated on first use): 8 vectors in the
+  // transposed layout, the column autocorrelations, partial sums, scalars
+  void* cg = nullptr;
+  double* cg_autoc = nullptr;
+  double* cg_part = nullptr;
+  double* cg_sc = nullptr;
   int jchunk = 1, nchunks = 1;
   int qchunk = 1, nqchunks = 1;  // long frames: frame pairs per power-sum chunk
   size_t bytes = 0;
@@ -131,7 +137,8 @@ int upload_table(ipfb_plan p, const std::vector<double>& t, int prec, void** dst
 }
 
 void free_plan(ipfb_plan p) {
-  void* ptrs[] = {p->win64, p->winT, p->twN, p->twB, p->twB64, p->work, p->work2, p->tmp, p->part, p->fac, p->twS};
+  void* ptrs[] = {p->win64, p->winT, p->twN, p->twB, p->twB64, p->work, p->work2, p->tmp, p->part, p->fac, p->twS,
+                  p->cg, p->cg_autoc, p->cg_part, p->cg_sc};
   for (void* q : ptrs)
     if (q) hipFree(q);
   delete p;
@@ -411,6 +418,90 @@ int ipfb_wiener_ex(ipfb_plan p, int infmt, const void* spec, const float* chan_s
 int ipfb_wiener(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, double phi, void* x_out,
                 void* stream) {
   return ipfb_wiener_ex(p, infmt, spec, chan_scale, phi, 1, x_out, stream);
+}
+
+int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, const uint8_t* mask,
+               const void* prior, double lam, double phi_x0, double phi_precond, int iters, const void* x_init,
+               void* x_out, double* resid_norms, void* stream) {
+  if (check_plan(p)) return IPFB_EINVAL;
+  if (!spec || !mask || !prior || !x_out) return fail(IPFB_EINVAL, "spec, mask, prior and x_out must be non-NULL");
+  if (infmt != IPFB_IN_C4 && infmt != IPFB_IN_CF32 && infmt != IPFB_IN_CF64)
+    return fail(IPFB_EINVAL, "unknown input format %d", infmt);
+  if (infmt == IPFB_IN_C4 && !chan_scale) return fail(IPFB_EINVAL, "chan_scale is required for IPFB_IN_C4");
+  if (!(lam >= 0.0) || !std::isfinite(lam)) return fail(IPFB_EINVAL, "lambda must be finite and >= 0");
+  if (!(phi_precond > 0.0) || !std::isfinite(phi_precond)) return fail(IPFB_EINVAL, "phi_precond must be > 0");
+  if (!(phi_x0 >= 0.0) || !std::isfinite(phi_x0)) return fail(IPFB_EINVAL, "phi_x0 must be finite and >= 0");
+  if (iters < 0) return fail(IPFB_EINVAL, "iters must be >= 0");
+  if (!p->row_lds || !p->col_lds)
+    return fail(IPFB_EUNSUPPORTED, "ipfb_ml_cg needs a plan that supports ipfb_wiener");
+  DeviceGuard g(p->dev);
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t b = p->nblock, S = (int64_t)p->lblock * b;
+  const size_t vb = (size_t)S * esize(p->prec);
+  if (!p->cg) {
+    int s2 = dev_alloc(p, &p->cg, 8 * vb);
+    if (!s2) s2 = dev_alloc(p, (void**)&p->cg_autoc, (size_t)p->lblock * (2 * p->ntap - 1) * sizeof(double));
+    if (!s2) s2 = dev_alloc(p, (void**)&p->cg_part, kCgParts * sizeof(double));
+    if (!s2) s2 = dev_alloc(p, (void**)&p->cg_sc, 8 * sizeof(double));
+    if (s2) return s2;
+  }
+  char* base = (char*)p->cg;
+  void* xT = base;
+  void* rT = base + vb;
+  void* zT = base + 2 * vb;
+  void* pT = base + 3 * vb;
+  void* qT = base + 4 * vb;
+  void* rhsT = base + 5 * vb;
+  void* maskT = base + 6 * vb;
+  void* priorT = base + 7 * vb;
+  void* dT = p->work2;
+  hipError_t e;
+  {
+    ProfScope ps("cg_setup", st);
+    if (infmt == IPFB_IN_C4) e = launch_dequant_factors(p->prec, chan_scale, p->lblock / 2 + 1, p->lblock, p->fac, st);
+    else e = hipSuccess;
+    if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec, p->fac, p->work, b, p->twN, st);
+    if (e == hipSuccess) e = launch_transpose(p->prec, p->work, dT, b, p->lblock, st);
+    if (e == hipSuccess) e = launch_mask_to_T(p->prec, mask, qT, S, st);
+    if (e == hipSuccess) e = launch_transpose(p->prec, qT, maskT, b, p->lblock, st);
+    if (e == hipSuccess) e = launch_transpose(p->prec, prior, priorT, b, p->lblock, st);
+    if (e == hipSuccess) e = launch_cg_autocorr(p->win64, p->lblock, p->ntap, p->cg_autoc, st);
+    if (e == hipSuccess)
+      e = launch_cg_rhs(p->prec, dT, rhsT, p->win64, maskT, priorT, lam, p->lblock, p->ntap, b, S, st);
+    if (e == hipSuccess) {
+      if (x_init) e = launch_transpose(p->prec, x_init, xT, b, p->lblock, st);
+      else e = launch_col_wiener(p->prec, p->log2b, dT, xT, p->lblock, p->ntap, p->win64, phi_x0, 1, p->twB,
+                                 p->twB64, st);
+    }
+    // r0 = rhs - H x0, z0 = M^-1 r0, p0 = z0, rho0 = r0.z0
+    if (e == hipSuccess) e = launch_cg_normal(p->prec, xT, qT, p->cg_autoc, maskT, lam, p->ntap, b, S, p->cg_part, st);
+    if (e == hipSuccess) e = launch_cg_resid(p->prec, rhsT, qT, rT, S, p->cg_part, st);
+    if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 2, p->cg_sc, resid_norms, 0, st);
+    if (e == hipSuccess)
+      e = launch_col_wiener(p->prec, p->log2b, rT, zT, p->lblock, p->ntap, p->win64, phi_precond, 1, p->twB,
+                            p->twB64, st, 1);
+    if (e == hipSuccess) e = launch_cg_p(p->prec, pT, zT, p->cg_sc, 0, S, st);
+    if (e == hipSuccess) e = launch_cg_dot(p->prec, rT, zT, S, p->cg_part, st);
+    if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 0, p->cg_sc, nullptr, 0, st);
+  }
+  for (int k = 1; k <= iters && e == hipSuccess; ++k) {
+    ProfScope ps("cg_iter", st);
+    e = launch_cg_normal(p->prec, pT, qT, p->cg_autoc, maskT, lam, p->ntap, b, S, p->cg_part, st);
+    if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 1, p->cg_sc, nullptr, 0, st);
+    if (e == hipSuccess) e = launch_cg_xr(p->prec, xT, rT, pT, qT, p->cg_sc, S, p->cg_part, st);
+    if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 2, p->cg_sc, resid_norms, k, st);
+    if (e == hipSuccess)
+      e = launch_col_wiener(p->prec, p->log2b, rT, zT, p->lblock, p->ntap, p->win64, phi_precond, 1, p->twB,
+                            p->twB64, st, 1);
+    if (e == hipSuccess) e = launch_cg_dot(p->prec, rT, zT, S, p->cg_part, st);
+    if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 3, p->cg_sc, nullptr, 0, st);
+    if (e == hipSuccess) e = launch_cg_p(p->prec, pT, zT, p->cg_sc, 1, S, st);
+  }
+  if (e == hipSuccess) {
+    ProfScope ps("cg_out", st);
+    e = launch_transpose(p->prec, xT, x_out, p->lblock, b, st);
+  }
+  return launched(e, "ipfb_ml_cg");
 }
 
 int ipfb_autospectrum(ipfb_plan p, const void* y, double* autospec, void* stream) {

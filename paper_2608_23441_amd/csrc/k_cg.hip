@@ -1,0 +1,252 @@
+// Maximum-likelihood reconstruction with a time-domain prior (Section 4.2):
+// minimise |d - A x|^2 + lam |D (x - prior)|^2, A = S W circular (acting on
+// the frames after the N-point inverse FFT), D = diag(mask), by
+// preconditioned conjugate gradient on (A^T A + lam D) x = A^T d + lam D prior.
+//
+// Vectors live in the transposed frame layout v_T[n][j] (sub-filter path n,
+// frame j), so A^T A is a (2p-1)-tap circulant stencil along contiguous rows:
+//   (A^T A x)_n[i] = sum_{t=-(p-1)}^{p-1} c_n[t] x_n[(i+t) mod b],
+//   c_n[t] = sum_r h[rN+n] h[(r+t)N+n]  (autocorrelation of the column taps).
+// Dot products and norms accumulate in FP64 per workgroup and are summed in a
+// fixed order by one workgroup, which also updates the CG scalars in device
+// memory: no host round trip inside the iteration loop.
+#include "fft_lds.hpp"
+#include "launch.hpp"
+
+namespace ipfb {
+
+constexpr int kCgNWG = 1024;  // workgroups of the element-wise kernels (fixed: deterministic sums)
+constexpr int kCgNT = 256;
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+// c_n[t] for t in [-(p-1), p-1], stored autoc[n * (2p-1) + t + p - 1], FP64
+__global__ __launch_bounds__(256) void k_cg_autocorr(const double* __restrict__ win, int N, int ntap,
+                                                     double* __restrict__ autoc) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  const int nt = 2 * ntap - 1;
+  for (int t = -(ntap - 1); t <= ntap - 1; ++t) {
+    double acc = 0.0;
+    for (int r = 0; r < ntap; ++r) {
+      const int s = r + t;
+      if (s < 0 || s >= ntap) continue;
+      acc += win[(int64_t)r * N + n] * win[(int64_t)s * N + n];
+    }
+    autoc[(int64_t)n * nt + t + ntap - 1] = acc;
+  }
+}
+
+// q = (A^T A + lam D) p ; partial sums of p.q
+template <typename T>
+__global__ __launch_bounds__(kCgNT) void k_cg_normal(const T* __restrict__ p, T* __restrict__ q,
+                                                     const double* __restrict__ autoc, const T* __restrict__ mask,
+                                                     double lam, int ntap, int64_t b, int64_t S,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[kCgNT];
+  const int nt = 2 * ntap - 1;
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kCgNT + threadIdx.x; e < S; e += (int64_t)gridDim.x * kCgNT) {
+    const int64_t n = e / b, i = e - n * b;
+    const T* row = p + n * b;
+    const double* c = autoc + n * nt;
+    double v = 0.0;
+    for (int t = 0; t < nt; ++t) {
+      int64_t k = i + t - (ntap - 1);
+      if (k < 0) k += b;
+      else if (k >= b) k -= b;
+      v += c[t] * (double)row[k];
+    }
+    const double pe = (double)p[e];
+    v += lam * (double)mask[e] * pe;
+    const T vt = T(v);
+    q[e] = vt;
+    acc += pe * (double)vt;
+  }
+  const double tot = block_sum<kCgNT>(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// rhs = A^T d + lam D prior : (A^T d)_n[i] = sum_r h[rN+n] d_n[(i-r) mod b]
+template <typename T>
+__global__ __launch_bounds__(kCgNT) void k_cg_rhs(const T* __restrict__ d, T* __restrict__ rhs,
+                                                  const double* __restrict__ win, const T* __restrict__ mask,
+                                                  const T* __restrict__ prior, double lam, int N, int ntap,
+                                                  int64_t b, int64_t S) {
+  for (int64_t e = (int64_t)blockIdx.x * kCgNT + threadIdx.x; e < S; e += (int64_t)gridDim.x * kCgNT) {
+    const int64_t n = e / b, i = e - n * b;
+    const T* row = d + n * b;
+    double v = 0.0;
+    for (int r = 0; r < ntap; ++r) {
+      int64_t k = (i - r) % b;
+      if (k < 0) k += b;
+      v += win[(int64_t)r * N + n] * (double)row[k];
+    }
+    v += lam * (double)mask[e] * (double)prior[e];
+    rhs[e] = T(v);
+  }
+}
+
+// r = rhs - q ; partial sums of r.r
+template <typename T>
+__global__ __launch_bounds__(kCgNT) void k_cg_resid(const T* __restrict__ rhs, const T* __restrict__ q,
+                                                    T* __restrict__ r, int64_t S, double* __restrict__ part) {
+  __shared__ double sh[kCgNT];
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kCgNT + threadIdx.x; e < S; e += (int64_t)gridDim.x * kCgNT) {
+    const T v = rhs[e] - q[e];
+    r[e] = v;
+    acc += (double)v * (double)v;
+  }
+  const double tot = block_sum<kCgNT>(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// partial sums of a.b
+template <typename T>
+__global__ __launch_bounds__(kCgNT) void k_cg_dot(const T* __restrict__ a, const T* __restrict__ c, int64_t S,
+                                                  double* __restrict__ part) {
+  __shared__ double sh[kCgNT];
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kCgNT + threadIdx.x; e < S; e += (int64_t)gridDim.x * kCgNT)
+    acc += (double)a[e] * (double)c[e];
+  const double tot = block_sum<kCgNT>(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// x += alpha p ; r -= alpha q ; partial sums of r.r
+template <typename T>
+__global__ __launch_bounds__(kCgNT) void k_cg_xr(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+                                                 const T* __restrict__ q, const double* __restrict__ sc, int64_t S,
+                                                 double* __restrict__ part) {
+  __shared__ double sh[kCgNT];
+  const T alpha = T(sc[2]);
+  double acc = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kCgNT + threadIdx.x; e < S; e += (int64_t)gridDim.x * kCgNT) {
+    x[e] += alpha * p[e];
+    const T v = r[e] - alpha * q[e];
+    r[e] = v;
+    acc += (double)v * (double)v;
+  }
+  const double tot = block_sum<kCgNT>(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// p = z + beta p   (beta from the scalars; first iteration: p = z with beta = 0)
+template <typename T>
+__global__ __launch_bounds__(kCgNT) void k_cg_p(T* __restrict__ p, const T* __restrict__ z,
+                                                const double* __restrict__ sc, int use_beta, int64_t S) {
+  const T beta = use_beta ? T(sc[4]) : T(0);
+  for (int64_t e = (int64_t)blockIdx.x * kCgNT + threadIdx.x; e < S; e += (int64_t)gridDim.x * kCgNT)
+    p[e] = z[e] + beta * p[e];
+}
+
+// one workgroup: sum the partials in a fixed order and update the scalars
+// sc = [rho, pq, alpha, rho_new, beta, rr]
+__global__ __launch_bounds__(kCgNWG) void k_cg_scalar(const double* __restrict__ part, int mode,
+                                                      double* __restrict__ sc, double* __restrict__ resid,
+                                                      int k) {
+  __shared__ double sh[kCgNWG];
+  const double tot = block_sum<kCgNWG>(part[threadIdx.x], sh);
+  if (threadIdx.x != 0) return;
+  switch (mode) {
+    case 0:  // rho0 = r.z
+      sc[0] = tot;
+      break;
+    case 1:  // alpha = rho / p.q (an exactly converged system stops moving)
+      sc[1] = tot;
+      sc[2] = (tot != 0.0) ? sc[0] / tot : 0.0;
+      break;
+    case 2:  // residual norm
+      sc[5] = tot;
+      if (resid) resid[k] = sqrt(tot);
+      break;
+    default:  // beta = rho_new / rho
+      sc[3] = tot;
+      sc[4] = (sc[0] != 0.0) ? tot / sc[0] : 0.0;
+      sc[0] = tot;
+      break;
+  }
+}
+
+// elementwise helpers used at set-up: out = (T) in for a byte mask
+template <typename T>
+__global__ __launch_bounds__(kCgNT) void k_mask_to_T(const uint8_t* __restrict__ m, T* __restrict__ out,
+                                                     int64_t S) {
+  for (int64_t e = (int64_t)blockIdx.x * kCgNT + threadIdx.x; e < S; e += (int64_t)gridDim.x * kCgNT)
+    out[e] = m[e] ? T(1) : T(0);
+}
+
+#define CG_DISPATCH(prec, call) \
+  do {                          \
+    if ((prec) == F32) {        \
+      using T = float;          \
+      call;                     \
+    } else {                    \
+      using T = double;         \
+      call;                     \
+    }                           \
+  } while (0)
+
+hipError_t launch_cg_autocorr(const double* win64, int N, int ntap, double* autoc, hipStream_t st) {
+  k_cg_autocorr<<<(N + 255) / 256, 256, 0, st>>>(win64, N, ntap, autoc);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_normal(int prec, const void* p, void* q, const double* autoc, const void* mask, double lam,
+                            int ntap, int64_t b, int64_t S, double* part, hipStream_t st) {
+  CG_DISPATCH(prec, (k_cg_normal<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)p, (T*)q, autoc, (const T*)mask, lam, ntap,
+                                                              b, S, part)));
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_rhs(int prec, const void* d, void* rhs, const double* win64, const void* mask,
+                         const void* prior, double lam, int N, int ntap, int64_t b, int64_t S, hipStream_t st) {
+  CG_DISPATCH(prec, (k_cg_rhs<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)d, (T*)rhs, win64, (const T*)mask,
+                                                           (const T*)prior, lam, N, ntap, b, S)));
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_resid(int prec, const void* rhs, const void* q, void* r, int64_t S, double* part,
+                           hipStream_t st) {
+  CG_DISPATCH(prec, (k_cg_resid<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)rhs, (const T*)q, (T*)r, S, part)));
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_dot(int prec, const void* a, const void* c, int64_t S, double* part, hipStream_t st) {
+  CG_DISPATCH(prec, (k_cg_dot<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)a, (const T*)c, S, part)));
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_xr(int prec, void* x, void* r, const void* p, const void* q, const double* sc, int64_t S,
+                        double* part, hipStream_t st) {
+  CG_DISPATCH(prec, (k_cg_xr<T><<<kCgNWG, kCgNT, 0, st>>>((T*)x, (T*)r, (const T*)p, (const T*)q, sc, S, part)));
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_p(int prec, void* p, const void* z, const double* sc, int use_beta, int64_t S,
+                       hipStream_t st) {
+  CG_DISPATCH(prec, (k_cg_p<T><<<kCgNWG, kCgNT, 0, st>>>((T*)p, (const T*)z, sc, use_beta, S)));
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_scalar(const double* part, int mode, double* sc, double* resid, int k, hipStream_t st) {
+  k_cg_scalar<<<1, kCgNWG, 0, st>>>(part, mode, sc, resid, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_to_T(int prec, const uint8_t* m, void* out, int64_t S, hipStream_t st) {
+  CG_DISPATCH(prec, (k_mask_to_T<T><<<kCgNWG, kCgNT, 0, st>>>(m, (T*)out, S)));
+  return hipGetLastError();
+}
+
+}  // namespace ipfb

@@ -41,6 +41,7 @@ struct GainArgs {
   double phi2;        // phi^2
   double gnorm;       // (1 + phi^2) / b  (or 1/b without the normalisation)
   int naive;          // phi == 0: 1/conj(W), truncated
+  int precond;        // real gain 1/(|W|^2 + phi^2) / b: the inverse of A^T A + phi^2 I
 };
 
 // G_n(f) for f in [0, b); twB64[m] = e^{-2 pi i m / b}.
@@ -59,6 +60,7 @@ __device__ __forceinline__ cx<double> wiener_gain(const GainArgs& ga, int n, int
     e = cmul(e, t1);
   }
   const double a2 = wr * wr + wi * wi;
+  if (ga.precond) return mk<double>(1.0 / ((a2 + ga.phi2) * (double)B), 0.0);
   if (ga.naive) {
     // plain division by conj(W); eigenvalues at rounding level are dropped
     if (sqrt(a2) <= 1e-12 * wabs) return mk<double>(0.0, 0.0);
@@ -152,13 +154,14 @@ static hipError_t launch_col_t(const void* d, void* xo, const GainArgs& ga, cons
 
 hipError_t launch_col_wiener(int prec, int log2b, const void* d, void* xo, int lblock, int ntap,
                              const double* win64, double phi, int normalise, const void* twB,
-                             const double* twB64, hipStream_t st) {
+                             const double* twB64, hipStream_t st, int precond) {
   GainArgs ga;
   ga.win = win64;
   ga.lblock = lblock;
   ga.ntap = ntap;
   ga.phi2 = phi * phi;
-  ga.naive = (phi == 0.0);
+  ga.naive = (phi == 0.0) && !precond;
+  ga.precond = precond;
   ga.gnorm = (normalise ? (1.0 + phi * phi) : 1.0) / (double)(1LL << log2b);
   if (prec == F32) {
     switch (log2b) {

@@ -241,10 +241,10 @@ __global__ __launch_bounds__((Up1sCfg<T, LOG2P1>::NT)) void k_up1_slide(
 template <typename T, int LOG2P2>
 struct Up2Cfg {
   static constexpr int P2 = 1 << LOG2P2;
-  static constexpr int KB0 = 131072 / (2 * P2 * (int)sizeof(cx<T>));
-  static constexpr int KB = KB0 > 16 ? 16 : KB0;  // rows per half
+  static constexpr int KB0 = 65536 / (2 * P2 * (int)sizeof(cx<T>));
+  static constexpr int KB = KB0 > 16 ? 16 : (KB0 < 1 ? 1 : KB0);  // rows per half (two workgroups per CU)
   static constexpr int LS = lds_len(P2);
-  static constexpr int EPT = sizeof(T) == 4 ? 32 : 16;  // one workgroup per CU: room for registers
+  static constexpr int EPT = sizeof(T) == 4 ? 16 : 8;
   static constexpr int NT0 = (2 * KB * P2) / EPT;
   static constexpr int NT = NT0 > 1024 ? 1024 : NT0;
   static constexpr int NOUT = 2 * KB * (P2 / 2 + 1);  // outputs per q
@@ -252,7 +252,7 @@ struct Up2Cfg {
 };
 
 template <typename T, int LOG2P2>
-__global__ __launch_bounds__((Up2Cfg<T, LOG2P2>::NT)) void k_up2(
+__global__ __launch_bounds__((Up2Cfg<T, LOG2P2>::NT), 4) void k_up2(
     const cx<T>* __restrict__ tmp, cx<T>* __restrict__ y, const cx<T>* __restrict__ tP2, int L, int P1,
     int64_t nblock, int64_t nq, int qchunk, int npb, double* __restrict__ part) {
   using Cfg = Up2Cfg<T, LOG2P2>;

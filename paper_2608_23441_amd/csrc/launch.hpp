@@ -27,9 +27,28 @@ hipError_t launch_dequant_factors(int prec, const float* chan_scale, int nchan, 
 
 // Column stage on the transposed frame matrix: per column n (contiguous in
 // d_T[n][0..b)), x_T[n] = F^-1[ G_n F d_T[n] ] with the FP64 gain.
+// precond = 1 applies the real gain 1/(|W_n|^2 + phi^2) instead (the inverse
+// of A^T A + phi^2 I, used as the CG preconditioner).
 hipError_t launch_col_wiener(int prec, int log2b, const void* d, void* xo, int lblock, int ntap,
                              const double* win64, double phi, int normalise, const void* twB,
-                             const double* twB64, hipStream_t st);
+                             const double* twB64, hipStream_t st, int precond = 0);
+
+// Maximum-likelihood CG pieces (vectors in the transposed layout [N][b]).
+hipError_t launch_cg_autocorr(const double* win64, int N, int ntap, double* autoc, hipStream_t st);
+hipError_t launch_cg_normal(int prec, const void* p, void* q, const double* autoc, const void* mask, double lam,
+                            int ntap, int64_t b, int64_t S, double* part, hipStream_t st);
+hipError_t launch_cg_rhs(int prec, const void* d, void* rhs, const double* win64, const void* mask,
+                         const void* prior, double lam, int N, int ntap, int64_t b, int64_t S, hipStream_t st);
+hipError_t launch_cg_resid(int prec, const void* rhs, const void* q, void* r, int64_t S, double* part,
+                           hipStream_t st);
+hipError_t launch_cg_dot(int prec, const void* a, const void* c, int64_t S, double* part, hipStream_t st);
+hipError_t launch_cg_xr(int prec, void* x, void* r, const void* p, const void* q, const double* sc, int64_t S,
+                        double* part, hipStream_t st);
+hipError_t launch_cg_p(int prec, void* p, const void* z, const double* sc, int use_beta, int64_t S,
+                       hipStream_t st);
+hipError_t launch_cg_scalar(const double* part, int mode, double* sc, double* resid, int k, hipStream_t st);
+hipError_t launch_mask_to_T(int prec, const uint8_t* m, void* out, int64_t S, hipStream_t st);
+constexpr int kCgParts = 1024;
 
 // Forward PFB with LDS-resident rows (N <= 2^kMaxLog2Row*).
 hipError_t launch_pfb_fwd_small(int prec, int log2n, const void* x, void* y, int64_t nblock, int ntap,

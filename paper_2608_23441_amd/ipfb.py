@@ -24,7 +24,7 @@ EXPORTS = (
     "ipfb_last_error", "ipfb_version", "ipfb_window_sinc_hamming", "ipfb_plan_create",
     "ipfb_plan_destroy", "ipfb_plan_workspace_size", "pfb_forward", "pfb_adjoint", "ipfb_wiener",
     "ipfb_wiener_ex", "upchannelize", "ipfb_autospectrum", "ipfb_quantize_c4",
-    "ipfb_profile_enable", "ipfb_profile_reset", "ipfb_profile_query",
+    "ipfb_profile_enable", "ipfb_profile_reset", "ipfb_profile_query", "ipfb_ml_cg",
 )
 
 
@@ -59,6 +59,7 @@ def lib():
         L.upchannelize.argtypes = [vp, vp, vp, vp, vp]
         L.ipfb_autospectrum.argtypes = [vp, vp, vp, vp]
         L.ipfb_quantize_c4.argtypes = [vp, vp, dbl, vp, vp, vp]
+        L.ipfb_ml_cg.argtypes = [vp, i32, vp, vp, vp, vp, dbl, dbl, dbl, i32, vp, vp, vp, vp]
         L.ipfb_profile_enable.argtypes = [i32]
         L.ipfb_profile_reset.argtypes = []
         L.ipfb_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
@@ -200,6 +201,44 @@ def ipfb_wiener(plan: Plan, spec, chan_scale=None, phi: float = 0.1, x_out=None,
                                 float(phi), int(bool(normalise)), plan._real(x_out, "x_out"),
                                 _stream(stream)))
     return x_out
+
+
+def _spec_fmt(plan, spec, chan_scale):
+    import torch
+    if spec.dtype == torch.uint8:
+        if chan_scale is None or chan_scale.dtype != torch.float32 or chan_scale.numel() != plan.nchan:
+            raise ValueError("chan_scale: float32 [nchan] is required for packed 4-bit spectra")
+        fmt = IN_C4
+    elif spec.dtype == torch.complex64:
+        fmt = IN_CF32
+    elif spec.dtype == torch.complex128:
+        fmt = IN_CF64
+    else:
+        raise ValueError("spec must be uint8 (packed 4-bit), complex64 or complex128")
+    if spec.numel() != plan.nblock * plan.nchan:
+        raise ValueError("spec must hold nblock * (lblock/2+1) values")
+    return fmt
+
+
+def ml_cg(plan: Plan, spec, chan_scale, mask, prior, lam: float = 1.0, phi_x0: float = 0.1,
+          phi_precond: float = 0.1, iters: int = 100, x_init=None, x_out=None, resid=True, stream=None):
+    """Maximum-likelihood reconstruction with a time-domain prior (PCG).
+    mask: uint8 [S] (time order); prior: real [S] in the plan precision.
+    Returns (x, residual norms [iters+1] float64 or None)."""
+    import torch
+    fmt = _spec_fmt(plan, spec, chan_scale)
+    S = plan.nblock * plan.lblock
+    if mask.dtype != torch.uint8 or mask.numel() != S:
+        raise ValueError("mask: uint8 [nblock*lblock]")
+    if x_out is None:
+        x_out = _empty((S,), plan.real_dtype)
+    norms = _empty((iters + 1,), torch.float64) if resid else None
+    _check(lib().ipfb_ml_cg(plan.handle, fmt, _ptr(spec, "spec"), _ptr(chan_scale, "chan_scale"),
+                            _ptr(mask, "mask"), plan._real(prior, "prior"), float(lam), float(phi_x0),
+                            float(phi_precond), int(iters),
+                            None if x_init is None else plan._real(x_init, "x_init"),
+                            plan._real(x_out, "x_out"), _ptr(norms, "resid"), _stream(stream)))
+    return x_out, norms
 
 
 def upchannelize(fine: Plan, x, y_fine=None, autospec=None, want_autospec: bool = True, stream=None):
