@@ -37,9 +37,9 @@ HBM_PEAK_GBPS = 8000.0
 #  ipfb_transpose_in  : 4 B d read + 4 B d_T write
 #  ipfb_cols          : 4 B d_T read + 4 B x_T write
 #  ipfb_transpose_out : 4 B x_T read + 4 B xhat write
-#  pfb_fwd_long       : pass 1 reads xhat (4 B) and writes the packed row
-#                       (4 B); pass 2 reads it (4 B) and writes the fine
-#                       spectra (4 B)
+#  pfb_fwd_long       : xhat read (4 B), fine window, fine spectra written
+#                       (4 B); the two passes' intermediate round trip is an
+#                       implementation cost and is not counted
 #  autospec_final     : the per-chunk power sums
 # The step is priced separately at the method's compulsory traffic (see
 # step_bytes), independent of this kernel split.
@@ -53,7 +53,7 @@ def kernel_bytes(name, N, b, Nf, bf, esz):
     if name in ("ipfb_transpose_in", "ipfb_cols", "ipfb_transpose_out"):
         return 2 * S * esz
     if name == "pfb_fwd_long":
-        return S * esz + 4 * Nf * esz + 2 * S * esz + bf * K * 2 * esz
+        return S * esz + 4 * Nf * esz + bf * K * 2 * esz
     if name == "autospec_final":
         return 8 * ((bf + 1) // 2 + 15) // 16 * K * 8 + K * 8
     return None
@@ -148,6 +148,43 @@ def cpu_baseline(N, p, Nf, phi, frames, seed):
             "seconds": dt}
 
 
+def ml_form(torch, ipfb, inputs):
+    """Maximum-likelihood CG form: lblock = 2048, ntap = 4, nblock = 8192,
+    4-bit spectra, saved samples on a random 10% mask (prior = the true
+    timestream), Wiener x0 and preconditioner (phi = 0.1), 100 iterations,
+    FP32 vectors with FP64 dots. Samples/s = S / (setup + 100 iterations)."""
+    N, p, b, iters = 2048, 4, 8192, 100
+    S = N * b
+    x, w, packed, scales = make_inputs(torch, ipfb, inputs, N, p, b, 5, 0, 0, 0.0, 2.5)
+    mask = torch.from_numpy(inputs.random_mask(S, 0.1, 505).astype("uint8")).cuda()
+    prior = torch.from_numpy(x.astype("float32")).cuda()
+    plan = ipfb.Plan(N, p, w, b, ipfb.F32)
+    xo = torch.empty(S, dtype=torch.float32, device="cuda")
+    ipfb.ml_cg(plan, packed, scales, mask, prior, 1.0, 0.1, 0.1, iters, x_out=xo)  # warm-up, allocates
+    torch.cuda.synchronize()
+    reps = 3
+    ipfb.profile_reset()
+    ipfb.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, norms = ipfb.ml_cg(plan, packed, scales, mask, prior, 1.0, 0.1, 0.1, iters, x_out=xo)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    ipfb.profile_enable(False)
+    it_ms, it_n = ipfb.profile_query("cg_iter")
+    ipfb.profile_reset()
+    nrm = norms.cpu().numpy()
+    # per-iteration compulsory traffic (FP32 vectors): H p (read p, write q) 8 B,
+    # x/r update (read x, p, r, q; write x, r) 24 B, z = M^-1 r (read r, write z)
+    # 8 B, r.z (read r, z) 8 B, p update (read z, p; write p) 12 B -> 60 B/sample
+    it_bytes = 60.0 * S
+    it_us = 1e3 * it_ms / max(it_n, 1)
+    return {"value": S / sec, "unit": "samples/s", "ms_per_solve": sec * 1e3, "iterations": iters,
+            "config": {"lblock": N, "ntap": p, "nblock": b, "mask_fraction": 0.1, "lambda": 1.0, "phi": 0.1},
+            "us_per_iteration": it_us, "iteration_hbm_GBps": it_bytes / (it_us * 1e-6) / 1e9,
+            "resid_norm_first_last": [float(nrm[0]), float(nrm[-1])]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +193,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the FP64 form")
     ap.add_argument("--cpu-frames", type=int, default=16384)
+    ap.add_argument("--no-ml", action="store_true", help="skip timing the ML-CG form")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy 5 times (HBM counter calibration) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -171,6 +211,15 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.probe_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"probe": "copy", "bytes_read_per_launch": src.numel() * 4,
+                          "bytes_written_per_launch": dst.numel() * 4}))
+        return
     N, p, b, u, phi = 4096, 4, 16384, 64, 0.1
     Nf = N * u
     bf = (N * b) // Nf
@@ -264,6 +313,8 @@ def main():
                             "hbm_GBps": sb64 / r64["sec_per_step"] / 1e9,
                             "per_kernel_us": {k: round(v["avg_us"], 2) for k, v in r64["per_kernel"].items()}}
         out["fp32_vs_fp64"] = agree
+    if not args.no_ml:
+        out["ml_form"] = ml_form(torch, ipfb, inputs)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(N, p, Nf, phi, args.cpu_frames, 2)
     print(json.dumps(out), flush=True)
