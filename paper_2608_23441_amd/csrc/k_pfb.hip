@@ -128,8 +128,8 @@ __global__ __launch_bounds__((Up1Cfg<T, LOG2P1>::NT)) void k_up1(
   const int tid = threadIdx.x;
   const int ncb = P2 / MB;
   const int64_t lg = xcd_remap(blockIdx.x, (int)(nq * ncb));
-  const int64_t q = lg % nq;  // neighbouring q share frames: keep them on one XCD
-  const int c0 = (int)(lg / nq) * MB;
+  const int64_t q = lg / ncb;
+  const int c0 = (int)(lg % ncb) * MB;  // neighbouring column blocks share an XCD
   const int64_t j0 = 2 * q;
   const bool has1 = (j0 + 1) < nblock;
   for (int e = tid; e < P1 * MB; e += NT) {
@@ -181,8 +181,10 @@ __global__ __launch_bounds__((Up1sCfg<T, LOG2P1>::NT)) void k_up1_slide(
   __shared__ cx<T> s[MB * LS];
   const int tid = threadIdx.x;
   const int ncb = P2 / MB;
-  const int cb = blockIdx.x % ncb;
-  const int64_t qa = (int64_t)(blockIdx.x / ncb) * qrange;
+  // neighbouring column blocks (the two halves of each 128-byte line) share an XCD
+  const int lg = xcd_remap(blockIdx.x, (int)gridDim.x);
+  const int cb = lg % ncb;
+  const int64_t qa = (int64_t)(lg / ncb) * qrange;
   const int64_t qb = (qa + qrange < nq) ? qa + qrange : nq;
   const int c0 = cb * MB;
   // sample offset of element i within a frame: off0 + i * (NT/MB) * P2
@@ -261,8 +263,9 @@ __global__ __launch_bounds__((Up2Cfg<T, LOG2P2>::NT), 4) void k_up2(
   __shared__ cx<T> s[2 * KB * LS];
   const int tid = threadIdx.x;
   const int K = L / 2 + 1;
-  const int w = blockIdx.x % npb;
-  const int qc = blockIdx.x / npb;
+  const int lg = xcd_remap(blockIdx.x, (int)gridDim.x);  // adjacent row blocks write the same lines
+  const int w = lg % npb;
+  const int qc = lg / npb;
   const bool special = (w == npb - 1);
   const int r0 = 1 + w * KB;
   const int count = special ? 1 : min(KB, P1 / 2 - r0);
