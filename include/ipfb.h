@@ -152,6 +152,30 @@ int ipfb_autospectrum(ipfb_plan plan, const void* y, double* autospec, void* str
 int ipfb_quantize_c4(ipfb_plan plan, const void* y, double levels_rms, uint8_t* packed, float* scales,
                      void* stream);
 
+/* Batched form: nstreams independent timestreams sharing lblock, ntap, the
+ * window and the precision, each with its own nblock (2 <= nblock <= 32768,
+ * any integer). Each stream is inverted exactly as ipfb_wiener does (Section
+ * 3.1 with the Section 4.1 gain), circularly over its own nblock frames: the
+ * b-point column DFTs of a stream whose nblock is not a power of two use
+ * Bluestein's chirp-z identity with FP64-built chirps and filter spectra.
+ * window: host, ntap*lblock doubles; nblock: host array [nstreams]; both
+ * copied. The plan owns per-length tables and one set of scratch buffers
+ * sized for the longest stream (streams run one after another). */
+typedef struct ipfb_bplan_s* ipfb_bplan;
+int ipfb_batched_plan_create(ipfb_bplan* out, int lblock, int ntap, const double* window, int nstreams,
+                             const int64_t* nblock, int prec);
+int ipfb_batched_plan_destroy(ipfb_bplan plan);
+int ipfb_batched_workspace_size(ipfb_bplan plan, size_t* bytes);
+/* on = 1 (default): a call replays one HIP graph holding every stream's
+ * launches, captured on the first call and again whenever the pointers, phi,
+ * format or normalisation change; on = 0: launch directly on the stream. */
+int ipfb_batched_use_graph(ipfb_bplan plan, int on);
+/* spec, chan_scale, x_out: host arrays [nstreams] of device pointers with the
+ * per-stream layouts of ipfb_wiener (chan_scale ignored unless IPFB_IN_C4).
+ * normalise as in ipfb_wiener_ex. Asynchronous on stream (NULL = default). */
+int ipfb_wiener_batched(ipfb_bplan plan, int infmt, const void* const* spec, const float* const* chan_scale,
+                        double phi, int normalise, void* const* x_out, void* stream);
+
 /* Instrumentation: per-kernel timing with HIP events recorded on the
  * launching stream around every kernel group the library enqueues (names:
  * "ipfb_rows", "ipfb_transpose_in", "ipfb_cols", "ipfb_transpose_out",

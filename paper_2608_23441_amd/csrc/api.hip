@@ -7,7 +7,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <complex>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -596,6 +598,344 @@ int ipfb_profile_query(const char* name, double* total_ms, int64_t* launches) {
   *total_ms = tot;
   *launches = n;
   return ok();
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Batched form: many independent streams with their own nblock, one lblock,
+// window and precision. Each stream runs the same steps as ipfb_wiener; a
+// stream whose nblock is a power of two uses the LDS column kernel, any other
+// length the Bluestein column path. The whole multi-stream sequence is
+// captured once into a HIP graph and replayed by one graph launch per call.
+// ============================================================================
+namespace {
+
+// In-place iterative radix-2 FFT (host, double): forward sign e^{-2 pi i jk/n}.
+void host_fft(std::vector<std::complex<double>>& a) {
+  const size_t n = a.size();
+  for (size_t i = 1, j = 0; i < n; ++i) {
+    size_t bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (size_t len = 2; len <= n; len <<= 1) {
+    std::vector<std::complex<double>> w(len / 2);
+    for (size_t k = 0; k < len / 2; ++k) {
+      const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)len;
+      w[k] = std::complex<double>((double)cosl(ang), (double)sinl(ang));
+    }
+    for (size_t i = 0; i < n; i += len)
+      for (size_t k = 0; k < len / 2; ++k) {
+        const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * w[k];
+        a[i + k] = u + v;
+        a[i + k + len / 2] = u - v;
+      }
+  }
+}
+
+struct BluTables {  // per distinct nblock b
+  int log2m = 0;
+  void* chirp = nullptr;  // [b] complex, plan precision
+  void* Crow = nullptr;   // [M1][M2] complex
+  double* twb64 = nullptr;  // [b] complex double
+  void* twB = nullptr;      // power-of-two b: Stockham table [b]
+};
+
+struct MTables {  // per distinct convolution length M
+  void* buf = nullptr;  // tM1 | tM2 | tLo (256) | tHi (max(1, M/256))
+  const void* tw4[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+}  // namespace
+
+struct ipfb_bplan_s {
+  int lblock = 0, ntap = 0, prec = 0, log2n = 0, dev = 0, nstreams = 0;
+  std::vector<int64_t> nblock;
+  double* win64 = nullptr;
+  void* twN = nullptr;
+  void* fac = nullptr;
+  std::map<int64_t, BluTables> blu;
+  std::map<int, MTables> mtab;
+  void* f0 = nullptr;  // two frame buffers of max_b * lblock reals
+  void* f1 = nullptr;
+  void* Tm = nullptr;  // Bluestein four-step scratch
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<uintptr_t> key;
+  bool use_graph = true;
+};
+
+namespace {
+
+int balloc(ipfb_bplan p, void** ptr, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (inject("alloc")) return fail(IPFB_ENOMEM, "device allocation of %zu bytes failed (injected)", bytes);
+  hipError_t e = hipMalloc(ptr, bytes);
+  if (e != hipSuccess) {
+    *ptr = nullptr;
+    hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? IPFB_ENOMEM : IPFB_EHIP, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  p->allocs.push_back(*ptr);
+  p->bytes += bytes;
+  return IPFB_OK;
+}
+
+int bupload(ipfb_bplan p, const std::vector<double>& t, int prec, void** dst) {
+  const size_t n = t.size();
+  int st = balloc(p, dst, n * esize(prec));
+  if (st) return st;
+  if (prec == IPFB_F64) return upload(*dst, t.data(), n * sizeof(double));
+  std::vector<float> f(n);
+  for (size_t i = 0; i < n; ++i) f[i] = (float)t[i];
+  return upload(*dst, f.data(), n * sizeof(float));
+}
+
+void free_bplan(ipfb_bplan p) {
+  if (p->exec) hipGraphExecDestroy(p->exec);
+  if (p->cap) hipStreamDestroy(p->cap);
+  for (void* q : p->allocs) hipFree(q);
+  delete p;
+}
+
+int blu_log2m(int64_t b) {
+  int l = 0;
+  while ((int64_t(1) << l) < 2 * b - 1) ++l;
+  return l < 2 ? 2 : l;
+}
+
+// chirp c_m = e^{i pi m^2 / b}, with m^2 reduced mod 2b in integers
+std::vector<double> chirp_table(int64_t b) {
+  std::vector<double> t(2 * b);
+  const long double pi = 3.14159265358979323846264338327950288L;
+  for (int64_t m = 0; m < b; ++m) {
+    const int64_t q = (m * m) % (2 * b);
+    const long double a = pi * (long double)q / (long double)b;
+    t[2 * m] = (double)cosl(a);
+    t[2 * m + 1] = (double)sinl(a);
+  }
+  return t;
+}
+
+int build_blu(ipfb_bplan p, int64_t b) {
+  BluTables bt;
+  if (is_pow2(b) && b >= 4 && ilog2(b) <= max_log2_col(p->prec)) {
+    std::vector<double> tb = twiddles(b);
+    int st = bupload(p, tb, p->prec, &bt.twB);
+    if (!st) st = bupload(p, tb, IPFB_F64, (void**)&bt.twb64);
+    if (st) return st;
+    p->blu[b] = bt;
+    return IPFB_OK;
+  }
+  bt.log2m = blu_log2m(b);
+  const int64_t M = int64_t(1) << bt.log2m;
+  const int l1 = (bt.log2m + 1) / 2, l2 = bt.log2m / 2;
+  const int64_t M1 = int64_t(1) << l1, M2 = int64_t(1) << l2;
+  std::vector<double> ch = chirp_table(b);
+  std::vector<std::complex<double>> c(M, {0.0, 0.0});
+  for (int64_t m = 0; m < b; ++m) {
+    c[m] = {ch[2 * m], ch[2 * m + 1]};
+    if (m > 0) c[M - m] = c[m];
+  }
+  host_fft(c);
+  std::vector<double> crow(2 * M);
+  for (int64_t k1 = 0; k1 < M1; ++k1)
+    for (int64_t k2 = 0; k2 < M2; ++k2) {
+      const std::complex<double> v = c[k1 + M1 * k2];
+      crow[2 * (k1 * M2 + k2)] = v.real();
+      crow[2 * (k1 * M2 + k2) + 1] = v.imag();
+    }
+  int st = bupload(p, ch, p->prec, &bt.chirp);
+  if (!st) st = bupload(p, crow, p->prec, &bt.Crow);
+  if (!st) st = bupload(p, twiddles(b), IPFB_F64, (void**)&bt.twb64);
+  if (st) return st;
+  p->blu[b] = bt;
+  if (!p->mtab.count(bt.log2m)) {
+    std::vector<double> t1 = twiddles(M1), t2 = twiddles(M2), tm = twiddles(M);
+    std::vector<double> all;
+    all.insert(all.end(), t1.begin(), t1.end());
+    all.insert(all.end(), t2.begin(), t2.end());
+    for (int m = 0; m < 256; ++m) {  // w_M^m, m < 256 (periodic in M)
+      all.push_back(tm[2 * (m % M)]);
+      all.push_back(tm[2 * (m % M) + 1]);
+    }
+    const int64_t nhi = M / 256 > 0 ? M / 256 : 1;
+    for (int64_t m = 0; m < nhi; ++m) {
+      all.push_back(tm[2 * ((256 * m) % M)]);
+      all.push_back(tm[2 * ((256 * m) % M) + 1]);
+    }
+    MTables mt;
+    st = bupload(p, all, p->prec, &mt.buf);
+    if (st) return st;
+    const size_t es = 2 * esize(p->prec);
+    const char* base = (const char*)mt.buf;
+    mt.tw4[0] = base;
+    mt.tw4[1] = base + M1 * es;
+    mt.tw4[2] = base + (M1 + M2) * es;
+    mt.tw4[3] = base + (M1 + M2 + 256) * es;
+    p->mtab[bt.log2m] = mt;
+  }
+  return IPFB_OK;
+}
+
+// All launches of one batched call on stream st.
+hipError_t enqueue_batched(ipfb_bplan p, int infmt, const void* const* spec, const float* const* sc, double phi,
+                           int normalise, void* const* xo, hipStream_t st) {
+  const int N = p->lblock;
+  const int K = N / 2 + 1;
+  hipError_t e = hipSuccess;
+  for (int s = 0; s < p->nstreams && e == hipSuccess; ++s) {
+    const int64_t b = p->nblock[s];
+    const BluTables& bt = p->blu[b];
+    if (infmt == IPFB_IN_C4) e = launch_dequant_factors(p->prec, sc[s], K, N, p->fac, st);
+    if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec[s], p->fac, p->f0, b, p->twN, st);
+    if (e == hipSuccess) e = launch_transpose(p->prec, p->f0, p->f1, b, N, st);  // d -> d_T in f1
+    if (e != hipSuccess) break;
+    if (bt.log2m == 0) {  // power of two: LDS column kernel, x_T in f0
+      e = launch_col_wiener(p->prec, ilog2(b), p->f1, p->f0, N, p->ntap, p->win64, phi, normalise, bt.twB, bt.twb64,
+                            st);
+    } else {  // Bluestein: Z in f0, A in f1 (d_T consumed by then), x_T in f0
+      const MTables& mt = p->mtab[bt.log2m];
+      e = launch_blu_columns(p->prec, p->f1, p->f0, p->Tm, p->f0, p->f1, bt.chirp, bt.Crow, bt.twb64, b, bt.log2m,
+                             N, p->ntap, p->win64, phi, normalise, mt.tw4, st);
+    }
+    if (e == hipSuccess) e = launch_transpose(p->prec, p->f0, xo[s], N, b, st);  // x_T -> x (time order)
+  }
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ipfb_batched_plan_create(ipfb_bplan* out, int lblock, int ntap, const double* window, int nstreams,
+                             const int64_t* nblock, int prec) {
+  if (!out) return fail(IPFB_EINVAL, "plan output pointer is NULL");
+  *out = nullptr;
+  if (!window || !nblock) return fail(IPFB_EINVAL, "window and nblock must be non-NULL host arrays");
+  if (prec != IPFB_F32 && prec != IPFB_F64) return fail(IPFB_EINVAL, "prec must be IPFB_F32 or IPFB_F64");
+  if (!is_pow2(lblock) || lblock < 4) return fail(IPFB_EINVAL, "lblock must be a power of two >= 4 (got %d)", lblock);
+  if (ilog2(lblock) > max_log2_row(prec)) return fail(IPFB_EUNSUPPORTED, "lblock too large for the inverse");
+  if (ntap < 1) return fail(IPFB_EINVAL, "ntap must be >= 1");
+  if (nstreams < 1) return fail(IPFB_EINVAL, "nstreams must be >= 1");
+  int64_t maxb = 0;
+  for (int s = 0; s < nstreams; ++s) {
+    if (nblock[s] < 2) return fail(IPFB_EINVAL, "stream %d: nblock must be >= 2", s);
+    if (nblock[s] > 32768) return fail(IPFB_EUNSUPPORTED, "stream %d: nblock > 32768 is not supported", s);
+    if (nblock[s] > maxb) maxb = nblock[s];
+  }
+  ipfb_bplan p = new ipfb_bplan_s();
+  p->lblock = lblock;
+  p->ntap = ntap;
+  p->prec = prec;
+  p->log2n = ilog2(lblock);
+  p->nstreams = nstreams;
+  p->nblock.assign(nblock, nblock + nstreams);
+  if (hipGetDevice(&p->dev) != hipSuccess) {
+    hipGetLastError();
+    delete p;
+    return fail(IPFB_EHIP, "no HIP device available");
+  }
+  const int64_t M = int64_t(1) << 20;
+  int st = balloc(p, (void**)&p->win64, (size_t)ntap * lblock * sizeof(double));
+  if (!st) st = upload(p->win64, window, (size_t)ntap * lblock * sizeof(double));
+  if (!st) st = bupload(p, twiddles(lblock), prec, &p->twN);
+  if (!st) st = balloc(p, &p->fac, (size_t)(lblock / 2 + 1) * esize(prec));
+  int maxlog2m = 0;
+  for (int s = 0; s < nstreams && !st; ++s)
+    if (!p->blu.count(nblock[s])) {
+      st = build_blu(p, nblock[s]);
+      if (!st && p->blu[nblock[s]].log2m > maxlog2m) maxlog2m = p->blu[nblock[s]].log2m;
+    }
+  const size_t fb = (size_t)maxb * lblock * esize(prec);
+  if (!st) st = balloc(p, &p->f0, fb);
+  if (!st) st = balloc(p, &p->f1, fb);
+  if (!st && maxlog2m > 0)
+    st = balloc(p, &p->Tm, (size_t)((lblock + 1) / 2) * ((size_t)1 << maxlog2m) * 2 * esize(prec));
+  (void)M;
+  if (!st && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
+    hipGetLastError();
+    st = fail(IPFB_EHIP, "hipStreamCreate failed");
+  }
+  if (st) {
+    std::string keep = g_err;
+    free_bplan(p);
+    g_err = keep;
+    return st;
+  }
+  *out = p;
+  return ok();
+}
+
+int ipfb_batched_plan_destroy(ipfb_bplan p) {
+  if (!p) return fail(IPFB_EINVAL, "plan is NULL");
+  DeviceGuard g(p->dev);
+  free_bplan(p);
+  return ok();
+}
+
+int ipfb_batched_workspace_size(ipfb_bplan p, size_t* bytes) {
+  if (!p || !bytes) return fail(IPFB_EINVAL, "NULL argument");
+  *bytes = p->bytes;
+  return ok();
+}
+
+int ipfb_batched_use_graph(ipfb_bplan p, int on) {
+  if (!p) return fail(IPFB_EINVAL, "plan is NULL");
+  p->use_graph = (on != 0);
+  return ok();
+}
+
+int ipfb_wiener_batched(ipfb_bplan p, int infmt, const void* const* spec, const float* const* chan_scale,
+                        double phi, int normalise, void* const* x_out, void* stream) {
+  if (!p) return fail(IPFB_EINVAL, "plan is NULL");
+  if (!spec || !x_out) return fail(IPFB_EINVAL, "spec and x_out must be non-NULL host arrays of device pointers");
+  if (infmt != IPFB_IN_C4 && infmt != IPFB_IN_CF32 && infmt != IPFB_IN_CF64)
+    return fail(IPFB_EINVAL, "unknown input format %d", infmt);
+  if (infmt == IPFB_IN_C4 && !chan_scale) return fail(IPFB_EINVAL, "chan_scale is required for IPFB_IN_C4");
+  if (!(phi >= 0.0) || !std::isfinite(phi)) return fail(IPFB_EINVAL, "phi must be finite and >= 0");
+  for (int s = 0; s < p->nstreams; ++s) {
+    if (!spec[s] || !x_out[s] || (infmt == IPFB_IN_C4 && !chan_scale[s]))
+      return fail(IPFB_EINVAL, "stream %d: NULL pointer", s);
+  }
+  DeviceGuard g(p->dev);
+  hipStream_t st = (hipStream_t)stream;
+  if (!p->use_graph) return launched(enqueue_batched(p, infmt, spec, chan_scale, phi, normalise, x_out, st), "ipfb_wiener_batched");
+  std::vector<uintptr_t> key;
+  key.push_back((uintptr_t)infmt);
+  key.push_back((uintptr_t)normalise);
+  uint64_t phibits;
+  memcpy(&phibits, &phi, sizeof(phibits));
+  key.push_back((uintptr_t)phibits);
+  for (int s = 0; s < p->nstreams; ++s) {
+    key.push_back((uintptr_t)spec[s]);
+    key.push_back((uintptr_t)(chan_scale ? chan_scale[s] : nullptr));
+    key.push_back((uintptr_t)x_out[s]);
+  }
+  if (!p->exec || key != p->key) {
+    if (p->exec) {
+      hipGraphExecDestroy(p->exec);
+      p->exec = nullptr;
+    }
+    hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return launched(e, "hipStreamBeginCapture");
+    hipError_t ee = enqueue_batched(p, infmt, spec, chan_scale, phi, normalise, x_out, p->cap);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(p->cap, &graph);
+    if (ee != hipSuccess) e = ee;
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+    if (graph) hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      p->exec = nullptr;
+      return launched(e, "graph capture of the batched inverse");
+    }
+    p->key = key;
+  }
+  return launched(hipGraphLaunch(p->exec, st), "ipfb_wiener_batched");
 }
 
 }  // extern "C"

@@ -1,0 +1,346 @@
+// Column stage of the circulant inverse PFB for an arbitrary number of frames
+// b (the batched form: streams of uneven length). The b-point DFT down each
+// sub-filter path (Section 3.1's decorrelation needs exactly length b: padding
+// would change the circulant) is computed with Bluestein's chirp-z identity
+//   jk = (j^2 + k^2 - (k-j)^2)/2  =>  X_k = conj(c_k) sum_j (x_j conj(c_j)) c_{k-j},
+//   c_m = exp(i pi m^2 / b),
+// a linear convolution evaluated as a cyclic one of power-of-two length
+// M >= 2b-1 against the precomputed spectrum C = FFT_M(c). Two real columns
+// (n, n+1) travel as one complex sequence. Each M-point FFT is a four-step
+// M = M1 * M2 over global memory:
+//   A  (per pair, block of MB consecutive j2): M1-point DFTs over j1 of
+//      a[j1 M2 + j2], twiddle w_M^{j2 k1}            -> T[pair][k1][j2]
+//   B  (per pair, block of KB rows k1): M2-point DFT along the row, times
+//      C[k1 + M1 k2] (or its conjugate), inverse M2-point DFT, conj twiddle
+//                                                     -> T in place
+//   A' (per pair, block of MB j2): inverse M1-point DFTs over k1 -> the cyclic
+//      convolution at j = j1 M2 + j2, times the post-chirp.
+// Between the two convolutions one kernel splits the two real spectra, applies
+// the FP64 Wiener gain of Section 4.1 and re-packs them (it needs X_k and
+// X_{b-k}, which the four-step places far apart).
+#include "fft_lds.hpp"
+#include "launch.hpp"
+
+namespace ipfb {
+
+struct BluTw {  // all e^{-2 pi i m / len} in the data precision
+  const void* tM1;   // [M1]
+  const void* tM2;   // [M2]
+  const void* tLo;   // [256]   w_M^{m & 255}
+  const void* tHi;   // [M/256] w_M^{256 (m >> 8)}
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> blu_twM(const cx<T>* lo, const cx<T>* hi, int m) {
+  return cmul(hi[m >> 8], lo[m & 255]);
+}
+
+template <int LOG2M1>
+struct BluACfg {
+  static constexpr int M1 = 1 << LOG2M1;
+  static constexpr int MB = 16;
+  static constexpr int LS = lds_len(M1);
+  static constexpr int NT0 = (M1 * MB) / 8;
+  static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 512 ? 512 : NT0);
+};
+
+// MODE 0: input = real pair from x_T [N][b] times conj(chirp); MODE 1: input = complex a [pair][b]
+template <typename T, int LOG2M1, int MODE>
+__global__ __launch_bounds__((BluACfg<LOG2M1>::NT)) void k_blu_A(
+    const void* __restrict__ in, cx<T>* __restrict__ Tm, const cx<T>* __restrict__ chirp, int64_t b, int M2,
+    int N, BluTw tw) {
+  using Cfg = BluACfg<LOG2M1>;
+  constexpr int M1 = Cfg::M1, LS = Cfg::LS, NT = Cfg::NT;
+  constexpr int MB = Cfg::MB;
+  __shared__ cx<T> s[MB * LS];
+  const int mb_eff = M2 < MB ? M2 : MB;
+  const int nblk = M2 / mb_eff;
+  const int64_t pair = blockIdx.x / nblk;
+  const int j20 = (blockIdx.x % nblk) * mb_eff;
+  for (int e = threadIdx.x; e < M1 * MB; e += NT) {
+    const int mb = e % MB, j1 = e / MB;
+    cx<T> v = mk<T>(T(0), T(0));
+    const int64_t j = (int64_t)j1 * M2 + j20 + mb;
+    if (mb < mb_eff && j < b) {
+      if constexpr (MODE == 0) {
+        const T* xT = reinterpret_cast<const T*>(in);
+        const int64_t n = 2 * pair;
+        const T re = xT[n * b + j];
+        const T im = (n + 1 < N) ? xT[(n + 1) * b + j] : T(0);
+        v = cmulc(mk<T>(re, im), chirp[j]);
+      } else {
+        v = reinterpret_cast<const cx<T>*>(in)[pair * b + j];
+      }
+    }
+    s[mb * LS + pidx(j1)] = v;
+  }
+  __syncthreads();
+  lds_fft<T, M1, NT, MB, -1>(s, LS, reinterpret_cast<const cx<T>*>(tw.tM1), 1);
+  const int M = M1 * M2;
+  cx<T>* tp = Tm + pair * (int64_t)M;
+  const cx<T>* lo = reinterpret_cast<const cx<T>*>(tw.tLo);
+  const cx<T>* hi = reinterpret_cast<const cx<T>*>(tw.tHi);
+  for (int e = threadIdx.x; e < M1 * MB; e += NT) {
+    const int mb = e % MB, k1 = e / MB;
+    if (mb >= mb_eff) continue;
+    const int j2 = j20 + mb;
+    tp[(int64_t)k1 * M2 + j2] = cmul(s[mb * LS + pidx(k1)], blu_twM(lo, hi, j2 * k1));
+  }
+}
+
+template <int LOG2M2>
+struct BluBCfg {
+  static constexpr int M2 = 1 << LOG2M2;
+  static constexpr int KB = 16;
+  static constexpr int LS = lds_len(M2);
+  static constexpr int NT0 = (M2 * KB) / 8;
+  static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 512 ? 512 : NT0);
+};
+
+template <typename T, int LOG2M2>
+__global__ __launch_bounds__((BluBCfg<LOG2M2>::NT)) void k_blu_B(cx<T>* __restrict__ Tm,
+                                                                 const cx<T>* __restrict__ Crow, int conjC,
+                                                                 int M1, BluTw tw) {
+  using Cfg = BluBCfg<LOG2M2>;
+  constexpr int M2 = Cfg::M2, LS = Cfg::LS, NT = Cfg::NT, KB = Cfg::KB;
+  __shared__ cx<T> s[KB * LS];
+  const int kb_eff = M1 < KB ? M1 : KB;
+  const int nblk = M1 / kb_eff;
+  const int64_t pair = blockIdx.x / nblk;
+  const int k10 = (blockIdx.x % nblk) * kb_eff;
+  const int M = M1 * M2;
+  cx<T>* tp = Tm + pair * (int64_t)M;
+  for (int e = threadIdx.x; e < KB * M2; e += NT) {
+    const int r = e / M2, c = e % M2;
+    cx<T> v = mk<T>(T(0), T(0));
+    if (r < kb_eff) v = tp[(int64_t)(k10 + r) * M2 + c];
+    s[r * LS + pidx(c)] = v;
+  }
+  __syncthreads();
+  const cx<T>* tM2 = reinterpret_cast<const cx<T>*>(tw.tM2);
+  lds_fft<T, M2, NT, KB, -1>(s, LS, tM2, 1);
+  for (int e = threadIdx.x; e < KB * M2; e += NT) {  // times C[k1 + M1 k2] (row layout Crow[k1][k2])
+    const int r = e / M2, k2 = e % M2;
+    if (r >= kb_eff) continue;
+    cx<T> h = Crow[(int64_t)(k10 + r) * M2 + k2];
+    if (conjC) h.y = -h.y;
+    s[r * LS + pidx(k2)] = cmul(s[r * LS + pidx(k2)], h);
+  }
+  __syncthreads();
+  lds_fft<T, M2, NT, KB, +1>(s, LS, tM2, 1);
+  const cx<T>* lo = reinterpret_cast<const cx<T>*>(tw.tLo);
+  const cx<T>* hi = reinterpret_cast<const cx<T>*>(tw.tHi);
+  for (int e = threadIdx.x; e < KB * M2; e += NT) {
+    const int r = e / M2, j2 = e % M2;
+    if (r >= kb_eff) continue;
+    const int k1 = k10 + r;
+    tp[(int64_t)k1 * M2 + j2] = cmulc(s[r * LS + pidx(j2)], blu_twM(lo, hi, j2 * k1));
+  }
+}
+
+// MODE 0: Z[pair][j] = conj(c_j) conv_j / M (the b-point DFT); MODE 1: output
+// the pair of real columns  x_T[n][j] + i x_T[n+1][j] = c_j conv_j / (M b)
+template <typename T, int LOG2M1, int MODE>
+__global__ __launch_bounds__((BluACfg<LOG2M1>::NT)) void k_blu_Ainv(
+    const cx<T>* __restrict__ Tm, void* __restrict__ out, const cx<T>* __restrict__ chirp, int64_t b, int M2,
+    int N, BluTw tw) {
+  using Cfg = BluACfg<LOG2M1>;
+  constexpr int M1 = Cfg::M1, LS = Cfg::LS, NT = Cfg::NT;
+  constexpr int MB = Cfg::MB;
+  __shared__ cx<T> s[MB * LS];
+  const int mb_eff = M2 < MB ? M2 : MB;
+  const int nblk = M2 / mb_eff;
+  const int64_t pair = blockIdx.x / nblk;
+  const int j20 = (blockIdx.x % nblk) * mb_eff;
+  const int M = M1 * M2;
+  const cx<T>* tp = Tm + pair * (int64_t)M;
+  for (int e = threadIdx.x; e < M1 * MB; e += NT) {
+    const int mb = e % MB, k1 = e / MB;
+    cx<T> v = mk<T>(T(0), T(0));
+    if (mb < mb_eff) v = tp[(int64_t)k1 * M2 + j20 + mb];
+    s[mb * LS + pidx(k1)] = v;
+  }
+  __syncthreads();
+  lds_fft<T, M1, NT, MB, +1>(s, LS, reinterpret_cast<const cx<T>*>(tw.tM1), 1);
+  const T sc = (MODE == 0) ? T(1.0 / (double)M) : T(1.0 / ((double)M * (double)b));
+  for (int e = threadIdx.x; e < M1 * MB; e += NT) {
+    const int mb = e % MB, j1 = e / MB;
+    if (mb >= mb_eff) continue;
+    const int64_t j = (int64_t)j1 * M2 + j20 + mb;
+    if (j >= b) continue;
+    const cx<T> v = scale(s[mb * LS + pidx(j1)], sc);
+    if constexpr (MODE == 0) {
+      reinterpret_cast<cx<T>*>(out)[pair * b + j] = cmulc(v, chirp[j]);
+    } else {
+      const cx<T> z = cmul(v, chirp[j]);
+      T* xT = reinterpret_cast<T*>(out);
+      const int64_t n = 2 * pair;
+      xT[n * b + j] = z.x;
+      if (n + 1 < N) xT[(n + 1) * b + j] = z.y;
+    }
+  }
+}
+
+// Split the two real spectra of each pair, apply the FP64 gain, re-pack, and
+// pre-multiply by the chirp for the inverse transform:
+//   X1 = (Z_k + conj Z_{b-k})/2,  X2 = (Z_k - conj Z_{b-k})/2i,
+//   a_k = (G_n(k) X1 + i G_{n+1}(k) X2) c_k.
+struct BluGain {
+  const double* win;  // [ntap][N]
+  int N, ntap;
+  double phi2, gnorm;  // gnorm = 1 + phi^2 (or 1)
+  int naive;
+};
+
+__device__ __forceinline__ cx<double> blu_gain(const BluGain& g, int n, const cx<double>* __restrict__ twb64,
+                                               int64_t f) {
+  const cx<double> t1 = twb64[f];
+  cx<double> e = mk<double>(1.0, 0.0);
+  double wr = 0.0, wi = 0.0, wabs = 0.0;
+  for (int r = 0; r < g.ntap; ++r) {
+    const double h = g.win[(int64_t)r * g.N + n];
+    wr += h * e.x;
+    wi += h * e.y;
+    wabs += fabs(h);
+    e = cmul(e, t1);
+  }
+  const double a2 = wr * wr + wi * wi;
+  if (g.naive) {
+    if (sqrt(a2) <= 1e-12 * wabs) return mk<double>(0.0, 0.0);
+    return mk<double>(wr / a2, wi / a2);
+  }
+  const double s = g.gnorm / (a2 + g.phi2);
+  return mk<double>(wr * s, wi * s);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_blu_gain(const cx<T>* __restrict__ Z, cx<T>* __restrict__ a,
+                                                  const cx<T>* __restrict__ chirp,
+                                                  const cx<double>* __restrict__ twb64, int64_t b, int64_t npairs,
+                                                  BluGain g) {
+  const int64_t total = npairs * b;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int64_t pair = e / b, k = e - pair * b;
+    const int64_t km = (k == 0) ? 0 : b - k;
+    const cx<T> zk = Z[pair * b + k], zm = Z[pair * b + km];
+    const cx<double> Zk = mk<double>(zk.x, zk.y), Zm = mk<double>(zm.x, -zm.y);  // conj Z_{b-k}
+    const cx<double> X1 = mk<double>(0.5 * (Zk.x + Zm.x), 0.5 * (Zk.y + Zm.y));
+    const cx<double> D = mk<double>(0.5 * (Zk.x - Zm.x), 0.5 * (Zk.y - Zm.y));
+    const cx<double> X2 = mk<double>(D.y, -D.x);  // D / i
+    const int n = (int)(2 * pair);
+    const cx<double> Y1 = cmul(blu_gain(g, n, twb64, k), X1);
+    cx<double> Y2 = mk<double>(0.0, 0.0);
+    if (n + 1 < g.N) Y2 = cmul(blu_gain(g, n + 1, twb64, k), X2);
+    const cx<double> zp = mk<double>(Y1.x - Y2.y, Y1.y + Y2.x);  // Y1 + i Y2
+    const cx<T> c = chirp[k];
+    const cx<double> out = cmul(zp, mk<double>(c.x, c.y));
+    a[pair * b + k] = mk<T>(T(out.x), T(out.y));
+  }
+}
+
+// ---- launchers ---------------------------------------------------------------
+template <typename T, int L1>
+static hipError_t launch_blu_A_t(int mode, const void* in, void* Tm, const void* chirp, int64_t b, int M2, int N,
+                                 int64_t npairs, const BluTw& tw, hipStream_t st) {
+  using Cfg = BluACfg<L1>;
+  const int mb_eff = M2 < Cfg::MB ? M2 : Cfg::MB;
+  const dim3 grid((unsigned)(npairs * (M2 / mb_eff)));
+  if (mode == 0)
+    k_blu_A<T, L1, 0><<<grid, Cfg::NT, 0, st>>>(in, (cx<T>*)Tm, (const cx<T>*)chirp, b, M2, N, tw);
+  else
+    k_blu_A<T, L1, 1><<<grid, Cfg::NT, 0, st>>>(in, (cx<T>*)Tm, (const cx<T>*)chirp, b, M2, N, tw);
+  return hipGetLastError();
+}
+
+template <typename T, int L1>
+static hipError_t launch_blu_Ainv_t(int mode, const void* Tm, void* out, const void* chirp, int64_t b, int M2,
+                                    int N, int64_t npairs, const BluTw& tw, hipStream_t st) {
+  using Cfg = BluACfg<L1>;
+  const int mb_eff = M2 < Cfg::MB ? M2 : Cfg::MB;
+  const dim3 grid((unsigned)(npairs * (M2 / mb_eff)));
+  if (mode == 0)
+    k_blu_Ainv<T, L1, 0><<<grid, Cfg::NT, 0, st>>>((const cx<T>*)Tm, out, (const cx<T>*)chirp, b, M2, N, tw);
+  else
+    k_blu_Ainv<T, L1, 1><<<grid, Cfg::NT, 0, st>>>((const cx<T>*)Tm, out, (const cx<T>*)chirp, b, M2, N, tw);
+  return hipGetLastError();
+}
+
+template <typename T, int L2>
+static hipError_t launch_blu_B_t(void* Tm, const void* Crow, int conjC, int M1, int64_t npairs, const BluTw& tw,
+                                 hipStream_t st) {
+  using Cfg = BluBCfg<L2>;
+  const int kb_eff = M1 < Cfg::KB ? M1 : Cfg::KB;
+  const dim3 grid((unsigned)(npairs * (M1 / kb_eff)));
+  k_blu_B<T, L2><<<grid, Cfg::NT, 0, st>>>((cx<T>*)Tm, (const cx<T>*)Crow, conjC, M1, tw);
+  return hipGetLastError();
+}
+
+#define BLU_L1_SWITCH(CALL)                                 \
+  switch (l1) {                                             \
+    case 1: CALL(1) case 2: CALL(2) case 3: CALL(3)         \
+    case 4: CALL(4) case 5: CALL(5) case 6: CALL(6)         \
+    case 7: CALL(7) case 8: CALL(8)                         \
+    default: return hipErrorInvalidValue;                   \
+  }
+
+template <typename T>
+static hipError_t blu_conv(int in_mode, const void* in, int out_mode, void* out, void* Tm, const void* chirp,
+                           const void* Crow, int conjC, int64_t b, int log2m, int N, int64_t npairs,
+                           const BluTw& tw, hipStream_t st) {
+  const int l1 = (log2m + 1) / 2, l2 = log2m / 2;
+  const int M1 = 1 << l1, M2 = 1 << l2;
+  hipError_t e;
+#define CALL_A(L) e = launch_blu_A_t<T, L>(in_mode, in, Tm, chirp, b, M2, N, npairs, tw, st); break;
+  BLU_L1_SWITCH(CALL_A)
+#undef CALL_A
+  if (e != hipSuccess) return e;
+  switch (l2) {
+#define CALL_B(L) \
+  case L: e = launch_blu_B_t<T, L>(Tm, Crow, conjC, M1, npairs, tw, st); break;
+    CALL_B(1) CALL_B(2) CALL_B(3) CALL_B(4) CALL_B(5) CALL_B(6) CALL_B(7) CALL_B(8)
+#undef CALL_B
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+#define CALL_AI(L) e = launch_blu_Ainv_t<T, L>(out_mode, Tm, out, chirp, b, M2, N, npairs, tw, st); break;
+  BLU_L1_SWITCH(CALL_AI)
+#undef CALL_AI
+  return e;
+}
+
+hipError_t launch_blu_columns(int prec, const void* dT, void* xT, void* Tm, void* Z, void* A, const void* chirp,
+                              const void* Crow, const double* twb64, int64_t b, int log2m, int N, int ntap,
+                              const double* win64, double phi, int normalise, const void* const tw4[4],
+                              hipStream_t st) {
+  const int64_t npairs = (N + 1) / 2;
+  BluTw tw{tw4[0], tw4[1], tw4[2], tw4[3]};
+  BluGain g;
+  g.win = win64;
+  g.N = N;
+  g.ntap = ntap;
+  g.phi2 = phi * phi;
+  g.gnorm = normalise ? 1.0 + phi * phi : 1.0;
+  g.naive = (phi == 0.0);
+  hipError_t e;
+  const unsigned ggrid = (unsigned)((npairs * b + 255) / 256 < 4096 ? (npairs * b + 255) / 256 : 4096);
+  if (prec == F32) {
+    e = blu_conv<float>(0, dT, 0, Z, Tm, chirp, Crow, 0, b, log2m, N, npairs, tw, st);
+    if (e == hipSuccess) {
+      k_blu_gain<float><<<ggrid, 256, 0, st>>>((const cx<float>*)Z, (cx<float>*)A, (const cx<float>*)chirp,
+                                               (const cx<double>*)twb64, b, npairs, g);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = blu_conv<float>(1, A, 1, xT, Tm, chirp, Crow, 1, b, log2m, N, npairs, tw, st);
+  } else {
+    e = blu_conv<double>(0, dT, 0, Z, Tm, chirp, Crow, 0, b, log2m, N, npairs, tw, st);
+    if (e == hipSuccess) {
+      k_blu_gain<double><<<ggrid, 256, 0, st>>>((const cx<double>*)Z, (cx<double>*)A, (const cx<double>*)chirp,
+                                                (const cx<double>*)twb64, b, npairs, g);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = blu_conv<double>(1, A, 1, xT, Tm, chirp, Crow, 1, b, log2m, N, npairs, tw, st);
+  }
+  return e;
+}
+
+}  // namespace ipfb

@@ -50,6 +50,17 @@ hipError_t launch_cg_scalar(const double* part, int mode, double* sc, double* re
 hipError_t launch_mask_to_T(int prec, const uint8_t* m, void* out, int64_t S, hipStream_t st);
 constexpr int kCgParts = 1024;
 
+// Arbitrary-length column stage (Bluestein): dT, xT [N][b] real; Tm scratch
+// ((N+1)/2 * 2^log2m complex), Z and A scratch ((N+1)/2 * b complex each, may
+// alias the frame buffers as long as they differ from dT/xT when live);
+// chirp [b] complex e^{i pi m^2/b}; Crow [M1][M2] complex = FFT_M of the
+// symmetric chirp filter in row layout; twb64 [b] double complex
+// e^{-2 pi i m/b}; tw4 = {tM1 [M1], tM2 [M2], tLo [256], tHi [max(1, M/256)]}.
+hipError_t launch_blu_columns(int prec, const void* dT, void* xT, void* Tm, void* Z, void* A, const void* chirp,
+                              const void* Crow, const double* twb64, int64_t b, int log2m, int N, int ntap,
+                              const double* win64, double phi, int normalise, const void* const tw4[4],
+                              hipStream_t st);
+
 // Forward PFB with LDS-resident rows (N <= 2^kMaxLog2Row*).
 hipError_t launch_pfb_fwd_small(int prec, int log2n, const void* x, void* y, int64_t nblock, int ntap,
                                 const void* winT, const void* twN, hipStream_t st);

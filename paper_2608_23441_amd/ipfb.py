@@ -25,6 +25,8 @@ EXPORTS = (
     "ipfb_plan_destroy", "ipfb_plan_workspace_size", "pfb_forward", "pfb_adjoint", "ipfb_wiener",
     "ipfb_wiener_ex", "upchannelize", "ipfb_autospectrum", "ipfb_quantize_c4",
     "ipfb_profile_enable", "ipfb_profile_reset", "ipfb_profile_query", "ipfb_ml_cg",
+    "ipfb_batched_plan_create", "ipfb_batched_plan_destroy", "ipfb_batched_workspace_size",
+    "ipfb_batched_use_graph", "ipfb_wiener_batched",
 )
 
 
@@ -60,6 +62,11 @@ def lib():
         L.ipfb_autospectrum.argtypes = [vp, vp, vp, vp]
         L.ipfb_quantize_c4.argtypes = [vp, vp, dbl, vp, vp, vp]
         L.ipfb_ml_cg.argtypes = [vp, i32, vp, vp, vp, vp, dbl, dbl, dbl, i32, vp, vp, vp, vp]
+        L.ipfb_batched_plan_create.argtypes = [ctypes.POINTER(vp), i32, i32, vp, i32, vp, i32]
+        L.ipfb_batched_plan_destroy.argtypes = [vp]
+        L.ipfb_batched_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.ipfb_batched_use_graph.argtypes = [vp, i32]
+        L.ipfb_wiener_batched.argtypes = [vp, i32, vp, vp, dbl, i32, vp, vp]
         L.ipfb_profile_enable.argtypes = [i32]
         L.ipfb_profile_reset.argtypes = []
         L.ipfb_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
@@ -285,3 +292,77 @@ def profile_query(name: str):
     n = ctypes.c_int64()
     _check(lib().ipfb_profile_query(name.encode(), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value
+
+
+class BatchedPlan:
+    """Plan for many streams with their own nblock (any integer up to 32768)."""
+
+    def __init__(self, lblock: int, ntap: int, window, nblocks, prec: int = F32):
+        self.lblock, self.ntap, self.prec = int(lblock), int(ntap), int(prec)
+        self.nblocks = [int(b) for b in nblocks]
+        w = np.ascontiguousarray(np.asarray(window, dtype=np.float64))
+        nb = np.ascontiguousarray(np.asarray(self.nblocks, dtype=np.int64))
+        h = ctypes.c_void_p()
+        _check(lib().ipfb_batched_plan_create(ctypes.byref(h), self.lblock, self.ntap, w.ctypes.data,
+                                              len(self.nblocks), nb.ctypes.data, self.prec))
+        self._h = h
+
+    @property
+    def nchan(self):
+        return self.lblock // 2 + 1
+
+    @property
+    def real_dtype(self):
+        import torch
+        return torch.float32 if self.prec == F32 else torch.float64
+
+    def use_graph(self, on: bool):
+        _check(lib().ipfb_batched_use_graph(self._h, int(bool(on))))
+
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().ipfb_batched_workspace_size(self._h, ctypes.byref(b)))
+        return b.value
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ipfb_batched_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def wiener_batched(bp: BatchedPlan, specs, chan_scales=None, phi: float = 0.1, x_outs=None,
+                   normalise: bool = True, stream=None):
+    """specs: list of per-stream spectra (uint8 packed with chan_scales, or complex);
+    returns the list of per-stream timestreams."""
+    import torch
+    ns = len(bp.nblocks)
+    if len(specs) != ns:
+        raise ValueError("one spectrum tensor per stream")
+    fmt = None
+    for s_, b in zip(specs, bp.nblocks):
+        f = IN_C4 if s_.dtype == torch.uint8 else IN_CF32 if s_.dtype == torch.complex64 else \
+            IN_CF64 if s_.dtype == torch.complex128 else None
+        if f is None or (fmt is not None and f != fmt):
+            raise ValueError("all streams need one spectrum dtype: uint8, complex64 or complex128")
+        fmt = f
+        if s_.numel() != b * bp.nchan:
+            raise ValueError("stream spectra must hold nblock * (lblock/2+1) values")
+    if fmt == IN_C4 and (chan_scales is None or len(chan_scales) != ns):
+        raise ValueError("packed 4-bit spectra need one float32 scale vector per stream")
+    if x_outs is None:
+        x_outs = [_empty((b * bp.lblock,), bp.real_dtype) for b in bp.nblocks]
+    for x, b in zip(x_outs, bp.nblocks):
+        if x.dtype != bp.real_dtype or x.numel() != b * bp.lblock:
+            raise ValueError("x_outs: one real tensor of nblock*lblock per stream")
+    P = ctypes.c_void_p * ns
+    sp = P(*[_ptr(t, "spec").value for t in specs])
+    xo = P(*[_ptr(t, "x_out").value for t in x_outs])
+    sc = P(*[_ptr(t, "chan_scale").value for t in chan_scales]) if fmt == IN_C4 else None
+    _check(lib().ipfb_wiener_batched(bp._h, fmt, sp, sc, float(phi), int(bool(normalise)), xo, _stream(stream)))
+    return x_outs
