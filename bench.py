@@ -185,6 +185,48 @@ def ml_form(torch, ipfb, inputs):
             "resid_norm_first_last": [float(nrm[0]), float(nrm[-1])]}
 
 
+def batched_form(torch, ipfb, inputs, nstreams):
+    """Batched form: nstreams independent streams, lblock = 4096, ntap = 4,
+    nblock ~ U[1024, 32768] (seed 4), stream s signal seed 4000+s, 4-bit
+    spectra, Wiener phi = 0.1, FP32; one graph launch per step. Inputs are
+    made on the GPU by the library's FP32 forward PFB and quantiser."""
+    N, p, phi = 4096, 4, 0.1
+    nbl = [int(b) for b in inputs.batched_nblocks(256, 1024, 32768, 4)[:nstreams]]
+    w = ipfb.window_sinc_hamming(p, N)
+    specs, scales, outs = [], [], []
+    for s_, b in enumerate(nbl):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(4000 + s_)
+        x = torch.randn(b * N, generator=g, device="cuda", dtype=torch.float32)
+        plan = ipfb.Plan(N, p, w, b, ipfb.F32)
+        y = ipfb.pfb_forward(plan, x)
+        pk, sc = ipfb.quantize_c4(plan, y, 2.5)
+        torch.cuda.synchronize()
+        specs.append(pk)
+        scales.append(sc)
+        outs.append(torch.empty(b * N, dtype=torch.float32, device="cuda"))
+        del x, y
+        plan.close()
+    bp = ipfb.BatchedPlan(N, p, w, nbl, ipfb.F32)
+    ipfb.wiener_batched(bp, specs, scales, phi, x_outs=outs)  # captures the graph
+    torch.cuda.synchronize()
+    steps = 3
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ipfb.wiener_batched(bp, specs, scales, phi, x_outs=outs)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    S = sum(b * N for b in nbl)
+    npow2 = sum(1 for b in nbl if b & (b - 1) == 0)
+    # compulsory traffic of the inverse (packed input, one d round trip, xhat out): 12.5 B/sample
+    alg = sum(b * (N // 2 + 1) + 4 * (N // 2 + 1) for b in nbl) + 12 * S
+    return {"value": S / sec, "unit": "samples/s", "s_per_step": sec, "steps": steps, "streams": len(nbl),
+            "samples": S, "power_of_two_streams": npow2, "graph": True,
+            "hbm_GBps": alg / sec / 1e9, "hbm_roofline_frac": alg / sec / 1e9 / HBM_PEAK_GBPS,
+            "config": {"lblock": N, "ntap": p, "nblock": "U[1024, 32768], seed 4", "phi": phi,
+                       "dtype": "f32"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +236,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the FP64 form")
     ap.add_argument("--cpu-frames", type=int, default=16384)
     ap.add_argument("--no-ml", action="store_true", help="skip timing the ML-CG form")
+    ap.add_argument("--no-batched", action="store_true", help="skip timing the batched form")
+    ap.add_argument("--batched-streams", type=int, default=256)
     ap.add_argument("--probe-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -315,6 +359,8 @@ def main():
         out["fp32_vs_fp64"] = agree
     if not args.no_ml:
         out["ml_form"] = ml_form(torch, ipfb, inputs)
+    if not args.no_batched:
+        out["batched_form"] = batched_form(torch, ipfb, inputs, args.batched_streams)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(N, p, Nf, phi, args.cpu_frames, 2)
     print(json.dumps(out), flush=True)
