@@ -22,10 +22,12 @@
  *    returns a message (per thread).
  *  - Real arrays are float (IPFB_F32 plans) or double (IPFB_F64 plans);
  *    complex arrays are pairs of the same type.
- *  - Lengths: lblock and nblock are powers of two with lblock >= 4,
- *    nblock >= 4. Inverse: lblock <= 32768 (F32) / 16384 (F64) and
- *    nblock <= 32768 (F32) / 16384 (F64). Forward PFB / up-channelization:
- *    lblock up to 2^20.
+ *  - Lengths: lblock is a power of two >= 4. Inverse: lblock <= 32768 (F32)
+ *    / 16384 (F64); nblock any integer in [2, 32768] (powers of two up to
+ *    2^15 (F32) / 2^14 (F64) use the LDS column kernel, other lengths the
+ *    Bluestein column path, set up on the first call). Forward PFB /
+ *    up-channelization: lblock up to 2^20, any nblock >= 1. ML-CG: nblock a
+ *    power of two within the LDS column limits.
  */
 #ifndef IPFB_H
 #define IPFB_H

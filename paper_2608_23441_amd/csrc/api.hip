@@ -96,6 +96,8 @@ struct ipfb_plan_s {
   // maximum-likelihood CG workspace (allocated on first use): 8 vectors in the
   // transposed layout, the column autocorrelations, partial sums, scalars
   void* cg = nullptr;
+  // nblock not a power of two: a one-stream batched plan runs the Bluestein column path
+  ipfb_bplan_s* blu1 = nullptr;
   double* cg_autoc = nullptr;
   double* cg_part = nullptr;
   double* cg_sc = nullptr;
@@ -138,7 +140,10 @@ int upload_table(ipfb_plan p, const std::vector<double>& t, int prec, void** dst
   return upload(*dst, f.data(), n * sizeof(float));
 }
 
+void free_bplan(ipfb_bplan p);
+
 void free_plan(ipfb_plan p) {
+  if (p->blu1) free_bplan(p->blu1);
   void* ptrs[] = {p->win64, p->winT, p->twN, p->twB, p->twB64, p->work, p->work2, p->tmp, p->part, p->fac, p->twS,
                   p->cg, p->cg_autoc, p->cg_part, p->cg_sc};
   for (void* q : ptrs)
@@ -388,9 +393,25 @@ int ipfb_wiener_ex(ipfb_plan p, int infmt, const void* spec, const float* chan_s
   if (!(phi >= 0.0) || !std::isfinite(phi)) return fail(IPFB_EINVAL, "phi must be finite and >= 0");
   if (!p->row_lds)
     return fail(IPFB_EUNSUPPORTED, "ipfb_wiener supports lblock <= 2^%d for this precision", max_log2_row(p->prec));
-  if (!p->col_lds)
-    return fail(IPFB_EUNSUPPORTED, "ipfb_wiener needs nblock a power of two in [4, 2^%d] (got %lld)",
-                max_log2_col(p->prec), (long long)p->nblock);
+  if (!p->col_lds) {
+    if (p->nblock < 2 || p->nblock > 32768)
+      return fail(IPFB_EUNSUPPORTED, "ipfb_wiener supports nblock in [2, 32768] (got %lld)", (long long)p->nblock);
+    DeviceGuard g(p->dev);
+    if (!p->blu1) {  // built on the first call: Bluestein tables for this nblock
+      std::vector<double> w((size_t)p->ntap * p->lblock);
+      if (hipMemcpy(w.data(), p->win64, w.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+        hipGetLastError();
+        return fail(IPFB_EHIP, "reading back the window failed");
+      }
+      int s2 = ipfb_batched_plan_create(&p->blu1, p->lblock, p->ntap, w.data(), 1, &p->nblock, p->prec);
+      if (s2) return s2;
+      ipfb_batched_use_graph(p->blu1, 0);
+    }
+    const void* sp[1] = {spec};
+    const float* scs[1] = {chan_scale};
+    void* xo[1] = {x_out};
+    return ipfb_wiener_batched(p->blu1, infmt, sp, chan_scale ? scs : nullptr, phi, normalise, xo, stream);
+  }
   DeviceGuard g(p->dev);
   hipStream_t st = (hipStream_t)stream;
   hipError_t e;

@@ -205,14 +205,48 @@ def test_bitwise_deterministic():
 
 
 def test_runtime_errors_reported():
-    N, p, b = 64, 4, 24  # nblock not a power of two: inverse unsupported, forward fine
+    N, p = 64, 4
     w = O.window_sinc_hamming(p, N)
-    plan = ipfb.Plan(N, p, w, b, ipfb.F32)
-    y = torch.zeros((b, N // 2 + 1), dtype=torch.complex64, device="cuda")
+    plan = ipfb.Plan(N, p, w, 40000, ipfb.F32)  # inverse limited to nblock <= 32768
+    y = torch.zeros((40000, N // 2 + 1), dtype=torch.complex64, device="cuda")
     with pytest.raises(ipfb.IpfbError) as e:
         ipfb.ipfb_wiener(plan, y, None, 0.1)
     assert e.value.status == ipfb.EUNSUPPORTED
     with pytest.raises(ipfb.IpfbError):
         ipfb.ipfb_wiener(plan, y, None, -1.0)
-    x = torch.zeros(N * b, dtype=torch.float32, device="cuda")
+    x = torch.zeros(N * 40000, dtype=torch.float32, device="cuda")
     ipfb.pfb_forward(plan, x)
+
+
+@pytest.mark.parametrize("prec,tol", [(ipfb.F64, 1e-11), (ipfb.F32, 1e-5)])
+@pytest.mark.parametrize("b", [24, 3, 1031])
+def test_ipfb_wiener_any_nblock(prec, tol, b):
+    # a single-stream plan with nblock not a power of two (Bluestein columns)
+    N, p = 256, 4
+    print(f"case ipfb_wiener nblock={b} prec={prec}", flush=True)
+    w, x, y, packed, s = _quantised_case(N, p, b, 90 + b)
+    ref = O.ipfb_wiener(packed, s, w, N, p, 0.1)
+    plan = ipfb.Plan(N, p, w, b, prec)
+    out = ipfb.ipfb_wiener(plan, _dev(packed), _dev(s), 0.1)
+    assert _rel(_host(out), ref) < tol
+    # exact recovery without quantisation at phi = 0 holds for any nblock
+    yx = O.pfb_forward(x, w, N, p)
+    xr = ipfb.ipfb_wiener(plan, _dev(yx.astype(np.complex64 if prec == ipfb.F32 else np.complex128)), None, 0.0)
+    assert _rel(_host(xr), x) < (1e-10 if prec == ipfb.F64 else 1e-3)
+
+
+def test_fault_injection_reports_errors(monkeypatch):
+    N, p, b = 64, 4, 16
+    w = O.window_sinc_hamming(p, N)
+    plan = ipfb.Plan(N, p, w, b, ipfb.F32)
+    y = torch.zeros((b, N // 2 + 1), dtype=torch.complex64, device="cuda")
+    monkeypatch.setenv("IPFB_FAULT_INJECT", "launch")
+    with pytest.raises(ipfb.IpfbError) as e:
+        ipfb.ipfb_wiener(plan, y, None, 0.1)
+    assert e.value.status == ipfb.EHIP
+    monkeypatch.setenv("IPFB_FAULT_INJECT", "alloc")
+    with pytest.raises(ipfb.IpfbError) as e:
+        ipfb.Plan(N, p, w, b, ipfb.F32)
+    assert e.value.status == ipfb.ENOMEM
+    monkeypatch.delenv("IPFB_FAULT_INJECT")
+    ipfb.ipfb_wiener(plan, y, None, 0.1)
