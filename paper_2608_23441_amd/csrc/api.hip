@@ -102,7 +102,7 @@ struct ipfb_plan_s {
   double* cg_part = nullptr;
   double* cg_sc = nullptr;
   int jchunk = 1, nchunks = 1;
-  int qchunk = 1, nqchunks = 1;  // long frames: frame pairs per power-sum chunk
+  int fchunk = 1, nfchunks = 1;  // long frames: frames per power-sum chunk
   size_t bytes = 0;
 };
 
@@ -298,16 +298,23 @@ int ipfb_plan_create(ipfb_plan* out, int lblock, int ntap, const double* window,
   if (!st && p->row_lds) st = dev_alloc(p, &p->work, frames_bytes);
   if (!st && p->row_lds && p->col_lds) st = dev_alloc(p, &p->work2, frames_bytes);
   if (!st && p->row_lds) st = dev_alloc(p, &p->fac, (size_t)(lblock / 2 + 1) * esize(prec));
-  if (!st && !p->row_lds) st = dev_alloc(p, &p->tmp, (size_t)(nblock + 1) * lblock * esize(prec));
+  if (!st && !p->row_lds) st = dev_alloc(p, &p->tmp, (size_t)nblock * lblock * esize(prec));
   if (!st && !p->row_lds) {
-    const int l1 = (p->log2n + 1) / 2, l2 = p->log2n / 2;
-    const int64_t P1 = int64_t(1) << l1, P2 = int64_t(1) << l2, nhi = lblock / 512;
-    std::vector<double> t1 = twiddles(P1), t2 = twiddles(P2), tl = twiddles(lblock);
+    // long frames: M = lblock/2-point complex FFTs, M = P1 * P2
+    const int log2m = p->log2n - 1;
+    const int64_t M = int64_t(1) << log2m;
+    const int64_t P1 = int64_t(1) << ((log2m + 1) / 2), P2 = int64_t(1) << (log2m / 2);
+    std::vector<double> t1 = twiddles(P1), t2 = twiddles(P2), tm = twiddles(M), tl = twiddles(lblock);
     std::vector<double> all;
     all.insert(all.end(), t1.begin(), t1.end());
     all.insert(all.end(), t2.begin(), t2.end());
-    all.insert(all.end(), tl.begin(), tl.begin() + 2 * 512);
-    for (int64_t m = 0; m < nhi; ++m) {
+    all.insert(all.end(), tm.begin(), tm.begin() + 2 * 512);  // e^{-2 pi i m/M}, m < 512
+    for (int64_t m = 0; m < M / 512; ++m) {                    // e^{-2 pi i 512 m/M}
+      all.push_back(tm[2 * (512 * m)]);
+      all.push_back(tm[2 * (512 * m) + 1]);
+    }
+    all.insert(all.end(), tl.begin(), tl.begin() + 2 * 512);  // e^{-2 pi i k/L}, k < 512
+    for (int64_t m = 0; m <= M / 512; ++m) {                   // e^{-2 pi i 512 m/L}, 512 m <= M
       all.push_back(tl[2 * (512 * m)]);
       all.push_back(tl[2 * (512 * m) + 1]);
     }
@@ -318,10 +325,10 @@ int ipfb_plan_create(ipfb_plan* out, int lblock, int ntap, const double* window,
     p->nchunks = (int)(nblock < 16 ? nblock : 16);
     p->jchunk = (int)((nblock + p->nchunks - 1) / p->nchunks);
     p->nchunks = (int)((nblock + p->jchunk - 1) / p->jchunk);
-    const int64_t nq = (nblock + 1) / 2;  // long frames: chunks of frame pairs
-    p->qchunk = (int)((nq + 31) / 32);  // up to 32 chunks: enough workgroups for the second pass
-    p->nqchunks = (int)((nq + p->qchunk - 1) / p->qchunk);
-    const int nrows = p->nchunks > p->nqchunks ? p->nchunks : p->nqchunks;
+    // long frames: the second FFT pass sums |Y|^2 over chunks of frames
+    p->fchunk = (int)((nblock + 31) / 32);  // up to 32 chunks: enough workgroups for that pass
+    p->nfchunks = (int)((nblock + p->fchunk - 1) / p->fchunk);
+    const int nrows = p->nchunks > p->nfchunks ? p->nchunks : p->nfchunks;
     st = dev_alloc(p, (void**)&p->part, (size_t)nrows * (lblock / 2 + 1) * sizeof(double));
   }
   if (st) {
@@ -359,7 +366,7 @@ int pfb_forward(ipfb_plan p, const void* x, void* y, void* stream) {
     e = launch_pfb_fwd_small(p->prec, p->log2n, x, y, p->nblock, p->ntap, p->winT, p->twN, st);
   } else {
     ProfScope ps("pfb_fwd_long", st);
-    e = launch_pfb_fwd_large(p->prec, p->log2n, x, y, p->nblock, p->ntap, p->winT, p->twS, p->tmp, p->qchunk,
+    e = launch_pfb_fwd_long(p->prec, p->log2n, x, y, p->nblock, p->ntap, p->winT, p->twS, p->tmp, p->fchunk,
                              nullptr, st);
   }
   return launched(e, "pfb_forward");
@@ -419,21 +426,15 @@ int ipfb_wiener_ex(ipfb_plan p, int infmt, const void* spec, const float* chan_s
     ProfScope ps("ipfb_rows", st);
     if (infmt == IPFB_IN_C4) e = launch_dequant_factors(p->prec, chan_scale, p->lblock / 2 + 1, p->lblock, p->fac, st);
     else e = hipSuccess;
-    if (e == hipSuccess)
-      e = launch_row_irfft(p->prec, p->log2n, infmt, spec, p->fac, p->work, p->nblock, p->twN, st);
+    if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec, p->fac, x_out, p->nblock, p->twN, st);
   }
-  if (e == hipSuccess) {  // d [b][N] -> d_T [N][b]
-    ProfScope ps("ipfb_transpose_in", st);
-    e = launch_transpose(p->prec, p->work, p->work2, p->nblock, p->lblock, st);
-  }
-  if (e == hipSuccess) {  // d_T -> x_T, both [N][b]
-    ProfScope ps("ipfb_cols", st);
-    e = launch_col_wiener(p->prec, p->log2b, p->work2, p->work, p->lblock, p->ntap, p->win64, phi, normalise, p->twB,
-                          p->twB64, st);
-  }
-  if (e == hipSuccess) {  // x_T [N][b] -> x [b][N]
-    ProfScope ps("ipfb_transpose_out", st);
-    e = launch_transpose(p->prec, p->work, x_out, p->lblock, p->nblock, st);
+  // column stage in place on x_out: d [b][N] -> x [b][N]
+  static const char* const pass_names[3] = {"ipfb_cols_fwd", "ipfb_cols_gain", "ipfb_cols_inv"};
+  for (int pass = 0; pass < 3 && e == hipSuccess; ++pass) {
+    if (p->log2b <= 9 && pass != 1) continue;  // one pass does the whole stage
+    ProfScope ps(pass_names[pass], st);
+    e = launch_col_wiener_nat(p->prec, p->log2b, pass, x_out, p->lblock, p->ntap, p->win64, phi, normalise, p->twB,
+                              p->twB64, st);
   }
   return launched(e, "ipfb_wiener");
 }
@@ -555,12 +556,12 @@ int upchannelize(ipfb_plan fine, const void* x, void* y_fine, double* autospec, 
     hipError_t e;
     {
       ProfScope ps("pfb_fwd_long", st);
-      e = launch_pfb_fwd_large(fine->prec, fine->log2n, x, y_fine, fine->nblock, fine->ntap, fine->winT, fine->twS,
-                               fine->tmp, fine->qchunk, fine->part, st);
+      e = launch_pfb_fwd_long(fine->prec, fine->log2n, x, y_fine, fine->nblock, fine->ntap, fine->winT, fine->twS,
+                               fine->tmp, fine->fchunk, fine->part, st);
     }
     if (e == hipSuccess) {
       ProfScope ps("autospec_final", st);
-      e = launch_power_final(fine->part, fine->nqchunks, K, 1.0 / (double)fine->nblock, autospec, st);
+      e = launch_power_final(fine->part, fine->nfchunks, K, 1.0 / (double)fine->nblock, autospec, st);
     }
     return launched(e, "upchannelize");
   }

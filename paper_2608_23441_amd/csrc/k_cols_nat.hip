@@ -1,0 +1,339 @@
+// Column stage of the circulant inverse PFB (Section 3.1 with the Wiener
+// weights of Section 4.1) computed in place on the frame matrix in its natural
+// layout d[j][n] (frame j, sub-filter path n), with no transposes.
+//
+// Adjacent paths are paired into one complex sequence per pair p,
+//   z_p[j] = d[j][2p] + i d[j][2p+1],
+// which is the frame matrix itself read as complex numbers. A tile of TP
+// adjacent pairs (128 bytes of every frame) is the unit of work, so every
+// global access is a run of at least 128 bytes.
+//
+// For b <= 512 one pass does everything: the b-point FFT of each z_p, the
+// separation of the two real spectra, the FP64 gains of both paths, and the
+// inverse FFT. Larger b uses the four-step split b = b1 * b2, j = b2 j1 + j2,
+// k = k1 + b1 k2:
+//   pass A: FFT over j1 (stride b2 frames), times e^{-2 pi i j2 k1 / b};
+//   pass B: FFT over j2 for the rows k1 and b1 - k1 together (so each
+//           frequency k meets its mirror b - k), gain, inverse FFT over k2,
+//           times e^{+2 pi i j2 k1 / b};
+//   pass C: inverse FFT over k1, giving x[b2 j1 + j2] in time order.
+// Every pass reads and writes exactly the same rows of its tile, so the three
+// passes run in place on one buffer.
+//
+// The gain of path n at frequency f,
+//   W_n(f) = sum_r h[rN + n] e^{-2 pi i r f / b},
+//   G = W (1 + phi^2) / (|W|^2 + phi^2) / b,
+// is evaluated on the fly in FP64 (Horner in e^{-2 pi i f/b}); the two paths
+// of a pair share one reciprocal. No N x b table ever touches HBM.
+#include "fft_lds.hpp"
+#include "launch.hpp"
+
+namespace ipfb {
+
+struct NatGain {
+  const double* win;  // [ntap][lblock], FP64
+  int lblock, ntap;
+  double phi2;        // phi^2
+  double gnorm;       // (1 + phi^2) / b, or 1/b without the normalisation
+  int naive;          // phi == 0: 1/conj(W), eigenvalues at rounding level dropped
+};
+
+template <typename T>
+struct NatCfg {
+  static constexpr int TP = 128 / (int)sizeof(cx<T>);  // pairs per tile: 128 bytes per frame
+  static constexpr int EPT = sizeof(T) == 4 ? 16 : 8;  // complex elements per thread in the FFTs
+  static constexpr int clampnt(int v) { return v < 64 ? 64 : (v > 1024 ? 1024 : v); }
+};
+
+// W(z) = sum_{r < ntap} h_r z^r by Horner, taps in registers (ntap <= 8).
+__device__ __forceinline__ cx<double> horner8(const double* h, int ntap, cx<double> z) {
+  cx<double> w = mk<double>(0.0, 0.0);
+#pragma unroll
+  for (int r = 7; r >= 0; --r) {
+    if (r < ntap) w = mk<double>(w.x * z.x - w.y * z.y + h[r], w.x * z.y + w.y * z.x);
+  }
+  return w;
+}
+
+// Same, taps read from global memory (any ntap).
+__device__ __forceinline__ cx<double> horner_g(const double* __restrict__ win, int N, int n, int ntap,
+                                               cx<double> z) {
+  cx<double> w = mk<double>(0.0, 0.0);
+  for (int r = ntap - 1; r >= 0; --r) {
+    const double h = win[(int64_t)r * N + n];
+    w = mk<double>(w.x * z.x - w.y * z.y + h, w.x * z.y + w.y * z.x);
+  }
+  return w;
+}
+
+// Gains of the two paths of a pair at one frequency. The truncation of the
+// naive inverse compares |W| with the tap magnitude sum (wsa, wsc).
+__device__ __forceinline__ void pair_gains(const NatGain& ga, cx<double> Wa, cx<double> Wc, double wsa,
+                                           double wsc, cx<double>& Ga, cx<double>& Gc) {
+  const double aa = Wa.x * Wa.x + Wa.y * Wa.y, ac = Wc.x * Wc.x + Wc.y * Wc.y;
+  if (ga.naive) {
+    const double sa = (sqrt(aa) <= 1e-12 * wsa) ? 0.0 : ga.gnorm / aa;
+    const double sc = (sqrt(ac) <= 1e-12 * wsc) ? 0.0 : ga.gnorm / ac;
+    Ga = mk<double>(Wa.x * sa, Wa.y * sa);
+    Gc = mk<double>(Wc.x * sc, Wc.y * sc);
+    return;
+  }
+  const double da = aa + ga.phi2, dc = ac + ga.phi2;
+  const double r = ga.gnorm / (da * dc);
+  const double sa = dc * r, sc = da * r;
+  Ga = mk<double>(Wa.x * sa, Wa.y * sa);
+  Gc = mk<double>(Wc.x * sc, Wc.y * sc);
+}
+
+// Passes A (DIR = -1) and C (DIR = +1): a b1-point FFT down the rows
+// b2 j1 + j2 of one tile, for one j2 per workgroup. All global loads of a
+// thread are issued before the first LDS write; the four-step twiddles of
+// pass A are gathered into LDS at the start.
+template <typename T, int LOG2B1, int LOG2B2, int DIR>
+__global__ __launch_bounds__((NatCfg<T>::clampnt(NatCfg<T>::TP * (1 << LOG2B1) / NatCfg<T>::EPT)), 4) void k_nat_outer(
+    cx<T>* __restrict__ z, int np, int t0, int ntile, const cx<T>* __restrict__ tw) {
+  constexpr int TP = NatCfg<T>::TP;
+  constexpr int B1 = 1 << LOG2B1, B2 = 1 << LOG2B2, B = B1 * B2;
+  constexpr int NT = NatCfg<T>::clampnt(TP * B1 / NatCfg<T>::EPT);
+  constexpr int LS = lds_len(B1);
+  constexpr int NE = TP * B1, IT = (NE + NT - 1) / NT;
+  __shared__ cx<T> s[TP * LS];
+  __shared__ cx<T> tws[DIR < 0 ? B1 : 1];
+  const int tid = threadIdx.x;
+  const int tile = blockIdx.x % ntile, j2 = blockIdx.x / ntile;
+  const int p0 = (t0 + tile) * TP;
+  if (DIR < 0)
+    for (int k1 = tid; k1 < B1; k1 += NT) tws[k1] = tw[j2 * k1];  // e^{-2 pi i j2 k1 / b}
+  cx<T> v[IT];
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = tid + i * NT, q = e % TP, j1 = e / TP;
+    v[i] = mk<T>(T(0), T(0));
+    if ((NE % NT == 0 || e < NE) && p0 + q < np) v[i] = z[(int64_t)(j1 * B2 + j2) * np + p0 + q];
+  }
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = tid + i * NT, q = e % TP, j1 = e / TP;
+    if (NE % NT == 0 || e < NE) s[q * LS + pidx(j1)] = v[i];
+  }
+  __syncthreads();
+  lds_fft<T, B1, NT, TP, DIR>(s, LS, tw, B / B1);
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = tid + i * NT, q = e % TP, k1 = e / TP;
+    if (NE % NT != 0 && e >= NE) continue;
+    cx<T> u = s[q * LS + pidx(k1)];
+    if (DIR < 0) u = cmul(u, tws[k1]);
+    if (p0 + q < np) z[(int64_t)(k1 * B2 + j2) * np + p0 + q] = u;
+  }
+}
+
+// Work item `it` of the gain pass (one frequency k and its mirror b - k):
+// row set and index of k (sk, k2) and of the mirror (sm, k2m). For kk > 0 the
+// items are k2 in [0, b2) of row ka, mirrored in row kb at b2-1-k2; for
+// kk = 0, k2 in [0, b2/2] of row 0 (mirror (b2-k2) mod b2) and then k2 in
+// [0, b2/2) of row b1/2 (mirror b2-1-k2).
+template <int NS, int B2>
+__device__ __forceinline__ void gain_item(int kk, int it, int& sk, int& k2, int& sm, int& k2m) {
+  if (NS == 2 && kk != 0) {
+    sk = 0; k2 = it; sm = 1; k2m = B2 - 1 - it;
+  } else if (it <= B2 / 2) {
+    sk = 0; k2 = it; sm = 0; k2m = (B2 - it) & (B2 - 1);
+  } else {
+    sk = 1; k2 = it - (B2 / 2 + 1); sm = 1; k2m = B2 - 1 - k2;
+  }
+}
+
+// Pass B (or the whole stage when b1 = 1): b2-point FFTs of the rows k1 and
+// b1 - k1 of one tile, separation of the two real spectra of each pair, FP64
+// gains, re-packing, inverse FFTs, and the inverse four-step twiddle.
+template <typename T, int LOG2B1, int LOG2B2>
+__global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * NatCfg<T>::TP * (1 << LOG2B2) /
+                                                 NatCfg<T>::EPT)),
+                             4) void k_nat_mid(cx<T>* __restrict__ z, int np, int t0, int ntile, NatGain ga,
+                                               const cx<T>* __restrict__ tw,
+                                               const cx<double>* __restrict__ tw64) {
+  constexpr int TP = NatCfg<T>::TP;
+  constexpr int B1 = 1 << LOG2B1, B2 = 1 << LOG2B2, B = B1 * B2;
+  constexpr int NS = B1 > 1 ? 2 : 1;  // row sets held by one workgroup
+  constexpr int NT = NatCfg<T>::clampnt(NS * TP * B2 / NatCfg<T>::EPT);
+  constexpr int LS = lds_len(B2);
+  constexpr int NE = NS * TP * B2, IT = (NE + NT - 1) / NT;
+  static_assert(NT % TP == 0, "a thread keeps one pair through the gain pass");
+  __shared__ cx<T> s[NS * TP * LS];
+  __shared__ cx<T> tws[B1 > 1 ? NS * B2 : 1];
+  const int tid = threadIdx.x;
+  const int tile = blockIdx.x % ntile, kk = blockIdx.x / ntile;
+  const int p0 = (t0 + tile) * TP;
+  // row sets: (k1, b1 - k1), or (0, b1/2) for kk = 0 (both their own mirrors)
+  const int ka = kk, kb = (kk == 0) ? B1 / 2 : B1 - kk;
+
+  if (B1 > 1)
+    for (int t = tid; t < NS * B2; t += NT) tws[t] = tw[(t % B2) * ((t / B2) ? kb : ka)];  // e^{-2 pi i j2 k1/b}
+  {
+    cx<T> v[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int e = tid + i * NT, q = e % TP, r = e / TP;
+      const int j2 = r % B2, k1 = (r / B2) ? kb : ka;
+      v[i] = mk<T>(T(0), T(0));
+      if ((NE % NT == 0 || e < NE) && p0 + q < np) v[i] = z[(int64_t)(k1 * B2 + j2) * np + p0 + q];
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+      const int e = tid + i * NT, q = e % TP, r = e / TP;
+      if (NE % NT == 0 || e < NE) s[(r / B2 * TP + q) * LS + pidx(r % B2)] = v[i];
+    }
+  }
+  __syncthreads();
+  lds_fft<T, B2, NT, NS * TP, -1>(s, LS, tw, B / B2);
+
+  {
+    constexpr int IPAR = NT / TP;  // items in flight across the workgroup
+    constexpr int NIMAX = (NS == 1) ? (B2 / 2 + 1) : (B2 + 1);
+    constexpr int IMAX = (NIMAX + IPAR - 1) / IPAR;
+    const int NI = (NS == 1) ? (B2 / 2 + 1) : (kk == 0 ? B2 + 1 : B2);
+    const int q = tid % TP;
+    const bool valid = p0 + q < np;
+    const int N = ga.lblock, na = 2 * (p0 + q), nc = na + 1;
+    // e^{-2 pi i f / b} for item it is base * u(it), u(it) = e^{-2 pi i it / b2}:
+    // base = e^{-2 pi i ka / b} for kk > 0; for kk = 0, 1 on row 0 and
+    // -e^{+i pi / b2} on row b1/2. u steps by e^{-2 pi i IPAR / b2} per item
+    // of this thread (a few FP64 roundings over at most IMAX steps).
+    cx<double> u = tw64[(B1 * (tid / TP)) & (B - 1)];
+    const cx<double> rho = tw64[(B1 * IPAR) & (B - 1)];
+    const cx<double> base_a = tw64[ka];
+    const cx<double> h1 = tw64[B1 / 2];
+    const cx<double> base_b = mk<double>(-h1.x, h1.y);
+    double ha[8], hc[8];
+    double wsa = 0.0, wsc = 0.0;
+    const bool regs = ga.ntap <= 8;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      ha[r] = (valid && r < ga.ntap) ? ga.win[(int64_t)r * N + na] : 0.0;
+      hc[r] = (valid && r < ga.ntap) ? ga.win[(int64_t)r * N + nc] : 0.0;
+    }
+    if (ga.naive && valid) {
+      for (int r = 0; r < ga.ntap; ++r) {
+        wsa += fabs(ga.win[(int64_t)r * N + na]);
+        wsc += fabs(ga.win[(int64_t)r * N + nc]);
+      }
+    }
+#pragma unroll 1
+    for (int i = 0; i < IMAX; ++i) {
+      const int it = tid / TP + i * IPAR;
+      if (it >= NI || !valid) break;
+      int sk, k2, sm, k2m;
+      gain_item<NS, B2>(kk, it, sk, k2, sm, k2m);
+      const cx<double> zf = cmul((NS == 2 && kk == 0 && sk == 1) ? base_b : base_a, u);
+      u = cmul(u, rho);
+      const bool self = (sk == sm) && (k2 == k2m);
+      cx<T>* pk = s + (sk * TP + q) * LS + pidx(k2);
+      cx<T>* pm = s + (sm * TP + q) * LS + pidx(k2m);
+      cx<double> Wa, Wc;
+      if (regs) {
+        Wa = horner8(ha, ga.ntap, zf);
+        Wc = horner8(hc, ga.ntap, zf);
+      } else {
+        Wa = horner_g(ga.win, N, na, ga.ntap, zf);
+        Wc = horner_g(ga.win, N, nc, ga.ntap, zf);
+      }
+      cx<double> Ga, Gc;
+      pair_gains(ga, Wa, Wc, wsa, wsc, Ga, Gc);
+      const cx<T> zk = *pk, zm = *pm;
+      if (self) {  // f = 0 or b/2: both spectra real there, gains real
+        *pk = mk<T>(T(Ga.x * (double)zk.x), T(Gc.x * (double)zk.y));
+      } else {
+        // A = (Z_k + conj Z_m)/2, C = (Z_k - conj Z_m)/(2i): the two real spectra
+        const double sx = (double)zk.x + (double)zm.x, sy = (double)zk.y - (double)zm.y;
+        const double dx = (double)zk.x - (double)zm.x, dy = (double)zk.y + (double)zm.y;
+        const cx<double> A = mk<double>(0.5 * sx, 0.5 * sy);
+        const cx<double> C = mk<double>(0.5 * dy, -0.5 * dx);
+        const cx<double> Ap = cmul(Ga, A), Cp = cmul(Gc, C);
+        // Z'_k = A' + i C',  Z'_{b-k} = conj(A') + i conj(C')
+        *pk = mk<T>(T(Ap.x - Cp.y), T(Ap.y + Cp.x));
+        *pm = mk<T>(T(Ap.x + Cp.y), T(Cp.x - Ap.y));
+      }
+    }
+  }
+  __syncthreads();
+  lds_fft<T, B2, NT, NS * TP, +1>(s, LS, tw, B / B2);
+
+#pragma unroll
+  for (int i = 0; i < IT; ++i) {
+    const int e = tid + i * NT, q = e % TP, r = e / TP;
+    if (NE % NT != 0 && e >= NE) continue;
+    const int j2 = r % B2, set = r / B2;
+    const int k1 = set ? kb : ka;
+    cx<T> v = s[(set * TP + q) * LS + pidx(j2)];
+    if (B1 > 1) v = cmulc(v, tws[r]);  // e^{+2 pi i j2 k1 / b}
+    if (p0 + q < np) z[(int64_t)(k1 * B2 + j2) * np + p0 + q] = v;
+  }
+}
+
+template <typename T, int LOG2B>
+static hipError_t launch_nat_t(int pass, void* zv, int lblock, int tile0, int ntiles, const NatGain& ga,
+                               const void* twv, const double* tw64v, hipStream_t st) {
+  using Cfg = NatCfg<T>;
+  cx<T>* z = (cx<T>*)zv;
+  const cx<T>* tw = (const cx<T>*)twv;
+  const cx<double>* tw64 = (const cx<double>*)tw64v;
+  const int np = lblock / 2;
+  const int nall = (np + Cfg::TP - 1) / Cfg::TP;
+  if (ntiles < 0 || tile0 + ntiles > nall) ntiles = nall - tile0;
+  if (tile0 < 0 || ntiles <= 0) return tile0 < 0 ? hipErrorInvalidValue : hipSuccess;
+  if constexpr (LOG2B <= 9) {
+    if (pass != 1) return hipSuccess;
+    constexpr int NT = Cfg::clampnt(Cfg::TP * (1 << LOG2B) / Cfg::EPT);
+    k_nat_mid<T, 0, LOG2B><<<dim3(ntiles), dim3(NT), 0, st>>>(z, np, tile0, ntiles, ga, tw, tw64);
+  } else {
+    constexpr int L1 = LOG2B / 2, L2 = LOG2B - L1;
+    constexpr int NTO = Cfg::clampnt(Cfg::TP * (1 << L1) / Cfg::EPT);
+    constexpr int NTM = Cfg::clampnt(2 * Cfg::TP * (1 << L2) / Cfg::EPT);
+    if (pass == 0)
+      k_nat_outer<T, L1, L2, -1><<<dim3(ntiles * (1 << L2)), dim3(NTO), 0, st>>>(z, np, tile0, ntiles, tw);
+    if (pass == 1)
+      k_nat_mid<T, L1, L2><<<dim3(ntiles * (1 << (L1 - 1))), dim3(NTM), 0, st>>>(z, np, tile0, ntiles, ga, tw,
+                                                                                   tw64);
+    if (pass == 2)
+      k_nat_outer<T, L1, L2, +1><<<dim3(ntiles * (1 << L2)), dim3(NTO), 0, st>>>(z, np, tile0, ntiles, tw);
+  }
+  return hipGetLastError();
+}
+
+#define NAT_CASE(T, L) \
+  case L: return launch_nat_t<T, L>(pass, z, lblock, tile0, ntiles, ga, twB, twB64, st);
+
+int nat_tiles(int prec, int lblock) {
+  const int tp = prec == F32 ? NatCfg<float>::TP : NatCfg<double>::TP;
+  return (lblock / 2 + tp - 1) / tp;
+}
+
+hipError_t launch_col_wiener_nat(int prec, int log2b, int pass, void* z, int lblock, int ntap, const double* win64,
+                                 double phi, int normalise, const void* twB, const double* twB64, hipStream_t st,
+                                 int tile0, int ntiles) {
+  if (lblock < 2 || (lblock & 1) || pass < 0 || pass > 2) return hipErrorInvalidValue;
+  NatGain ga;
+  ga.win = win64;
+  ga.lblock = lblock;
+  ga.ntap = ntap;
+  ga.phi2 = phi * phi;
+  ga.naive = phi == 0.0;
+  ga.gnorm = (normalise ? (1.0 + phi * phi) : 1.0) / (double)(1LL << log2b);
+  if (prec == F32) {
+    switch (log2b) {
+      NAT_CASE(float, 2) NAT_CASE(float, 3) NAT_CASE(float, 4) NAT_CASE(float, 5) NAT_CASE(float, 6)
+      NAT_CASE(float, 7) NAT_CASE(float, 8) NAT_CASE(float, 9) NAT_CASE(float, 10) NAT_CASE(float, 11)
+      NAT_CASE(float, 12) NAT_CASE(float, 13) NAT_CASE(float, 14) NAT_CASE(float, 15)
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (log2b) {
+    NAT_CASE(double, 2) NAT_CASE(double, 3) NAT_CASE(double, 4) NAT_CASE(double, 5) NAT_CASE(double, 6)
+    NAT_CASE(double, 7) NAT_CASE(double, 8) NAT_CASE(double, 9) NAT_CASE(double, 10) NAT_CASE(double, 11)
+    NAT_CASE(double, 12) NAT_CASE(double, 13) NAT_CASE(double, 14)
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace ipfb

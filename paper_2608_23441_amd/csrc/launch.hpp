@@ -33,6 +33,18 @@ hipError_t launch_col_wiener(int prec, int log2b, const void* d, void* xo, int l
                              const double* win64, double phi, int normalise, const void* twB,
                              const double* twB64, hipStream_t st, int precond = 0);
 
+// The same column stage on the natural layout z = d[b][N] (read as N/2
+// complex pairs per frame), in place: on return z holds x[b][N] in time
+// order. pass 0, 1, 2 launch the four-step passes A, B, C in that order;
+// for b <= 512 pass 1 does the whole stage and passes 0 and 2 launch nothing.
+// The work splits into nat_tiles() column tiles (128 bytes of every frame);
+// one call covers tiles [tile0, tile0 + ntiles) (ntiles < 0: to the end), and
+// the three passes of a tile range may run before those of the next range.
+int nat_tiles(int prec, int lblock);
+hipError_t launch_col_wiener_nat(int prec, int log2b, int pass, void* z, int lblock, int ntap, const double* win64,
+                                 double phi, int normalise, const void* twB, const double* twB64, hipStream_t st,
+                                 int tile0 = 0, int ntiles = -1);
+
 // Maximum-likelihood CG pieces (vectors in the transposed layout [N][b]).
 hipError_t launch_cg_autocorr(const double* win64, int N, int ntap, double* autoc, hipStream_t st);
 hipError_t launch_cg_normal(int prec, const void* p, void* q, const double* autoc, const void* mask, double lam,
@@ -65,15 +77,16 @@ hipError_t launch_blu_columns(int prec, const void* dT, void* xT, void* Tm, void
 hipError_t launch_pfb_fwd_small(int prec, int log2n, const void* x, void* y, int64_t nblock, int ntap,
                                 const void* winT, const void* twN, hipStream_t st);
 
-// Forward PFB for long frames (2^15 <= N <= 2^20): two frames per complex
-// N-point FFT, N = P1 * P2 (P1 = 2^ceil(log2 N / 2)), in two passes through
-// tmp ((nblock+1)/2 * N complex). part: NULL, or [ceil(nq / qchunk)][N/2+1] doubles receiving
-// per-chunk sums of |Y_jk|^2 (nq = (nblock+1)/2 frame pairs).
-// twS: small tables [P1 | P2 | 512 | L/512] of e^{-2 pi i m/P1}, e^{-2 pi i m/P2},
-// e^{-2 pi i m/L} (m < 512) and e^{-2 pi i 512 m/L}.
-hipError_t launch_pfb_fwd_large(int prec, int log2n, const void* x, void* y, int64_t nblock, int ntap,
-                                const void* winT, const void* twS, void* tmp, int qchunk, double* part,
-                                hipStream_t st);
+// Forward PFB for long frames (2^15 <= N <= 2^20): one frame per complex
+// M = N/2-point FFT (even and odd samples packed), M = P1 * P2 with
+// P1 = 2^ceil(log2 M / 2), in two passes through tmp (nblock * M complex).
+// part: NULL, or [ceil(nblock / fchunk)][N/2+1] doubles receiving per-chunk
+// sums of |Y_jk|^2. twS: tables [P1 | P2 | 512 | M/512 | 512 | M/512 + 1] of
+// e^{-2 pi i m/P1}, e^{-2 pi i m/P2}, e^{-2 pi i m/M} (m < 512),
+// e^{-2 pi i 512 m/M}, e^{-2 pi i k/N} (k < 512), e^{-2 pi i 512 m/N}.
+hipError_t launch_pfb_fwd_long(int prec, int log2n, const void* x, void* y, int64_t nblock, int ntap,
+                               const void* winT, const void* twS, void* tmp, int fchunk, double* part,
+                               hipStream_t st);
 
 // out[c][r] = in[r][c] for an in[rows][cols] matrix (64 x 64 LDS tiles)
 hipError_t launch_transpose(int prec, const void* in, void* out, int64_t rows, int64_t cols, hipStream_t st);

@@ -66,7 +66,9 @@ def test_ml_cg_zero_iterations_is_wiener():
     plan = ipfb.Plan(N, p, w, b, ipfb.F64)
     xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(mask.astype(np.uint8)), _dev(x), 1.0, 0.1, 0.1, 0)
     xw = ipfb.ipfb_wiener(plan, _dev(packed), _dev(s), 0.1)
-    assert np.array_equal(_host(xg), _host(xw))
+    # the same Wiener estimate through two column-stage layouts: equal up to
+    # FP64 rounding order
+    assert _rel(_host(xg), _host(xw)) < 1e-13
 
 
 def test_ml_cg_toy_model_one_saved_sample():
