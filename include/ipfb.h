@@ -103,7 +103,9 @@ int pfb_adjoint(ipfb_plan plan, const void* y, void* x, void* stream);
  * spec: [nblock][lblock/2+1] in format infmt. chan_scale: device float
  * [lblock/2+1] for IPFB_IN_C4, ignored (may be NULL) otherwise.
  * x_out: [nblock*lblock] real, time order. The imaginary parts of the DC and
- * Nyquist channels are ignored. */
+ * Nyquist channels are ignored. The row stage writes the frame matrix into
+ * x_out and the column stage transforms it there in place, so x_out must not
+ * overlap spec or chan_scale. */
 int ipfb_wiener(ipfb_plan plan, int infmt, const void* spec, const float* chan_scale, double phi,
                 void* x_out, void* stream);
 
@@ -180,8 +182,10 @@ int ipfb_wiener_batched(ipfb_bplan plan, int infmt, const void* const* spec, con
 
 /* Instrumentation: per-kernel timing with HIP events recorded on the
  * launching stream around every kernel group the library enqueues (names:
- * "ipfb_rows", "ipfb_transpose_in", "ipfb_cols", "ipfb_transpose_out",
- * "pfb_fwd", "pfb_fwd_long", "adj_rows", "adj_gather", "autospec_partial",
+ * "ipfb_rows", "ipfb_cols_fwd", "ipfb_cols_gain", "ipfb_cols_inv" (the three
+ * column passes of ipfb_wiener; one pass, "ipfb_cols_gain", for nblock <= 512),
+ * "pfb_fwd", "pfb_fwd_long_p1", "pfb_fwd_long_p2" (the two FFT passes of a
+ * long-frame forward PFB), "adj_rows", "adj_gather", "autospec_partial",
  * "autospec_final", "cg_setup", "cg_iter", "cg_out").
  * ipfb_profile_enable(1) starts recording (process-wide); ipfb_profile_query
  * waits for the recorded events and returns the summed milliseconds and

@@ -23,8 +23,8 @@
 // The gain of path n at frequency f,
 //   W_n(f) = sum_r h[rN + n] e^{-2 pi i r f / b},
 //   G = W (1 + phi^2) / (|W|^2 + phi^2) / b,
-// is evaluated on the fly in FP64 (Horner in e^{-2 pi i f/b}); the two paths
-// of a pair share one reciprocal. No N x b table ever touches HBM.
+// is evaluated on the fly in FP64 (as a polynomial in e^{-2 pi i f/b}); the
+// two paths of a pair share one reciprocal. No N x b table ever touches HBM.
 #include "fft_lds.hpp"
 #include "launch.hpp"
 
@@ -45,17 +45,7 @@ struct NatCfg {
   static constexpr int clampnt(int v) { return v < 64 ? 64 : (v > 1024 ? 1024 : v); }
 };
 
-// W(z) = sum_{r < ntap} h_r z^r by Horner, taps in registers (ntap <= 8).
-__device__ __forceinline__ cx<double> horner8(const double* h, int ntap, cx<double> z) {
-  cx<double> w = mk<double>(0.0, 0.0);
-#pragma unroll
-  for (int r = 7; r >= 0; --r) {
-    if (r < ntap) w = mk<double>(w.x * z.x - w.y * z.y + h[r], w.x * z.y + w.y * z.x);
-  }
-  return w;
-}
-
-// Same, taps read from global memory (any ntap).
+// W(z) = sum_{r < ntap} h_r z^r by Horner, taps read from global memory (any ntap).
 __device__ __forceinline__ cx<double> horner_g(const double* __restrict__ win, int N, int n, int ntap,
                                                cx<double> z) {
   cx<double> w = mk<double>(0.0, 0.0);
@@ -79,7 +69,11 @@ __device__ __forceinline__ void pair_gains(const NatGain& ga, cx<double> Wa, cx<
     return;
   }
   const double da = aa + ga.phi2, dc = ac + ga.phi2;
-  const double r = ga.gnorm / (da * dc);
+  // 1/(da dc): hardware reciprocal refined by one Newton step (error ~1 ulp)
+  const double den = da * dc;
+  double rc = __builtin_amdgcn_rcp(den);
+  rc = rc * fma(-den, rc, 2.0);
+  const double r = ga.gnorm * rc;
   const double sa = dc * r, sc = da * r;
   Ga = mk<double>(Wa.x * sa, Wa.y * sa);
   Gc = mk<double>(Wc.x * sc, Wc.y * sc);
@@ -99,11 +93,14 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(NatCfg<T>::TP * (1 << LOG2B1) /
   constexpr int NE = TP * B1, IT = (NE + NT - 1) / NT;
   __shared__ cx<T> s[TP * LS];
   __shared__ cx<T> tws[DIR < 0 ? B1 : 1];
+  __shared__ cx<T> twf[B1];  // e^{-2 pi i m / b1}: the FFT's table, LDS-resident
   const int tid = threadIdx.x;
   const int tile = blockIdx.x % ntile, j2 = blockIdx.x / ntile;
   const int p0 = (t0 + tile) * TP;
-  if (DIR < 0)
-    for (int k1 = tid; k1 < B1; k1 += NT) tws[k1] = tw[j2 * k1];  // e^{-2 pi i j2 k1 / b}
+  for (int m = tid; m < B1; m += NT) {
+    twf[m] = tw[m * B2];
+    if (DIR < 0) tws[m] = tw[j2 * m];  // e^{-2 pi i j2 k1 / b}
+  }
   cx<T> v[IT];
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
@@ -117,7 +114,7 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(NatCfg<T>::TP * (1 << LOG2B1) /
     if (NE % NT == 0 || e < NE) s[q * LS + pidx(j1)] = v[i];
   }
   __syncthreads();
-  lds_fft<T, B1, NT, TP, DIR>(s, LS, tw, B / B1);
+  lds_fft<T, B1, NT, TP, DIR>(s, LS, twf, 1);
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
     const int e = tid + i * NT, q = e % TP, k1 = e / TP;
@@ -147,7 +144,7 @@ __device__ __forceinline__ void gain_item(int kk, int it, int& sk, int& k2, int&
 // Pass B (or the whole stage when b1 = 1): b2-point FFTs of the rows k1 and
 // b1 - k1 of one tile, separation of the two real spectra of each pair, FP64
 // gains, re-packing, inverse FFTs, and the inverse four-step twiddle.
-template <typename T, int LOG2B1, int LOG2B2>
+template <typename T, int LOG2B1, int LOG2B2, int NTAP>
 __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * NatCfg<T>::TP * (1 << LOG2B2) /
                                                  NatCfg<T>::EPT)),
                              4) void k_nat_mid(cx<T>* __restrict__ z, int np, int t0, int ntile, NatGain ga,
@@ -162,6 +159,8 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * N
   static_assert(NT % TP == 0, "a thread keeps one pair through the gain pass");
   __shared__ cx<T> s[NS * TP * LS];
   __shared__ cx<T> tws[B1 > 1 ? NS * B2 : 1];
+  __shared__ cx<T> twf[B2];  // e^{-2 pi i m / b2}: the FFTs' table, LDS-resident
+  __shared__ cx<double> twz[B2];  // the same in FP64, for the gains
   const int tid = threadIdx.x;
   const int tile = blockIdx.x % ntile, kk = blockIdx.x / ntile;
   const int p0 = (t0 + tile) * TP;
@@ -170,6 +169,10 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * N
 
   if (B1 > 1)
     for (int t = tid; t < NS * B2; t += NT) tws[t] = tw[(t % B2) * ((t / B2) ? kb : ka)];  // e^{-2 pi i j2 k1/b}
+  for (int m = tid; m < B2; m += NT) {
+    twf[m] = tw[m * B1];
+    twz[m] = tw64[m * B1];
+  }
   {
     cx<T> v[IT];
 #pragma unroll
@@ -186,7 +189,7 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * N
     }
   }
   __syncthreads();
-  lds_fft<T, B2, NT, NS * TP, -1>(s, LS, tw, B / B2);
+  lds_fft<T, B2, NT, NS * TP, -1>(s, LS, twf, 1);
 
   {
     constexpr int IPAR = NT / TP;  // items in flight across the workgroup
@@ -196,60 +199,73 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * N
     const int q = tid % TP;
     const bool valid = p0 + q < np;
     const int N = ga.lblock, na = 2 * (p0 + q), nc = na + 1;
-    // e^{-2 pi i f / b} for item it is base * u(it), u(it) = e^{-2 pi i it / b2}:
+    // e^{-2 pi i f / b} for f = k1 + b1 k2 is base * e^{-2 pi i k2 / b2}, with
     // base = e^{-2 pi i ka / b} for kk > 0; for kk = 0, 1 on row 0 and
-    // -e^{+i pi / b2} on row b1/2. u steps by e^{-2 pi i IPAR / b2} per item
-    // of this thread (a few FP64 roundings over at most IMAX steps).
-    cx<double> u = tw64[(B1 * (tid / TP)) & (B - 1)];
-    const cx<double> rho = tw64[(B1 * IPAR) & (B - 1)];
+    // -e^{+i pi / b2} on row b1/2 (the items of row b1/2 count k2 from b2/2+1).
     const cx<double> base_a = tw64[ka];
     const cx<double> h1 = tw64[B1 / 2];
     const cx<double> base_b = mk<double>(-h1.x, h1.y);
-    double ha[8], hc[8];
-    double wsa = 0.0, wsc = 0.0;
-    const bool regs = ga.ntap <= 8;
+    constexpr int HT = NTAP > 0 ? NTAP : 1;
+    double ha[HT], hc[HT];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      ha[r] = (valid && r < ga.ntap) ? ga.win[(int64_t)r * N + na] : 0.0;
-      hc[r] = (valid && r < ga.ntap) ? ga.win[(int64_t)r * N + nc] : 0.0;
+    for (int r = 0; r < HT; ++r) {
+      ha[r] = (NTAP > 0 && valid) ? ga.win[(int64_t)r * N + na] : 0.0;
+      hc[r] = (NTAP > 0 && valid) ? ga.win[(int64_t)r * N + nc] : 0.0;
     }
+    double wsa = 0.0, wsc = 0.0;
     if (ga.naive && valid) {
       for (int r = 0; r < ga.ntap; ++r) {
         wsa += fabs(ga.win[(int64_t)r * N + na]);
         wsc += fabs(ga.win[(int64_t)r * N + nc]);
       }
     }
+    // two items per step: their gain chains are independent, so they overlap
 #pragma unroll 1
-    for (int i = 0; i < IMAX; ++i) {
-      const int it = tid / TP + i * IPAR;
-      if (it >= NI || !valid) break;
-      int sk, k2, sm, k2m;
-      gain_item<NS, B2>(kk, it, sk, k2, sm, k2m);
-      const cx<double> zf = cmul((NS == 2 && kk == 0 && sk == 1) ? base_b : base_a, u);
-      u = cmul(u, rho);
-      const bool self = (sk == sm) && (k2 == k2m);
-      cx<T>* pk = s + (sk * TP + q) * LS + pidx(k2);
-      cx<T>* pm = s + (sm * TP + q) * LS + pidx(k2m);
-      cx<double> Wa, Wc;
-      if (regs) {
-        Wa = horner8(ha, ga.ntap, zf);
-        Wc = horner8(hc, ga.ntap, zf);
-      } else {
-        Wa = horner_g(ga.win, N, na, ga.ntap, zf);
-        Wc = horner_g(ga.win, N, nc, ga.ntap, zf);
+    for (int i = 0; i < IMAX; i += 2) {
+      int sk[2], k2[2], sm[2], k2m[2];
+      bool ok[2];
+      cx<T> zk[2], zm[2];
+      cx<double> Ga[2], Gc[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int it = tid / TP + (i + u) * IPAR;
+        ok[u] = valid && (i + u < IMAX) && it < NI;
+        gain_item<NS, B2>(kk, ok[u] ? it : 0, sk[u], k2[u], sm[u], k2m[u]);
+        zk[u] = s[(sk[u] * TP + q) * LS + pidx(k2[u])];
+        zm[u] = s[(sm[u] * TP + q) * LS + pidx(k2m[u])];
       }
-      cx<double> Ga, Gc;
-      pair_gains(ga, Wa, Wc, wsa, wsc, Ga, Gc);
-      const cx<T> zk = *pk, zm = *pm;
-      if (self) {  // f = 0 or b/2: both spectra real there, gains real
-        *pk = mk<T>(T(Ga.x * (double)zk.x), T(Gc.x * (double)zk.y));
-      } else {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int kz = (NS == 2 && kk == 0 && sk[u] == 1) ? k2[u] + B2 / 2 + 1 : k2[u];
+        const cx<double> zf = cmul((NS == 2 && kk == 0 && sk[u] == 1) ? base_b : base_a, twz[kz & (B2 - 1)]);
+        cx<double> Wa, Wc;
+        if constexpr (NTAP == 4) {
+          const cx<double> z2 = cmul(zf, zf), z3 = cmul(z2, zf);
+          Wa = mk<double>(ha[0] + ha[1] * zf.x + ha[2] * z2.x + ha[3] * z3.x,
+                          ha[1] * zf.y + ha[2] * z2.y + ha[3] * z3.y);
+          Wc = mk<double>(hc[0] + hc[1] * zf.x + hc[2] * z2.x + hc[3] * z3.x,
+                          hc[1] * zf.y + hc[2] * z2.y + hc[3] * z3.y);
+        } else {
+          Wa = horner_g(ga.win, N, na, ga.ntap, zf);
+          Wc = horner_g(ga.win, N, nc, ga.ntap, zf);
+        }
+        pair_gains(ga, Wa, Wc, wsa, wsc, Ga[u], Gc[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        if (!ok[u]) continue;
+        cx<T>* pk = s + (sk[u] * TP + q) * LS + pidx(k2[u]);
+        cx<T>* pm = s + (sm[u] * TP + q) * LS + pidx(k2m[u]);
+        if (sk[u] == sm[u] && k2[u] == k2m[u]) {  // f = 0 or b/2: both spectra real there, gains real
+          *pk = mk<T>(T(Ga[u].x * (double)zk[u].x), T(Gc[u].x * (double)zk[u].y));
+          continue;
+        }
         // A = (Z_k + conj Z_m)/2, C = (Z_k - conj Z_m)/(2i): the two real spectra
-        const double sx = (double)zk.x + (double)zm.x, sy = (double)zk.y - (double)zm.y;
-        const double dx = (double)zk.x - (double)zm.x, dy = (double)zk.y + (double)zm.y;
+        const double sx = (double)zk[u].x + (double)zm[u].x, sy = (double)zk[u].y - (double)zm[u].y;
+        const double dx = (double)zk[u].x - (double)zm[u].x, dy = (double)zk[u].y + (double)zm[u].y;
         const cx<double> A = mk<double>(0.5 * sx, 0.5 * sy);
         const cx<double> C = mk<double>(0.5 * dy, -0.5 * dx);
-        const cx<double> Ap = cmul(Ga, A), Cp = cmul(Gc, C);
+        const cx<double> Ap = cmul(Ga[u], A), Cp = cmul(Gc[u], C);
         // Z'_k = A' + i C',  Z'_{b-k} = conj(A') + i conj(C')
         *pk = mk<T>(T(Ap.x - Cp.y), T(Ap.y + Cp.x));
         *pm = mk<T>(T(Ap.x + Cp.y), T(Cp.x - Ap.y));
@@ -257,7 +273,7 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * N
     }
   }
   __syncthreads();
-  lds_fft<T, B2, NT, NS * TP, +1>(s, LS, tw, B / B2);
+  lds_fft<T, B2, NT, NS * TP, +1>(s, LS, twf, 1);
 
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
@@ -285,16 +301,22 @@ static hipError_t launch_nat_t(int pass, void* zv, int lblock, int tile0, int nt
   if constexpr (LOG2B <= 9) {
     if (pass != 1) return hipSuccess;
     constexpr int NT = Cfg::clampnt(Cfg::TP * (1 << LOG2B) / Cfg::EPT);
-    k_nat_mid<T, 0, LOG2B><<<dim3(ntiles), dim3(NT), 0, st>>>(z, np, tile0, ntiles, ga, tw, tw64);
+    if (ga.ntap == 4)
+      k_nat_mid<T, 0, LOG2B, 4><<<dim3(ntiles), dim3(NT), 0, st>>>(z, np, tile0, ntiles, ga, tw, tw64);
+    else
+      k_nat_mid<T, 0, LOG2B, 0><<<dim3(ntiles), dim3(NT), 0, st>>>(z, np, tile0, ntiles, ga, tw, tw64);
   } else {
     constexpr int L1 = LOG2B / 2, L2 = LOG2B - L1;
     constexpr int NTO = Cfg::clampnt(Cfg::TP * (1 << L1) / Cfg::EPT);
     constexpr int NTM = Cfg::clampnt(2 * Cfg::TP * (1 << L2) / Cfg::EPT);
     if (pass == 0)
       k_nat_outer<T, L1, L2, -1><<<dim3(ntiles * (1 << L2)), dim3(NTO), 0, st>>>(z, np, tile0, ntiles, tw);
-    if (pass == 1)
-      k_nat_mid<T, L1, L2><<<dim3(ntiles * (1 << (L1 - 1))), dim3(NTM), 0, st>>>(z, np, tile0, ntiles, ga, tw,
-                                                                                   tw64);
+    if (pass == 1 && ga.ntap == 4)
+      k_nat_mid<T, L1, L2, 4><<<dim3(ntiles * (1 << (L1 - 1))), dim3(NTM), 0, st>>>(z, np, tile0, ntiles, ga, tw,
+                                                                                      tw64);
+    if (pass == 1 && ga.ntap != 4)
+      k_nat_mid<T, L1, L2, 0><<<dim3(ntiles * (1 << (L1 - 1))), dim3(NTM), 0, st>>>(z, np, tile0, ntiles, ga, tw,
+                                                                                      tw64);
     if (pass == 2)
       k_nat_outer<T, L1, L2, +1><<<dim3(ntiles * (1 << L2)), dim3(NTO), 0, st>>>(z, np, tile0, ntiles, tw);
   }

@@ -399,22 +399,23 @@ static hipError_t launch_lf2_t(const void* tmp, void* y, const LfTw<T>& tw, int 
 }
 
 template <typename T>
-static hipError_t launch_long_t(int log2n, const void* x, void* y, int64_t nblock, int ntap, const void* winT,
-                                const void* twS, void* tmp, int fchunk, double* part, hipStream_t st) {
+static hipError_t launch_long_t(int pass, int log2n, const void* x, void* y, int64_t nblock, int ntap,
+                                const void* winT, const void* twS, void* tmp, int fchunk, double* part,
+                                hipStream_t st) {
   if (nblock == 0) return hipSuccess;
   const int log2m = log2n - 1;
   const int l1 = (log2m + 1) / 2, l2 = log2m / 2;
   const int M = 1 << log2m, P1 = 1 << l1, P2 = 1 << l2;
   const LfTw<T> tw = lf_tables<T>(twS, P1, P2, M);
-  hipError_t e;
-  switch (l1) {
+  hipError_t e = hipSuccess;
+  if (pass != 1) switch (l1) {
     case 7: e = launch_lf1_t<T, 7>(x, tmp, nblock, ntap, winT, tw, M, P2, st); break;
     case 8: e = launch_lf1_t<T, 8>(x, tmp, nblock, ntap, winT, tw, M, P2, st); break;
     case 9: e = launch_lf1_t<T, 9>(x, tmp, nblock, ntap, winT, tw, M, P2, st); break;
     case 10: e = launch_lf1_t<T, 10>(x, tmp, nblock, ntap, winT, tw, M, P2, st); break;
     default: return hipErrorInvalidValue;
   }
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || pass == 0) return e;
   switch (l2) {
     case 7: return launch_lf2_t<T, 7>(tmp, y, tw, M, P1, nblock, fchunk, part, st);
     case 8: return launch_lf2_t<T, 8>(tmp, y, tw, M, P1, nblock, fchunk, part, st);
@@ -423,12 +424,12 @@ static hipError_t launch_long_t(int log2n, const void* x, void* y, int64_t nbloc
   }
 }
 
-hipError_t launch_pfb_fwd_long(int prec, int log2n, const void* x, void* y, int64_t nblock, int ntap,
+hipError_t launch_pfb_fwd_long(int prec, int log2n, int pass, const void* x, void* y, int64_t nblock, int ntap,
                                const void* winT, const void* twS, void* tmp, int fchunk, double* part,
                                hipStream_t st) {
-  if (log2n < 15 || log2n > 20) return hipErrorInvalidValue;
-  if (prec == F32) return launch_long_t<float>(log2n, x, y, nblock, ntap, winT, twS, tmp, fchunk, part, st);
-  return launch_long_t<double>(log2n, x, y, nblock, ntap, winT, twS, tmp, fchunk, part, st);
+  if (log2n < 15 || log2n > 20 || pass < -1 || pass > 1) return hipErrorInvalidValue;
+  if (prec == F32) return launch_long_t<float>(pass, log2n, x, y, nblock, ntap, winT, twS, tmp, fchunk, part, st);
+  return launch_long_t<double>(pass, log2n, x, y, nblock, ntap, winT, twS, tmp, fchunk, part, st);
 }
 
 }  // namespace ipfb

@@ -84,7 +84,8 @@ hipError_t launch_pfb_fwd_small(int prec, int log2n, const void* x, void* y, int
 // sums of |Y_jk|^2. twS: tables [P1 | P2 | 512 | M/512 | 512 | M/512 + 1] of
 // e^{-2 pi i m/P1}, e^{-2 pi i m/P2}, e^{-2 pi i m/M} (m < 512),
 // e^{-2 pi i 512 m/M}, e^{-2 pi i k/N} (k < 512), e^{-2 pi i 512 m/N}.
-hipError_t launch_pfb_fwd_long(int prec, int log2n, const void* x, void* y, int64_t nblock, int ntap,
+// pass 0 launches the first FFT pass only, 1 the second only, -1 both.
+hipError_t launch_pfb_fwd_long(int prec, int log2n, int pass, const void* x, void* y, int64_t nblock, int ntap,
                                const void* winT, const void* twS, void* tmp, int fchunk, double* part,
                                hipStream_t st);
 
