@@ -41,7 +41,7 @@ HBM_PEAK_GBPS = 8000.0
 #  pfb_fwd_long_p1 : xhat read (4 B), fine window, per-spectrum intermediate
 #                    written (4 B)
 #  pfb_fwd_long_p2 : intermediate read (4 B), fine spectra written (4 B)
-#  autospec_final  : the per-chunk power sums
+#  autospec_final  : sums the per-chunk power sums (a few MB; not priced)
 # The step is priced separately at the method's compulsory traffic (see
 # step_bytes), independent of this kernel split.
 
@@ -57,9 +57,6 @@ def kernel_bytes(name, N, b, Nf, bf, esz):
         return S * esz + 4 * Nf * esz + bf * (Nf // 2) * 2 * esz
     if name == "pfb_fwd_long_p2":
         return bf * (Nf // 2) * 2 * esz + bf * K * 2 * esz
-    if name == "autospec_final":
-        fchunk = (bf + 31) // 32
-        return ((bf + fchunk - 1) // fchunk) * K * 8 + K * 8
     return None
 
 

@@ -328,7 +328,7 @@ int ipfb_plan_create(ipfb_plan* out, int lblock, int ntap, const double* window,
     p->jchunk = (int)((nblock + p->nchunks - 1) / p->nchunks);
     p->nchunks = (int)((nblock + p->jchunk - 1) / p->jchunk);
     // long frames: the second FFT pass sums |Y|^2 over chunks of frames
-    p->fchunk = (int)((nblock + 31) / 32);  // up to 32 chunks: enough workgroups for that pass
+    p->fchunk = p->row_lds ? 1 : lf_frame_chunk(prec, p->log2n, nblock);
     p->nfchunks = (int)((nblock + p->fchunk - 1) / p->fchunk);
     const int nrows = p->nchunks > p->nfchunks ? p->nchunks : p->nfchunks;
     st = dev_alloc(p, (void**)&p->part, (size_t)nrows * (lblock / 2 + 1) * sizeof(double));

@@ -424,6 +424,35 @@ static hipError_t launch_long_t(int pass, int log2n, const void* x, void* y, int
   }
 }
 
+template <typename T, int L2>
+static int lf_chunk_t(int P1, int64_t nblock) {
+  using Cfg = Lf2Cfg<T, L2>;
+  const int ngrp = (P1 / 2 - 1 + Cfg::KB - 1) / Cfg::KB;
+  int64_t nch = resident_workgroups(k_lf2<T, L2>, Cfg::NT) / (ngrp + 1);
+  if (nch < 1) nch = 1;
+  if (nch > nblock) nch = nblock;
+  return (int)((nblock + nch - 1) / nch);
+}
+
+int lf_frame_chunk(int prec, int log2n, int64_t nblock) {
+  if (log2n < 15 || log2n > 20 || nblock < 1) return 1;
+  const int log2m = log2n - 1;
+  const int l1 = (log2m + 1) / 2, l2 = log2m / 2;
+  const int P1 = 1 << l1;
+  if (prec == F32) {
+    switch (l2) {
+      case 7: return lf_chunk_t<float, 7>(P1, nblock);
+      case 8: return lf_chunk_t<float, 8>(P1, nblock);
+      default: return lf_chunk_t<float, 9>(P1, nblock);
+    }
+  }
+  switch (l2) {
+    case 7: return lf_chunk_t<double, 7>(P1, nblock);
+    case 8: return lf_chunk_t<double, 8>(P1, nblock);
+    default: return lf_chunk_t<double, 9>(P1, nblock);
+  }
+}
+
 hipError_t launch_pfb_fwd_long(int prec, int log2n, int pass, const void* x, void* y, int64_t nblock, int ntap,
                                const void* winT, const void* twS, void* tmp, int fchunk, double* part,
                                hipStream_t st) {

@@ -86,6 +86,100 @@ __global__ __launch_bounds__((RowCfg<T, LOG2N>::NT)) void k_row_irfft(
   }
 }
 
+// Persistent form for 4-bit spectra: each workgroup inverts frames j, j + G,
+// j + 2G, ... (G = grid size). The per-channel factors and the pre-twiddles
+// e^{+2 pi i k/N} sit in LDS for the workgroup's life; a frame's packed
+// bytes (an unaligned run of N/2+1 bytes) arrive as aligned 4-byte words
+// staged through LDS, and the next frame's words are fetched into registers
+// while the current frame's FFT runs.
+template <typename T, int LOG2N>
+struct RowPCfg {
+  static constexpr int H = 1 << (LOG2N - 1);
+  static constexpr int EPT = 8;
+  static constexpr int NT0 = H / EPT;
+  static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 1024 ? 1024 : NT0);
+  static constexpr int LS = lds_len(H);
+  static constexpr int RAWW = (H + 1 + 3) / 4 + 2;  // words covering the run from its aligned start
+  static constexpr int DPT = (RAWW + NT - 1) / NT;  // words fetched per thread
+  static constexpr int LDSB = LS * (int)sizeof(cx<T>) + (H + 1) * (int)sizeof(T) + H * (int)sizeof(cx<T>) + RAWW * 4;
+};
+
+template <typename T, int LOG2N>
+__global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
+    const unsigned char* __restrict__ in, const T* __restrict__ fac, T* __restrict__ out, int64_t nrows,
+    const cx<T>* __restrict__ twN) {
+  using Cfg = RowPCfg<T, LOG2N>;
+  constexpr int N = 1 << LOG2N, H = Cfg::H, NT = Cfg::NT, LS = Cfg::LS, EPT = Cfg::EPT;
+  constexpr int RAWW = Cfg::RAWW, DPT = Cfg::DPT;
+  static_assert(H % NT == 0 || NT == 64, "frame must split over the threads");
+  __shared__ cx<T> s[LS];
+  __shared__ T facs[H + 1];
+  __shared__ cx<T> wt[H];
+  __shared__ unsigned int raw[RAWW];
+  const int tid = threadIdx.x;
+  const int64_t total = nrows * (int64_t)(H + 1);
+  for (int k = tid; k <= H; k += NT) facs[k] = fac[k];
+  for (int k = tid; k < H; k += NT) wt[k] = conj(twN[k]);  // e^{+2 pi i k / N}
+  unsigned int pf[DPT];
+  auto fetch = [&](int64_t j) {
+    const int64_t b0 = j * (int64_t)(H + 1);
+    const int64_t a0 = b0 & ~int64_t(3);
+    const int nd = (int)((b0 + H + 1 - a0 + 3) >> 2);
+#pragma unroll
+    for (int d = 0; d < DPT; ++d) {
+      const int idx = tid + d * NT;
+      const int64_t byte = a0 + 4 * (int64_t)idx;
+      pf[d] = 0u;
+      if (idx < nd) {
+        if (byte + 4 <= total) {
+          pf[d] = *reinterpret_cast<const unsigned int*>(in + byte);
+        } else {  // the array's last word may be partial: read its bytes one by one
+          unsigned int w = 0u;
+          for (int q = 0; q < 4 && byte + q < total; ++q) w |= (unsigned int)in[byte + q] << (8 * q);
+          pf[d] = w;
+        }
+      }
+    }
+  };
+  int64_t j = blockIdx.x;
+  if (j < nrows) fetch(j);
+  for (; j < nrows; j += gridDim.x) {
+#pragma unroll
+    for (int d = 0; d < DPT; ++d) {
+      const int idx = tid + d * NT;
+      if (idx < RAWW) raw[idx] = pf[d];
+    }
+    __syncthreads();
+    if (j + gridDim.x < nrows) fetch(j + gridDim.x);  // in flight during the FFT
+    const unsigned char* rb = reinterpret_cast<const unsigned char*>(raw) + (int)((j * (int64_t)(H + 1)) & 3);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int k = tid + i * NT;
+      if (k >= H) continue;
+      const signed char bk = (signed char)rb[k], bm = (signed char)rb[H - k];
+      const T fk = facs[k], fm = facs[H - k];
+      cx<T> yk = mk<T>(T(bk >> 4) * fk, T((signed char)(bk << 4) >> 4) * fk);
+      cx<T> ym = mk<T>(T(bm >> 4) * fm, T((signed char)(bm << 4) >> 4) * fm);
+      if (k == 0) {  // DC and Nyquist imaginary parts carry nothing for a real frame
+        yk.y = T(0);
+        ym.y = T(0);
+      }
+      const cx<T> a = yk + conj(ym);
+      const cx<T> t = cmul(wt[k], yk - conj(ym));
+      s[pidx(k)] = mk<T>(a.x - t.y, a.y + t.x);  // a + i t
+    }
+    __syncthreads();
+    lds_fft<T, H, NT, 1, +1>(s, LS, twN, 2);
+    cx<T>* orow = reinterpret_cast<cx<T>*>(out + j * (int64_t)N);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int m = tid + i * NT;
+      if (m < H) orow[m] = s[pidx(m)];
+    }
+    __syncthreads();  // s and raw are rewritten for the next frame
+  }
+}
+
 template <typename T, int LOG2N>
 static hipError_t launch_row_t(int fmt, const void* in, const void* fac, void* out, int64_t nrows,
                                const void* twN, hipStream_t st) {
@@ -95,6 +189,15 @@ static hipError_t launch_row_t(int fmt, const void* in, const void* fac, void* o
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(twN);
   T* o = reinterpret_cast<T*>(out);
   const T* sc = reinterpret_cast<const T*>(fac);
+  if constexpr (LOG2N >= 9 && RowPCfg<T, LOG2N>::LDSB <= 65536) {
+    if (fmt == IN_C4) {
+      using Cp = RowPCfg<T, LOG2N>;
+      const int64_t res = resident_workgroups(k_row_c4p<T, LOG2N>, Cp::NT);
+      const int64_t g = nrows < res ? nrows : res;
+      k_row_c4p<T, LOG2N><<<dim3((unsigned)g), dim3(Cp::NT), 0, st>>>((const unsigned char*)in, sc, o, nrows, tw);
+      return hipGetLastError();
+    }
+  }
   switch (fmt) {
     case IN_C4: k_row_irfft<T, LOG2N, IN_C4><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(in, sc, o, nrows, tw); break;
     case IN_CF32: k_row_irfft<T, LOG2N, IN_CF32><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(in, sc, o, nrows, tw); break;

@@ -7,6 +7,26 @@
 namespace ipfb {
 
 enum Prec { F32 = 0, F64 = 1 };
+
+// How many workgroups of `kernel` (nt threads, static LDS only) the current
+// device holds at once: the grid for kernels that loop over their work.
+// Cached per kernel and device.
+template <typename K>
+inline int resident_workgroups(K kernel, int nt) {
+  static int cache[16] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) dev = 0;
+  const int slot = dev < 16 ? dev : 15;
+  if (cache[slot] > 0) return cache[slot];
+  int cus = 0, per = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, nt, 0) != hipSuccess) per = 0;
+  hipGetLastError();
+  if (cus < 1) cus = 1;
+  if (per < 1) per = 1;
+  cache[slot] = cus * per;
+  return cache[slot];
+}
 // Input spectrum formats of the inverse (match the public header).
 enum InFmt { IN_C4 = 0, IN_CF32 = 2, IN_CF64 = 3, IN_ADJ = 100 };
 
@@ -84,6 +104,9 @@ hipError_t launch_pfb_fwd_small(int prec, int log2n, const void* x, void* y, int
 // sums of |Y_jk|^2. twS: tables [P1 | P2 | 512 | M/512 | 512 | M/512 + 1] of
 // e^{-2 pi i m/P1}, e^{-2 pi i m/P2}, e^{-2 pi i m/M} (m < 512),
 // e^{-2 pi i 512 m/M}, e^{-2 pi i k/N} (k < 512), e^{-2 pi i 512 m/N}.
+// Frames per power-sum chunk of the second pass: one workgroup per row group
+// and chunk, about as many workgroups as the device holds at once.
+int lf_frame_chunk(int prec, int log2n, int64_t nblock);
 // pass 0 launches the first FFT pass only, 1 the second only, -1 both.
 hipError_t launch_pfb_fwd_long(int prec, int log2n, int pass, const void* x, void* y, int64_t nblock, int ntap,
                                const void* winT, const void* twS, void* tmp, int fchunk, double* part,
