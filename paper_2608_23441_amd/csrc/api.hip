@@ -430,9 +430,14 @@ int ipfb_wiener_ex(ipfb_plan p, int infmt, const void* spec, const float* chan_s
   hipError_t e;
   {
     ProfScope ps("ipfb_rows", st);
-    if (infmt == IPFB_IN_C4) e = launch_dequant_factors(p->prec, chan_scale, p->lblock / 2 + 1, p->lblock, p->fac, st);
-    else e = hipSuccess;
-    if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec, p->fac, x_out, p->nblock, p->twN, st);
+    e = hipErrorNotSupported;
+    if (infmt == IPFB_IN_C4) e = launch_row_c4(p->prec, p->log2n, spec, chan_scale, x_out, p->nblock, p->twN, st);
+    if (e == hipErrorNotSupported) {
+      hipGetLastError();
+      if (infmt == IPFB_IN_C4) e = launch_dequant_factors(p->prec, chan_scale, p->lblock / 2 + 1, p->lblock, p->fac, st);
+      else e = hipSuccess;
+      if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec, p->fac, x_out, p->nblock, p->twN, st);
+    }
   }
   // column stage in place on x_out: d [b][N] -> x [b][N]
   static const char* const pass_names[3] = {"ipfb_cols_fwd", "ipfb_cols_gain", "ipfb_cols_inv"};
@@ -820,18 +825,30 @@ hipError_t enqueue_batched(ipfb_bplan p, int infmt, const void* const* spec, con
   for (int s = 0; s < p->nstreams && e == hipSuccess; ++s) {
     const int64_t b = p->nblock[s];
     const BluTables& bt = p->blu[b];
-    if (infmt == IPFB_IN_C4) e = launch_dequant_factors(p->prec, sc[s], K, N, p->fac, st);
-    if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec[s], p->fac, p->f0, b, p->twN, st);
-    if (e == hipSuccess) e = launch_transpose(p->prec, p->f0, p->f1, b, N, st);  // d -> d_T in f1
-    if (e != hipSuccess) break;
-    if (bt.log2m == 0) {  // power of two: LDS column kernel, x_T in f0
-      e = launch_col_wiener(p->prec, ilog2(b), p->f1, p->f0, N, p->ntap, p->win64, phi, normalise, bt.twB, bt.twb64,
-                            st);
-    } else {  // Bluestein: Z in f0, A in f1 (d_T consumed by then), x_T in f0
-      const MTables& mt = p->mtab[bt.log2m];
-      e = launch_blu_columns(p->prec, p->f1, p->f0, p->Tm, p->f0, p->f1, bt.chirp, bt.Crow, bt.twb64, b, bt.log2m,
-                             N, p->ntap, p->win64, phi, normalise, mt.tw4, st);
+    // power of two: rows straight into the output, columns in place there;
+    // otherwise rows into f0 for the transposed Bluestein path
+    void* rows_out = bt.log2m == 0 ? xo[s] : p->f0;
+    e = hipErrorNotSupported;
+    if (infmt == IPFB_IN_C4) e = launch_row_c4(p->prec, p->log2n, spec[s], sc[s], rows_out, b, p->twN, st);
+    if (e == hipErrorNotSupported) {
+      hipGetLastError();
+      e = hipSuccess;
+      if (infmt == IPFB_IN_C4) e = launch_dequant_factors(p->prec, sc[s], K, N, p->fac, st);
+      if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec[s], p->fac, rows_out, b, p->twN, st);
     }
+    if (e != hipSuccess) break;
+    if (bt.log2m == 0) {
+      for (int pass = 0; pass < 3 && e == hipSuccess; ++pass)
+        e = launch_col_wiener_nat(p->prec, ilog2(b), pass, xo[s], N, p->ntap, p->win64, phi, normalise, bt.twB,
+                                  bt.twb64, st);
+      continue;
+    }
+    // Bluestein: d -> d_T in f1; Z in f0, A in f1 (d_T consumed by then), x_T in f0
+    e = launch_transpose(p->prec, p->f0, p->f1, b, N, st);
+    if (e != hipSuccess) break;
+    const MTables& mt = p->mtab[bt.log2m];
+    e = launch_blu_columns(p->prec, p->f1, p->f0, p->Tm, p->f0, p->f1, bt.chirp, bt.Crow, bt.twb64, b, bt.log2m, N,
+                           p->ntap, p->win64, phi, normalise, mt.tw4, st);
     if (e == hipSuccess) e = launch_transpose(p->prec, p->f0, xo[s], N, b, st);  // x_T -> x (time order)
   }
   return e;
@@ -886,6 +903,9 @@ int ipfb_batched_plan_create(ipfb_bplan* out, int lblock, int ntap, const double
   if (!st && maxlog2m > 0)
     st = balloc(p, &p->Tm, (size_t)((lblock + 1) / 2) * ((size_t)1 << maxlog2m) * 2 * esize(prec));
   (void)M;
+  // prime the row kernel's occupancy query outside any later graph capture
+  if (!st && launch_row_c4(prec, p->log2n, nullptr, nullptr, nullptr, 0, nullptr, nullptr) != hipSuccess)
+    hipGetLastError();
   if (!st && hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess) {
     hipGetLastError();
     st = fail(IPFB_EHIP, "hipStreamCreate failed");

@@ -257,18 +257,21 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * N
         cx<T>* pk = s + (sk[u] * TP + q) * LS + pidx(k2[u]);
         cx<T>* pm = s + (sm[u] * TP + q) * LS + pidx(k2m[u]);
         if (sk[u] == sm[u] && k2[u] == k2m[u]) {  // f = 0 or b/2: both spectra real there, gains real
-          *pk = mk<T>(T(Ga[u].x * (double)zk[u].x), T(Gc[u].x * (double)zk[u].y));
+          *pk = mk<T>(T(Ga[u].x) * zk[u].x, T(Gc[u].x) * zk[u].y);
           continue;
         }
-        // A = (Z_k + conj Z_m)/2, C = (Z_k - conj Z_m)/(2i): the two real spectra
-        const double sx = (double)zk[u].x + (double)zm[u].x, sy = (double)zk[u].y - (double)zm[u].y;
-        const double dx = (double)zk[u].x - (double)zm[u].x, dy = (double)zk[u].y + (double)zm[u].y;
-        const cx<double> A = mk<double>(0.5 * sx, 0.5 * sy);
-        const cx<double> C = mk<double>(0.5 * dy, -0.5 * dx);
-        const cx<double> Ap = cmul(Ga[u], A), Cp = cmul(Gc[u], C);
+        // The gains are formed in FP64 and rounded once to the data precision;
+        // the split and re-pack of the two real spectra run in the data
+        // precision, like the FFTs around them. With g = G/2:
+        //   A' = g_a (Z_k + conj Z_m),  C' = g_c (Z_k - conj Z_m) / i
+        const cx<T> ga = mk<T>(T(0.5 * Ga[u].x), T(0.5 * Ga[u].y));
+        const cx<T> gc = mk<T>(T(0.5 * Gc[u].x), T(0.5 * Gc[u].y));
+        const cx<T> A2 = mk<T>(zk[u].x + zm[u].x, zk[u].y - zm[u].y);
+        const cx<T> C2 = mk<T>(zk[u].y + zm[u].y, zm[u].x - zk[u].x);
+        const cx<T> Ap = cmul(ga, A2), Cp = cmul(gc, C2);
         // Z'_k = A' + i C',  Z'_{b-k} = conj(A') + i conj(C')
-        *pk = mk<T>(T(Ap.x - Cp.y), T(Ap.y + Cp.x));
-        *pm = mk<T>(T(Ap.x + Cp.y), T(Cp.x - Ap.y));
+        *pk = mk<T>(Ap.x - Cp.y, Ap.y + Cp.x);
+        *pm = mk<T>(Ap.x + Cp.y, Cp.x - Ap.y);
       }
     }
   }

@@ -106,20 +106,21 @@ struct RowPCfg {
 
 template <typename T, int LOG2N>
 __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
-    const unsigned char* __restrict__ in, const T* __restrict__ fac, T* __restrict__ out, int64_t nrows,
-    const cx<T>* __restrict__ twN) {
+    const unsigned char* __restrict__ in, const float* __restrict__ chan_scale, T* __restrict__ out,
+    int64_t nrows, const cx<T>* __restrict__ twN) {
   using Cfg = RowPCfg<T, LOG2N>;
   constexpr int N = 1 << LOG2N, H = Cfg::H, NT = Cfg::NT, LS = Cfg::LS, EPT = Cfg::EPT;
   constexpr int RAWW = Cfg::RAWW, DPT = Cfg::DPT;
   static_assert(H % NT == 0 || NT == 64, "frame must split over the threads");
   __shared__ cx<T> s[LS];
   __shared__ T facs[H + 1];
-  __shared__ cx<T> wt[H];
+  __shared__ cx<T> wt[H];  // e^{+2 pi i k / N}: pre-twiddles
   __shared__ unsigned int raw[RAWW];
   const int tid = threadIdx.x;
   const int64_t total = nrows * (int64_t)(H + 1);
-  for (int k = tid; k <= H; k += NT) facs[k] = fac[k];
-  for (int k = tid; k < H; k += NT) wt[k] = conj(twN[k]);  // e^{+2 pi i k / N}
+  // dequantisation factor 1/(s_k N), formed in FP64 from the stored FP32 scale
+  for (int k = tid; k <= H; k += NT) facs[k] = T(1.0 / ((double)chan_scale[k] * (double)N));
+  for (int k = tid; k < H; k += NT) wt[k] = conj(twN[k]);
   unsigned int pf[DPT];
   auto fetch = [&](int64_t j) {
     const int64_t b0 = j * (int64_t)(H + 1);
@@ -169,6 +170,8 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
       s[pidx(k)] = mk<T>(a.x - t.y, a.y + t.x);  // a + i t
     }
     __syncthreads();
+    // the FFT's own twiddles stay in global memory (L2): an LDS copy would
+    // cost a workgroup per CU, which costs more than their latency
     lds_fft<T, H, NT, 1, +1>(s, LS, twN, 2);
     cx<T>* orow = reinterpret_cast<cx<T>*>(out + j * (int64_t)N);
 #pragma unroll
@@ -189,15 +192,6 @@ static hipError_t launch_row_t(int fmt, const void* in, const void* fac, void* o
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(twN);
   T* o = reinterpret_cast<T*>(out);
   const T* sc = reinterpret_cast<const T*>(fac);
-  if constexpr (LOG2N >= 9 && RowPCfg<T, LOG2N>::LDSB <= 65536) {
-    if (fmt == IN_C4) {
-      using Cp = RowPCfg<T, LOG2N>;
-      const int64_t res = resident_workgroups(k_row_c4p<T, LOG2N>, Cp::NT);
-      const int64_t g = nrows < res ? nrows : res;
-      k_row_c4p<T, LOG2N><<<dim3((unsigned)g), dim3(Cp::NT), 0, st>>>((const unsigned char*)in, sc, o, nrows, tw);
-      return hipGetLastError();
-    }
-  }
   switch (fmt) {
     case IN_C4: k_row_irfft<T, LOG2N, IN_C4><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(in, sc, o, nrows, tw); break;
     case IN_CF32: k_row_irfft<T, LOG2N, IN_CF32><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(in, sc, o, nrows, tw); break;
@@ -225,6 +219,40 @@ hipError_t launch_row_irfft(int prec, int log2n, int fmt, const void* in, const 
     ROW_CASE(double, 7) ROW_CASE(double, 8) ROW_CASE(double, 9) ROW_CASE(double, 10) ROW_CASE(double, 11)
     ROW_CASE(double, 12) ROW_CASE(double, 13) ROW_CASE(double, 14)
     default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int LOG2N>
+static hipError_t launch_row_c4_t(const void* in, const float* chan_scale, void* out, int64_t nrows,
+                                  const void* twN, hipStream_t st) {
+  if constexpr (LOG2N >= 9 && RowPCfg<T, LOG2N>::LDSB <= 81920) {
+    using Cp = RowPCfg<T, LOG2N>;
+    const int64_t res = resident_workgroups(k_row_c4p<T, LOG2N>, Cp::NT);  // (cached after the first call)
+    if (nrows == 0) return hipSuccess;
+    const int64_t g = nrows < res ? nrows : res;
+    k_row_c4p<T, LOG2N><<<dim3((unsigned)g), dim3(Cp::NT), 0, st>>>(
+        (const unsigned char*)in, chan_scale, (T*)out, nrows, (const cx<T>*)twN);
+    return hipGetLastError();
+  } else {
+    return hipErrorNotSupported;
+  }
+}
+
+#define ROWC4_CASE(T, L) \
+  case L: return launch_row_c4_t<T, L>(in, chan_scale, out, nrows, twN, st);
+
+hipError_t launch_row_c4(int prec, int log2n, const void* in, const float* chan_scale, void* out, int64_t nrows,
+                         const void* twN, hipStream_t st) {
+  if (prec == F32) {
+    switch (log2n) {
+      ROWC4_CASE(float, 9) ROWC4_CASE(float, 10) ROWC4_CASE(float, 11) ROWC4_CASE(float, 12)
+      ROWC4_CASE(float, 13)
+      default: return hipErrorNotSupported;
+    }
+  }
+  switch (log2n) {
+    ROWC4_CASE(double, 9) ROWC4_CASE(double, 10) ROWC4_CASE(double, 11) ROWC4_CASE(double, 12)
+    default: return hipErrorNotSupported;
   }
 }
 

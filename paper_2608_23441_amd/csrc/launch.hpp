@@ -44,6 +44,13 @@ hipError_t launch_row_irfft(int prec, int log2n, int fmt, const void* in, const 
                             void* out, int64_t nrows, const void* twN, hipStream_t st);
 hipError_t launch_dequant_factors(int prec, const float* chan_scale, int nchan, int N, void* fac,
                                   hipStream_t st);
+// The row stage for 4-bit spectra in one persistent kernel that forms the
+// factors 1/(s_k N) itself; hipErrorNotSupported where the frame length has
+// no such kernel (then use launch_dequant_factors + launch_row_irfft).
+// nrows = 0 launches nothing (it primes the occupancy query, for callers that
+// later launch inside a graph capture).
+hipError_t launch_row_c4(int prec, int log2n, const void* in, const float* chan_scale, void* out, int64_t nrows,
+                         const void* twN, hipStream_t st);
 
 // Column stage on the transposed frame matrix: per column n (contiguous in
 // d_T[n][0..b)), x_T[n] = F^-1[ G_n F d_T[n] ] with the FP64 gain.

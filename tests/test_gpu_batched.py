@@ -49,7 +49,7 @@ def test_batched_small_uneven(prec, tol):
 def test_batched_production_lengths_fp32():
     # production frame length with Bluestein lengths up to M = 65536
     N, p = 4096, 4
-    nblocks = [1031, 3000, 16385]
+    nblocks = [1031, 3000, 16385, 2048]
     print("case batched production lengths", flush=True)
     w, data = _streams(N, p, nblocks, 4100)
     bp = ipfb.BatchedPlan(N, p, w, nblocks, ipfb.F32)

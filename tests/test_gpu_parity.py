@@ -54,6 +54,24 @@ def test_ipfb_wiener_c4(prec, N, p, b, phi):
     assert _rel(_host(out), ref) < TOL[prec]
 
 
+# The three-pass (four-step) column stage, b > 512: partial column tiles
+# (lblock/2 below the 16-pair tile), tap counts other than 4 (the generic gain
+# kernel), phi = 0 with the four-step, and the b1 x b2 splits 32x32 ... 128x256.
+@pytest.mark.parametrize("prec,N,p,b,phi", [
+    (ipfb.F64, 8, 4, 1024, 0.1), (ipfb.F32, 8, 4, 1024, 0.1),
+    (ipfb.F64, 64, 3, 4096, 0.1), (ipfb.F32, 64, 5, 4096, 0.2),
+    (ipfb.F64, 16, 4, 8192, 0.0), (ipfb.F32, 64, 4, 2048, 0.0),
+    (ipfb.F32, 32, 4, 32768, 0.1), (ipfb.F64, 256, 4, 16384, 0.1),
+])
+def test_ipfb_wiener_four_step_columns(prec, N, p, b, phi):
+    print(f"case ipfb_wiener four-step prec={prec} N={N} p={p} b={b} phi={phi}", flush=True)
+    w, x, y, packed, s = _quantised_case(N, p, b, 300 + N + b)
+    ref = O.ipfb_wiener(packed, s, w, N, p, phi)
+    plan = ipfb.Plan(N, p, w, b, prec)
+    out = ipfb.ipfb_wiener(plan, _dev(packed), _dev(s), phi)
+    assert _rel(_host(out), ref) < TOL[prec]
+
+
 @pytest.mark.parametrize("prec,fmt", [(ipfb.F64, "c128"), (ipfb.F32, "c64"), (ipfb.F64, "c64"),
                                       (ipfb.F32, "c128")])
 def test_ipfb_wiener_complex_inputs_and_unnormalised(prec, fmt):
