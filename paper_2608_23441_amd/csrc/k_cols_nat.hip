@@ -219,15 +219,17 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * N
         wsc += fabs(ga.win[(int64_t)r * N + nc]);
       }
     }
-    // two items per step: their gain chains are independent, so they overlap
+    // IL items per step (their gain chains are independent). Two would overlap
+    // better but spill registers, and spilled registers cost HBM traffic.
+    constexpr int IL = 1;
 #pragma unroll 1
-    for (int i = 0; i < IMAX; i += 2) {
-      int sk[2], k2[2], sm[2], k2m[2];
-      bool ok[2];
-      cx<T> zk[2], zm[2];
-      cx<double> Ga[2], Gc[2];
+    for (int i = 0; i < IMAX; i += IL) {
+      int sk[IL], k2[IL], sm[IL], k2m[IL];
+      bool ok[IL];
+      cx<T> zk[IL], zm[IL];
+      cx<double> Ga[IL], Gc[IL];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < IL; ++u) {
         const int it = tid / TP + (i + u) * IPAR;
         ok[u] = valid && (i + u < IMAX) && it < NI;
         gain_item<NS, B2>(kk, ok[u] ? it : 0, sk[u], k2[u], sm[u], k2m[u]);
@@ -235,7 +237,7 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * N
         zm[u] = s[(sm[u] * TP + q) * LS + pidx(k2m[u])];
       }
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < IL; ++u) {
         const int kz = (NS == 2 && kk == 0 && sk[u] == 1) ? k2[u] + B2 / 2 + 1 : k2[u];
         const cx<double> zf = cmul((NS == 2 && kk == 0 && sk[u] == 1) ? base_b : base_a, twz[kz & (B2 - 1)]);
         cx<double> Wa, Wc;
@@ -252,7 +254,7 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * N
         pair_gains(ga, Wa, Wc, wsa, wsc, Ga[u], Gc[u]);
       }
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < IL; ++u) {
         if (!ok[u]) continue;
         cx<T>* pk = s + (sk[u] * TP + q) * LS + pidx(k2[u]);
         cx<T>* pm = s + (sm[u] * TP + q) * LS + pidx(k2m[u]);
