@@ -173,108 +173,123 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * N
     twf[m] = tw[m * B1];
     twz[m] = tw64[m * B1];
   }
+  constexpr int IPAR = NT / TP;  // gain items in flight across the workgroup
+  constexpr int NIMAX = (NS == 1) ? (B2 / 2 + 1) : (B2 + 1);
+  constexpr int IMAX = (NIMAX + IPAR - 1) / IPAR;
+  const int NI = (NS == 1) ? (B2 / 2 + 1) : (kk == 0 ? B2 + 1 : B2);
+  const int q = tid % TP;
+  const bool valid = p0 + q < np;
+  const int N = ga.lblock, na = 2 * (p0 + q), nc = na + 1;
+  // e^{-2 pi i f / b} for f = k1 + b1 k2 is base * e^{-2 pi i k2 / b2}, with
+  // base = e^{-2 pi i ka / b} for kk > 0; for kk = 0, 1 on row 0 and
+  // -e^{+i pi / b2} on row b1/2 (the items of row b1/2 count k2 from b2/2+1).
+  const cx<double> base_a = tw64[ka];
+  const cx<double> h1 = tw64[B1 / 2];
+  const cx<double> base_b = mk<double>(-h1.x, h1.y);
+  constexpr int HT = NTAP > 0 ? NTAP : 1;
+  double ha[HT], hc[HT];
+#pragma unroll
+  for (int r = 0; r < HT; ++r) {
+    ha[r] = (NTAP > 0 && valid) ? ga.win[(int64_t)r * N + na] : 0.0;
+    hc[r] = (NTAP > 0 && valid) ? ga.win[(int64_t)r * N + nc] : 0.0;
+  }
+  double wsa = 0.0, wsc = 0.0;
+  if (ga.naive && valid) {
+    for (int r = 0; r < ga.ntap; ++r) {
+      wsa += fabs(ga.win[(int64_t)r * N + na]);
+      wsc += fabs(ga.win[(int64_t)r * N + nc]);
+    }
+  }
+  // gains of item `it` (FP64): the two paths of pair q at the item's frequency
+  auto gains = [&](int it, cx<double>& Ga, cx<double>& Gc) {
+    int sk, k2, sm, k2m;
+    gain_item<NS, B2>(kk, it, sk, k2, sm, k2m);
+    const int kz = (NS == 2 && kk == 0 && sk == 1) ? k2 + B2 / 2 + 1 : k2;
+    const cx<double> zf = cmul((NS == 2 && kk == 0 && sk == 1) ? base_b : base_a, twz[kz & (B2 - 1)]);
+    cx<double> Wa, Wc;
+    if constexpr (NTAP == 4) {
+      const cx<double> z2 = cmul(zf, zf), z3 = cmul(z2, zf);
+      Wa = mk<double>(ha[0] + ha[1] * zf.x + ha[2] * z2.x + ha[3] * z3.x, ha[1] * zf.y + ha[2] * z2.y + ha[3] * z3.y);
+      Wc = mk<double>(hc[0] + hc[1] * zf.x + hc[2] * z2.x + hc[3] * z3.x, hc[1] * zf.y + hc[2] * z2.y + hc[3] * z3.y);
+    } else {
+      Wa = horner_g(ga.win, N, na, ga.ntap, zf);
+      Wc = horner_g(ga.win, N, nc, ga.ntap, zf);
+    }
+    pair_gains(ga, Wa, Wc, wsa, wsc, Ga, Gc);
+  };
+  // FP32 form with 4 taps: the first NPRE gains of this thread are formed
+  // (FP64, then rounded once) while the workgroup's loads are in flight, and
+  // kept in registers until the spectra are ready; the rest follow the FFT
+  // (only where the register budget holds them without spilling: b2 = 128)
+  constexpr bool PRE = sizeof(T) == 4 && NTAP == 4 && B2 == 128;
+  constexpr int NPRE = PRE ? (IMAX < 2 ? IMAX : 2) : 1;  // gains held across the FFT
+  cx<T> gpre[NPRE][2];
   {
     cx<T> v[IT];
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
-      const int e = tid + i * NT, q = e % TP, r = e / TP;
+      const int e = tid + i * NT, qq = e % TP, r = e / TP;
       const int j2 = r % B2, k1 = (r / B2) ? kb : ka;
       v[i] = mk<T>(T(0), T(0));
-      if ((NE % NT == 0 || e < NE) && p0 + q < np) v[i] = z[(int64_t)(k1 * B2 + j2) * np + p0 + q];
+      if ((NE % NT == 0 || e < NE) && p0 + qq < np) v[i] = z[(int64_t)(k1 * B2 + j2) * np + p0 + qq];
+    }
+    if constexpr (PRE) {
+      __syncthreads();  // twz ready (the loads above stay in flight)
+#pragma unroll
+      for (int i = 0; i < NPRE; ++i) {
+        const int it = tid / TP + i * IPAR;
+        cx<double> Ga = mk<double>(0.0, 0.0), Gc = Ga;
+        if (valid && it < NI) gains(it, Ga, Gc);
+        gpre[i][0] = mk<T>(T(Ga.x), T(Ga.y));
+        gpre[i][1] = mk<T>(T(Gc.x), T(Gc.y));
+      }
     }
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
-      const int e = tid + i * NT, q = e % TP, r = e / TP;
-      if (NE % NT == 0 || e < NE) s[(r / B2 * TP + q) * LS + pidx(r % B2)] = v[i];
+      const int e = tid + i * NT, qq = e % TP, r = e / TP;
+      if (NE % NT == 0 || e < NE) s[(r / B2 * TP + qq) * LS + pidx(r % B2)] = v[i];
     }
   }
   __syncthreads();
   lds_fft<T, B2, NT, NS * TP, -1>(s, LS, twf, 1);
 
+  // apply: split the two real spectra of pair q at frequency k (and b - k),
+  // weight them, re-pack; with g = G/2,
+  //   A' = g_a (Z_k + conj Z_m),  C' = g_c (Z_k - conj Z_m) / i
+  auto apply = [&](int it, cx<T> gat, cx<T> gct) {
+    int sk, k2, sm, k2m;
+    gain_item<NS, B2>(kk, it, sk, k2, sm, k2m);
+    cx<T>* pk = s + (sk * TP + q) * LS + pidx(k2);
+    cx<T>* pm = s + (sm * TP + q) * LS + pidx(k2m);
+    const cx<T> zk = *pk, zm = *pm;
+    if (sk == sm && k2 == k2m) {  // f = 0 or b/2: both spectra real there, gains real
+      *pk = mk<T>(gat.x * zk.x, gct.x * zk.y);
+      return;
+    }
+    const cx<T> ha2 = mk<T>(T(0.5) * gat.x, T(0.5) * gat.y), hc2 = mk<T>(T(0.5) * gct.x, T(0.5) * gct.y);
+    const cx<T> A2 = mk<T>(zk.x + zm.x, zk.y - zm.y);
+    const cx<T> C2 = mk<T>(zk.y + zm.y, zm.x - zk.x);
+    const cx<T> Ap = cmul(ha2, A2), Cp = cmul(hc2, C2);
+    // Z'_k = A' + i C',  Z'_{b-k} = conj(A') + i conj(C')
+    *pk = mk<T>(Ap.x - Cp.y, Ap.y + Cp.x);
+    *pm = mk<T>(Ap.x + Cp.y, Cp.x - Ap.y);
+  };
+  if constexpr (PRE) {
+#pragma unroll
+    for (int i = 0; i < NPRE; ++i) {
+      const int it = tid / TP + i * IPAR;
+      if (valid && it < NI) apply(it, gpre[i][0], gpre[i][1]);
+    }
+  }
   {
-    constexpr int IPAR = NT / TP;  // items in flight across the workgroup
-    constexpr int NIMAX = (NS == 1) ? (B2 / 2 + 1) : (B2 + 1);
-    constexpr int IMAX = (NIMAX + IPAR - 1) / IPAR;
-    const int NI = (NS == 1) ? (B2 / 2 + 1) : (kk == 0 ? B2 + 1 : B2);
-    const int q = tid % TP;
-    const bool valid = p0 + q < np;
-    const int N = ga.lblock, na = 2 * (p0 + q), nc = na + 1;
-    // e^{-2 pi i f / b} for f = k1 + b1 k2 is base * e^{-2 pi i k2 / b2}, with
-    // base = e^{-2 pi i ka / b} for kk > 0; for kk = 0, 1 on row 0 and
-    // -e^{+i pi / b2} on row b1/2 (the items of row b1/2 count k2 from b2/2+1).
-    const cx<double> base_a = tw64[ka];
-    const cx<double> h1 = tw64[B1 / 2];
-    const cx<double> base_b = mk<double>(-h1.x, h1.y);
-    constexpr int HT = NTAP > 0 ? NTAP : 1;
-    double ha[HT], hc[HT];
-#pragma unroll
-    for (int r = 0; r < HT; ++r) {
-      ha[r] = (NTAP > 0 && valid) ? ga.win[(int64_t)r * N + na] : 0.0;
-      hc[r] = (NTAP > 0 && valid) ? ga.win[(int64_t)r * N + nc] : 0.0;
-    }
-    double wsa = 0.0, wsc = 0.0;
-    if (ga.naive && valid) {
-      for (int r = 0; r < ga.ntap; ++r) {
-        wsa += fabs(ga.win[(int64_t)r * N + na]);
-        wsc += fabs(ga.win[(int64_t)r * N + nc]);
-      }
-    }
-    // IL items per step (their gain chains are independent). Two would overlap
-    // better but spill registers, and spilled registers cost HBM traffic.
-    constexpr int IL = 1;
 #pragma unroll 1
-    for (int i = 0; i < IMAX; i += IL) {
-      int sk[IL], k2[IL], sm[IL], k2m[IL];
-      bool ok[IL];
-      cx<T> zk[IL], zm[IL];
-      cx<double> Ga[IL], Gc[IL];
-#pragma unroll
-      for (int u = 0; u < IL; ++u) {
-        const int it = tid / TP + (i + u) * IPAR;
-        ok[u] = valid && (i + u < IMAX) && it < NI;
-        gain_item<NS, B2>(kk, ok[u] ? it : 0, sk[u], k2[u], sm[u], k2m[u]);
-        zk[u] = s[(sk[u] * TP + q) * LS + pidx(k2[u])];
-        zm[u] = s[(sm[u] * TP + q) * LS + pidx(k2m[u])];
-      }
-#pragma unroll
-      for (int u = 0; u < IL; ++u) {
-        const int kz = (NS == 2 && kk == 0 && sk[u] == 1) ? k2[u] + B2 / 2 + 1 : k2[u];
-        const cx<double> zf = cmul((NS == 2 && kk == 0 && sk[u] == 1) ? base_b : base_a, twz[kz & (B2 - 1)]);
-        cx<double> Wa, Wc;
-        if constexpr (NTAP == 4) {
-          const cx<double> z2 = cmul(zf, zf), z3 = cmul(z2, zf);
-          Wa = mk<double>(ha[0] + ha[1] * zf.x + ha[2] * z2.x + ha[3] * z3.x,
-                          ha[1] * zf.y + ha[2] * z2.y + ha[3] * z3.y);
-          Wc = mk<double>(hc[0] + hc[1] * zf.x + hc[2] * z2.x + hc[3] * z3.x,
-                          hc[1] * zf.y + hc[2] * z2.y + hc[3] * z3.y);
-        } else {
-          Wa = horner_g(ga.win, N, na, ga.ntap, zf);
-          Wc = horner_g(ga.win, N, nc, ga.ntap, zf);
-        }
-        pair_gains(ga, Wa, Wc, wsa, wsc, Ga[u], Gc[u]);
-      }
-#pragma unroll
-      for (int u = 0; u < IL; ++u) {
-        if (!ok[u]) continue;
-        cx<T>* pk = s + (sk[u] * TP + q) * LS + pidx(k2[u]);
-        cx<T>* pm = s + (sm[u] * TP + q) * LS + pidx(k2m[u]);
-        if (sk[u] == sm[u] && k2[u] == k2m[u]) {  // f = 0 or b/2: both spectra real there, gains real
-          *pk = mk<T>(T(Ga[u].x) * zk[u].x, T(Gc[u].x) * zk[u].y);
-          continue;
-        }
-        // The gains are formed in FP64 and rounded once to the data precision;
-        // the split and re-pack of the two real spectra run in the data
-        // precision, like the FFTs around them. With g = G/2:
-        //   A' = g_a (Z_k + conj Z_m),  C' = g_c (Z_k - conj Z_m) / i
-        const cx<T> ga = mk<T>(T(0.5 * Ga[u].x), T(0.5 * Ga[u].y));
-        const cx<T> gc = mk<T>(T(0.5 * Gc[u].x), T(0.5 * Gc[u].y));
-        const cx<T> A2 = mk<T>(zk[u].x + zm[u].x, zk[u].y - zm[u].y);
-        const cx<T> C2 = mk<T>(zk[u].y + zm[u].y, zm[u].x - zk[u].x);
-        const cx<T> Ap = cmul(ga, A2), Cp = cmul(gc, C2);
-        // Z'_k = A' + i C',  Z'_{b-k} = conj(A') + i conj(C')
-        *pk = mk<T>(Ap.x - Cp.y, Ap.y + Cp.x);
-        *pm = mk<T>(Ap.x + Cp.y, Cp.x - Ap.y);
-      }
+    for (int i = PRE ? NPRE : 0; i < IMAX; ++i) {
+      const int it = tid / TP + i * IPAR;
+      if (!valid || it >= NI) break;
+      cx<double> Ga, Gc;
+      gains(it, Ga, Gc);
+      // the gains are formed in FP64 and rounded once to the data precision
+      apply(it, mk<T>(T(Ga.x), T(Ga.y)), mk<T>(T(Gc.x), T(Gc.y)));
     }
   }
   __syncthreads();
