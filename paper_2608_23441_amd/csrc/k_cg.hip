@@ -76,6 +76,127 @@ __global__ __launch_bounds__(kCgNT) void k_cg_normal(const T* __restrict__ p, T*
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
+// Row-tiled forms of the two stencils: workgroup g takes rows g, g + G, ...
+// (G = kCgNWG), each row in chunks of kCgCH elements staged in LDS with a
+// halo of HMAX on both sides (wrapped circularly at the row ends), so no
+// element index is ever divided or reduced modulo b except in the halo.
+constexpr int kCgCH = kCgNT * 8;
+constexpr int kCgHMAX = 64;  // ntap - 1 up to this; longer windows use the element-wise kernels
+
+template <typename T>
+__device__ __forceinline__ void cg_stage_row(const T* __restrict__ row, T* tile, int64_t c0, int len, int h,
+                                             int64_t b) {
+  for (int i = threadIdx.x; i < len + 2 * h; i += kCgNT) {
+    int64_t k = c0 + i - h;
+    if (k < 0 || k >= b) {
+      k %= b;
+      if (k < 0) k += b;
+    }
+    tile[i] = row[k];
+  }
+}
+
+// q = (A^T A + lam D) p ; partial sums of p.q. Work items are (row, chunk)
+// pairs; a workgroup fetches its next item's elements into registers while
+// the current one is computed.
+template <typename T>
+__global__ __launch_bounds__(kCgNT) void k_cg_normal_rows(const T* __restrict__ p, T* __restrict__ q,
+                                                          const double* __restrict__ autoc,
+                                                          const T* __restrict__ mask, double lam, int ntap, int64_t b,
+                                                          int64_t nrows, double* __restrict__ part) {
+  constexpr int EPT = kCgCH / kCgNT;
+  __shared__ double sh[kCgNT];
+  __shared__ double tile[kCgCH + 2 * kCgHMAX];  // widened once when staged
+  __shared__ double cs[2 * kCgHMAX + 1];
+  const int tid = threadIdx.x;
+  const int h = ntap - 1, nt = 2 * ntap - 1;
+  const int64_t nch = (b + kCgCH - 1) / kCgCH;
+  const int64_t nw = nrows * nch;
+  T pm[EPT], mm[EPT], ph = T(0);
+  auto fetch = [&](int64_t w) {
+    const int64_t n = w / nch, c0 = (w - n * nch) * kCgCH;
+    const int len = (int)((b - c0) < kCgCH ? (b - c0) : kCgCH);
+    const T* row = p + n * b;
+    const T* mrow = mask + n * b;
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int i = tid + k * kCgNT;
+      pm[k] = i < len ? row[c0 + i] : T(0);
+      mm[k] = i < len ? mrow[c0 + i] : T(0);
+    }
+    if (tid < 2 * h) {  // halo: h elements before the chunk, h after, wrapped at the row ends
+      int64_t pos = tid < h ? c0 - h + tid : c0 + len + (tid - h);
+      if (pos < 0 || pos >= b) {
+        pos %= b;
+        if (pos < 0) pos += b;
+      }
+      ph = row[pos];
+    }
+  };
+  double acc = 0.0;
+  int64_t w = blockIdx.x;
+  if (w < nw) fetch(w);
+  for (; w < nw; w += gridDim.x) {
+    const int64_t n = w / nch, c0 = (w - n * nch) * kCgCH;
+    const int len = (int)((b - c0) < kCgCH ? (b - c0) : kCgCH);
+    double lm[EPT];
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int i = tid + k * kCgNT;
+      if (i < len) tile[h + i] = (double)pm[k];
+      lm[k] = lam * (double)mm[k];
+    }
+    if (tid < 2 * h) tile[tid < h ? tid : len + tid] = (double)ph;
+    for (int t = tid; t < nt; t += kCgNT) cs[t] = autoc[n * nt + t];
+    __syncthreads();
+    if (w + gridDim.x < nw) fetch(w + gridDim.x);  // in flight during the stencil
+#pragma unroll
+    for (int k = 0; k < EPT; ++k) {
+      const int i = tid + k * kCgNT;
+      if (i >= len) continue;
+      double v = 0.0;
+      for (int t = 0; t < nt; ++t) v += cs[t] * tile[i + t];
+      const double pe = tile[i + h];
+      v += lm[k] * pe;
+      const T vt = T(v);
+      q[n * b + c0 + i] = vt;
+      acc += pe * (double)vt;
+    }
+    __syncthreads();  // the next item overwrites the tile
+  }
+  const double tot = block_sum<kCgNT>(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// rhs = A^T d + lam D prior
+template <typename T>
+__global__ __launch_bounds__(kCgNT) void k_cg_rhs_rows(const T* __restrict__ d, T* __restrict__ rhs,
+                                                       const double* __restrict__ win, const T* __restrict__ mask,
+                                                       const T* __restrict__ prior, double lam, int N, int ntap,
+                                                       int64_t b, int64_t nrows) {
+  __shared__ T tile[kCgCH + 2 * kCgHMAX];
+  __shared__ double hs[kCgHMAX + 1];
+  const int h = ntap - 1;
+  for (int64_t n = blockIdx.x; n < nrows; n += gridDim.x) {
+    const T* row = d + n * b;
+    __syncthreads();
+    for (int r = threadIdx.x; r < ntap; r += kCgNT) hs[r] = win[(int64_t)r * N + n];
+    for (int64_t c0 = 0; c0 < b; c0 += kCgCH) {
+      const int len = (int)((b - c0) < kCgCH ? (b - c0) : kCgCH);
+      cg_stage_row(row, tile, c0, len, h, b);
+      __syncthreads();
+      for (int i = threadIdx.x; i < len; i += kCgNT) {
+        double v = 0.0;
+        for (int r = 0; r < ntap; ++r) v += hs[r] * (double)tile[i + h - r];  // d_n[(i - r) mod b]
+        const int64_t e = n * b + c0 + i;
+        v += lam * (double)mask[e] * (double)prior[e];
+        rhs[e] = T(v);
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // rhs = A^T d + lam D prior : (A^T d)_n[i] = sum_r h[rN+n] d_n[(i-r) mod b]
 template <typename T>
 __global__ __launch_bounds__(kCgNT) void k_cg_rhs(const T* __restrict__ d, T* __restrict__ rhs,
@@ -204,15 +325,23 @@ hipError_t launch_cg_autocorr(const double* win64, int N, int ntap, double* auto
 
 hipError_t launch_cg_normal(int prec, const void* p, void* q, const double* autoc, const void* mask, double lam,
                             int ntap, int64_t b, int64_t S, double* part, hipStream_t st) {
-  CG_DISPATCH(prec, (k_cg_normal<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)p, (T*)q, autoc, (const T*)mask, lam, ntap,
-                                                              b, S, part)));
+  if (ntap - 1 <= kCgHMAX && b > 0)
+    CG_DISPATCH(prec, (k_cg_normal_rows<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)p, (T*)q, autoc, (const T*)mask, lam,
+                                                                   ntap, b, S / b, part)));
+  else
+    CG_DISPATCH(prec, (k_cg_normal<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)p, (T*)q, autoc, (const T*)mask, lam,
+                                                              ntap, b, S, part)));
   return hipGetLastError();
 }
 
 hipError_t launch_cg_rhs(int prec, const void* d, void* rhs, const double* win64, const void* mask,
                          const void* prior, double lam, int N, int ntap, int64_t b, int64_t S, hipStream_t st) {
-  CG_DISPATCH(prec, (k_cg_rhs<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)d, (T*)rhs, win64, (const T*)mask,
-                                                           (const T*)prior, lam, N, ntap, b, S)));
+  if (ntap - 1 <= kCgHMAX && b > 0)
+    CG_DISPATCH(prec, (k_cg_rhs_rows<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)d, (T*)rhs, win64, (const T*)mask,
+                                                                (const T*)prior, lam, N, ntap, b, S / b)));
+  else
+    CG_DISPATCH(prec, (k_cg_rhs<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)d, (T*)rhs, win64, (const T*)mask,
+                                                             (const T*)prior, lam, N, ntap, b, S)));
   return hipGetLastError();
 }
 

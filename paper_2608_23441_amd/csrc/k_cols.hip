@@ -71,6 +71,43 @@ __device__ __forceinline__ cx<double> wiener_gain(const GainArgs& ga, int n, int
   return mk<double>(wr * s, wi * s);
 }
 
+// Both gains of a split pair, G_n(k) and G_n(b/2 - k), for 4 taps. With
+// z = e^{-2 pi i k/b}, E = h0 + h2 z^2 and O = h1 z + h3 z^3:
+//   W(k) = E + O,  W(b/2 - k) = conj(E - O)   (z at b/2 - k is -conj z),
+// and the two denominators share one reciprocal.
+template <int B>
+__device__ __forceinline__ void gain_pair4(const GainArgs& ga, int n, int k, const cx<double>* __restrict__ twB64,
+                                           cx<double>& Gk, cx<double>& Gm) {
+  const int N = ga.lblock;
+  const double h0 = ga.win[n], h1 = ga.win[N + n], h2 = ga.win[2 * N + n], h3 = ga.win[3 * N + n];
+  const cx<double> z = twB64[k];
+  const cx<double> z2 = cmul(z, z), z3 = cmul(z2, z);
+  const cx<double> E = mk<double>(h0 + h2 * z2.x, h2 * z2.y);
+  const cx<double> O = mk<double>(h1 * z.x + h3 * z3.x, h1 * z.y + h3 * z3.y);
+  const cx<double> Wk = E + O, Wm = conj(E - O);
+  const double ak = Wk.x * Wk.x + Wk.y * Wk.y, am = Wm.x * Wm.x + Wm.y * Wm.y;
+  if (ga.naive) {  // plain division by conj(W); eigenvalues at rounding level are dropped
+    const double wabs = fabs(h0) + fabs(h1) + fabs(h2) + fabs(h3);
+    const double sk = (sqrt(ak) <= 1e-12 * wabs) ? 0.0 : 1.0 / (ak * (double)B);
+    const double sm = (sqrt(am) <= 1e-12 * wabs) ? 0.0 : 1.0 / (am * (double)B);
+    Gk = mk<double>(Wk.x * sk, Wk.y * sk);
+    Gm = mk<double>(Wm.x * sm, Wm.y * sm);
+    return;
+  }
+  const double dk = ak + ga.phi2, dm = am + ga.phi2;
+  const double den = dk * dm;
+  double rc = __builtin_amdgcn_rcp(den);
+  rc = rc * fma(-den, rc, 2.0);  // one Newton step: ~1 ulp
+  if (ga.precond) {
+    Gk = mk<double>(dm * rc / (double)B, 0.0);
+    Gm = mk<double>(dk * rc / (double)B, 0.0);
+    return;
+  }
+  const double sk = ga.gnorm * dm * rc, sm = ga.gnorm * dk * rc;
+  Gk = mk<double>(Wk.x * sk, Wk.y * sk);
+  Gm = mk<double>(Wm.x * sm, Wm.y * sm);
+}
+
 template <typename T, int LOG2B>
 __global__ __launch_bounds__((ColCfg<T, LOG2B>::NT), (ColCfg<T, LOG2B>::WPE)) void k_col_wiener(
     const T* __restrict__ dT, T* __restrict__ xT, GainArgs ga, const cx<T>* __restrict__ twB,
@@ -119,8 +156,15 @@ __global__ __launch_bounds__((ColCfg<T, LOG2B>::NT), (ColCfg<T, LOG2B>::WPE)) vo
     // X[k] = A/2 - i e B/2 ;  X[H-k] = conj(A)/2 - i conj(e B)/2
     const cx<double> Xk = mk<double>(0.5 * (A.x + eB.y), 0.5 * (A.y - eB.x));
     const cx<double> Xm = mk<double>(0.5 * (A.x - eB.y), 0.5 * (-A.y - eB.x));
-    const cx<double> Yk = cmul(wiener_gain<B>(ga, n, k, twB64), Xk);
-    const cx<double> Ym = cmul(wiener_gain<B>(ga, n, km, twB64), Xm);
+    cx<double> Gk, Gm;
+    if (ga.ntap == 4) {
+      gain_pair4<B>(ga, n, k, twB64, Gk, Gm);
+    } else {
+      Gk = wiener_gain<B>(ga, n, k, twB64);
+      Gm = wiener_gain<B>(ga, n, km, twB64);
+    }
+    const cx<double> Yk = cmul(Gk, Xk);
+    const cx<double> Ym = cmul(Gm, Xm);
     // Z'[k] = P + i conj(e) Q ;  Z'[H-k] = conj(P) + i e conj(Q)
     const cx<double> P = Yk + conj(Ym);
     const cx<double> Q = Yk - conj(Ym);
