@@ -180,6 +180,32 @@ int ipfb_batched_use_graph(ipfb_bplan plan, int on);
 int ipfb_wiener_batched(ipfb_bplan plan, int infmt, const void* const* spec, const float* const* chan_scale,
                         double phi, int normalise, void* const* x_out, void* stream);
 
+/* Shape of the Bluestein column path for the streams whose convolution length
+ * is M = 2^log2m (M the least power of two >= 2 nblock - 1, for nblock not a
+ * power of two): shape = {l1, mb, kb, pchunk}: the four-step split
+ * M = 2^l1 * 2^(log2m - l1) (1 <= l1 <= 8, 1 <= log2m - l1 <= 8), the
+ * column-tile width mb and the row-tile height kb of the FFT passes (8, 16 or
+ * 32), and the column pairs per launch group (0: all lblock/2 at once).
+ * Every valid shape gives the same result up to rounding; they differ in
+ * speed only. Where M1 or M2 is below 32 the tile width 16 is used whatever
+ * mb or kb says. The default is {ceil(log2m/2), 16, 16, 0}. get: IPFB_EINVAL if
+ * the plan has no stream of that length. set: IPFB_EINVAL for an invalid
+ * shape; it waits for the device to go idle (it re-lays the chirp filter
+ * spectra for a new split), so it must not overlap a batched call. */
+int ipfb_batched_get_shape(ipfb_bplan plan, int log2m, int shape[4]);
+int ipfb_batched_set_shape(ipfb_bplan plan, int log2m, const int shape[4]);
+/* Autotuner of the batched form: for each convolution length of the plan, a
+ * coordinate search (split, then kb, then mb, then pchunk) times the column
+ * path of the longest stream of that length on the plan's own scratch buffers
+ * (three timed runs after a warm-up, best kept) and installs the fastest
+ * shape. cache_path (NULL: the IPFB_TUNE_CACHE environment variable; neither:
+ * no cache) names a JSON file of shapes keyed by device, precision, lblock,
+ * ntap and log2m: entries found there are installed without timing (force = 0)
+ * and new results are merged into it. Plan creation installs the cache's
+ * matching entries when IPFB_TUNE_CACHE is set. Synchronous; it overwrites
+ * the plan's scratch buffers and must not overlap a batched call. */
+int ipfb_batched_tune(ipfb_bplan plan, const char* cache_path, int force);
+
 /* Instrumentation: per-kernel timing with HIP events recorded on the
  * launching stream around every kernel group the library enqueues (names:
  * "ipfb_rows", "ipfb_cols_fwd", "ipfb_cols_gain", "ipfb_cols_inv" (the three

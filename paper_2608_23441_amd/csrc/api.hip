@@ -16,6 +16,7 @@
 
 #include "../../include/ipfb.h"
 #include "launch.hpp"
+#include "tune_cache.hpp"
 
 using namespace ipfb;
 
@@ -671,6 +672,7 @@ void host_fft(std::vector<std::complex<double>>& a) {
 
 struct BluTables {  // per distinct nblock b
   int log2m = 0;
+  int crow_l1 = 0;        // split the Crow layout is built for
   void* chirp = nullptr;  // [b] complex, plan precision
   void* Crow = nullptr;   // [M1][M2] complex
   double* twb64 = nullptr;  // [b] complex double
@@ -678,8 +680,7 @@ struct BluTables {  // per distinct nblock b
 };
 
 struct MTables {  // per distinct convolution length M
-  void* buf = nullptr;  // tM1 | tM2 | tLo (256) | tHi (max(1, M/256))
-  const void* tw4[4] = {nullptr, nullptr, nullptr, nullptr};
+  void* buf = nullptr;  // tLo (256) | tHi (max(1, M/256))
 };
 
 }  // namespace
@@ -692,6 +693,10 @@ struct ipfb_bplan_s {
   void* fac = nullptr;
   std::map<int64_t, BluTables> blu;
   std::map<int, MTables> mtab;
+  std::map<int, BluCfg> bcfg;  // per log2m: shape of the Bluestein column path
+  void* pow2tw = nullptr;      // e^{-2 pi i m/2^l} for l = 1..8, table l at offset 2^l - 2
+  double tuned_us = 0.0;       // sum over lengths of the chosen shapes' time (last tune)
+  int64_t blu_maxb = 0;
   void* f0 = nullptr;  // two frame buffers of max_b * lblock reals
   void* f1 = nullptr;
   void* Tm = nullptr;  // Bluestein four-step scratch
@@ -755,20 +760,11 @@ std::vector<double> chirp_table(int64_t b) {
   return t;
 }
 
-int build_blu(ipfb_bplan p, int64_t b) {
-  BluTables bt;
-  if (is_pow2(b) && b >= 4 && ilog2(b) <= max_log2_col(p->prec)) {
-    std::vector<double> tb = twiddles(b);
-    int st = bupload(p, tb, p->prec, &bt.twB);
-    if (!st) st = bupload(p, tb, IPFB_F64, (void**)&bt.twb64);
-    if (st) return st;
-    p->blu[b] = bt;
-    return IPFB_OK;
-  }
-  bt.log2m = blu_log2m(b);
+// Crow[k1][k2] = C[k1 + M1 k2], C = FFT_M of the symmetric chirp filter, for
+// the split M1 = 2^l1 (host, double), re-uploaded into bt.Crow.
+int blu_upload_crow(ipfb_bplan p, int64_t b, BluTables& bt, int l1) {
   const int64_t M = int64_t(1) << bt.log2m;
-  const int l1 = (bt.log2m + 1) / 2, l2 = bt.log2m / 2;
-  const int64_t M1 = int64_t(1) << l1, M2 = int64_t(1) << l2;
+  const int64_t M1 = int64_t(1) << l1, M2 = M / M1;
   std::vector<double> ch = chirp_table(b);
   std::vector<std::complex<double>> c(M, {0.0, 0.0});
   for (int64_t m = 0; m < b; ++m) {
@@ -783,16 +779,49 @@ int build_blu(ipfb_bplan p, int64_t b) {
       crow[2 * (k1 * M2 + k2)] = v.real();
       crow[2 * (k1 * M2 + k2) + 1] = v.imag();
     }
-  int st = bupload(p, ch, p->prec, &bt.chirp);
-  if (!st) st = bupload(p, crow, p->prec, &bt.Crow);
+  int st;
+  if (!bt.Crow) {
+    st = bupload(p, crow, p->prec, &bt.Crow);
+  } else if (p->prec == IPFB_F64) {
+    st = upload(bt.Crow, crow.data(), crow.size() * sizeof(double));
+  } else {
+    std::vector<float> f(crow.begin(), crow.end());
+    st = upload(bt.Crow, f.data(), f.size() * sizeof(float));
+  }
+  if (!st) bt.crow_l1 = l1;
+  return st;
+}
+
+int build_blu(ipfb_bplan p, int64_t b) {
+  BluTables bt;
+  if (is_pow2(b) && b >= 4 && ilog2(b) <= max_log2_col(p->prec)) {
+    std::vector<double> tb = twiddles(b);
+    int st = bupload(p, tb, p->prec, &bt.twB);
+    if (!st) st = bupload(p, tb, IPFB_F64, (void**)&bt.twb64);
+    if (st) return st;
+    p->blu[b] = bt;
+    return IPFB_OK;
+  }
+  bt.log2m = blu_log2m(b);
+  const int64_t M = int64_t(1) << bt.log2m;
+  if (!p->bcfg.count(bt.log2m)) p->bcfg[bt.log2m] = blu_cfg_default(bt.log2m);
+  int st = bupload(p, chirp_table(b), p->prec, &bt.chirp);
+  if (!st) st = blu_upload_crow(p, b, bt, p->bcfg[bt.log2m].l1);
   if (!st) st = bupload(p, twiddles(b), IPFB_F64, (void**)&bt.twb64);
   if (st) return st;
   p->blu[b] = bt;
+  if (!p->pow2tw) {
+    std::vector<double> bank;
+    for (int l = 1; l <= 8; ++l) {
+      std::vector<double> t = twiddles(int64_t(1) << l);
+      bank.insert(bank.end(), t.begin(), t.end());
+    }
+    st = bupload(p, bank, p->prec, &p->pow2tw);
+    if (st) return st;
+  }
   if (!p->mtab.count(bt.log2m)) {
-    std::vector<double> t1 = twiddles(M1), t2 = twiddles(M2), tm = twiddles(M);
+    std::vector<double> tm = twiddles(M);
     std::vector<double> all;
-    all.insert(all.end(), t1.begin(), t1.end());
-    all.insert(all.end(), t2.begin(), t2.end());
     for (int m = 0; m < 256; ++m) {  // w_M^m, m < 256 (periodic in M)
       all.push_back(tm[2 * (m % M)]);
       all.push_back(tm[2 * (m % M) + 1]);
@@ -805,14 +834,169 @@ int build_blu(ipfb_bplan p, int64_t b) {
     MTables mt;
     st = bupload(p, all, p->prec, &mt.buf);
     if (st) return st;
-    const size_t es = 2 * esize(p->prec);
-    const char* base = (const char*)mt.buf;
-    mt.tw4[0] = base;
-    mt.tw4[1] = base + M1 * es;
-    mt.tw4[2] = base + (M1 + M2) * es;
-    mt.tw4[3] = base + (M1 + M2 + 256) * es;
     p->mtab[bt.log2m] = mt;
   }
+  return IPFB_OK;
+}
+
+// The four twiddle tables of the Bluestein kernels for length 2^log2m split at l1.
+void blu_tw4(ipfb_bplan p, int log2m, int l1, const void* tw4[4]) {
+  const size_t es = 2 * esize(p->prec);
+  const char* bank = (const char*)p->pow2tw;
+  const int l2 = log2m - l1;
+  tw4[0] = bank + ((size_t(1) << l1) - 2) * es;
+  tw4[1] = bank + ((size_t(1) << l2) - 2) * es;
+  tw4[2] = p->mtab[log2m].buf;
+  tw4[3] = (const char*)p->mtab[log2m].buf + 256 * es;
+}
+
+// Makes cfg the shape used for length 2^log2m (re-laying Crow of every
+// stream of that length for a new split); drops the captured graph.
+int blu_apply_cfg(ipfb_bplan p, int log2m, const BluCfg& cfg) {
+  if (!blu_cfg_valid(log2m, cfg)) return fail(IPFB_EINVAL, "invalid Bluestein shape for 2^%d", log2m);
+  if (hipDeviceSynchronize() != hipSuccess) {  // no call in flight may read a Crow being re-laid
+    hipGetLastError();
+    return fail(IPFB_EHIP, "hipDeviceSynchronize failed");
+  }
+  for (auto& kv : p->blu) {
+    if (kv.second.log2m != log2m || kv.second.crow_l1 == cfg.l1) continue;
+    int st = blu_upload_crow(p, kv.first, kv.second, cfg.l1);
+    if (st) return st;
+  }
+  p->bcfg[log2m] = cfg;
+  if (p->exec) {
+    hipGraphExecDestroy(p->exec);
+    p->exec = nullptr;
+  }
+  p->key.clear();
+  return IPFB_OK;
+}
+
+// ---- autotuner ---------------------------------------------------------------
+std::string tune_key(ipfb_bplan p, int log2m) {
+  hipDeviceProp_t prop;
+  std::string arch = "gpu";
+  int cus = 0;
+  if (hipGetDeviceProperties(&prop, p->dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    cus = prop.multiProcessorCount;
+  } else {
+    hipGetLastError();
+  }
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s:%dcu|%s|N%d|T%d|m%d", arch.c_str(), cus, p->prec == IPFB_F64 ? "f64" : "f32",
+           p->lblock, p->ntap, log2m);
+  return buf;
+}
+
+// Loads the entries of the cache file that match this plan's lengths.
+int tune_load(ipfb_bplan p, const std::string& path) {
+  std::map<std::string, TuneEntry> ent;
+  if (!tune_cache_read(path, ent)) return fail(IPFB_EINVAL, "tune cache %s does not parse", path.c_str());
+  for (auto& kv : p->bcfg) {
+    auto it = ent.find(tune_key(p, kv.first));
+    if (it == ent.end()) continue;
+    BluCfg c;
+    c.l1 = it->second.l1;
+    c.mb = it->second.mb;
+    c.kb = it->second.kb;
+    c.pchunk = it->second.pchunk;
+    if (!blu_cfg_valid(kv.first, c)) continue;  // stale entry: keep the current shape
+    int st = blu_apply_cfg(p, kv.first, c);
+    if (st) return st;
+  }
+  return IPFB_OK;
+}
+
+// Best of three timed runs (after one warm-up) of the Bluestein column path
+// for stream length b under shape cfg, on the plan's own buffers.
+int blu_time(ipfb_bplan p, int64_t b, const BluCfg& cfg, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+             double* us) {
+  BluTables& bt = p->blu[b];
+  if (bt.crow_l1 != cfg.l1) {
+    int s2 = blu_upload_crow(p, b, bt, cfg.l1);
+    if (s2) return s2;
+  }
+  const void* tw4[4];
+  blu_tw4(p, bt.log2m, cfg.l1, tw4);
+  double best = 1e300;
+  for (int r = 0; r < 4; ++r) {
+    hipError_t e = hipEventRecord(e0, st);
+    if (e == hipSuccess)
+      e = launch_blu_columns(p->prec, p->f1, p->f0, p->Tm, p->f0, p->f1, bt.chirp, bt.Crow, bt.twb64, b, bt.log2m,
+                             cfg, p->lblock, p->ntap, p->win64, 0.1, 1, tw4, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      hipGetLastError();
+      return fail(IPFB_EHIP, "autotuner run failed: %s", hipGetErrorString(e));
+    }
+    if (r > 0 && ms * 1e3 < best) best = ms * 1e3;
+  }
+  *us = best;
+  return IPFB_OK;
+}
+
+// Coordinate search per convolution length: split, then B tile, then A tile,
+// then pairs per launch group; each stage keeps the fastest candidate.
+int tune_length(ipfb_bplan p, int log2m, BluCfg* out, double* out_us) {
+  int64_t b = 0;  // the longest stream of this length stands for all of them
+  for (auto& kv : p->blu)
+    if (kv.second.log2m == log2m && kv.first > b) b = kv.first;
+  if (b == 0) return fail(IPFB_EINVAL, "no stream of convolution length 2^%d", log2m);
+  hipStream_t st = p->cap;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    hipGetLastError();
+    if (e0) hipEventDestroy(e0);
+    return fail(IPFB_EHIP, "hipEventCreate failed");
+  }
+  BluCfg best = blu_cfg_default(log2m);
+  double best_us = 0.0;
+  int st2 = blu_time(p, b, best, st, e0, e1, &best_us);
+  auto trial = [&](BluCfg c) {
+    if (st2 || !blu_cfg_valid(log2m, c)) return;
+    double us = 0.0;
+    st2 = blu_time(p, b, c, st, e0, e1, &us);
+    if (!st2 && us < best_us) {
+      best = c;
+      best_us = us;
+    }
+  };
+  const int d = (log2m + 1) / 2;
+  for (int l1 : {d - 1, d + 1}) {
+    BluCfg c = best;
+    c.l1 = l1;
+    trial(c);
+  }
+  const BluCfg after_split = best;
+  for (int kb : {8, 32}) {
+    BluCfg c = after_split;
+    c.kb = kb;
+    trial(c);
+  }
+  const BluCfg after_kb = best;
+  for (int mb : {8, 32}) {
+    BluCfg c = after_kb;
+    c.mb = mb;
+    trial(c);
+  }
+  const BluCfg after_mb = best;
+  const int npairs = (p->lblock + 1) / 2;
+  for (int pc : {512, 256, 128, 64}) {
+    if (pc >= npairs) continue;
+    BluCfg c = after_mb;
+    c.pchunk = pc;
+    trial(c);
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st2) return st2;
+  *out = best;
+  *out_us = best_us;
   return IPFB_OK;
 }
 
@@ -846,9 +1030,11 @@ hipError_t enqueue_batched(ipfb_bplan p, int infmt, const void* const* spec, con
     // Bluestein: d -> d_T in f1; Z in f0, A in f1 (d_T consumed by then), x_T in f0
     e = launch_transpose(p->prec, p->f0, p->f1, b, N, st);
     if (e != hipSuccess) break;
-    const MTables& mt = p->mtab[bt.log2m];
-    e = launch_blu_columns(p->prec, p->f1, p->f0, p->Tm, p->f0, p->f1, bt.chirp, bt.Crow, bt.twb64, b, bt.log2m, N,
-                           p->ntap, p->win64, phi, normalise, mt.tw4, st);
+    const BluCfg& cfg = p->bcfg[bt.log2m];
+    const void* tw4[4];
+    blu_tw4(p, bt.log2m, cfg.l1, tw4);
+    e = launch_blu_columns(p->prec, p->f1, p->f0, p->Tm, p->f0, p->f1, bt.chirp, bt.Crow, bt.twb64, b, bt.log2m, cfg,
+                           N, p->ntap, p->win64, phi, normalise, tw4, st);
     if (e == hipSuccess) e = launch_transpose(p->prec, p->f0, xo[s], N, b, st);  // x_T -> x (time order)
   }
   return e;
@@ -897,12 +1083,16 @@ int ipfb_batched_plan_create(ipfb_bplan* out, int lblock, int ntap, const double
       st = build_blu(p, nblock[s]);
       if (!st && p->blu[nblock[s]].log2m > maxlog2m) maxlog2m = p->blu[nblock[s]].log2m;
     }
+  p->blu_maxb = maxb;
   const size_t fb = (size_t)maxb * lblock * esize(prec);
   if (!st) st = balloc(p, &p->f0, fb);
   if (!st) st = balloc(p, &p->f1, fb);
   if (!st && maxlog2m > 0)
     st = balloc(p, &p->Tm, (size_t)((lblock + 1) / 2) * ((size_t)1 << maxlog2m) * 2 * esize(prec));
   (void)M;
+  // shapes tuned earlier for this device and problem
+  const char* cache = getenv("IPFB_TUNE_CACHE");
+  if (!st && cache && *cache) st = tune_load(p, cache);
   // prime the row kernel's occupancy query outside any later graph capture
   if (!st && launch_row_c4(prec, p->log2n, nullptr, nullptr, nullptr, 0, nullptr, nullptr) != hipSuccess)
     hipGetLastError();
@@ -924,6 +1114,89 @@ int ipfb_batched_plan_destroy(ipfb_bplan p) {
   if (!p) return fail(IPFB_EINVAL, "plan is NULL");
   DeviceGuard g(p->dev);
   free_bplan(p);
+  return ok();
+}
+
+int ipfb_batched_get_shape(ipfb_bplan p, int log2m, int shape[4]) {
+  if (!p || !shape) return fail(IPFB_EINVAL, "NULL argument");
+  auto it = p->bcfg.find(log2m);
+  if (it == p->bcfg.end()) return fail(IPFB_EINVAL, "the plan has no stream of convolution length 2^%d", log2m);
+  shape[0] = it->second.l1;
+  shape[1] = it->second.mb;
+  shape[2] = it->second.kb;
+  shape[3] = it->second.pchunk;
+  return ok();
+}
+
+int ipfb_batched_set_shape(ipfb_bplan p, int log2m, const int shape[4]) {
+  if (!p || !shape) return fail(IPFB_EINVAL, "NULL argument");
+  if (!p->bcfg.count(log2m)) return fail(IPFB_EINVAL, "the plan has no stream of convolution length 2^%d", log2m);
+  BluCfg c;
+  c.l1 = shape[0];
+  c.mb = shape[1];
+  c.kb = shape[2];
+  c.pchunk = shape[3];
+  DeviceGuard g(p->dev);
+  int st = blu_apply_cfg(p, log2m, c);
+  return st ? st : ok();
+}
+
+int ipfb_batched_tune(ipfb_bplan p, const char* cache_path, int force) {
+  if (!p) return fail(IPFB_EINVAL, "plan is NULL");
+  DeviceGuard g(p->dev);
+  if (hipDeviceSynchronize() != hipSuccess) {
+    hipGetLastError();
+    return fail(IPFB_EHIP, "hipDeviceSynchronize failed");
+  }
+  std::string path = cache_path ? cache_path : "";
+  if (path.empty()) {
+    const char* env = getenv("IPFB_TUNE_CACHE");
+    if (env) path = env;
+  }
+  std::map<std::string, TuneEntry> have;
+  if (!path.empty() && !force && !tune_cache_read(path, have)) have.clear();  // unparsable: tune afresh
+  std::map<std::string, TuneEntry> fresh;
+  double total = 0.0;
+  std::vector<int> lengths;
+  for (auto& kv : p->bcfg) lengths.push_back(kv.first);
+  if (!lengths.empty() && hipMemset(p->f0, 0, (size_t)p->blu_maxb * p->lblock * esize(p->prec)) != hipSuccess) {
+    hipGetLastError();
+    return fail(IPFB_EHIP, "hipMemset failed");
+  }
+  if (!lengths.empty() && hipMemset(p->f1, 0, (size_t)p->blu_maxb * p->lblock * esize(p->prec)) != hipSuccess) {
+    hipGetLastError();
+    return fail(IPFB_EHIP, "hipMemset failed");
+  }
+  for (int log2m : lengths) {
+    const std::string key = tune_key(p, log2m);
+    auto it = have.find(key);
+    BluCfg c;
+    double us = 0.0;
+    if (it != have.end()) {
+      c.l1 = it->second.l1;
+      c.mb = it->second.mb;
+      c.kb = it->second.kb;
+      c.pchunk = it->second.pchunk;
+      us = it->second.us;
+    }
+    if (it == have.end() || !blu_cfg_valid(log2m, c)) {
+      int st = tune_length(p, log2m, &c, &us);
+      if (st) return st;
+      TuneEntry t;
+      t.l1 = c.l1;
+      t.mb = c.mb;
+      t.kb = c.kb;
+      t.pchunk = c.pchunk;
+      t.us = us;
+      fresh[key] = t;
+    }
+    int st = blu_apply_cfg(p, log2m, c);
+    if (st) return st;
+    total += us;
+  }
+  p->tuned_us = total;
+  if (!path.empty() && !fresh.empty() && !tune_cache_write(path, fresh))
+    return fail(IPFB_EINVAL, "cannot write the tune cache %s", path.c_str());
   return ok();
 }
 

@@ -18,6 +18,12 @@
 // Between the two convolutions one kernel splits the two real spectra, applies
 // the FP64 Wiener gain of Section 4.1 and re-packs them (it needs X_k and
 // X_{b-k}, which the four-step places far apart).
+// Tunables (picked per convolution length by the batched plan's autotuner):
+// the split M1 = 2^l1, the tile widths MB (columns per A/A' block) and KB (rows
+// per B block), and the number of pairs per launch group (the four-step
+// scratch of one group stays in the last-level cache when the group is small).
+// The factor w_M^m = tHi[m >> 8] tLo[m & 255] comes from LDS copies of both
+// tables (M <= 2^16, so tHi has at most 256 entries).
 #include "fft_lds.hpp"
 #include "launch.hpp"
 
@@ -30,32 +36,51 @@ struct BluTw {  // all e^{-2 pi i m / len} in the data precision
   const void* tHi;   // [M/256] w_M^{256 (m >> 8)}
 };
 
+constexpr int kBluMaxLog2M = 16;
+
 template <typename T>
 __device__ __forceinline__ cx<T> blu_twM(const cx<T>* lo, const cx<T>* hi, int m) {
   return cmul(hi[m >> 8], lo[m & 255]);
 }
 
-template <int LOG2M1>
+// LDS copies of tLo [256] and tHi [M/256]
+template <typename T, int NT>
+__device__ __forceinline__ void blu_tw_lds(cx<T>* lo, cx<T>* hi, const BluTw& tw, int M) {
+  const cx<T>* glo = reinterpret_cast<const cx<T>*>(tw.tLo);
+  const cx<T>* ghi = reinterpret_cast<const cx<T>*>(tw.tHi);
+  const int nhi = M >> 8;
+  for (int i = threadIdx.x; i < 256; i += NT) {
+    lo[i] = glo[i];
+    if (i < nhi) hi[i] = ghi[i];
+  }
+  if (nhi == 0 && threadIdx.x == 0) hi[0] = ghi[0];
+}
+
+template <int LOG2M1, int MB_>
 struct BluACfg {
   static constexpr int M1 = 1 << LOG2M1;
-  static constexpr int MB = 16;
+  static constexpr int MB = MB_;
   static constexpr int LS = lds_len(M1);
   static constexpr int NT0 = (M1 * MB) / 8;
   static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 512 ? 512 : NT0);
 };
 
-// MODE 0: input = real pair from x_T [N][b] times conj(chirp); MODE 1: input = complex a [pair][b]
-template <typename T, int LOG2M1, int MODE>
-__global__ __launch_bounds__((BluACfg<LOG2M1>::NT)) void k_blu_A(
+// MODE 0: input = real pair from x_T [N][b] times conj(chirp); MODE 1: input = complex a [pair][b].
+// Pairs pair0 + blockIdx.x / (M2 / MB); Tm holds the launch group's pairs only.
+template <typename T, int LOG2M1, int MB_, int MODE>
+__global__ __launch_bounds__((BluACfg<LOG2M1, MB_>::NT)) void k_blu_A(
     const void* __restrict__ in, cx<T>* __restrict__ Tm, const cx<T>* __restrict__ chirp, int64_t b, int M2,
-    int N, BluTw tw) {
-  using Cfg = BluACfg<LOG2M1>;
+    int N, int64_t pair0, BluTw tw) {
+  using Cfg = BluACfg<LOG2M1, MB_>;
   constexpr int M1 = Cfg::M1, LS = Cfg::LS, NT = Cfg::NT;
   constexpr int MB = Cfg::MB;
   __shared__ cx<T> s[MB * LS];
+  __shared__ cx<T> tlo[256], thi[256];
+  const int M = M1 * M2;
+  blu_tw_lds<T, NT>(tlo, thi, tw, M);
   const int mb_eff = M2 < MB ? M2 : MB;
   const int nblk = M2 / mb_eff;
-  const int64_t pair = blockIdx.x / nblk;
+  const int64_t lpair = blockIdx.x / nblk, pair = pair0 + lpair;
   const int j20 = (blockIdx.x % nblk) * mb_eff;
   for (int e = threadIdx.x; e < M1 * MB; e += NT) {
     const int mb = e % MB, j1 = e / MB;
@@ -76,39 +101,38 @@ __global__ __launch_bounds__((BluACfg<LOG2M1>::NT)) void k_blu_A(
   }
   __syncthreads();
   lds_fft<T, M1, NT, MB, -1>(s, LS, reinterpret_cast<const cx<T>*>(tw.tM1), 1);
-  const int M = M1 * M2;
-  cx<T>* tp = Tm + pair * (int64_t)M;
-  const cx<T>* lo = reinterpret_cast<const cx<T>*>(tw.tLo);
-  const cx<T>* hi = reinterpret_cast<const cx<T>*>(tw.tHi);
+  cx<T>* tp = Tm + lpair * (int64_t)M;
   for (int e = threadIdx.x; e < M1 * MB; e += NT) {
     const int mb = e % MB, k1 = e / MB;
     if (mb >= mb_eff) continue;
     const int j2 = j20 + mb;
-    tp[(int64_t)k1 * M2 + j2] = cmul(s[mb * LS + pidx(k1)], blu_twM(lo, hi, j2 * k1));
+    tp[(int64_t)k1 * M2 + j2] = cmul(s[mb * LS + pidx(k1)], blu_twM(tlo, thi, j2 * k1));
   }
 }
 
-template <int LOG2M2>
+template <int LOG2M2, int KB_>
 struct BluBCfg {
   static constexpr int M2 = 1 << LOG2M2;
-  static constexpr int KB = 16;
+  static constexpr int KB = KB_;
   static constexpr int LS = lds_len(M2);
   static constexpr int NT0 = (M2 * KB) / 8;
   static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 512 ? 512 : NT0);
 };
 
-template <typename T, int LOG2M2>
-__global__ __launch_bounds__((BluBCfg<LOG2M2>::NT)) void k_blu_B(cx<T>* __restrict__ Tm,
-                                                                 const cx<T>* __restrict__ Crow, int conjC,
-                                                                 int M1, BluTw tw) {
-  using Cfg = BluBCfg<LOG2M2>;
+template <typename T, int LOG2M2, int KB_>
+__global__ __launch_bounds__((BluBCfg<LOG2M2, KB_>::NT)) void k_blu_B(cx<T>* __restrict__ Tm,
+                                                                      const cx<T>* __restrict__ Crow, int conjC,
+                                                                      int M1, BluTw tw) {
+  using Cfg = BluBCfg<LOG2M2, KB_>;
   constexpr int M2 = Cfg::M2, LS = Cfg::LS, NT = Cfg::NT, KB = Cfg::KB;
   __shared__ cx<T> s[KB * LS];
+  __shared__ cx<T> tlo[256], thi[256];
+  const int M = M1 * M2;
+  blu_tw_lds<T, NT>(tlo, thi, tw, M);
   const int kb_eff = M1 < KB ? M1 : KB;
   const int nblk = M1 / kb_eff;
   const int64_t pair = blockIdx.x / nblk;
   const int k10 = (blockIdx.x % nblk) * kb_eff;
-  const int M = M1 * M2;
   cx<T>* tp = Tm + pair * (int64_t)M;
   for (int e = threadIdx.x; e < KB * M2; e += NT) {
     const int r = e / M2, c = e % M2;
@@ -128,32 +152,30 @@ __global__ __launch_bounds__((BluBCfg<LOG2M2>::NT)) void k_blu_B(cx<T>* __restri
   }
   __syncthreads();
   lds_fft<T, M2, NT, KB, +1>(s, LS, tM2, 1);
-  const cx<T>* lo = reinterpret_cast<const cx<T>*>(tw.tLo);
-  const cx<T>* hi = reinterpret_cast<const cx<T>*>(tw.tHi);
   for (int e = threadIdx.x; e < KB * M2; e += NT) {
     const int r = e / M2, j2 = e % M2;
     if (r >= kb_eff) continue;
     const int k1 = k10 + r;
-    tp[(int64_t)k1 * M2 + j2] = cmulc(s[r * LS + pidx(j2)], blu_twM(lo, hi, j2 * k1));
+    tp[(int64_t)k1 * M2 + j2] = cmulc(s[r * LS + pidx(j2)], blu_twM(tlo, thi, j2 * k1));
   }
 }
 
 // MODE 0: Z[pair][j] = conj(c_j) conv_j / M (the b-point DFT); MODE 1: output
 // the pair of real columns  x_T[n][j] + i x_T[n+1][j] = c_j conv_j / (M b)
-template <typename T, int LOG2M1, int MODE>
-__global__ __launch_bounds__((BluACfg<LOG2M1>::NT)) void k_blu_Ainv(
+template <typename T, int LOG2M1, int MB_, int MODE>
+__global__ __launch_bounds__((BluACfg<LOG2M1, MB_>::NT)) void k_blu_Ainv(
     const cx<T>* __restrict__ Tm, void* __restrict__ out, const cx<T>* __restrict__ chirp, int64_t b, int M2,
-    int N, BluTw tw) {
-  using Cfg = BluACfg<LOG2M1>;
+    int N, int64_t pair0, BluTw tw) {
+  using Cfg = BluACfg<LOG2M1, MB_>;
   constexpr int M1 = Cfg::M1, LS = Cfg::LS, NT = Cfg::NT;
   constexpr int MB = Cfg::MB;
   __shared__ cx<T> s[MB * LS];
   const int mb_eff = M2 < MB ? M2 : MB;
   const int nblk = M2 / mb_eff;
-  const int64_t pair = blockIdx.x / nblk;
+  const int64_t lpair = blockIdx.x / nblk, pair = pair0 + lpair;
   const int j20 = (blockIdx.x % nblk) * mb_eff;
   const int M = M1 * M2;
-  const cx<T>* tp = Tm + pair * (int64_t)M;
+  const cx<T>* tp = Tm + lpair * (int64_t)M;
   for (int e = threadIdx.x; e < M1 * MB; e += NT) {
     const int mb = e % MB, k1 = e / MB;
     cx<T> v = mk<T>(T(0), T(0));
@@ -213,14 +235,72 @@ __device__ __forceinline__ cx<double> blu_gain(const BluGain& g, int n, const cx
   return mk<double>(wr * s, wi * s);
 }
 
+// Gains of paths n and n+1 (4 taps each) at one frequency: W as a cubic in
+// z = e^{-2 pi i k/b}, the two denominators sharing one reciprocal.
+__device__ __forceinline__ void blu_gain_pair4(const BluGain& g, int n, bool has1, cx<double> z, cx<double>& Ga,
+                                               cx<double>& Gc) {
+  const int N = g.N;
+  const double a0 = g.win[n], a1 = g.win[N + n], a2 = g.win[2 * N + n], a3 = g.win[3 * N + n];
+  const int m = has1 ? n + 1 : n;
+  const double c0 = g.win[m], c1 = g.win[N + m], c2 = g.win[2 * N + m], c3 = g.win[3 * N + m];
+  const cx<double> z2 = cmul(z, z), z3 = cmul(z2, z);
+  const cx<double> Wa = mk<double>(a0 + a1 * z.x + a2 * z2.x + a3 * z3.x, a1 * z.y + a2 * z2.y + a3 * z3.y);
+  const cx<double> Wc = mk<double>(c0 + c1 * z.x + c2 * z2.x + c3 * z3.x, c1 * z.y + c2 * z2.y + c3 * z3.y);
+  const double aa = Wa.x * Wa.x + Wa.y * Wa.y, ac = Wc.x * Wc.x + Wc.y * Wc.y;
+  if (g.naive) {
+    const double wa = fabs(a0) + fabs(a1) + fabs(a2) + fabs(a3), wc = fabs(c0) + fabs(c1) + fabs(c2) + fabs(c3);
+    const double sa = (sqrt(aa) <= 1e-12 * wa) ? 0.0 : 1.0 / aa;
+    const double sc = (sqrt(ac) <= 1e-12 * wc) ? 0.0 : 1.0 / ac;
+    Ga = mk<double>(Wa.x * sa, Wa.y * sa);
+    Gc = mk<double>(Wc.x * sc, Wc.y * sc);
+    return;
+  }
+  const double da = aa + g.phi2, dc = ac + g.phi2;
+  const double den = da * dc;
+  double rc = __builtin_amdgcn_rcp(den);
+  rc = rc * fma(-den, rc, 2.0);  // one Newton step: ~1 ulp
+  const double sa = g.gnorm * dc * rc, sc = g.gnorm * da * rc;
+  Ga = mk<double>(Wa.x * sa, Wa.y * sa);
+  Gc = mk<double>(Wc.x * sc, Wc.y * sc);
+}
+
+// one pair (pair0 + blockIdx.y) per grid row, frequencies k = blockIdx.x * 256 + tid (grid-strided)
+template <typename T>
+__global__ __launch_bounds__(256) void k_blu_gain2(const cx<T>* __restrict__ Z, cx<T>* __restrict__ a,
+                                                   const cx<T>* __restrict__ chirp,
+                                                   const cx<double>* __restrict__ twb64, int64_t b, int64_t pair0,
+                                                   BluGain g) {
+  const int64_t pair = pair0 + blockIdx.y;
+  const int n = (int)(2 * pair);
+  const bool has1 = n + 1 < g.N;
+  const cx<T>* zp = Z + pair * b;
+  cx<T>* ap = a + pair * b;
+  for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < b; k += (int64_t)gridDim.x * 256) {
+    const int64_t km = (k == 0) ? 0 : b - k;
+    const cx<T> zk = zp[k], zm = zp[km];
+    const cx<double> Zk = mk<double>(zk.x, zk.y), Zm = mk<double>(zm.x, -zm.y);  // conj Z_{b-k}
+    const cx<double> X1 = mk<double>(0.5 * (Zk.x + Zm.x), 0.5 * (Zk.y + Zm.y));
+    const cx<double> D = mk<double>(0.5 * (Zk.x - Zm.x), 0.5 * (Zk.y - Zm.y));
+    const cx<double> X2 = mk<double>(D.y, -D.x);  // D / i
+    cx<double> Ga, Gc;
+    blu_gain_pair4(g, n, has1, twb64[k], Ga, Gc);
+    const cx<double> Y1 = cmul(Ga, X1);
+    const cx<double> Y2 = has1 ? cmul(Gc, X2) : mk<double>(0.0, 0.0);
+    const cx<double> zo = mk<double>(Y1.x - Y2.y, Y1.y + Y2.x);  // Y1 + i Y2
+    const cx<T> c = chirp[k];
+    const cx<double> out = cmul(zo, mk<double>(c.x, c.y));
+    ap[k] = mk<T>(T(out.x), T(out.y));
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_blu_gain(const cx<T>* __restrict__ Z, cx<T>* __restrict__ a,
                                                   const cx<T>* __restrict__ chirp,
-                                                  const cx<double>* __restrict__ twb64, int64_t b, int64_t npairs,
-                                                  BluGain g) {
+                                                  const cx<double>* __restrict__ twb64, int64_t b, int64_t pair0,
+                                                  int64_t npairs, BluGain g) {
   const int64_t total = npairs * b;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    const int64_t pair = e / b, k = e - pair * b;
+    const int64_t lp = e / b, k = e - lp * b, pair = pair0 + lp;
     const int64_t km = (k == 0) ? 0 : b - k;
     const cx<T> zk = Z[pair * b + k], zm = Z[pair * b + km];
     const cx<double> Zk = mk<double>(zk.x, zk.y), Zm = mk<double>(zm.x, -zm.y);  // conj Z_{b-k}
@@ -239,80 +319,160 @@ __global__ __launch_bounds__(256) void k_blu_gain(const cx<T>* __restrict__ Z, c
 }
 
 // ---- launchers ---------------------------------------------------------------
-template <typename T, int L1>
+// Tile widths other than 16 exist for M1, M2 >= 2^kBluTileMinLog2 only.
+constexpr int kBluTileMinLog2 = 5;
+
+template <typename T, int L1, int MB>
 static hipError_t launch_blu_A_t(int mode, const void* in, void* Tm, const void* chirp, int64_t b, int M2, int N,
-                                 int64_t npairs, const BluTw& tw, hipStream_t st) {
-  using Cfg = BluACfg<L1>;
+                                 int64_t pair0, int64_t npairs, const BluTw& tw, hipStream_t st) {
+  using Cfg = BluACfg<L1, MB>;
   const int mb_eff = M2 < Cfg::MB ? M2 : Cfg::MB;
   const dim3 grid((unsigned)(npairs * (M2 / mb_eff)));
   if (mode == 0)
-    k_blu_A<T, L1, 0><<<grid, Cfg::NT, 0, st>>>(in, (cx<T>*)Tm, (const cx<T>*)chirp, b, M2, N, tw);
+    k_blu_A<T, L1, MB, 0><<<grid, Cfg::NT, 0, st>>>(in, (cx<T>*)Tm, (const cx<T>*)chirp, b, M2, N, pair0, tw);
   else
-    k_blu_A<T, L1, 1><<<grid, Cfg::NT, 0, st>>>(in, (cx<T>*)Tm, (const cx<T>*)chirp, b, M2, N, tw);
+    k_blu_A<T, L1, MB, 1><<<grid, Cfg::NT, 0, st>>>(in, (cx<T>*)Tm, (const cx<T>*)chirp, b, M2, N, pair0, tw);
   return hipGetLastError();
 }
 
-template <typename T, int L1>
+template <typename T, int L1, int MB>
 static hipError_t launch_blu_Ainv_t(int mode, const void* Tm, void* out, const void* chirp, int64_t b, int M2,
-                                    int N, int64_t npairs, const BluTw& tw, hipStream_t st) {
-  using Cfg = BluACfg<L1>;
+                                    int N, int64_t pair0, int64_t npairs, const BluTw& tw, hipStream_t st) {
+  using Cfg = BluACfg<L1, MB>;
   const int mb_eff = M2 < Cfg::MB ? M2 : Cfg::MB;
   const dim3 grid((unsigned)(npairs * (M2 / mb_eff)));
   if (mode == 0)
-    k_blu_Ainv<T, L1, 0><<<grid, Cfg::NT, 0, st>>>((const cx<T>*)Tm, out, (const cx<T>*)chirp, b, M2, N, tw);
+    k_blu_Ainv<T, L1, MB, 0><<<grid, Cfg::NT, 0, st>>>((const cx<T>*)Tm, out, (const cx<T>*)chirp, b, M2, N, pair0,
+                                                       tw);
   else
-    k_blu_Ainv<T, L1, 1><<<grid, Cfg::NT, 0, st>>>((const cx<T>*)Tm, out, (const cx<T>*)chirp, b, M2, N, tw);
+    k_blu_Ainv<T, L1, MB, 1><<<grid, Cfg::NT, 0, st>>>((const cx<T>*)Tm, out, (const cx<T>*)chirp, b, M2, N, pair0,
+                                                       tw);
   return hipGetLastError();
+}
+
+template <typename T, int L2, int KB>
+static hipError_t launch_blu_B_t(void* Tm, const void* Crow, int conjC, int M1, int64_t npairs, const BluTw& tw,
+                                 hipStream_t st) {
+  using Cfg = BluBCfg<L2, KB>;
+  const int kb_eff = M1 < Cfg::KB ? M1 : Cfg::KB;
+  const dim3 grid((unsigned)(npairs * (M1 / kb_eff)));
+  k_blu_B<T, L2, KB><<<grid, Cfg::NT, 0, st>>>((cx<T>*)Tm, (const cx<T>*)Crow, conjC, M1, tw);
+  return hipGetLastError();
+}
+
+// One A (fwd = 1) or A' (fwd = 0) launch with tile width mb.
+template <typename T, int L1>
+static hipError_t blu_col_pass(int fwd, int mb, int mode, const void* in, void* out, const void* chirp, int64_t b,
+                               int M2, int N, int64_t pair0, int64_t npairs, const BluTw& tw, hipStream_t st) {
+  if (L1 < kBluTileMinLog2) mb = 16;
+  switch (mb) {
+#define BLU_CASE(MB)                                                                                          \
+  case MB:                                                                                                   \
+    return fwd ? launch_blu_A_t<T, L1, (L1 < kBluTileMinLog2 ? 16 : MB)>(mode, in, out, chirp, b, M2, N,     \
+                                                                         pair0, npairs, tw, st)              \
+               : launch_blu_Ainv_t<T, L1, (L1 < kBluTileMinLog2 ? 16 : MB)>(mode, in, out, chirp, b, M2, N,  \
+                                                                            pair0, npairs, tw, st);
+    BLU_CASE(8) BLU_CASE(16) BLU_CASE(32)
+#undef BLU_CASE
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename T, int L2>
-static hipError_t launch_blu_B_t(void* Tm, const void* Crow, int conjC, int M1, int64_t npairs, const BluTw& tw,
-                                 hipStream_t st) {
-  using Cfg = BluBCfg<L2>;
-  const int kb_eff = M1 < Cfg::KB ? M1 : Cfg::KB;
-  const dim3 grid((unsigned)(npairs * (M1 / kb_eff)));
-  k_blu_B<T, L2><<<grid, Cfg::NT, 0, st>>>((cx<T>*)Tm, (const cx<T>*)Crow, conjC, M1, tw);
-  return hipGetLastError();
+static hipError_t blu_row_pass(int kb, void* Tm, const void* Crow, int conjC, int M1, int64_t npairs,
+                               const BluTw& tw, hipStream_t st) {
+  if (L2 < kBluTileMinLog2) kb = 16;
+  switch (kb) {
+#define BLU_CASE(KB) \
+  case KB: return launch_blu_B_t<T, L2, (L2 < kBluTileMinLog2 ? 16 : KB)>(Tm, Crow, conjC, M1, npairs, tw, st);
+    BLU_CASE(8) BLU_CASE(16) BLU_CASE(32)
+#undef BLU_CASE
+    default: return hipErrorInvalidValue;
+  }
 }
 
-#define BLU_L1_SWITCH(CALL)                                 \
-  switch (l1) {                                             \
+#define BLU_L_SWITCH(L, CALL)                               \
+  switch (L) {                                              \
     case 1: CALL(1) case 2: CALL(2) case 3: CALL(3)         \
     case 4: CALL(4) case 5: CALL(5) case 6: CALL(6)         \
     case 7: CALL(7) case 8: CALL(8)                         \
     default: return hipErrorInvalidValue;                   \
   }
 
+// One cyclic convolution of length M = 2^l1 * 2^(log2m - l1) for pairs [pair0, pair0 + npairs).
 template <typename T>
 static hipError_t blu_conv(int in_mode, const void* in, int out_mode, void* out, void* Tm, const void* chirp,
-                           const void* Crow, int conjC, int64_t b, int log2m, int N, int64_t npairs,
-                           const BluTw& tw, hipStream_t st) {
-  const int l1 = (log2m + 1) / 2, l2 = log2m / 2;
+                           const void* Crow, int conjC, int64_t b, int log2m, const BluCfg& cfg, int N,
+                           int64_t pair0, int64_t npairs, const BluTw& tw, hipStream_t st) {
+  const int l1 = cfg.l1, l2 = log2m - cfg.l1;
   const int M1 = 1 << l1, M2 = 1 << l2;
   hipError_t e;
-#define CALL_A(L) e = launch_blu_A_t<T, L>(in_mode, in, Tm, chirp, b, M2, N, npairs, tw, st); break;
-  BLU_L1_SWITCH(CALL_A)
+#define CALL_A(L) \
+  e = blu_col_pass<T, L>(1, cfg.mb, in_mode, in, Tm, chirp, b, M2, N, pair0, npairs, tw, st); break;
+  BLU_L_SWITCH(l1, CALL_A)
 #undef CALL_A
   if (e != hipSuccess) return e;
-  switch (l2) {
-#define CALL_B(L) \
-  case L: e = launch_blu_B_t<T, L>(Tm, Crow, conjC, M1, npairs, tw, st); break;
-    CALL_B(1) CALL_B(2) CALL_B(3) CALL_B(4) CALL_B(5) CALL_B(6) CALL_B(7) CALL_B(8)
+#define CALL_B(L) e = blu_row_pass<T, L>(cfg.kb, Tm, Crow, conjC, M1, npairs, tw, st); break;
+  BLU_L_SWITCH(l2, CALL_B)
 #undef CALL_B
-    default: return hipErrorInvalidValue;
-  }
   if (e != hipSuccess) return e;
-#define CALL_AI(L) e = launch_blu_Ainv_t<T, L>(out_mode, Tm, out, chirp, b, M2, N, npairs, tw, st); break;
-  BLU_L1_SWITCH(CALL_AI)
+#define CALL_AI(L) \
+  e = blu_col_pass<T, L>(0, cfg.mb, out_mode, Tm, out, chirp, b, M2, N, pair0, npairs, tw, st); break;
+  BLU_L_SWITCH(l1, CALL_AI)
 #undef CALL_AI
   return e;
 }
 
-hipError_t launch_blu_columns(int prec, const void* dT, void* xT, void* Tm, void* Z, void* A, const void* chirp,
-                              const void* Crow, const double* twb64, int64_t b, int log2m, int N, int ntap,
-                              const double* win64, double phi, int normalise, const void* const tw4[4],
-                              hipStream_t st) {
+bool blu_cfg_valid(int log2m, const BluCfg& c) {
+  const int l2 = log2m - c.l1;
+  if (log2m < 2 || log2m > kBluMaxLog2M) return false;
+  if (c.l1 < 1 || c.l1 > 8 || l2 < 1 || l2 > 8) return false;
+  if (c.mb != 8 && c.mb != 16 && c.mb != 32) return false;
+  if (c.kb != 8 && c.kb != 16 && c.kb != 32) return false;
+  return c.pchunk >= 0;
+}
+
+BluCfg blu_cfg_default(int log2m) {
+  BluCfg c;
+  c.l1 = (log2m + 1) / 2;
+  c.mb = 16;
+  c.kb = 16;
+  c.pchunk = 0;
+  return c;
+}
+
+template <typename T>
+static hipError_t blu_columns_t(const void* dT, void* xT, void* Tm, void* Z, void* A, const void* chirp,
+                                const void* Crow, const double* twb64, int64_t b, int log2m, const BluCfg& cfg,
+                                int N, int ntap, const BluGain& g, const BluTw& tw, hipStream_t st) {
   const int64_t npairs = (N + 1) / 2;
+  const int64_t chunk = (cfg.pchunk > 0 && cfg.pchunk < npairs) ? cfg.pchunk : npairs;
+  hipError_t e = hipSuccess;
+  for (int64_t p0 = 0; p0 < npairs && e == hipSuccess; p0 += chunk) {
+    const int64_t np = (npairs - p0) < chunk ? (npairs - p0) : chunk;
+    e = blu_conv<T>(0, dT, 0, Z, Tm, chirp, Crow, 0, b, log2m, cfg, N, p0, np, tw, st);
+    if (e != hipSuccess) break;
+    if (ntap == 4 && np <= 65535) {
+      // 4 taps: one pair per grid row, no division per element
+      const dim3 grid((unsigned)((b + 255) / 256 < 64 ? (b + 255) / 256 : 64), (unsigned)np);
+      k_blu_gain2<T><<<grid, 256, 0, st>>>((const cx<T>*)Z, (cx<T>*)A, (const cx<T>*)chirp,
+                                           (const cx<double>*)twb64, b, p0, g);
+    } else {
+      const unsigned grid = (unsigned)((np * b + 255) / 256 < 4096 ? (np * b + 255) / 256 : 4096);
+      k_blu_gain<T><<<grid, 256, 0, st>>>((const cx<T>*)Z, (cx<T>*)A, (const cx<T>*)chirp,
+                                          (const cx<double>*)twb64, b, p0, np, g);
+    }
+    e = hipGetLastError();
+    if (e == hipSuccess) e = blu_conv<T>(1, A, 1, xT, Tm, chirp, Crow, 1, b, log2m, cfg, N, p0, np, tw, st);
+  }
+  return e;
+}
+
+hipError_t launch_blu_columns(int prec, const void* dT, void* xT, void* Tm, void* Z, void* A, const void* chirp,
+                              const void* Crow, const double* twb64, int64_t b, int log2m, const BluCfg& cfg,
+                              int N, int ntap, const double* win64, double phi, int normalise,
+                              const void* const tw4[4], hipStream_t st) {
+  if (!blu_cfg_valid(log2m, cfg)) return hipErrorInvalidValue;
   BluTw tw{tw4[0], tw4[1], tw4[2], tw4[3]};
   BluGain g;
   g.win = win64;
@@ -321,26 +481,9 @@ hipError_t launch_blu_columns(int prec, const void* dT, void* xT, void* Tm, void
   g.phi2 = phi * phi;
   g.gnorm = normalise ? 1.0 + phi * phi : 1.0;
   g.naive = (phi == 0.0);
-  hipError_t e;
-  const unsigned ggrid = (unsigned)((npairs * b + 255) / 256 < 4096 ? (npairs * b + 255) / 256 : 4096);
-  if (prec == F32) {
-    e = blu_conv<float>(0, dT, 0, Z, Tm, chirp, Crow, 0, b, log2m, N, npairs, tw, st);
-    if (e == hipSuccess) {
-      k_blu_gain<float><<<ggrid, 256, 0, st>>>((const cx<float>*)Z, (cx<float>*)A, (const cx<float>*)chirp,
-                                               (const cx<double>*)twb64, b, npairs, g);
-      e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = blu_conv<float>(1, A, 1, xT, Tm, chirp, Crow, 1, b, log2m, N, npairs, tw, st);
-  } else {
-    e = blu_conv<double>(0, dT, 0, Z, Tm, chirp, Crow, 0, b, log2m, N, npairs, tw, st);
-    if (e == hipSuccess) {
-      k_blu_gain<double><<<ggrid, 256, 0, st>>>((const cx<double>*)Z, (cx<double>*)A, (const cx<double>*)chirp,
-                                                (const cx<double>*)twb64, b, npairs, g);
-      e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = blu_conv<double>(1, A, 1, xT, Tm, chirp, Crow, 1, b, log2m, N, npairs, tw, st);
-  }
-  return e;
+  if (prec == F32)
+    return blu_columns_t<float>(dT, xT, Tm, Z, A, chirp, Crow, twb64, b, log2m, cfg, N, ntap, g, tw, st);
+  return blu_columns_t<double>(dT, xT, Tm, Z, A, chirp, Crow, twb64, b, log2m, cfg, N, ntap, g, tw, st);
 }
 
 }  // namespace ipfb

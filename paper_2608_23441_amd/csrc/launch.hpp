@@ -89,16 +89,26 @@ hipError_t launch_cg_scalar(const double* part, int mode, double* sc, double* re
 hipError_t launch_mask_to_T(int prec, const uint8_t* m, void* out, int64_t S, hipStream_t st);
 constexpr int kCgParts = 1024;
 
+// Tunable shape of the Bluestein column path for one convolution length
+// M = 2^log2m: split M1 = 2^l1 (1 <= l1, log2m - l1 <= 8), tile widths
+// mb, kb in {8, 16, 32}, pairs per launch group (0: all).
+struct BluCfg {
+  int l1 = 0, mb = 16, kb = 16, pchunk = 0;
+};
+bool blu_cfg_valid(int log2m, const BluCfg& c);
+BluCfg blu_cfg_default(int log2m);
+
 // Arbitrary-length column stage (Bluestein): dT, xT [N][b] real; Tm scratch
-// ((N+1)/2 * 2^log2m complex), Z and A scratch ((N+1)/2 * b complex each, may
-// alias the frame buffers as long as they differ from dT/xT when live);
-// chirp [b] complex e^{i pi m^2/b}; Crow [M1][M2] complex = FFT_M of the
-// symmetric chirp filter in row layout; twb64 [b] double complex
-// e^{-2 pi i m/b}; tw4 = {tM1 [M1], tM2 [M2], tLo [256], tHi [max(1, M/256)]}.
+// (min(pchunk, (N+1)/2) * 2^log2m complex), Z and A scratch ((N+1)/2 * b
+// complex each; Z may alias xT and A may alias dT: pair p's rows are read
+// before they are overwritten); chirp [b] complex e^{i pi m^2/b}; Crow
+// [M1][M2] complex = FFT_M of the symmetric chirp filter in row layout for
+// the split cfg.l1; twb64 [b] double complex e^{-2 pi i m/b};
+// tw4 = {tM1 [M1], tM2 [M2], tLo [256], tHi [max(1, M/256)]}.
 hipError_t launch_blu_columns(int prec, const void* dT, void* xT, void* Tm, void* Z, void* A, const void* chirp,
-                              const void* Crow, const double* twb64, int64_t b, int log2m, int N, int ntap,
-                              const double* win64, double phi, int normalise, const void* const tw4[4],
-                              hipStream_t st);
+                              const void* Crow, const double* twb64, int64_t b, int log2m, const BluCfg& cfg,
+                              int N, int ntap, const double* win64, double phi, int normalise,
+                              const void* const tw4[4], hipStream_t st);
 
 // Forward PFB with LDS-resident rows (N <= 2^kMaxLog2Row*).
 hipError_t launch_pfb_fwd_small(int prec, int log2n, const void* x, void* y, int64_t nblock, int ntap,

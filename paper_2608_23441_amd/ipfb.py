@@ -26,7 +26,8 @@ EXPORTS = (
     "ipfb_wiener_ex", "upchannelize", "ipfb_autospectrum", "ipfb_quantize_c4",
     "ipfb_profile_enable", "ipfb_profile_reset", "ipfb_profile_query", "ipfb_ml_cg",
     "ipfb_batched_plan_create", "ipfb_batched_plan_destroy", "ipfb_batched_workspace_size",
-    "ipfb_batched_use_graph", "ipfb_wiener_batched",
+    "ipfb_batched_use_graph", "ipfb_wiener_batched", "ipfb_batched_get_shape",
+    "ipfb_batched_set_shape", "ipfb_batched_tune",
 )
 
 
@@ -67,6 +68,9 @@ def lib():
         L.ipfb_batched_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.ipfb_batched_use_graph.argtypes = [vp, i32]
         L.ipfb_wiener_batched.argtypes = [vp, i32, vp, vp, dbl, i32, vp, vp]
+        L.ipfb_batched_get_shape.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.ipfb_batched_set_shape.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.ipfb_batched_tune.argtypes = [vp, ctypes.c_char_p, i32]
         L.ipfb_profile_enable.argtypes = [i32]
         L.ipfb_profile_reset.argtypes = []
         L.ipfb_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
@@ -323,6 +327,35 @@ class BatchedPlan:
         b = ctypes.c_size_t()
         _check(lib().ipfb_batched_workspace_size(self._h, ctypes.byref(b)))
         return b.value
+
+    def conv_lengths(self):
+        """log2 of the Bluestein convolution length of every stream whose
+        nblock is not a power of two (sorted, distinct)."""
+        out = set()
+        for b in self.nblocks:
+            if b >= 4 and b & (b - 1) == 0 and b.bit_length() - 1 <= (15 if self.prec == F32 else 14):
+                continue
+            m = 2
+            while (1 << m) < 2 * b - 1:
+                m += 1
+            out.add(m)
+        return sorted(out)
+
+    def get_shape(self, log2m: int):
+        """(l1, mb, kb, pchunk) used for convolution length 2^log2m."""
+        a = (ctypes.c_int * 4)()
+        _check(lib().ipfb_batched_get_shape(self._h, int(log2m), a))
+        return tuple(a)
+
+    def set_shape(self, log2m: int, shape):
+        a = (ctypes.c_int * 4)(*[int(v) for v in shape])
+        _check(lib().ipfb_batched_set_shape(self._h, int(log2m), a))
+
+    def tune(self, cache_path=None, force: bool = False):
+        """Run the autotuner (see ipfb_batched_tune); returns {log2m: shape}."""
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(lib().ipfb_batched_tune(self._h, path, int(bool(force))))
+        return {m: self.get_shape(m) for m in self.conv_lengths()}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -95,3 +95,85 @@ def test_batched_rejects_bad_plans():
         ipfb.BatchedPlan(64, 4, w, [12, 40000], ipfb.F32)
     with pytest.raises(ipfb.IpfbError):
         ipfb.BatchedPlan(64, 4, w, [1], ipfb.F32)
+
+
+def _check_streams(bp, data, nblocks, w, N, p, tol, what):
+    outs = ipfb.wiener_batched(bp, [torch.from_numpy(pk).cuda() for pk, _ in data],
+                               [torch.from_numpy(sc).cuda() for _, sc in data], 0.1)
+    torch.cuda.synchronize()
+    for (pk, sc), b, xo in zip(data, nblocks, outs):
+        ref = O.ipfb_wiener(pk, sc, w, N, p, 0.1)
+        err = _rel(xo.cpu().numpy().astype(np.float64), ref)
+        assert err < tol, (what, b, err)
+
+
+@pytest.mark.parametrize("prec,tol", [(ipfb.F64, 1e-11), (ipfb.F32, 1e-5)])
+def test_batched_every_shape_matches_oracle(prec, tol):
+    # every split, both non-default tile widths and ragged launch groups
+    N, p = 64, 4
+    nblocks = [37, 300, 1031]  # convolution lengths 2^7, 2^10, 2^12
+    print(f"case batched shapes prec={prec}", flush=True)
+    w, data = _streams(N, p, nblocks, 4300)
+    bp = ipfb.BatchedPlan(N, p, w, nblocks, prec)
+    bp.use_graph(False)
+    assert bp.conv_lengths() == [7, 10, 12]
+    for m in bp.conv_lengths():
+        d = (m + 1) // 2
+        assert bp.get_shape(m) == (d, 16, 16, 0)
+        shapes = [(l1, 16, 16, 0) for l1 in range(max(1, m - 8), min(8, m - 1) + 1)]
+        shapes += [(d, 8, 16, 0), (d, 32, 16, 0), (d, 16, 8, 0), (d, 16, 32, 0), (d, 8, 32, 5), (d, 32, 8, 7)]
+        for sh in shapes:
+            bp.set_shape(m, sh)
+            assert bp.get_shape(m) == sh
+            _check_streams(bp, data, nblocks, w, N, p, tol, (m, sh))
+        bp.set_shape(m, (d, 16, 16, 0))
+
+
+def test_batched_shape_rejects_invalid():
+    N, p = 64, 4
+    w = O.window_sinc_hamming(p, N)
+    bp = ipfb.BatchedPlan(N, p, w, [300], ipfb.F32)
+    for bad in [(9, 16, 16, 0), (1, 16, 16, 0), (5, 12, 16, 0), (5, 16, 64, 0), (5, 16, 16, -1)]:
+        with pytest.raises(ipfb.IpfbError):
+            bp.set_shape(10, bad)
+    with pytest.raises(ipfb.IpfbError):
+        bp.get_shape(11)  # no stream of that length
+    assert bp.get_shape(10) == (5, 16, 16, 0)
+
+
+def test_batched_autotuner_and_cache(tmp_path, monkeypatch):
+    import json
+    N, p = 256, 4
+    nblocks = [300, 1031, 777]
+    print("case batched autotuner", flush=True)
+    w, data = _streams(N, p, nblocks, 4400)
+    cache = tmp_path / "tune.json"
+    bp = ipfb.BatchedPlan(N, p, w, nblocks, ipfb.F32)
+    tuned = bp.tune(str(cache))
+    assert set(tuned) == {10, 11, 12}
+    doc = json.loads(cache.read_text())
+    keys = sorted(doc["entries"])
+    assert len(keys) == 3 and all("|f32|N256|T4|m" in k for k in keys)
+    for k, e in doc["entries"].items():
+        m = int(k.rsplit("|m", 1)[1])
+        assert (e["l1"], e["mb"], e["kb"], e["pchunk"]) == tuned[m]
+        assert e["us"] > 0
+    _check_streams(bp, data, nblocks, w, N, p, 1e-5, "tuned")
+    # a plan created with the cache in the environment installs the same shapes
+    monkeypatch.setenv("IPFB_TUNE_CACHE", str(cache))
+    bp2 = ipfb.BatchedPlan(N, p, w, nblocks, ipfb.F32)
+    assert {m: bp2.get_shape(m) for m in bp2.conv_lengths()} == tuned
+    _check_streams(bp2, data, nblocks, w, N, p, 1e-5, "from cache")
+    # a hand-edited entry (other spacing, extra field) is read as well
+    key = [k for k in keys if k.endswith("|m11")][0]
+    cache.write_text('{ "entries" : { "%s" : { "note": "manual", "l1" : 4, "mb": 32, "kb": 8, "pchunk": 3, '
+                     '"us": 1.0 } }, "version": 1 }' % key)
+    bp3 = ipfb.BatchedPlan(N, p, w, nblocks, ipfb.F32)
+    assert bp3.get_shape(11) == (4, 32, 8, 3)
+    assert bp3.get_shape(10) == (5, 16, 16, 0)  # no entry: default
+    _check_streams(bp3, data, nblocks, w, N, p, 1e-5, "hand-edited")
+    # tune with the env cache: the entry found is kept, the missing ones are timed and merged
+    bp3.tune()
+    doc = json.loads(cache.read_text())
+    assert len(doc["entries"]) == 3
+    assert doc["entries"][key]["l1"] == 4
