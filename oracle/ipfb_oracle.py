@@ -230,6 +230,82 @@ def ipfb_wiener(packed: np.ndarray, scales_f32: np.ndarray, window: np.ndarray,
 
 
 # ----------------------------------------------------------------------------
+# Linear boundary and streaming inversion (Section 3.1: real data are not
+# circulant; the data are extended to b frames and the circulant inverse
+# corrupts only samples within a decorrelation-kernel width of the ends, the
+# kernel widths shown with the decorrelation-kernel figure).
+# ----------------------------------------------------------------------------
+
+
+def ipfb_linear_from_spectra(yhat: np.ndarray, window: np.ndarray, lblock: int, ntap: int,
+                             phi: float, normalise: bool = True) -> np.ndarray:
+    """Inverse of nspec spectra of a linear (non-wrapping) PFB over
+    b = nspec + p - 1 frames: d_j from the row inverse for j < nspec, the p - 1
+    appended rows set to zero (READING: the extension of d_n to b frames is a
+    zero extension), then the circulant inverse over b frames. Returns
+    x[j*N + n] for the b frames."""
+    d = row_inverse(yhat, lblock)
+    nspec = d.shape[0]
+    dpad = np.zeros((nspec + ntap - 1, lblock), dtype=np.float64)
+    dpad[:nspec] = d
+    return column_inverse(dpad, window, lblock, ntap, phi, normalise).reshape(-1)
+
+
+def stream_chunks(nspec: int, ntap: int, chunk: int, halo: int):
+    """Chunk geometry of the streaming (overlap-save) inverse.
+
+    READING (the paper announces a streaming inverse without details): a stream
+    of nspec spectra covers nframes = nspec + p - 1 frames. Each window holds
+    m = chunk - (p - 1) consecutive spectra, zero-extended to chunk frames, and
+    is inverted on its own; a window keeps L = m - 2*halo frames, those at least
+    halo frames from its first frame and from its last spectrum. Window c keeps
+    output frames [c L, min((c+1) L, nframes)); it starts at spectrum
+    s0 = max(0, min(c L - halo, nspec - m)) (the stream's ends pull it inwards)
+    and holds min(m, nspec - s0) spectra. Returns a list of
+    (s0, nvalid, k0, offset, nkeep): window frames [offset, offset + nkeep)
+    become output frames [k0, k0 + nkeep).
+    """
+    m = chunk - (ntap - 1)
+    L = m - 2 * halo
+    if nspec < 1 or m < 1 or L < 1:
+        raise ValueError("need nspec >= 1 and chunk - (ntap - 1) - 2*halo >= 1")
+    nframes = nspec + ntap - 1
+    out = []
+    k0 = 0
+    while k0 < nframes:
+        s0 = max(0, min(k0 - halo, nspec - m))
+        nvalid = min(m, nspec - s0)
+        nkeep = min(L, nframes - k0)
+        out.append((s0, nvalid, k0, k0 - s0, nkeep))
+        k0 += L
+    return out
+
+
+def ipfb_stream_from_spectra(yhat: np.ndarray, window: np.ndarray, lblock: int, ntap: int,
+                             phi: float, chunk: int, halo: int, normalise: bool = True) -> np.ndarray:
+    """Streaming inverse: every window of stream_chunks inverted as in
+    ipfb_linear_from_spectra but over `chunk` frames, the kept frames
+    assembled. Returns x[j*N + n] for nspec + p - 1 frames."""
+    y = np.asarray(yhat)
+    nspec = y.shape[0]
+    x = np.zeros((nspec + ntap - 1, lblock), dtype=np.float64)
+    for s0, nvalid, k0, off, nkeep in stream_chunks(nspec, ntap, chunk, halo):
+        d = np.zeros((chunk, lblock), dtype=np.float64)
+        d[:nvalid] = row_inverse(y[s0:s0 + nvalid], lblock)
+        xw = column_inverse(d, window, lblock, ntap, phi, normalise)
+        x[k0:k0 + nkeep] = xw[off:off + nkeep]
+    return x.reshape(-1)
+
+
+def ipfb_stream(packed: np.ndarray, scales_f32: np.ndarray, window: np.ndarray, lblock: int,
+                ntap: int, phi: float, chunk: int, halo: int, normalise: bool = True) -> np.ndarray:
+    """Dequantise packed 4-bit spectra of a linear PFB, then the streaming inverse."""
+    qr, qi = unpack_c4(packed)
+    return ipfb_stream_from_spectra(dequantize(qr, qi, scales_f32), window, lblock, ntap, phi,
+                                    chunk, halo, normalise)
+
+
+# ----------------------------------------------------------------------------
 # Dense references for tiny sizes (Section 3.1 circulant matrix; Appendix C's
 # Tikhonov-regularised pseudo-inverse).
 # ----------------------------------------------------------------------------

@@ -350,3 +350,83 @@ def test_tones_peak_in_expected_channel():
         k = int(round(fi * Nf))
         lo, hi = k - 3, k + 4
         assert lo + int(np.argmax(A[lo:hi])) == k
+
+
+# ---- linear boundary and streaming inverse ----------------------------------
+
+def _dominant_window(N, p):
+    # first tap dominant in every column: |W_n(f)| >= 1 - 0.37 > 0, so the
+    # inverse kernel is causal and decays geometrically (ratio <= 0.37)
+    n = np.arange(N)
+    taps = [1.0 + 0.1 * np.cos(n), 0.15 + 0.05 * np.sin(n), -0.1 + 0 * n, 0.05 + 0.02 * np.cos(3 * n)]
+    return np.concatenate(taps[:p])
+
+
+@pytest.mark.parametrize("nspec,p,chunk,halo", [(300, 4, 64, 8), (20, 4, 64, 8), (61, 4, 64, 8),
+                                                (1000, 3, 128, 0), (5, 4, 8, 1), (4097, 4, 256, 100)])
+def test_stream_geometry_partitions_the_output(nspec, p, chunk, halo):
+    ch = O.stream_chunks(nspec, p, chunk, halo)
+    m, L = chunk - (p - 1), chunk - (p - 1) - 2 * halo
+    nframes = nspec + p - 1
+    k = 0
+    for s0, nvalid, k0, off, nkeep in ch:
+        assert k0 == k and 1 <= nkeep <= L
+        assert 0 <= s0 and 1 <= nvalid <= m and s0 + nvalid <= nspec
+        assert 0 <= off and off + nkeep <= chunk
+        if s0 == k0 - halo and nvalid == m:  # interior window: halo on both sides
+            assert off == halo and off + nkeep <= nvalid - halo
+        k += nkeep
+    assert k == nframes
+
+
+def test_linear_inverse_exact_except_at_the_extended_end():
+    # Section 3.1: the circulant model is exact for the wrapped rows only, so a
+    # noise-free linear PFB is recovered exactly away from the zero-extended end
+    N, p, nspec = 16, 4, 400
+    w = _dominant_window(N, p)
+    x = np.random.default_rng(11).standard_normal((nspec + p - 1) * N)
+    y = O.pfb_forward(x, w, N, p, circular=False)
+    err = np.abs(O.ipfb_linear_from_spectra(y, w, N, p, 0.0) - x).reshape(-1, N).max(axis=1)
+    assert err[:-80].max() < 1e-12
+    assert err[-3:].max() > 1e-3  # the end is corrupted, as the paper says
+
+
+def test_stream_recovers_noise_free_timestream():
+    # the end corruption decays by about 1.7x per frame for this window, so a
+    # 64-frame halo keeps every window edge below 1e-12
+    N, p, nspec, chunk = 16, 4, 1000, 256
+    w = _dominant_window(N, p)
+    x = np.random.default_rng(12).standard_normal((nspec + p - 1) * N)
+    y = O.pfb_forward(x, w, N, p, circular=False)
+    good = np.abs(O.ipfb_stream_from_spectra(y, w, N, p, 0.0, chunk, 64) - x).reshape(-1, N).max(axis=1)
+    assert good[:-80].max() < 1e-12
+    # a halo too small leaves window-edge corruption inside the stream
+    bad = np.abs(O.ipfb_stream_from_spectra(y, w, N, p, 0.0, chunk, 1) - x).reshape(-1, N).max(axis=1)
+    assert bad[:-80].max() > 1e-6
+
+
+def test_stream_single_window_is_the_linear_inverse():
+    N, p, chunk = 32, 4, 64
+    w = O.window_sinc_hamming(p, N)
+    nspec = chunk - (p - 1)
+    x = np.random.default_rng(13).standard_normal((nspec + p - 1) * N)
+    y = O.pfb_forward(x, w, N, p, circular=False)
+    ref = O.ipfb_linear_from_spectra(y, w, N, p, 0.1)
+    for halo in (0, 5, 20):
+        assert np.abs(O.ipfb_stream_from_spectra(y, w, N, p, 0.1, chunk, halo) - ref).max() < 1e-13
+
+
+def test_stream_converges_to_linear_inverse_as_halo_grows():
+    # Wiener kernels decay (the decorrelation-kernel figure), so the window
+    # boundaries stop mattering once the halo exceeds their width
+    N, p, nspec = 16, 4, 1000
+    w = O.window_sinc_hamming(p, N)
+    x = np.random.default_rng(14).standard_normal((nspec + p - 1) * N)
+    y = O.pfb_forward(x, w, N, p, circular=False)
+    ref = O.ipfb_linear_from_spectra(y, w, N, p, 0.1).reshape(-1, N)
+    diffs = []
+    for halo in (8, 32, 64, 100):
+        xs = O.ipfb_stream_from_spectra(y, w, N, p, 0.1, 256, halo).reshape(-1, N)
+        diffs.append(np.abs(xs - ref)[200:-200].max())
+    assert all(a > 10 * b for a, b in zip(diffs, diffs[1:]))
+    assert diffs[-1] < 1e-5
