@@ -235,10 +235,51 @@ def batched_form(torch, ipfb, inputs, nstreams):
             "samples": S, "power_of_two_streams": npow2, "graph": True,
             "s_per_step_default_shapes": sec_default, "tune_s": tune_s,
             "shapes": {f"2^{m}": {"default": list(default_shapes[m]), "tuned": list(shapes[m])} for m in shapes},
-            "shape_fields": ["l1", "mb", "kb", "pchunk"],
+            "shape_fields": ["l1", "mb", "kb", "pchunk", "fuse"],
             "hbm_GBps": alg / sec / 1e9, "hbm_roofline_frac": alg / sec / 1e9 / HBM_PEAK_GBPS,
             "config": {"lblock": N, "ntap": p, "nblock": "U[1024, 32768], seed 4", "phi": phi,
                        "dtype": "f32"}}
+
+
+def streaming_form(torch, ipfb, nframes=65536, chunk=16384, halo=256):
+    """Linear-boundary streaming inverse: one stream of nframes = 65536 frames
+    (lblock 4096, ntap 4: 2^28 samples), white noise seed 6, the linear PFB's
+    nframes - 3 spectra (the first spectra of the circular PFB over the same
+    frames), 4-bit; windows of 16384 frames with a 256-frame halo, phi = 0.1,
+    FP32. Inputs made on the GPU by the library's forward PFB and quantiser."""
+    N, p, phi = 4096, 4, 0.1
+    w = ipfb.window_sinc_hamming(p, N)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(6)
+    x = torch.randn(nframes * N, generator=g, device="cuda", dtype=torch.float32)
+    plan = ipfb.Plan(N, p, w, nframes, ipfb.F32)
+    y = ipfb.pfb_forward(plan, x)
+    pk, sc = ipfb.quantize_c4(plan, y, 2.5)
+    nspec = nframes - (p - 1)
+    pk = pk[:nspec].contiguous()
+    torch.cuda.synchronize()
+    del x, y, plan
+    sp = ipfb.StreamPlan(N, p, w, chunk, halo, ipfb.F32)
+    out = torch.empty(nframes * N, dtype=torch.float32, device="cuda")
+    steps = 5
+    for _ in range(2):
+        ipfb.wiener_stream(sp, pk, sc, phi, x_out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ipfb.wiener_stream(sp, pk, sc, phi, x_out=out)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    S = nframes * N
+    L = chunk - (p - 1) - 2 * halo
+    nwin = (nframes + L - 1) // L
+    # compulsory traffic as for the block inverse: packed in, one d round trip, x out
+    alg = nspec * (N // 2 + 1) + 4 * (N // 2 + 1) + 12 * S
+    return {"value": S / sec, "unit": "samples/s", "s_per_step": sec, "steps": steps, "samples": S,
+            "windows": nwin, "window_frames_per_output_frame": nwin * chunk / nframes,
+            "hbm_GBps": alg / sec / 1e9, "hbm_roofline_frac": alg / sec / 1e9 / HBM_PEAK_GBPS,
+            "config": {"lblock": N, "ntap": p, "nframes": nframes, "nspec": nspec, "chunk": chunk,
+                       "halo": halo, "phi": phi, "dtype": "f32", "boundary": "linear"}}
 
 
 def main():
@@ -252,6 +293,7 @@ def main():
     ap.add_argument("--no-ml", action="store_true", help="skip timing the ML-CG form")
     ap.add_argument("--no-batched", action="store_true", help="skip timing the batched form")
     ap.add_argument("--batched-streams", type=int, default=256)
+    ap.add_argument("--no-stream", action="store_true", help="skip timing the streaming (linear boundary) form")
     ap.add_argument("--probe-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -379,6 +421,8 @@ def main():
         out["ml_form"] = ml_form(torch, ipfb, inputs)
     if not args.no_batched:
         out["batched_form"] = batched_form(torch, ipfb, inputs, args.batched_streams)
+    if not args.no_stream:
+        out["streaming_form"] = streaming_form(torch, ipfb)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(N, p, Nf, phi, args.cpu_frames, 2)
     print(json.dumps(out), flush=True)

@@ -114,6 +114,34 @@ int ipfb_wiener(ipfb_plan plan, int infmt, const void* spec, const float* chan_s
 int ipfb_wiener_ex(ipfb_plan plan, int infmt, const void* spec, const float* chan_scale, double phi,
                    int normalise, void* x_out, void* stream);
 
+/* Linear boundary, streaming (Section 3.1: real data are not circulant; the
+ * data are extended to b frames, and the circulant inverse corrupts only the
+ * samples within a decorrelation-kernel width of the ends). Input: nspec
+ * spectra of a linear (non-wrapping) PFB, spectrum j from frames j..j+p-1,
+ * covering nframes = nspec + ntap - 1 frames. The stream is inverted in
+ * windows of `chunk` frames (overlap-save): a window holds
+ * m = chunk - (ntap - 1) consecutive spectra, zero-extended to chunk frames,
+ * and is inverted as ipfb_wiener_ex inverts a circular block; it keeps
+ * L = m - 2 halo frames, those at least halo frames from its first frame and
+ * from its last spectrum. Window c keeps output frames [c L, min((c+1) L,
+ * nframes)) and starts at spectrum max(0, min(c L - halo, nspec - m)),
+ * holding min(m, nspec - start) spectra (the stream's ends pull it inwards).
+ * With nspec = m the result is the single-window zero-extension inverse.
+ * chunk: a power of two in [4, 2^15] (F32) / [4, 2^14] (F64), with
+ * chunk - (ntap - 1) - 2 halo >= 1; lblock as for ipfb_wiener's LDS path
+ * (<= 2^15 F32 / 2^14 F64). The plan owns one window of chunk * lblock
+ * samples and the tables. */
+typedef struct ipfb_splan_s* ipfb_splan;
+int ipfb_stream_plan_create(ipfb_splan* out, int lblock, int ntap, const double* window, int64_t chunk, int halo,
+                            int prec);
+int ipfb_stream_plan_destroy(ipfb_splan plan);
+/* spec: [nspec][lblock/2+1] in format infmt (chan_scale as for ipfb_wiener);
+ * x_out: [(nspec + ntap - 1) * lblock] real, time order, must not overlap spec.
+ * normalise as in ipfb_wiener_ex. Asynchronous on stream; windows run one
+ * after another on it, so calls on one plan must not overlap. */
+int ipfb_wiener_stream(ipfb_splan plan, int infmt, const void* spec, const float* chan_scale, int64_t nspec,
+                       double phi, int normalise, void* x_out, void* stream);
+
 /* Up-channelization (Section 4.3): the forward PFB re-applied with the fine
  * plan's longer frame lblock_f (= u * lblock) and its window, circular over
  * nblock_f = S / lblock_f frames.
@@ -182,20 +210,22 @@ int ipfb_wiener_batched(ipfb_bplan plan, int infmt, const void* const* spec, con
 
 /* Shape of the Bluestein column path for the streams whose convolution length
  * is M = 2^log2m (M the least power of two >= 2 nblock - 1, for nblock not a
- * power of two): shape = {l1, mb, kb, pchunk}: the four-step split
+ * power of two): shape = {l1, mb, kb, pchunk, fuse}: the four-step split
  * M = 2^l1 * 2^(log2m - l1) (1 <= l1 <= 8, 1 <= log2m - l1 <= 8), the
  * column-tile width mb and the row-tile height kb of the FFT passes (8, 16 or
- * 32), and the column pairs per launch group (0: all lblock/2 at once).
+ * 32), the column pairs per launch group (0: all lblock/2 at once), and
+ * fuse = 1 to run the inverse of the first chirp convolution, the gain and
+ * the forward transform of the second as one pass (0: three passes).
  * Every valid shape gives the same result up to rounding; they differ in
  * speed only. Where M1 or M2 is below 32 the tile width 16 is used whatever
- * mb or kb says. The default is {ceil(log2m/2), 16, 16, 0}. get: IPFB_EINVAL if
+ * mb or kb says. The default is {ceil(log2m/2), 16, 16, 0, 1}. get: IPFB_EINVAL if
  * the plan has no stream of that length. set: IPFB_EINVAL for an invalid
  * shape; it waits for the device to go idle (it re-lays the chirp filter
  * spectra for a new split), so it must not overlap a batched call. */
-int ipfb_batched_get_shape(ipfb_bplan plan, int log2m, int shape[4]);
-int ipfb_batched_set_shape(ipfb_bplan plan, int log2m, const int shape[4]);
+int ipfb_batched_get_shape(ipfb_bplan plan, int log2m, int shape[5]);
+int ipfb_batched_set_shape(ipfb_bplan plan, int log2m, const int shape[5]);
 /* Autotuner of the batched form: for each convolution length of the plan, a
- * coordinate search (split, then kb, then mb, then pchunk) times the column
+ * coordinate search ((fuse, mb) jointly, then l1, kb, pchunk) times the column
  * path of the longest stream of that length on the plan's own scratch buffers
  * (three timed runs after a warm-up, best kept) and installs the fastest
  * shape. cache_path (NULL: the IPFB_TUNE_CACHE environment variable; neither:

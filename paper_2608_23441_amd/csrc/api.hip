@@ -456,6 +456,112 @@ int ipfb_wiener(ipfb_plan p, int infmt, const void* spec, const float* chan_scal
   return ipfb_wiener_ex(p, infmt, spec, chan_scale, phi, 1, x_out, stream);
 }
 
+// ---- linear boundary, streaming -------------------------------------------
+struct ipfb_splan_s {
+  ipfb_plan inner = nullptr;  // nblock = chunk: tables and the window buffer
+  int64_t chunk = 0;
+  int halo = 0;
+};
+
+int ipfb_stream_plan_create(ipfb_splan* out, int lblock, int ntap, const double* window, int64_t chunk, int halo,
+                            int prec) {
+  if (!out) return fail(IPFB_EINVAL, "plan output pointer is NULL");
+  *out = nullptr;
+  if (prec != IPFB_F32 && prec != IPFB_F64) return fail(IPFB_EINVAL, "prec must be IPFB_F32 or IPFB_F64");
+  if (ntap < 1) return fail(IPFB_EINVAL, "ntap must be >= 1 (got %d)", ntap);
+  if (!is_pow2(chunk) || chunk < 4 || ilog2(chunk) > max_log2_col(prec))
+    return fail(IPFB_EINVAL, "chunk must be a power of two in [4, 2^%d] (got %lld)", max_log2_col(prec),
+                (long long)chunk);
+  if (halo < 0) return fail(IPFB_EINVAL, "halo must be >= 0");
+  if (chunk - (ntap - 1) - 2 * (int64_t)halo < 1)
+    return fail(IPFB_EINVAL, "chunk - (ntap - 1) - 2 halo must be >= 1 (chunk %lld, ntap %d, halo %d)",
+                (long long)chunk, ntap, halo);
+  ipfb_plan inner = nullptr;
+  int st = ipfb_plan_create(&inner, lblock, ntap, window, chunk, prec);
+  if (st) return st;
+  if (!inner->row_lds) {
+    ipfb_plan_destroy(inner);
+    return fail(IPFB_EUNSUPPORTED, "the streaming inverse supports lblock <= 2^%d for this precision",
+                max_log2_row(prec));
+  }
+  ipfb_splan sp = new ipfb_splan_s();
+  sp->inner = inner;
+  sp->chunk = chunk;
+  sp->halo = halo;
+  *out = sp;
+  return ok();
+}
+
+int ipfb_stream_plan_destroy(ipfb_splan sp) {
+  if (!sp) return fail(IPFB_EINVAL, "plan is NULL");
+  int st = ipfb_plan_destroy(sp->inner);
+  delete sp;
+  return st ? st : ok();
+}
+
+int ipfb_wiener_stream(ipfb_splan sp, int infmt, const void* spec, const float* chan_scale, int64_t nspec,
+                       double phi, int normalise, void* x_out, void* stream) {
+  if (!sp) return fail(IPFB_EINVAL, "plan is NULL");
+  ipfb_plan p = sp->inner;
+  if (!spec || !x_out) return fail(IPFB_EINVAL, "spec and x_out must be non-NULL device pointers");
+  if (infmt != IPFB_IN_C4 && infmt != IPFB_IN_CF32 && infmt != IPFB_IN_CF64)
+    return fail(IPFB_EINVAL, "unknown input format %d", infmt);
+  if (infmt == IPFB_IN_C4 && !chan_scale) return fail(IPFB_EINVAL, "chan_scale is required for IPFB_IN_C4");
+  if (!(phi >= 0.0) || !std::isfinite(phi)) return fail(IPFB_EINVAL, "phi must be finite and >= 0");
+  if (nspec < 1) return fail(IPFB_EINVAL, "nspec must be >= 1");
+  DeviceGuard g(p->dev);
+  hipStream_t st = (hipStream_t)stream;
+  const int N = p->lblock, K = N / 2 + 1;
+  const size_t es = esize(p->prec), fb = (size_t)N * es;
+  const size_t inb = infmt == IPFB_IN_C4 ? 1 : (infmt == IPFB_IN_CF32 ? 8 : 16);
+  const int64_t B = sp->chunk, h = sp->halo, m = B - (p->ntap - 1), L = m - 2 * h;
+  const int64_t nframes = nspec + p->ntap - 1;
+  char* work = (char*)p->work;
+  char* xo = (char*)x_out;
+  hipError_t e = hipSuccess;
+  bool row_c4 = infmt == IPFB_IN_C4;
+  if (row_c4) {  // the persistent row kernel exists for this frame length?
+    e = launch_row_c4(p->prec, p->log2n, nullptr, nullptr, nullptr, 0, nullptr, st);
+    if (e == hipErrorNotSupported) {
+      hipGetLastError();
+      row_c4 = false;
+      e = launch_dequant_factors(p->prec, chan_scale, K, N, p->fac, st);
+    }
+  }
+  // windows of the overlap-save reading: window c keeps output frames
+  // [c L, c L + nkeep); it starts at spectrum s0 and holds nvalid spectra,
+  // zero-extended to B frames
+  for (int64_t k0 = 0; k0 < nframes && e == hipSuccess; k0 += L) {
+    int64_t s0 = k0 - h < nspec - m ? k0 - h : nspec - m;
+    if (s0 < 0) s0 = 0;
+    const int64_t nvalid = nspec - s0 < m ? nspec - s0 : m;
+    const int64_t nkeep = nframes - k0 < L ? nframes - k0 : L;
+    const int64_t off = k0 - s0;
+    const char* sp_in = (const char*)spec + (size_t)s0 * K * inb;
+    if (row_c4)
+      e = launch_row_c4(p->prec, p->log2n, sp_in, chan_scale, work, nvalid, p->twN, st);
+    else
+      e = launch_row_irfft(p->prec, p->log2n, infmt, sp_in, p->fac, work, nvalid, p->twN, st);
+    if (e == hipSuccess && nvalid < B) e = launch_zero(work + (size_t)nvalid * fb, (size_t)(B - nvalid) * fb, st);
+    if (e != hipSuccess) break;
+    if (p->log2b > 9) {
+      for (int pass = 0; pass < 2 && e == hipSuccess; ++pass)
+        e = launch_col_wiener_nat(p->prec, p->log2b, pass, work, N, p->ntap, p->win64, phi, normalise, p->twB,
+                                  p->twB64, st);
+      if (e == hipSuccess)
+        e = launch_col_wiener_nat(p->prec, p->log2b, 2, work, N, p->ntap, p->win64, phi, normalise, p->twB,
+                                  p->twB64, st, 0, -1, xo + (size_t)k0 * fb, (int)off, (int)nkeep);
+    } else {
+      e = launch_col_wiener_nat(p->prec, p->log2b, 1, work, N, p->ntap, p->win64, phi, normalise, p->twB, p->twB64,
+                                st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(xo + (size_t)k0 * fb, work + (size_t)off * fb, (size_t)nkeep * fb,
+                           hipMemcpyDeviceToDevice, st);
+    }
+  }
+  return launched(e, "ipfb_wiener_stream");
+}
+
 int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, const uint8_t* mask,
                const void* prior, double lam, double phi_x0, double phi_precond, int iters, const void* x_init,
                void* x_out, double* resid_norms, void* stream) {
@@ -902,6 +1008,7 @@ int tune_load(ipfb_bplan p, const std::string& path) {
     c.mb = it->second.mb;
     c.kb = it->second.kb;
     c.pchunk = it->second.pchunk;
+    c.fuse = it->second.fuse;
     if (!blu_cfg_valid(kv.first, c)) continue;  // stale entry: keep the current shape
     int st = blu_apply_cfg(p, kv.first, c);
     if (st) return st;
@@ -940,8 +1047,9 @@ int blu_time(ipfb_bplan p, int64_t b, const BluCfg& cfg, hipStream_t st, hipEven
   return IPFB_OK;
 }
 
-// Coordinate search per convolution length: split, then B tile, then A tile,
-// then pairs per launch group; each stage keeps the fastest candidate.
+// Coordinate search per convolution length: fused or not jointly with the
+// column tile, then the split, the row tile and the pairs per launch group;
+// each stage keeps the fastest.
 int tune_length(ipfb_bplan p, int log2m, BluCfg* out, double* out_us) {
   int64_t b = 0;  // the longest stream of this length stands for all of them
   for (auto& kv : p->blu)
@@ -966,9 +1074,20 @@ int tune_length(ipfb_bplan p, int log2m, BluCfg* out, double* out_us) {
       best_us = us;
     }
   };
+  // fused or not together with the column tile (the fused pass is the most
+  // sensitive to the tile width), then the split, then the row tile
+  for (int fuse : {1, 0})
+    for (int mb : {8, 16, 32}) {
+      BluCfg c = best;
+      c.fuse = fuse;
+      c.mb = mb;
+      if (c.fuse == best.fuse && c.mb == best.mb) continue;
+      trial(c);
+    }
+  const BluCfg after_tile = best;
   const int d = (log2m + 1) / 2;
   for (int l1 : {d - 1, d + 1}) {
-    BluCfg c = best;
+    BluCfg c = after_tile;
     c.l1 = l1;
     trial(c);
   }
@@ -976,12 +1095,6 @@ int tune_length(ipfb_bplan p, int log2m, BluCfg* out, double* out_us) {
   for (int kb : {8, 32}) {
     BluCfg c = after_split;
     c.kb = kb;
-    trial(c);
-  }
-  const BluCfg after_kb = best;
-  for (int mb : {8, 32}) {
-    BluCfg c = after_kb;
-    c.mb = mb;
     trial(c);
   }
   const BluCfg after_mb = best;
@@ -1117,7 +1230,7 @@ int ipfb_batched_plan_destroy(ipfb_bplan p) {
   return ok();
 }
 
-int ipfb_batched_get_shape(ipfb_bplan p, int log2m, int shape[4]) {
+int ipfb_batched_get_shape(ipfb_bplan p, int log2m, int shape[5]) {
   if (!p || !shape) return fail(IPFB_EINVAL, "NULL argument");
   auto it = p->bcfg.find(log2m);
   if (it == p->bcfg.end()) return fail(IPFB_EINVAL, "the plan has no stream of convolution length 2^%d", log2m);
@@ -1125,10 +1238,11 @@ int ipfb_batched_get_shape(ipfb_bplan p, int log2m, int shape[4]) {
   shape[1] = it->second.mb;
   shape[2] = it->second.kb;
   shape[3] = it->second.pchunk;
+  shape[4] = it->second.fuse;
   return ok();
 }
 
-int ipfb_batched_set_shape(ipfb_bplan p, int log2m, const int shape[4]) {
+int ipfb_batched_set_shape(ipfb_bplan p, int log2m, const int shape[5]) {
   if (!p || !shape) return fail(IPFB_EINVAL, "NULL argument");
   if (!p->bcfg.count(log2m)) return fail(IPFB_EINVAL, "the plan has no stream of convolution length 2^%d", log2m);
   BluCfg c;
@@ -1136,6 +1250,7 @@ int ipfb_batched_set_shape(ipfb_bplan p, int log2m, const int shape[4]) {
   c.mb = shape[1];
   c.kb = shape[2];
   c.pchunk = shape[3];
+  c.fuse = shape[4];
   DeviceGuard g(p->dev);
   int st = blu_apply_cfg(p, log2m, c);
   return st ? st : ok();
@@ -1177,6 +1292,7 @@ int ipfb_batched_tune(ipfb_bplan p, const char* cache_path, int force) {
       c.mb = it->second.mb;
       c.kb = it->second.kb;
       c.pchunk = it->second.pchunk;
+      c.fuse = it->second.fuse;
       us = it->second.us;
     }
     if (it == have.end() || !blu_cfg_valid(log2m, c)) {
@@ -1187,6 +1303,7 @@ int ipfb_batched_tune(ipfb_bplan p, const char* cache_path, int force) {
       t.mb = c.mb;
       t.kb = c.kb;
       t.pchunk = c.pchunk;
+      t.fuse = c.fuse;
       t.us = us;
       fresh[key] = t;
     }

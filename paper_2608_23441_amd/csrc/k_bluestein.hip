@@ -318,6 +318,121 @@ __global__ __launch_bounds__(256) void k_blu_gain(const cx<T>* __restrict__ Z, c
   }
 }
 
+// The inverse transform of the first convolution, the gain and the forward
+// transform of the second convolution in one pass over the four-step scratch.
+// With b = q M2 + r, the partner b - j of j = j1 M2 + j2 (1 <= j < b) lies in
+// column (r - j2) mod M2, row q - j1 - [j2 > r]; the columns pair up as
+// u = ceil(r/2) + t and r - u (mod M2), t < M2/2 (+1 when r is even: then
+// u = r/2 and u = r/2 + M2/2 are their own partners). A workgroup takes H
+// consecutive t, i.e. up to 2H columns closed under the pairing, so each
+// X_k meets X_{b-k} in LDS (k = 0 is its own partner). Per column: inverse
+// M1-point DFT over k1, Z_j = conv_j conj(c_j) / M, the gain of the two
+// packed real spectra, a_j = (G_n X1 + i G_{n+1} X2) c_j (zero for j >= b),
+// forward M1-point DFT, twiddle w_M^{j2 k1}, back to the same columns.
+template <int LOG2M1, int H>
+struct BluMidCfg {
+  static constexpr int M1 = 1 << LOG2M1;
+  static constexpr int C = 2 * H;
+  static constexpr int LS = lds_len(M1);
+  static constexpr int NT0 = (M1 * C) / 8;
+  static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 512 ? 512 : NT0);
+};
+
+template <typename T, int LOG2M1, int H, bool TAP4>
+__global__ __launch_bounds__((BluMidCfg<LOG2M1, H>::NT)) void k_blu_mid(
+    cx<T>* __restrict__ Tm, const cx<T>* __restrict__ chirp, const cx<double>* __restrict__ twb64, int64_t b,
+    int M2, int64_t pair0, BluGain g, BluTw tw) {
+  using Cfg = BluMidCfg<LOG2M1, H>;
+  constexpr int M1 = Cfg::M1, LS = Cfg::LS, NT = Cfg::NT, C = Cfg::C;
+  __shared__ cx<T> s[C * LS];
+  __shared__ cx<T> tlo[256], thi[256];
+  __shared__ int col[C], mate[C];
+  const int M = M1 * M2;
+  blu_tw_lds<T, NT>(tlo, thi, tw, M);
+  const int q = (int)(b / M2), r = (int)(b - (int64_t)q * M2);
+  const int npc = (r & 1) ? M2 / 2 : M2 / 2 + 1;  // number of column pairs
+  const int nrun = (npc + H - 1) / H;
+  const int64_t lpair = blockIdx.x / nrun, pair = pair0 + lpair;
+  const int t0 = (blockIdx.x % nrun) * H;
+  const int c0 = (r + 1) / 2;
+  if (threadIdx.x < H) {  // slot i: column u; slot H + i: its partner (-1: none)
+    const int i = threadIdx.x;
+    int u = -1, l = -1;
+    if (t0 + i < npc) {
+      u = (c0 + t0 + i) & (M2 - 1);
+      l = (r - u) & (M2 - 1);
+      if (l == u) l = -1;
+    }
+    col[i] = u;
+    col[H + i] = l;
+    mate[i] = (l >= 0) ? H + i : i;
+    mate[H + i] = i;
+  }
+  __syncthreads();
+  cx<T>* tp = Tm + lpair * (int64_t)M;
+  for (int e = threadIdx.x; e < M1 * C; e += NT) {
+    const int sl = e % C, k1 = e / C;
+    const int j2 = col[sl];
+    s[sl * LS + pidx(k1)] = (j2 >= 0) ? tp[(int64_t)k1 * M2 + j2] : mk<T>(T(0), T(0));
+  }
+  __syncthreads();
+  lds_fft<T, M1, NT, C, +1>(s, LS, reinterpret_cast<const cx<T>*>(tw.tM1), 1);
+  // Each pair {j, b - j} is done by the thread holding its smaller member: the
+  // gains at b - j are the conjugates of those at j (real taps), so
+  // a_j = (Y1 + i Y2) c_j and a_{b-j} = (conj Y1 + i conj Y2) c_{b-j} with
+  // Y1 = G_n(j) X1(j), Y2 = G_{n+1}(j) X2(j). Rows j >= b become zero.
+  const int n = (int)(2 * pair);
+  const bool has1 = n + 1 < g.N;
+  const double invM = 1.0 / (double)M;
+#pragma unroll 1
+  for (int e = threadIdx.x; e < M1 * C; e += NT) {
+    const int sl = e % C, j1 = e / C;
+    const int j2 = col[sl];
+    if (j2 < 0) continue;
+    const int64_t j = (int64_t)j1 * M2 + j2;
+    cx<T>* sj = s + sl * LS + pidx(j1);
+    if (j >= b) {
+      *sj = mk<T>(T(0), T(0));
+      continue;
+    }
+    const int64_t jm = (j == 0) ? 0 : b - j;
+    if (jm < j) continue;  // the partner's thread does this pair
+    cx<T>* sm = sj;
+    if (jm != j) sm = s + mate[sl] * LS + pidx(q - j1 - (j2 > r ? 1 : 0));
+    const cx<T> cj = chirp[j], cm = chirp[jm];
+    const cx<double> c = mk<double>(cj.x, cj.y), cmd = mk<double>(cm.x, cm.y);
+    const cx<T> v = *sj, w = *sm;
+    const cx<double> Zk = cmulc(mk<double>(v.x * invM, v.y * invM), c);
+    const cx<double> Zm = cmulc(mk<double>(w.x * invM, w.y * invM), cmd);
+    // X1 = (Z_j + conj Z_{b-j}) / 2, X2 = (Z_j - conj Z_{b-j}) / 2i
+    const cx<double> X1 = mk<double>(0.5 * (Zk.x + Zm.x), 0.5 * (Zk.y - Zm.y));
+    const cx<double> X2 = mk<double>(0.5 * (Zk.y + Zm.y), -0.5 * (Zk.x - Zm.x));
+    cx<double> Ga, Gc;
+    if constexpr (TAP4) {
+      blu_gain_pair4(g, n, has1, twb64[j], Ga, Gc);
+    } else {
+      Ga = blu_gain(g, n, twb64, j);
+      Gc = has1 ? blu_gain(g, n + 1, twb64, j) : mk<double>(0.0, 0.0);
+    }
+    const cx<double> Y1 = cmul(Ga, X1);
+    const cx<double> Y2 = has1 ? cmul(Gc, X2) : mk<double>(0.0, 0.0);
+    const cx<double> oj = cmul(mk<double>(Y1.x - Y2.y, Y1.y + Y2.x), c);  // (Y1 + i Y2) c_j
+    *sj = mk<T>(T(oj.x), T(oj.y));
+    if (jm != j) {
+      const cx<double> om = cmul(mk<double>(Y1.x + Y2.y, -Y1.y + Y2.x), cmd);  // (conj Y1 + i conj Y2) c_{b-j}
+      *sm = mk<T>(T(om.x), T(om.y));
+    }
+  }
+  __syncthreads();
+  lds_fft<T, M1, NT, C, -1>(s, LS, reinterpret_cast<const cx<T>*>(tw.tM1), 1);
+  for (int e = threadIdx.x; e < M1 * C; e += NT) {
+    const int sl = e % C, k1 = e / C;
+    const int j2 = col[sl];
+    if (j2 < 0) continue;
+    tp[(int64_t)k1 * M2 + j2] = cmul(s[sl * LS + pidx(k1)], blu_twM(tlo, thi, j2 * k1));
+  }
+}
+
 // ---- launchers ---------------------------------------------------------------
 // Tile widths other than 16 exist for M1, M2 >= 2^kBluTileMinLog2 only.
 constexpr int kBluTileMinLog2 = 5;
@@ -399,28 +514,63 @@ static hipError_t blu_row_pass(int kb, void* Tm, const void* Crow, int conjC, in
     default: return hipErrorInvalidValue;                   \
   }
 
-// One cyclic convolution of length M = 2^l1 * 2^(log2m - l1) for pairs [pair0, pair0 + npairs).
+// The steps of one cyclic convolution of length M = 2^l1 * 2^(log2m - l1)
+// for pairs [pair0, pair0 + npairs): step 0 = A, 1 = B, 2 = A'.
 template <typename T>
-static hipError_t blu_conv(int in_mode, const void* in, int out_mode, void* out, void* Tm, const void* chirp,
+static hipError_t blu_step(int step, int mode, const void* in, void* out, void* Tm, const void* chirp,
                            const void* Crow, int conjC, int64_t b, int log2m, const BluCfg& cfg, int N,
                            int64_t pair0, int64_t npairs, const BluTw& tw, hipStream_t st) {
   const int l1 = cfg.l1, l2 = log2m - cfg.l1;
   const int M1 = 1 << l1, M2 = 1 << l2;
-  hipError_t e;
+  hipError_t e = hipErrorInvalidValue;
+  if (step == 0) {
 #define CALL_A(L) \
-  e = blu_col_pass<T, L>(1, cfg.mb, in_mode, in, Tm, chirp, b, M2, N, pair0, npairs, tw, st); break;
-  BLU_L_SWITCH(l1, CALL_A)
+  e = blu_col_pass<T, L>(1, cfg.mb, mode, in, Tm, chirp, b, M2, N, pair0, npairs, tw, st); break;
+    BLU_L_SWITCH(l1, CALL_A)
 #undef CALL_A
-  if (e != hipSuccess) return e;
+  } else if (step == 1) {
 #define CALL_B(L) e = blu_row_pass<T, L>(cfg.kb, Tm, Crow, conjC, M1, npairs, tw, st); break;
-  BLU_L_SWITCH(l2, CALL_B)
+    BLU_L_SWITCH(l2, CALL_B)
 #undef CALL_B
-  if (e != hipSuccess) return e;
+  } else {
 #define CALL_AI(L) \
-  e = blu_col_pass<T, L>(0, cfg.mb, out_mode, Tm, out, chirp, b, M2, N, pair0, npairs, tw, st); break;
-  BLU_L_SWITCH(l1, CALL_AI)
+  e = blu_col_pass<T, L>(0, cfg.mb, mode, Tm, out, chirp, b, M2, N, pair0, npairs, tw, st); break;
+    BLU_L_SWITCH(l1, CALL_AI)
 #undef CALL_AI
+  }
   return e;
+}
+
+template <typename T, int L1, int H>
+static hipError_t launch_blu_mid_t(void* Tm, const void* chirp, const double* twb64, int64_t b, int M2,
+                                   int64_t pair0, int64_t npairs, const BluGain& g, const BluTw& tw,
+                                   hipStream_t st) {
+  using Cfg = BluMidCfg<L1, H>;
+  const int r = (int)(b % M2);
+  const int Tp = (r & 1) ? M2 / 2 : M2 / 2 + 1;
+  const dim3 grid((unsigned)(npairs * ((Tp + H - 1) / H)));
+  if (g.ntap == 4)
+    k_blu_mid<T, L1, H, true><<<grid, Cfg::NT, 0, st>>>((cx<T>*)Tm, (const cx<T>*)chirp, (const cx<double>*)twb64,
+                                                         b, M2, pair0, g, tw);
+  else
+    k_blu_mid<T, L1, H, false><<<grid, Cfg::NT, 0, st>>>((cx<T>*)Tm, (const cx<T>*)chirp,
+                                                          (const cx<double>*)twb64, b, M2, pair0, g, tw);
+  return hipGetLastError();
+}
+
+template <typename T, int L1>
+static hipError_t blu_mid_pass(int mb, void* Tm, const void* chirp, const double* twb64, int64_t b, int M2,
+                               int64_t pair0, int64_t npairs, const BluGain& g, const BluTw& tw, hipStream_t st) {
+  if (L1 < kBluTileMinLog2) mb = 16;
+  switch (mb) {
+#define BLU_CASE(MB)                                                                                        \
+  case MB:                                                                                                 \
+    return launch_blu_mid_t<T, L1, (L1 < kBluTileMinLog2 ? 8 : MB / 2)>(Tm, chirp, twb64, b, M2, pair0,    \
+                                                                        npairs, g, tw, st);
+    BLU_CASE(8) BLU_CASE(16) BLU_CASE(32)
+#undef BLU_CASE
+    default: return hipErrorInvalidValue;
+  }
 }
 
 bool blu_cfg_valid(int log2m, const BluCfg& c) {
@@ -429,6 +579,7 @@ bool blu_cfg_valid(int log2m, const BluCfg& c) {
   if (c.l1 < 1 || c.l1 > 8 || l2 < 1 || l2 > 8) return false;
   if (c.mb != 8 && c.mb != 16 && c.mb != 32) return false;
   if (c.kb != 8 && c.kb != 16 && c.kb != 32) return false;
+  if (c.fuse != 0 && c.fuse != 1) return false;
   return c.pchunk >= 0;
 }
 
@@ -438,6 +589,7 @@ BluCfg blu_cfg_default(int log2m) {
   c.mb = 16;
   c.kb = 16;
   c.pchunk = 0;
+  c.fuse = 1;
   return c;
 }
 
@@ -450,7 +602,19 @@ static hipError_t blu_columns_t(const void* dT, void* xT, void* Tm, void* Z, voi
   hipError_t e = hipSuccess;
   for (int64_t p0 = 0; p0 < npairs && e == hipSuccess; p0 += chunk) {
     const int64_t np = (npairs - p0) < chunk ? (npairs - p0) : chunk;
-    e = blu_conv<T>(0, dT, 0, Z, Tm, chirp, Crow, 0, b, log2m, cfg, N, p0, np, tw, st);
+    e = blu_step<T>(0, 0, dT, nullptr, Tm, chirp, Crow, 0, b, log2m, cfg, N, p0, np, tw, st);
+    if (e == hipSuccess) e = blu_step<T>(1, 0, nullptr, nullptr, Tm, chirp, Crow, 0, b, log2m, cfg, N, p0, np, tw, st);
+    if (e != hipSuccess) break;
+    if (cfg.fuse) {
+      const int M2 = 1 << (log2m - cfg.l1);
+#define CALL_M(L) e = blu_mid_pass<T, L>(cfg.mb, Tm, chirp, twb64, b, M2, p0, np, g, tw, st); break;
+      BLU_L_SWITCH(cfg.l1, CALL_M)
+#undef CALL_M
+      if (e == hipSuccess) e = blu_step<T>(1, 0, nullptr, nullptr, Tm, chirp, Crow, 1, b, log2m, cfg, N, p0, np, tw, st);
+      if (e == hipSuccess) e = blu_step<T>(2, 1, nullptr, xT, Tm, chirp, Crow, 1, b, log2m, cfg, N, p0, np, tw, st);
+      continue;
+    }
+    e = blu_step<T>(2, 0, nullptr, Z, Tm, chirp, Crow, 0, b, log2m, cfg, N, p0, np, tw, st);
     if (e != hipSuccess) break;
     if (ntap == 4 && np <= 65535) {
       // 4 taps: one pair per grid row, no division per element
@@ -463,7 +627,8 @@ static hipError_t blu_columns_t(const void* dT, void* xT, void* Tm, void* Z, voi
                                           (const cx<double>*)twb64, b, p0, np, g);
     }
     e = hipGetLastError();
-    if (e == hipSuccess) e = blu_conv<T>(1, A, 1, xT, Tm, chirp, Crow, 1, b, log2m, cfg, N, p0, np, tw, st);
+    for (int step = 0; step < 3 && e == hipSuccess; ++step)
+      e = blu_step<T>(step, 1, A, xT, Tm, chirp, Crow, 1, b, log2m, cfg, N, p0, np, tw, st);
   }
   return e;
 }

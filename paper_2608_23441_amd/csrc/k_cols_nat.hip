@@ -85,7 +85,8 @@ __device__ __forceinline__ void pair_gains(const NatGain& ga, cx<double> Wa, cx<
 // pass A are gathered into LDS at the start.
 template <typename T, int LOG2B1, int LOG2B2, int DIR>
 __global__ __launch_bounds__((NatCfg<T>::clampnt(NatCfg<T>::TP * (1 << LOG2B1) / NatCfg<T>::EPT)), 4) void k_nat_outer(
-    cx<T>* __restrict__ z, int np, int t0, int ntile, const cx<T>* __restrict__ tw) {
+    cx<T>* __restrict__ z, int np, int t0, int ntile, const cx<T>* __restrict__ tw, cx<T>* __restrict__ out,
+    int r0, int nr) {
   constexpr int TP = NatCfg<T>::TP;
   constexpr int B1 = 1 << LOG2B1, B2 = 1 << LOG2B2, B = B1 * B2;
   constexpr int NT = NatCfg<T>::clampnt(TP * B1 / NatCfg<T>::EPT);
@@ -121,7 +122,13 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(NatCfg<T>::TP * (1 << LOG2B1) /
     if (NE % NT != 0 && e >= NE) continue;
     cx<T> u = s[q * LS + pidx(k1)];
     if (DIR < 0) u = cmul(u, tws[k1]);
-    if (p0 + q < np) z[(int64_t)(k1 * B2 + j2) * np + p0 + q] = u;
+    if (p0 + q >= np) continue;
+    const int row = k1 * B2 + j2;
+    if (DIR > 0 && out) {  // only the frames [r0, r0 + nr), to out
+      if (row >= r0 && row < r0 + nr) out[(int64_t)(row - r0) * np + p0 + q] = u;
+    } else {
+      z[(int64_t)row * np + p0 + q] = u;
+    }
   }
 }
 
@@ -309,7 +316,7 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * N
 
 template <typename T, int LOG2B>
 static hipError_t launch_nat_t(int pass, void* zv, int lblock, int tile0, int ntiles, const NatGain& ga,
-                               const void* twv, const double* tw64v, hipStream_t st) {
+                               const void* twv, const double* tw64v, hipStream_t st, void* out, int r0, int nr) {
   using Cfg = NatCfg<T>;
   cx<T>* z = (cx<T>*)zv;
   const cx<T>* tw = (const cx<T>*)twv;
@@ -319,6 +326,7 @@ static hipError_t launch_nat_t(int pass, void* zv, int lblock, int tile0, int nt
   if (ntiles < 0 || tile0 + ntiles > nall) ntiles = nall - tile0;
   if (tile0 < 0 || ntiles <= 0) return tile0 < 0 ? hipErrorInvalidValue : hipSuccess;
   if constexpr (LOG2B <= 9) {
+    if (out) return hipErrorInvalidValue;  // the one-pass form works in place only
     if (pass != 1) return hipSuccess;
     constexpr int NT = Cfg::clampnt(Cfg::TP * (1 << LOG2B) / Cfg::EPT);
     if (ga.ntap == 4)
@@ -330,7 +338,8 @@ static hipError_t launch_nat_t(int pass, void* zv, int lblock, int tile0, int nt
     constexpr int NTO = Cfg::clampnt(Cfg::TP * (1 << L1) / Cfg::EPT);
     constexpr int NTM = Cfg::clampnt(2 * Cfg::TP * (1 << L2) / Cfg::EPT);
     if (pass == 0)
-      k_nat_outer<T, L1, L2, -1><<<dim3(ntiles * (1 << L2)), dim3(NTO), 0, st>>>(z, np, tile0, ntiles, tw);
+      k_nat_outer<T, L1, L2, -1><<<dim3(ntiles * (1 << L2)), dim3(NTO), 0, st>>>(z, np, tile0, ntiles, tw, nullptr,
+                                                                                  0, 0);
     if (pass == 1 && ga.ntap == 4)
       k_nat_mid<T, L1, L2, 4><<<dim3(ntiles * (1 << (L1 - 1))), dim3(NTM), 0, st>>>(z, np, tile0, ntiles, ga, tw,
                                                                                       tw64);
@@ -338,13 +347,14 @@ static hipError_t launch_nat_t(int pass, void* zv, int lblock, int tile0, int nt
       k_nat_mid<T, L1, L2, 0><<<dim3(ntiles * (1 << (L1 - 1))), dim3(NTM), 0, st>>>(z, np, tile0, ntiles, ga, tw,
                                                                                       tw64);
     if (pass == 2)
-      k_nat_outer<T, L1, L2, +1><<<dim3(ntiles * (1 << L2)), dim3(NTO), 0, st>>>(z, np, tile0, ntiles, tw);
+      k_nat_outer<T, L1, L2, +1><<<dim3(ntiles * (1 << L2)), dim3(NTO), 0, st>>>(z, np, tile0, ntiles, tw,
+                                                                                  (cx<T>*)out, r0, nr);
   }
   return hipGetLastError();
 }
 
 #define NAT_CASE(T, L) \
-  case L: return launch_nat_t<T, L>(pass, z, lblock, tile0, ntiles, ga, twB, twB64, st);
+  case L: return launch_nat_t<T, L>(pass, z, lblock, tile0, ntiles, ga, twB, twB64, st, out, r0, nr);
 
 int nat_tiles(int prec, int lblock) {
   const int tp = prec == F32 ? NatCfg<float>::TP : NatCfg<double>::TP;
@@ -353,8 +363,9 @@ int nat_tiles(int prec, int lblock) {
 
 hipError_t launch_col_wiener_nat(int prec, int log2b, int pass, void* z, int lblock, int ntap, const double* win64,
                                  double phi, int normalise, const void* twB, const double* twB64, hipStream_t st,
-                                 int tile0, int ntiles) {
+                                 int tile0, int ntiles, void* out, int r0, int nr) {
   if (lblock < 2 || (lblock & 1) || pass < 0 || pass > 2) return hipErrorInvalidValue;
+  if (out && (pass != 2 || r0 < 0 || nr < 0 || r0 + nr > (1 << log2b))) return hipErrorInvalidValue;
   NatGain ga;
   ga.win = win64;
   ga.lblock = lblock;

@@ -40,4 +40,29 @@ hipError_t launch_transpose(int prec, const void* in, void* out, int64_t rows, i
   return hipGetLastError();
 }
 
+// 16-byte stores over the aligned body, single bytes over the ends
+__global__ __launch_bounds__(256) void k_zero(unsigned char* __restrict__ p, size_t head, size_t nvec,
+                                              size_t bytes) {
+  const size_t stride = (size_t)gridDim.x * 256;
+  const size_t i0 = (size_t)blockIdx.x * 256 + threadIdx.x;
+  uint4* v = reinterpret_cast<uint4*>(p + head);
+  for (size_t i = i0; i < nvec; i += stride) v[i] = make_uint4(0u, 0u, 0u, 0u);
+  const size_t tail0 = head + nvec * 16;
+  for (size_t i = i0; i < head; i += stride) p[i] = 0;
+  for (size_t i = tail0 + i0; i < bytes; i += stride) p[i] = 0;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  unsigned char* c = (unsigned char*)p;
+  size_t head = (16 - ((uintptr_t)c & 15)) & 15;
+  if (head > bytes) head = bytes;
+  const size_t nvec = (bytes - head) / 16;
+  size_t blocks = (nvec + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 4096) blocks = 4096;
+  k_zero<<<dim3((unsigned)blocks), 256, 0, st>>>(c, head, nvec, bytes);
+  return hipGetLastError();
+}
+
 }  // namespace ipfb

@@ -67,10 +67,12 @@ hipError_t launch_col_wiener(int prec, int log2b, const void* d, void* xo, int l
 // The work splits into nat_tiles() column tiles (128 bytes of every frame);
 // one call covers tiles [tile0, tile0 + ntiles) (ntiles < 0: to the end), and
 // the three passes of a tile range may run before those of the next range.
+// out != NULL (pass 2 with b > 512 only): frames [r0, r0 + nr) of the result
+// go to out (nr frames, same row layout) instead of z, and the others nowhere.
 int nat_tiles(int prec, int lblock);
 hipError_t launch_col_wiener_nat(int prec, int log2b, int pass, void* z, int lblock, int ntap, const double* win64,
                                  double phi, int normalise, const void* twB, const double* twB64, hipStream_t st,
-                                 int tile0 = 0, int ntiles = -1);
+                                 int tile0 = 0, int ntiles = -1, void* out = nullptr, int r0 = 0, int nr = 0);
 
 // Maximum-likelihood CG pieces (vectors in the transposed layout [N][b]).
 hipError_t launch_cg_autocorr(const double* win64, int N, int ntap, double* autoc, hipStream_t st);
@@ -91,9 +93,11 @@ constexpr int kCgParts = 1024;
 
 // Tunable shape of the Bluestein column path for one convolution length
 // M = 2^log2m: split M1 = 2^l1 (1 <= l1, log2m - l1 <= 8), tile widths
-// mb, kb in {8, 16, 32}, pairs per launch group (0: all).
+// mb, kb in {8, 16, 32}, pairs per launch group (0: all), fuse = 1: the
+// inverse of the first convolution, the gain and the forward of the second in
+// one pass over the scratch (0: three kernels through Z and A).
 struct BluCfg {
-  int l1 = 0, mb = 16, kb = 16, pchunk = 0;
+  int l1 = 0, mb = 16, kb = 16, pchunk = 0, fuse = 1;
 };
 bool blu_cfg_valid(int log2m, const BluCfg& c);
 BluCfg blu_cfg_default(int log2m);
@@ -128,6 +132,9 @@ int lf_frame_chunk(int prec, int log2n, int64_t nblock);
 hipError_t launch_pfb_fwd_long(int prec, int log2n, int pass, const void* x, void* y, int64_t nblock, int ntap,
                                const void* winT, const void* twS, void* tmp, int fchunk, double* part,
                                hipStream_t st);
+
+// bytes zero bytes at p (a kernel, so that it may sit in a captured graph)
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 
 // out[c][r] = in[r][c] for an in[rows][cols] matrix (64 x 64 LDS tiles)
 hipError_t launch_transpose(int prec, const void* in, void* out, int64_t rows, int64_t cols, hipStream_t st);

@@ -27,7 +27,8 @@ EXPORTS = (
     "ipfb_profile_enable", "ipfb_profile_reset", "ipfb_profile_query", "ipfb_ml_cg",
     "ipfb_batched_plan_create", "ipfb_batched_plan_destroy", "ipfb_batched_workspace_size",
     "ipfb_batched_use_graph", "ipfb_wiener_batched", "ipfb_batched_get_shape",
-    "ipfb_batched_set_shape", "ipfb_batched_tune",
+    "ipfb_batched_set_shape", "ipfb_batched_tune", "ipfb_stream_plan_create", "ipfb_stream_plan_destroy",
+    "ipfb_wiener_stream",
 )
 
 
@@ -71,6 +72,9 @@ def lib():
         L.ipfb_batched_get_shape.argtypes = [vp, i32, ctypes.POINTER(i32)]
         L.ipfb_batched_set_shape.argtypes = [vp, i32, ctypes.POINTER(i32)]
         L.ipfb_batched_tune.argtypes = [vp, ctypes.c_char_p, i32]
+        L.ipfb_stream_plan_create.argtypes = [ctypes.POINTER(vp), i32, i32, vp, i64, i32, i32]
+        L.ipfb_stream_plan_destroy.argtypes = [vp]
+        L.ipfb_wiener_stream.argtypes = [vp, i32, vp, vp, i64, dbl, i32, vp, vp]
         L.ipfb_profile_enable.argtypes = [i32]
         L.ipfb_profile_reset.argtypes = []
         L.ipfb_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
@@ -342,13 +346,13 @@ class BatchedPlan:
         return sorted(out)
 
     def get_shape(self, log2m: int):
-        """(l1, mb, kb, pchunk) used for convolution length 2^log2m."""
-        a = (ctypes.c_int * 4)()
+        """(l1, mb, kb, pchunk, fuse) used for convolution length 2^log2m."""
+        a = (ctypes.c_int * 5)()
         _check(lib().ipfb_batched_get_shape(self._h, int(log2m), a))
         return tuple(a)
 
     def set_shape(self, log2m: int, shape):
-        a = (ctypes.c_int * 4)(*[int(v) for v in shape])
+        a = (ctypes.c_int * 5)(*[int(v) for v in shape])
         _check(lib().ipfb_batched_set_shape(self._h, int(log2m), a))
 
     def tune(self, cache_path=None, force: bool = False):
@@ -399,3 +403,63 @@ def wiener_batched(bp: BatchedPlan, specs, chan_scales=None, phi: float = 0.1, x
     sc = P(*[_ptr(t, "chan_scale").value for t in chan_scales]) if fmt == IN_C4 else None
     _check(lib().ipfb_wiener_batched(bp._h, fmt, sp, sc, float(phi), int(bool(normalise)), xo, _stream(stream)))
     return x_outs
+
+
+class StreamPlan:
+    """Plan of the streaming (overlap-save) inverse of a linear PFB: windows of
+    `chunk` frames, `halo` frames discarded at each window edge."""
+
+    def __init__(self, lblock: int, ntap: int, window, chunk: int, halo: int, prec: int = F32):
+        self.lblock, self.ntap, self.chunk, self.halo, self.prec = int(lblock), int(ntap), int(chunk), int(halo), int(prec)
+        w = np.ascontiguousarray(np.asarray(window, dtype=np.float64))
+        h = ctypes.c_void_p()
+        _check(lib().ipfb_stream_plan_create(ctypes.byref(h), self.lblock, self.ntap, w.ctypes.data, self.chunk,
+                                             self.halo, self.prec))
+        self._h = h
+
+    @property
+    def nchan(self):
+        return self.lblock // 2 + 1
+
+    @property
+    def real_dtype(self):
+        import torch
+        return torch.float32 if self.prec == F32 else torch.float64
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ipfb_stream_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def wiener_stream(sp: StreamPlan, spec, chan_scale=None, phi: float = 0.1, x_out=None, normalise: bool = True,
+                  stream=None):
+    """Streaming inverse of nspec linear-PFB spectra (uint8 [nspec][nchan] with
+    chan_scale, or complex [nspec][nchan]); returns (nspec + ntap - 1) * lblock samples."""
+    import torch
+    if spec.dtype == torch.uint8:
+        if chan_scale is None or chan_scale.dtype != torch.float32 or chan_scale.numel() != sp.nchan:
+            raise ValueError("chan_scale: float32 [nchan] is required for packed 4-bit spectra")
+        fmt = IN_C4
+    elif spec.dtype in (torch.complex64, torch.complex128):
+        fmt = IN_CF32 if spec.dtype == torch.complex64 else IN_CF64
+        chan_scale = None
+    else:
+        raise ValueError("spec must be uint8 (packed 4-bit), complex64 or complex128")
+    if spec.numel() % sp.nchan != 0 or spec.numel() == 0:
+        raise ValueError("spec must hold nspec * (lblock/2+1) values")
+    nspec = spec.numel() // sp.nchan
+    nout = (nspec + sp.ntap - 1) * sp.lblock
+    if x_out is None:
+        x_out = _empty((nout,), sp.real_dtype)
+    elif x_out.numel() != nout or not x_out.is_contiguous():
+        raise ValueError(f"x_out must be a contiguous tensor of {nout} samples")
+    _check(lib().ipfb_wiener_stream(sp._h, fmt, _ptr(spec, "spec"), _ptr(chan_scale, "chan_scale"), int(nspec),
+                                    float(phi), int(bool(normalise)), _ptr(x_out, "x_out"), _stream(stream)))
+    return x_out
