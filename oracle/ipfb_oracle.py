@@ -476,6 +476,24 @@ def ml_pcg(d: np.ndarray, window: np.ndarray, lblock: int, ntap: int,
     return x.reshape(-1), np.array(norms)
 
 
+def saved_paths(beta: float, R: int, lblock: int) -> int:
+    """L from beta = L/(RN) (Section 4.2.2). READING: L is rounded to the
+    nearest even number, so that the saved paths sit symmetrically around the
+    frame centre (Section 4.3: 1% -> 82 and 10% -> 820 paths at N = 2048, R = 4)."""
+    return int(2 * round(beta * R * lblock / 2.0))
+
+
+def structured_mask(lblock: int, nblock: int, R: int, L: int) -> np.ndarray:
+    """Prior mask of the sample-saving strategy (Section 4.2.2): every R-th
+    sample (frames j = 0, R, 2R, ...) of the L sub-filter paths
+    n in [N/2 - L/2, N/2 + L/2), the paths around N/2 that the quantisation
+    noise corrupts most. uint8 [nblock * lblock], time order."""
+    m = np.zeros((nblock, lblock), dtype=np.uint8)
+    n0 = lblock // 2 - L // 2
+    m[::R, n0:n0 + L] = 1
+    return m.reshape(-1)
+
+
 def ml_dense_solve(d, window, lblock, ntap, mask, prior, lam):
     """The converged ML answer on tiny sizes by a dense solve of the normal
     equations (A^T A + lam D) x = A^T d + lam D prior."""

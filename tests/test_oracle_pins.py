@@ -430,3 +430,49 @@ def test_stream_converges_to_linear_inverse_as_halo_grows():
         diffs.append(np.abs(xs - ref)[200:-200].max())
     assert all(a > 10 * b for a, b in zip(diffs, diffs[1:]))
     assert diffs[-1] < 1e-5
+
+
+# ---- structured prior mask (Section 4.2.2 sample saving, Section 4.3 results) -
+
+def test_saved_paths_match_the_paper():
+    g = GOLD["cg_saved_paths"]["value"]
+    assert O.saved_paths(0.01, 4, 2048) == g["0.01"]
+    assert O.saved_paths(0.10, 4, 2048) == g["0.10"]
+
+
+@pytest.mark.parametrize("N,b,R,L", [(2048, 64, 4, 82), (64, 512, 4, 26), (64, 10, 4, 8), (32, 7, 3, 2)])
+def test_structured_mask_layout(N, b, R, L):
+    m = O.structured_mask(N, b, R, L).reshape(b, N)
+    rows = np.arange(b) % R == 0
+    assert m[~rows].sum() == 0
+    assert int(m.sum()) == L * int(rows.sum())
+    assert np.array_equal(m, m[:, ::-1])  # symmetric about the frame centre
+    assert m[0, N // 2] == 1 and m[0, N // 2 - L // 2] == 1 and m[0, N // 2 + L // 2 - 1] == 1
+    if b % R == 0:
+        assert abs(m.mean() - L / (R * N)) < 1e-15  # beta = L / (R N)
+
+
+def test_structured_prior_beats_wiener_at_the_worst_channel():
+    # Section 4.3's trend at a small size: 25 CG iterations from the Wiener
+    # solution with a structured prior cut the worst-case delta, roughly
+    # halving it at 3 % saved and more at 10 %
+    N, p, b, u = 64, 4, 512, 8
+    w = O.window_sinc_hamming(p, N)
+    x = I.gaussian_timestream(N * b, 21)
+    y = O.pfb_forward(x, w, N, p)
+    sc = O.channel_scales(y, 1 / GOLD["quantizer_spacing_over_rms"]["value"])
+    qr, qi = O.quantize(y, sc)
+    yq = O.dequantize(qr, qi, sc)
+    xw = O.ipfb_wiener_from_spectra(yq, w, N, p, 0.1)
+    wf = O.window_sinc_hamming(4, N * u)
+    Yt = O.upchannelize(x, N * u, 4, wf)
+    dw = O.autospectrum_error(Yt, O.upchannelize(xw, N * u, 4, wf)).max()
+    d = O.row_inverse(yq, N)
+    worst = {}
+    for beta in (0.03, 0.10):
+        m = O.structured_mask(N, b, 4, O.saved_paths(beta, 4, N))
+        xm, _ = O.ml_pcg(d, w, N, p, m, x, 1.0, 0.1, 25, xw)
+        worst[beta] = O.autospectrum_error(Yt, O.upchannelize(xm, N * u, 4, wf)).max()
+    assert 0.04 < dw < 0.25  # the Wiener worst case, as at N = 2048
+    assert worst[0.03] < 0.6 * dw
+    assert worst[0.10] < 0.5 * dw and worst[0.10] < worst[0.03]
