@@ -175,6 +175,31 @@ int ipfb_ml_cg(ipfb_plan plan, int infmt, const void* spec, const float* chan_sc
 /* Autospectrum alone: autospec[k] = (1/nspec) sum_j |y_jk|^2 (double). */
 int ipfb_autospectrum(ipfb_plan plan, const void* y, double* autospec, void* stream);
 
+/* Prior mask of the sample-saving strategy (Section 4.2.2): every R-th
+ * sample of the L sub-filter paths around the frame centre, i.e.
+ * mask[j*lblock + n] = 1 for j = 0 mod R and lblock/2 - L/2 <= n <
+ * lblock/2 + L/2, else 0; the saved fraction is beta = L/(R lblock) when R
+ * divides nblock. mask: device uint8 [nblock*lblock] (ipfb_ml_cg's layout).
+ * L even, 0 <= L <= lblock; R >= 1. */
+int ipfb_mask_structured(ipfb_plan plan, int R, int L, uint8_t* mask, void* stream);
+
+/* Appendix B diagnostics. delta(f) = <|X(f) - Xhat(f)|^2> / <|X(f)|^2>, the
+ * relative error of the power spectrum.
+ * ipfb_delta_analytic: the prediction for white input from the plan's window,
+ * at sub-stream frequencies f = k / nfreq, k < nfreq (out: device double
+ * [nfreq]), with W_n(f) = sum_r h[rN+n] e^{-2 pi i r f}:
+ *   phi > 0 (Wiener):  1 - (1/N) sum_n |W_n|^2 / (|W_n|^2 + phi^2)
+ *   phi = 0 (naive):   (1/snr) (1/N) sum_n 1 / |W_n|^2   (snr > 0 required).
+ * ipfb_autospectrum_error: the measured (Monte-Carlo) delta on the fine plan's
+ * channels, delta[k] = sum_j |Y_jk - Yhat_jk|^2 / sum_j |Y_jk|^2 with Y, Yhat
+ * the up-channelized spectra (as upchannelize) of x_true and x_hat (device
+ * [nblock_f * lblock_f] real each, plan precision; delta: device double
+ * [lblock_f/2+1]; a channel with no power in x_true gives 0/0). The plan
+ * allocates a workspace of one timestream, one set of spectra and two
+ * autospectra on the first call. */
+int ipfb_delta_analytic(ipfb_plan plan, int64_t nfreq, double phi, double snr, double* out, void* stream);
+int ipfb_autospectrum_error(ipfb_plan fine, const void* x_true, const void* x_hat, double* delta, void* stream);
+
 /* Input synthesis (Section 4.3 quantiser): per-channel scale
  * s_k = float(levels_rms / sigma_k), sigma_k = sqrt(mean_j |y_jk|^2 / 2)
  * (1 for a channel with no power), then q = clip(rint(s_k y), -7, 7) on real

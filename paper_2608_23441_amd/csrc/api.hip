@@ -104,6 +104,9 @@ struct ipfb_plan_s {
   double* cg_sc = nullptr;
   int jchunk = 1, nchunks = 1;
   int fchunk = 1, nfchunks = 1;  // long frames: frames per power-sum chunk
+  // Appendix B diagnostics (allocated on first use): x_true - x_hat, the
+  // spectra of either, and the two autospectra
+  void* diag = nullptr;
   size_t bytes = 0;
 };
 
@@ -146,7 +149,7 @@ void free_bplan(ipfb_bplan p);
 void free_plan(ipfb_plan p) {
   if (p->blu1) free_bplan(p->blu1);
   void* ptrs[] = {p->win64, p->winT, p->twN, p->twB, p->twB64, p->work, p->work2, p->tmp, p->part, p->fac, p->twS,
-                  p->cg, p->cg_autoc, p->cg_part, p->cg_sc};
+                  p->cg, p->cg_autoc, p->cg_part, p->cg_sc, p->diag};
   for (void* q : ptrs)
     if (q) hipFree(q);
   delete p;
@@ -688,6 +691,54 @@ int upchannelize(ipfb_plan fine, const void* x, void* y_fine, double* autospec, 
   if (s) return s;
   if (autospec) return ipfb_autospectrum(fine, y_fine, autospec, stream);
   return ok();
+}
+
+int ipfb_mask_structured(ipfb_plan p, int R, int L, uint8_t* mask, void* stream) {
+  if (check_plan(p)) return IPFB_EINVAL;
+  if (!mask) return fail(IPFB_EINVAL, "mask must be a non-NULL device pointer");
+  if (R < 1) return fail(IPFB_EINVAL, "R must be >= 1");
+  if (L < 0 || L > p->lblock || (L & 1)) return fail(IPFB_EINVAL, "L must be even and in [0, lblock]");
+  DeviceGuard g(p->dev);
+  return launched(launch_mask_structured(mask, p->lblock, p->nblock, R, L, (hipStream_t)stream),
+                  "ipfb_mask_structured");
+}
+
+int ipfb_delta_analytic(ipfb_plan p, int64_t nfreq, double phi, double snr, double* out, void* stream) {
+  if (check_plan(p)) return IPFB_EINVAL;
+  if (!out) return fail(IPFB_EINVAL, "out must be a non-NULL device pointer");
+  if (nfreq < 1 || nfreq > (int64_t(1) << 31) - 1) return fail(IPFB_EINVAL, "nfreq must be in [1, 2^31)");
+  if (!(phi >= 0.0) || !std::isfinite(phi)) return fail(IPFB_EINVAL, "phi must be finite and >= 0");
+  if (phi == 0.0 && !(snr > 0.0 && std::isfinite(snr))) return fail(IPFB_EINVAL, "phi = 0 needs a finite snr > 0");
+  DeviceGuard g(p->dev);
+  return launched(launch_delta_analytic(p->win64, p->lblock, p->ntap, nfreq, phi, snr, out, (hipStream_t)stream),
+                  "ipfb_delta_analytic");
+}
+
+int ipfb_autospectrum_error(ipfb_plan fine, const void* x_true, const void* x_hat, double* delta, void* stream) {
+  if (check_plan(fine)) return IPFB_EINVAL;
+  if (!x_true || !x_hat || !delta) return fail(IPFB_EINVAL, "x_true, x_hat and delta must be non-NULL");
+  DeviceGuard g(fine->dev);
+  const int64_t S = (int64_t)fine->nblock * fine->lblock;
+  const int K = fine->lblock / 2 + 1;
+  const size_t es = esize(fine->prec);
+  const size_t diff_b = (size_t)S * es, y_b = (size_t)fine->nblock * K * 2 * es;
+  if (!fine->diag) {
+    int s2 = dev_alloc(fine, &fine->diag, diff_b + y_b + 2 * (size_t)K * sizeof(double));
+    if (s2) return s2;
+  }
+  char* base = (char*)fine->diag;
+  void* diff = base;
+  void* Y = base + diff_b;
+  double* A_true = (double*)(base + diff_b + y_b);
+  double* A_diff = A_true + K;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_sub(fine->prec, x_true, x_hat, diff, S, st);
+  if (e != hipSuccess) return launched(e, "ipfb_autospectrum_error");
+  // the forward PFB is linear: the spectra of x_true - x_hat are Y - Yhat
+  int s2 = upchannelize(fine, x_true, Y, A_true, stream);
+  if (!s2) s2 = upchannelize(fine, diff, Y, A_diff, stream);
+  if (s2) return s2;
+  return launched(launch_ratio(A_diff, A_true, delta, K, st), "ipfb_autospectrum_error");
 }
 
 int ipfb_quantize_c4(ipfb_plan p, const void* y, double levels_rms, uint8_t* packed, float* scales, void* stream) {

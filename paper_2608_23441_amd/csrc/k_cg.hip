@@ -262,13 +262,18 @@ __global__ __launch_bounds__(kCgNT) void k_cg_xr(T* __restrict__ x, T* __restric
   if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 
-// p = z + beta p   (beta from the scalars; first iteration: p = z with beta = 0)
+// p = z + beta p   (beta from the scalars); first iteration p = z, without
+// reading p (the workspace starts uninitialised, and 0 * NaN is NaN)
 template <typename T>
 __global__ __launch_bounds__(kCgNT) void k_cg_p(T* __restrict__ p, const T* __restrict__ z,
                                                 const double* __restrict__ sc, int use_beta, int64_t S) {
-  const T beta = use_beta ? T(sc[4]) : T(0);
-  for (int64_t e = (int64_t)blockIdx.x * kCgNT + threadIdx.x; e < S; e += (int64_t)gridDim.x * kCgNT)
-    p[e] = z[e] + beta * p[e];
+  const int64_t e0 = (int64_t)blockIdx.x * kCgNT + threadIdx.x, stride = (int64_t)gridDim.x * kCgNT;
+  if (!use_beta) {
+    for (int64_t e = e0; e < S; e += stride) p[e] = z[e];
+    return;
+  }
+  const T beta = T(sc[4]);
+  for (int64_t e = e0; e < S; e += stride) p[e] = z[e] + beta * p[e];
 }
 
 // one workgroup: sum the partials in a fixed order and update the scalars

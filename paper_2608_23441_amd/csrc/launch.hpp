@@ -133,6 +133,17 @@ hipError_t launch_pfb_fwd_long(int prec, int log2n, int pass, const void* x, voi
                                const void* winT, const void* twS, void* tmp, int fchunk, double* part,
                                hipStream_t st);
 
+// Appendix B diagnostics: d = a - b (n reals); out = num / den (n doubles);
+// the predicted delta(f) at f = k / nfreq for white input (phi > 0: Wiener,
+// phi = 0: naive with the given SNR).
+hipError_t launch_sub(int prec, const void* a, const void* b, void* d, int64_t n, hipStream_t st);
+hipError_t launch_ratio(const double* num, const double* den, double* out, int n, hipStream_t st);
+hipError_t launch_delta_analytic(const double* win64, int N, int ntap, int64_t nfreq, double phi, double snr,
+                                 double* out, hipStream_t st);
+
+// the structured prior mask: 1 at frames j = 0 mod R of paths [N/2 - L/2, N/2 + L/2)
+hipError_t launch_mask_structured(uint8_t* mask, int N, int64_t nblock, int R, int L, hipStream_t st);
+
 // bytes zero bytes at p (a kernel, so that it may sit in a captured graph)
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 

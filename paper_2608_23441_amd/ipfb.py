@@ -28,7 +28,7 @@ EXPORTS = (
     "ipfb_batched_plan_create", "ipfb_batched_plan_destroy", "ipfb_batched_workspace_size",
     "ipfb_batched_use_graph", "ipfb_wiener_batched", "ipfb_batched_get_shape",
     "ipfb_batched_set_shape", "ipfb_batched_tune", "ipfb_stream_plan_create", "ipfb_stream_plan_destroy",
-    "ipfb_wiener_stream",
+    "ipfb_wiener_stream", "ipfb_delta_analytic", "ipfb_autospectrum_error", "ipfb_mask_structured",
 )
 
 
@@ -75,6 +75,9 @@ def lib():
         L.ipfb_stream_plan_create.argtypes = [ctypes.POINTER(vp), i32, i32, vp, i64, i32, i32]
         L.ipfb_stream_plan_destroy.argtypes = [vp]
         L.ipfb_wiener_stream.argtypes = [vp, i32, vp, vp, i64, dbl, i32, vp, vp]
+        L.ipfb_delta_analytic.argtypes = [vp, i64, dbl, dbl, vp, vp]
+        L.ipfb_autospectrum_error.argtypes = [vp, vp, vp, vp, vp]
+        L.ipfb_mask_structured.argtypes = [vp, i32, i32, vp, vp]
         L.ipfb_profile_enable.argtypes = [i32]
         L.ipfb_profile_reset.argtypes = []
         L.ipfb_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
@@ -284,6 +287,35 @@ def quantize_c4(plan: Plan, y, levels_rms: float = 2.5, stream=None):
     _check(lib().ipfb_quantize_c4(plan.handle, plan._cplx(y, "y"), float(levels_rms), _ptr(packed, "packed"),
                                   _ptr(scales, "scales"), _stream(stream)))
     return packed, scales
+
+
+def mask_structured(plan: Plan, R: int, L: int, out=None, stream=None):
+    """The structured prior mask (uint8 [nblock * lblock] on the GPU)."""
+    import torch
+    if out is None:
+        out = _empty((plan.nblock * plan.lblock,), torch.uint8)
+    _check(lib().ipfb_mask_structured(plan.handle, int(R), int(L), _ptr(out, "mask"), _stream(stream)))
+    return out
+
+
+def delta_analytic(plan: Plan, nfreq: int, phi: float = 0.1, snr: float = 0.0, out=None, stream=None):
+    """Appendix B's predicted delta(f) at f = k / nfreq (float64 [nfreq] on the GPU)."""
+    import torch
+    if out is None:
+        out = _empty((int(nfreq),), torch.float64)
+    _check(lib().ipfb_delta_analytic(plan.handle, int(nfreq), float(phi), float(snr), _ptr(out, "out"),
+                                     _stream(stream)))
+    return out
+
+
+def autospectrum_error(fine: Plan, x_true, x_hat, out=None, stream=None):
+    """Measured delta on the fine plan's channels (float64 [lblock_f/2+1])."""
+    import torch
+    if out is None:
+        out = _empty((fine.nchan,), torch.float64)
+    _check(lib().ipfb_autospectrum_error(fine.handle, fine._real(x_true, "x_true"), fine._real(x_hat, "x_hat"),
+                                         _ptr(out, "out"), _stream(stream)))
+    return out
 
 
 def profile_enable(on: bool = True):

@@ -148,3 +148,20 @@ def test_autograd_backward_is_adjoint_and_finite_differences_fp32():
     lm = np.real(np.vdot(c, O.pfb_forward(x0 - h * v, w, N, p)))
     fd = (lp - lm) / (2 * h)
     assert abs(fd - np.dot(g, v)) / abs(fd) < 1e-4
+
+
+@pytest.mark.parametrize("prec", [ipfb.F32, ipfb.F64])
+def test_ml_cg_reads_no_workspace_before_writing_it(prec):
+    # device memory handed back with NaN in it; the CG workspace is allocated
+    # afterwards and may land on those pages: the first search direction must
+    # be set, not updated from whatever the workspace held
+    N, p, b = 64, 4, 512
+    w, x, packed, s, mask, d = _ml_case(N, p, b, 330)
+    poison = torch.full((64 << 20,), float("nan"), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    del poison
+    torch.cuda.empty_cache()
+    plan = ipfb.Plan(N, p, w, b, prec)
+    dt = torch.float64 if prec == ipfb.F64 else torch.float32
+    xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(mask.astype(np.uint8)), _dev(x).to(dt), 1.0, 0.1, 0.1, 3)
+    assert np.all(np.isfinite(_host(xg))) and np.all(np.isfinite(_host(ng)))
