@@ -214,6 +214,45 @@ def column_inverse(d: np.ndarray, window: np.ndarray, lblock: int, ntap: int,
     return np.fft.ifft(G * D, axis=0).real
 
 
+def filter_gain(W: np.ndarray, kind: str, param: float = 0.0, nu: np.ndarray | None = None,
+                normalise: bool = True) -> np.ndarray:
+    """Other eigenvalue filters (Section 4.1: the circulant form gives the
+    eigenspectrum W_n(f), so any filter H_n(f) applies as G = H / conj(W)).
+
+    kind "threshold": H = 1 where |W| >= param, else 0 (the truncated
+    pseudo-inverse; eigenvalues below the threshold are dropped).
+    kind "psd": the general Wiener filter S/(S+N) with a noise-to-signal ratio
+    per frequency, nu[f] = N(f)/S(f) (an array of length b, read as
+    nu[min(f, b - f)]), H = |W|^2 (1 + nu) / (|W|^2 + nu), the (1 + nu) factor
+    dropped with normalise=False; a constant nu = phi^2 is the Wiener filter.
+    W: [b, N]; returns G [b, N].
+    """
+    W = np.asarray(W, dtype=np.complex128)
+    b = W.shape[0]
+    a2 = np.abs(W) ** 2
+    if kind == "threshold":
+        keep = np.abs(W) >= param
+        G = np.zeros_like(W)
+        G[keep] = 1.0 / np.conj(W[keep])
+        return G
+    if kind == "psd":
+        f = np.arange(b)
+        v = np.asarray(nu, dtype=np.float64)[np.minimum(f, b - f) % b][:, None]
+        c = (1.0 + v) if normalise else 1.0
+        return W * c / (a2 + v)
+    raise ValueError(kind)
+
+
+def column_inverse_filter(d: np.ndarray, window: np.ndarray, lblock: int, ntap: int, kind: str,
+                          param: float = 0.0, nu: np.ndarray | None = None,
+                          normalise: bool = True) -> np.ndarray:
+    """xhat_n = F^dagger[ G_n . F d_n ] with a filter_gain eigenvalue filter."""
+    d = np.asarray(d, dtype=np.float64)
+    W = column_spectra(window, lblock, ntap, d.shape[0])
+    G = filter_gain(W, kind, param, nu, normalise)
+    return np.fft.ifft(G * np.fft.fft(d, axis=0), axis=0).real
+
+
 def ipfb_wiener_from_spectra(yhat: np.ndarray, window: np.ndarray, lblock: int,
                              ntap: int, phi: float, normalise: bool = True) -> np.ndarray:
     """Full circulant inverse of (dequantised) spectra; returns x[j*N+n] float64."""

@@ -476,3 +476,40 @@ def test_structured_prior_beats_wiener_at_the_worst_channel():
     assert 0.04 < dw < 0.25  # the Wiener worst case, as at N = 2048
     assert worst[0.03] < 0.6 * dw
     assert worst[0.10] < 0.5 * dw and worst[0.10] < worst[0.03]
+
+
+# ---- other eigenvalue filters (Section 4.1: arbitrary filtering of the eigenspectrum)
+
+def test_threshold_filter_is_the_truncated_pseudo_inverse():
+    # numpy's SVD-based pinv of the dense circulant with the same cut: the
+    # circulant's singular values are |W_n(f)|
+    N, p, b = 8, 4, 24
+    w = O.window_sinc_hamming(p, N)
+    d = np.random.default_rng(31).standard_normal((b, N))
+    W = O.column_spectra(w, N, p, b)
+    for n in range(N):
+        tau = np.quantile(np.abs(W[:, n]), 0.3)  # drop about 30 % of the eigenvalues
+        wn = w.reshape(p, N)[:, n]
+        C = O.dense_circulant(wn, b)
+        sv = np.linalg.svd(C, compute_uv=False)
+        rc = (tau * (1 - 1e-9)) / sv.max()  # keep singular values >= tau
+        ref = np.linalg.pinv(C, rcond=rc) @ d[:, n]
+        got = O.column_inverse_filter(d, w, N, p, "threshold", tau * (1 - 1e-9))[:, n]
+        assert np.abs(got - ref).max() < 1e-10 * max(1.0, np.abs(ref).max())
+
+
+def test_psd_filter_is_a_dense_map_solve_and_reduces_to_wiener():
+    N, p, b = 8, 4, 20
+    w = O.window_sinc_hamming(p, N)
+    d = np.random.default_rng(32).standard_normal((b, N))
+    f = np.arange(b)
+    nu = 0.01 + 0.2 * np.cos(np.pi * f / b) ** 2  # symmetric: nu(f) = nu(b - f)
+    got = O.column_inverse_filter(d, w, N, p, "psd", nu=nu, normalise=False)
+    # (C^T C + Nu) x = C^T d with Nu the circulant whose eigenvalues are nu
+    Nu = np.real(np.fft.ifft(np.fft.fft(np.eye(b), axis=0) * nu[:, None], axis=0))
+    for n in range(N):
+        C = O.dense_circulant(w.reshape(p, N)[:, n], b)
+        ref = np.linalg.solve(C.T @ C + Nu, C.T @ d[:, n])
+        assert np.abs(got[:, n] - ref).max() < 1e-10
+    const = O.column_inverse_filter(d, w, N, p, "psd", nu=np.full(b, 0.09))
+    assert np.abs(const - O.column_inverse(d, w, N, p, 0.3)).max() < 1e-12
