@@ -114,6 +114,24 @@ int ipfb_wiener(ipfb_plan plan, int infmt, const void* spec, const float* chan_s
 int ipfb_wiener_ex(ipfb_plan plan, int infmt, const void* spec, const float* chan_scale, double phi,
                    int normalise, void* x_out, void* stream);
 
+/* Other eigenvalue filters (Section 4.1: the circulant form gives the
+ * eigenspectrum W_n(f) of every sub-filter, so any filter H_n(f) applies as
+ * G = H / conj(W) at no extra cost). As ipfb_wiener_ex, with the gain
+ *   IPFB_FILTER_WIENER:    the Wiener filter with phi = param;
+ *   IPFB_FILTER_THRESHOLD: H = 1 where |W_n(f)| >= param, else 0 (the
+ *                          truncated pseudo-inverse);
+ *   IPFB_FILTER_NU:        the general Wiener filter S/(S+N) with a
+ *                          noise-to-signal ratio per frequency,
+ *                          H = |W|^2 (1 + nu_f) / (|W|^2 + nu_f) (the
+ *                          (1 + nu_f) factor dropped with normalise = 0);
+ *                          nu: device double [nblock/2 + 1], nu_f >= 0 for
+ *                          f = 0 .. nblock/2 (nu_{b-f} is taken as nu_f).
+ * Power-of-two nblock only (the LDS column path); param is ignored for
+ * IPFB_FILTER_NU and nu for the others. */
+enum { IPFB_FILTER_WIENER = 0, IPFB_FILTER_THRESHOLD = 1, IPFB_FILTER_NU = 2 };
+int ipfb_wiener_filter(ipfb_plan plan, int infmt, const void* spec, const float* chan_scale, int kind, double param,
+                       const double* nu, int normalise, void* x_out, void* stream);
+
 /* Linear boundary, streaming (Section 3.1: real data are not circulant; the
  * data are extended to b frames, and the circulant inverse corrupts only the
  * samples within a decorrelation-kernel width of the ends). Input: nspec

@@ -400,6 +400,43 @@ int pfb_adjoint(ipfb_plan p, const void* y, void* x, void* stream) {
   return launched(e, "pfb_adjoint");
 }
 
+}  // extern "C"
+
+namespace {
+
+// Row stage into x_out, then the column stage in place there (power-of-two
+// nblock); kind/param/nu select the eigenvalue filter of the gain pass.
+int wiener_lds(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, int kind, double param,
+               const double* nu, int normalise, void* x_out, void* stream) {
+  DeviceGuard g(p->dev);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e;
+  {
+    ProfScope ps("ipfb_rows", st);
+    e = hipErrorNotSupported;
+    if (infmt == IPFB_IN_C4) e = launch_row_c4(p->prec, p->log2n, spec, chan_scale, x_out, p->nblock, p->twN, st);
+    if (e == hipErrorNotSupported) {
+      hipGetLastError();
+      if (infmt == IPFB_IN_C4) e = launch_dequant_factors(p->prec, chan_scale, p->lblock / 2 + 1, p->lblock, p->fac, st);
+      else e = hipSuccess;
+      if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec, p->fac, x_out, p->nblock, p->twN, st);
+    }
+  }
+  // column stage in place on x_out: d [b][N] -> x [b][N]
+  static const char* const pass_names[3] = {"ipfb_cols_fwd", "ipfb_cols_gain", "ipfb_cols_inv"};
+  for (int pass = 0; pass < 3 && e == hipSuccess; ++pass) {
+    if (p->log2b <= 9 && pass != 1) continue;  // one pass does the whole stage
+    ProfScope ps(pass_names[pass], st);
+    e = launch_col_wiener_nat(p->prec, p->log2b, pass, x_out, p->lblock, p->ntap, p->win64, param, normalise, p->twB,
+                              p->twB64, st, 0, -1, nullptr, 0, 0, kind, nu);
+  }
+  return launched(e, "ipfb_wiener");
+}
+
+}  // namespace
+
+extern "C" {
+
 int ipfb_wiener_ex(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, double phi, int normalise,
                    void* x_out, void* stream) {
   if (check_plan(p)) return IPFB_EINVAL;
@@ -429,29 +466,25 @@ int ipfb_wiener_ex(ipfb_plan p, int infmt, const void* spec, const float* chan_s
     void* xo[1] = {x_out};
     return ipfb_wiener_batched(p->blu1, infmt, sp, chan_scale ? scs : nullptr, phi, normalise, xo, stream);
   }
-  DeviceGuard g(p->dev);
-  hipStream_t st = (hipStream_t)stream;
-  hipError_t e;
-  {
-    ProfScope ps("ipfb_rows", st);
-    e = hipErrorNotSupported;
-    if (infmt == IPFB_IN_C4) e = launch_row_c4(p->prec, p->log2n, spec, chan_scale, x_out, p->nblock, p->twN, st);
-    if (e == hipErrorNotSupported) {
-      hipGetLastError();
-      if (infmt == IPFB_IN_C4) e = launch_dequant_factors(p->prec, chan_scale, p->lblock / 2 + 1, p->lblock, p->fac, st);
-      else e = hipSuccess;
-      if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec, p->fac, x_out, p->nblock, p->twN, st);
-    }
-  }
-  // column stage in place on x_out: d [b][N] -> x [b][N]
-  static const char* const pass_names[3] = {"ipfb_cols_fwd", "ipfb_cols_gain", "ipfb_cols_inv"};
-  for (int pass = 0; pass < 3 && e == hipSuccess; ++pass) {
-    if (p->log2b <= 9 && pass != 1) continue;  // one pass does the whole stage
-    ProfScope ps(pass_names[pass], st);
-    e = launch_col_wiener_nat(p->prec, p->log2b, pass, x_out, p->lblock, p->ntap, p->win64, phi, normalise, p->twB,
-                              p->twB64, st);
-  }
-  return launched(e, "ipfb_wiener");
+  return wiener_lds(p, infmt, spec, chan_scale, 0, phi, nullptr, normalise, x_out, stream);
+}
+
+int ipfb_wiener_filter(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, int kind, double param,
+                       const double* nu, int normalise, void* x_out, void* stream) {
+  if (check_plan(p)) return IPFB_EINVAL;
+  if (!spec || !x_out) return fail(IPFB_EINVAL, "spec and x_out must be non-NULL device pointers");
+  if (infmt != IPFB_IN_C4 && infmt != IPFB_IN_CF32 && infmt != IPFB_IN_CF64)
+    return fail(IPFB_EINVAL, "unknown input format %d", infmt);
+  if (infmt == IPFB_IN_C4 && !chan_scale) return fail(IPFB_EINVAL, "chan_scale is required for IPFB_IN_C4");
+  if (kind != IPFB_FILTER_WIENER && kind != IPFB_FILTER_THRESHOLD && kind != IPFB_FILTER_NU)
+    return fail(IPFB_EINVAL, "unknown filter kind %d", kind);
+  if (kind != IPFB_FILTER_NU && (!(param >= 0.0) || !std::isfinite(param)))
+    return fail(IPFB_EINVAL, "param must be finite and >= 0");
+  if (kind == IPFB_FILTER_NU && !nu) return fail(IPFB_EINVAL, "the noise-to-signal filter needs nu");
+  if (!p->row_lds || !p->col_lds)
+    return fail(IPFB_EUNSUPPORTED, "ipfb_wiener_filter needs a power-of-two nblock <= 2^%d and lblock <= 2^%d",
+                max_log2_col(p->prec), max_log2_row(p->prec));
+  return wiener_lds(p, infmt, spec, chan_scale, kind, param, nu, normalise, x_out, stream);
 }
 
 int ipfb_wiener(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, double phi, void* x_out,

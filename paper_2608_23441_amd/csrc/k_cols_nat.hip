@@ -33,10 +33,17 @@ namespace ipfb {
 struct NatGain {
   const double* win;  // [ntap][lblock], FP64
   int lblock, ntap;
-  double phi2;        // phi^2
-  double gnorm;       // (1 + phi^2) / b, or 1/b without the normalisation
+  double phi2;        // phi^2 (threshold filter: tau^2)
+  double gnorm;       // (1 + phi^2) / b, or 1/b without the normalisation (other filters: 1/b)
   int naive;          // phi == 0: 1/conj(W), eigenvalues at rounding level dropped
+  const double* nu;   // noise-to-signal filter: nu[f], f in [0, b/2]
+  int norm;           // noise-to-signal filter: keep the (1 + nu) factor
 };
+
+// Filter kinds of the gain pass (a template parameter, so the Wiener pass is
+// unchanged by the others): 0 Wiener / naive, 1 hard threshold |W| >= tau,
+// 2 Wiener with a noise-to-signal ratio per frequency.
+constexpr int kGainWiener = 0, kGainThreshold = 1, kGainNu = 2;
 
 template <typename T>
 struct NatCfg {
@@ -75,6 +82,27 @@ __device__ __forceinline__ void pair_gains(const NatGain& ga, cx<double> Wa, cx<
   rc = rc * fma(-den, rc, 2.0);
   const double r = ga.gnorm * rc;
   const double sa = dc * r, sc = da * r;
+  Ga = mk<double>(Wa.x * sa, Wa.y * sa);
+  Gc = mk<double>(Wc.x * sc, Wc.y * sc);
+}
+
+// The other filters at frequency f in [0, b/2] (the same gain for both paths' formula):
+// threshold: G = W / |W|^2 / b where |W|^2 >= tau^2, else 0;
+// noise-to-signal: G = W c / (|W|^2 + nu_f) / b, c = 1 + nu_f or 1.
+template <int GK>
+__device__ __forceinline__ void pair_gains_kind(const NatGain& ga, cx<double> Wa, cx<double> Wc, int f,
+                                                cx<double>& Ga, cx<double>& Gc) {
+  const double aa = Wa.x * Wa.x + Wa.y * Wa.y, ac = Wc.x * Wc.x + Wc.y * Wc.y;
+  double sa, sc;
+  if constexpr (GK == kGainThreshold) {
+    sa = aa >= ga.phi2 ? ga.gnorm / aa : 0.0;
+    sc = ac >= ga.phi2 ? ga.gnorm / ac : 0.0;
+  } else {
+    const double v = ga.nu[f];
+    const double c = (ga.norm ? 1.0 + v : 1.0) * ga.gnorm;
+    sa = c / (aa + v);
+    sc = c / (ac + v);
+  }
   Ga = mk<double>(Wa.x * sa, Wa.y * sa);
   Gc = mk<double>(Wc.x * sc, Wc.y * sc);
 }
@@ -151,7 +179,7 @@ __device__ __forceinline__ void gain_item(int kk, int it, int& sk, int& k2, int&
 // Pass B (or the whole stage when b1 = 1): b2-point FFTs of the rows k1 and
 // b1 - k1 of one tile, separation of the two real spectra of each pair, FP64
 // gains, re-packing, inverse FFTs, and the inverse four-step twiddle.
-template <typename T, int LOG2B1, int LOG2B2, int NTAP>
+template <typename T, int LOG2B1, int LOG2B2, int NTAP, int GK = kGainWiener>
 __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * NatCfg<T>::TP * (1 << LOG2B2) /
                                                  NatCfg<T>::EPT)),
                              4) void k_nat_mid(cx<T>* __restrict__ z, int np, int t0, int ntile, NatGain ga,
@@ -222,13 +250,20 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * N
       Wa = horner_g(ga.win, N, na, ga.ntap, zf);
       Wc = horner_g(ga.win, N, nc, ga.ntap, zf);
     }
-    pair_gains(ga, Wa, Wc, wsa, wsc, Ga, Gc);
+    if constexpr (GK == kGainWiener) {
+      pair_gains(ga, Wa, Wc, wsa, wsc, Ga, Gc);
+    } else {
+      // the item's frequency: row k1 of its set (b1/2 for the second set of
+      // kk = 0) plus b1 k2, folded to [0, b/2] (the filter is even in f)
+      const int f = ((NS == 2 && kk == 0 && sk == 1) ? B1 / 2 : ka) + B1 * k2;
+      pair_gains_kind<GK>(ga, Wa, Wc, f <= B - f ? f : B - f, Ga, Gc);
+    }
   };
   // FP32 form with 4 taps: the first NPRE gains of this thread are formed
   // (FP64, then rounded once) while the workgroup's loads are in flight, and
   // kept in registers until the spectra are ready; the rest follow the FFT
   // (only where the register budget holds them without spilling: b2 = 128)
-  constexpr bool PRE = sizeof(T) == 4 && NTAP == 4 && B2 == 128;
+  constexpr bool PRE = sizeof(T) == 4 && NTAP == 4 && B2 == 128 && GK == kGainWiener;
   constexpr int NPRE = PRE ? (IMAX < 2 ? IMAX : 2) : 1;  // gains held across the FFT
   cx<T> gpre[NPRE][2];
   {
@@ -314,9 +349,25 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * N
   }
 }
 
+// The gain pass with the filter kind chosen at run time: the Wiener filter
+// with the 4-tap fast path, the other kinds with the generic tap loop.
+template <typename T, int L1, int L2>
+static void launch_mid(int kind, dim3 grid, dim3 nt, cx<T>* z, int np, int tile0, int ntiles, const NatGain& ga,
+                       const cx<T>* tw, const cx<double>* tw64, hipStream_t st) {
+  if (kind == kGainThreshold)
+    k_nat_mid<T, L1, L2, 0, kGainThreshold><<<grid, nt, 0, st>>>(z, np, tile0, ntiles, ga, tw, tw64);
+  else if (kind == kGainNu)
+    k_nat_mid<T, L1, L2, 0, kGainNu><<<grid, nt, 0, st>>>(z, np, tile0, ntiles, ga, tw, tw64);
+  else if (ga.ntap == 4)
+    k_nat_mid<T, L1, L2, 4><<<grid, nt, 0, st>>>(z, np, tile0, ntiles, ga, tw, tw64);
+  else
+    k_nat_mid<T, L1, L2, 0><<<grid, nt, 0, st>>>(z, np, tile0, ntiles, ga, tw, tw64);
+}
+
 template <typename T, int LOG2B>
 static hipError_t launch_nat_t(int pass, void* zv, int lblock, int tile0, int ntiles, const NatGain& ga,
-                               const void* twv, const double* tw64v, hipStream_t st, void* out, int r0, int nr) {
+                               const void* twv, const double* tw64v, hipStream_t st, void* out, int r0, int nr,
+                               int kind) {
   using Cfg = NatCfg<T>;
   cx<T>* z = (cx<T>*)zv;
   const cx<T>* tw = (const cx<T>*)twv;
@@ -329,10 +380,7 @@ static hipError_t launch_nat_t(int pass, void* zv, int lblock, int tile0, int nt
     if (out) return hipErrorInvalidValue;  // the one-pass form works in place only
     if (pass != 1) return hipSuccess;
     constexpr int NT = Cfg::clampnt(Cfg::TP * (1 << LOG2B) / Cfg::EPT);
-    if (ga.ntap == 4)
-      k_nat_mid<T, 0, LOG2B, 4><<<dim3(ntiles), dim3(NT), 0, st>>>(z, np, tile0, ntiles, ga, tw, tw64);
-    else
-      k_nat_mid<T, 0, LOG2B, 0><<<dim3(ntiles), dim3(NT), 0, st>>>(z, np, tile0, ntiles, ga, tw, tw64);
+    launch_mid<T, 0, LOG2B>(kind, dim3(ntiles), dim3(NT), z, np, tile0, ntiles, ga, tw, tw64, st);
   } else {
     constexpr int L1 = LOG2B / 2, L2 = LOG2B - L1;
     constexpr int NTO = Cfg::clampnt(Cfg::TP * (1 << L1) / Cfg::EPT);
@@ -340,12 +388,8 @@ static hipError_t launch_nat_t(int pass, void* zv, int lblock, int tile0, int nt
     if (pass == 0)
       k_nat_outer<T, L1, L2, -1><<<dim3(ntiles * (1 << L2)), dim3(NTO), 0, st>>>(z, np, tile0, ntiles, tw, nullptr,
                                                                                   0, 0);
-    if (pass == 1 && ga.ntap == 4)
-      k_nat_mid<T, L1, L2, 4><<<dim3(ntiles * (1 << (L1 - 1))), dim3(NTM), 0, st>>>(z, np, tile0, ntiles, ga, tw,
-                                                                                      tw64);
-    if (pass == 1 && ga.ntap != 4)
-      k_nat_mid<T, L1, L2, 0><<<dim3(ntiles * (1 << (L1 - 1))), dim3(NTM), 0, st>>>(z, np, tile0, ntiles, ga, tw,
-                                                                                      tw64);
+    if (pass == 1)
+      launch_mid<T, L1, L2>(kind, dim3(ntiles * (1 << (L1 - 1))), dim3(NTM), z, np, tile0, ntiles, ga, tw, tw64, st);
     if (pass == 2)
       k_nat_outer<T, L1, L2, +1><<<dim3(ntiles * (1 << L2)), dim3(NTO), 0, st>>>(z, np, tile0, ntiles, tw,
                                                                                   (cx<T>*)out, r0, nr);
@@ -354,7 +398,7 @@ static hipError_t launch_nat_t(int pass, void* zv, int lblock, int tile0, int nt
 }
 
 #define NAT_CASE(T, L) \
-  case L: return launch_nat_t<T, L>(pass, z, lblock, tile0, ntiles, ga, twB, twB64, st, out, r0, nr);
+  case L: return launch_nat_t<T, L>(pass, z, lblock, tile0, ntiles, ga, twB, twB64, st, out, r0, nr, kind);
 
 int nat_tiles(int prec, int lblock) {
   const int tp = prec == F32 ? NatCfg<float>::TP : NatCfg<double>::TP;
@@ -363,8 +407,9 @@ int nat_tiles(int prec, int lblock) {
 
 hipError_t launch_col_wiener_nat(int prec, int log2b, int pass, void* z, int lblock, int ntap, const double* win64,
                                  double phi, int normalise, const void* twB, const double* twB64, hipStream_t st,
-                                 int tile0, int ntiles, void* out, int r0, int nr) {
+                                 int tile0, int ntiles, void* out, int r0, int nr, int kind, const double* nu) {
   if (lblock < 2 || (lblock & 1) || pass < 0 || pass > 2) return hipErrorInvalidValue;
+  if (kind < kGainWiener || kind > kGainNu || (kind == kGainNu && !nu)) return hipErrorInvalidValue;
   if (out && (pass != 2 || r0 < 0 || nr < 0 || r0 + nr > (1 << log2b))) return hipErrorInvalidValue;
   NatGain ga;
   ga.win = win64;
@@ -373,6 +418,12 @@ hipError_t launch_col_wiener_nat(int prec, int log2b, int pass, void* z, int lbl
   ga.phi2 = phi * phi;
   ga.naive = phi == 0.0;
   ga.gnorm = (normalise ? (1.0 + phi * phi) : 1.0) / (double)(1LL << log2b);
+  ga.nu = nu;
+  ga.norm = normalise;
+  if (kind != kGainWiener) {  // phi carries tau for the threshold filter
+    ga.naive = 0;
+    ga.gnorm = 1.0 / (double)(1LL << log2b);
+  }
   if (prec == F32) {
     switch (log2b) {
       NAT_CASE(float, 2) NAT_CASE(float, 3) NAT_CASE(float, 4) NAT_CASE(float, 5) NAT_CASE(float, 6)

@@ -69,10 +69,14 @@ hipError_t launch_col_wiener(int prec, int log2b, const void* d, void* xo, int l
 // the three passes of a tile range may run before those of the next range.
 // out != NULL (pass 2 with b > 512 only): frames [r0, r0 + nr) of the result
 // go to out (nr frames, same row layout) instead of z, and the others nowhere.
+// kind (the gain pass): 0 the Wiener filter (phi), 1 the hard threshold
+// |W| >= phi, 2 the Wiener filter with noise-to-signal nu[f] per frequency
+// (f in [0, b/2], device doubles).
 int nat_tiles(int prec, int lblock);
 hipError_t launch_col_wiener_nat(int prec, int log2b, int pass, void* z, int lblock, int ntap, const double* win64,
                                  double phi, int normalise, const void* twB, const double* twB64, hipStream_t st,
-                                 int tile0 = 0, int ntiles = -1, void* out = nullptr, int r0 = 0, int nr = 0);
+                                 int tile0 = 0, int ntiles = -1, void* out = nullptr, int r0 = 0, int nr = 0,
+                                 int kind = 0, const double* nu = nullptr);
 
 // Maximum-likelihood CG pieces (vectors in the transposed layout [N][b]).
 hipError_t launch_cg_autocorr(const double* win64, int N, int ntap, double* autoc, hipStream_t st);

@@ -29,7 +29,9 @@ EXPORTS = (
     "ipfb_batched_use_graph", "ipfb_wiener_batched", "ipfb_batched_get_shape",
     "ipfb_batched_set_shape", "ipfb_batched_tune", "ipfb_stream_plan_create", "ipfb_stream_plan_destroy",
     "ipfb_wiener_stream", "ipfb_delta_analytic", "ipfb_autospectrum_error", "ipfb_mask_structured",
+    "ipfb_wiener_filter",
 )
+FILTER_WIENER, FILTER_THRESHOLD, FILTER_NU = 0, 1, 2
 
 
 class IpfbError(RuntimeError):
@@ -78,6 +80,7 @@ def lib():
         L.ipfb_delta_analytic.argtypes = [vp, i64, dbl, dbl, vp, vp]
         L.ipfb_autospectrum_error.argtypes = [vp, vp, vp, vp, vp]
         L.ipfb_mask_structured.argtypes = [vp, i32, i32, vp, vp]
+        L.ipfb_wiener_filter.argtypes = [vp, i32, vp, vp, i32, dbl, vp, i32, vp, vp]
         L.ipfb_profile_enable.argtypes = [i32]
         L.ipfb_profile_reset.argtypes = []
         L.ipfb_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
@@ -218,6 +221,22 @@ def ipfb_wiener(plan: Plan, spec, chan_scale=None, phi: float = 0.1, x_out=None,
     _check(lib().ipfb_wiener_ex(plan.handle, fmt, _ptr(spec, "spec"), _ptr(chan_scale, "chan_scale"),
                                 float(phi), int(bool(normalise)), plan._real(x_out, "x_out"),
                                 _stream(stream)))
+    return x_out
+
+
+def wiener_filter(plan: Plan, spec, chan_scale=None, kind: int = FILTER_WIENER, param: float = 0.1, nu=None,
+                  x_out=None, normalise: bool = True, stream=None):
+    """The circulant inverse with another eigenvalue filter (ipfb_wiener_filter);
+    nu: float64 [nblock/2 + 1] on the GPU for FILTER_NU."""
+    import torch
+    fmt = _spec_fmt(plan, spec, chan_scale)
+    if kind == FILTER_NU and (nu is None or nu.dtype != torch.float64 or nu.numel() != plan.nblock // 2 + 1):
+        raise ValueError("nu: float64 [nblock/2 + 1] is required for FILTER_NU")
+    if x_out is None:
+        x_out = _empty((plan.nblock * plan.lblock,), plan.real_dtype)
+    _check(lib().ipfb_wiener_filter(plan.handle, fmt, _ptr(spec, "spec"), _ptr(chan_scale, "chan_scale"), int(kind),
+                                    float(param), _ptr(nu, "nu"), int(bool(normalise)), plan._real(x_out, "x_out"),
+                                    _stream(stream)))
     return x_out
 
 

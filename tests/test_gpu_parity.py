@@ -268,3 +268,43 @@ def test_fault_injection_reports_errors(monkeypatch):
     assert e.value.status == ipfb.ENOMEM
     monkeypatch.delenv("IPFB_FAULT_INJECT")
     ipfb.ipfb_wiener(plan, y, None, 0.1)
+
+
+# ---- other eigenvalue filters ------------------------------------------------
+@pytest.mark.parametrize("prec,tol", [(ipfb.F64, 1e-11), (ipfb.F32, 1e-5)])
+@pytest.mark.parametrize("N,p,b", [(64, 4, 256), (128, 4, 4096), (64, 3, 1024), (32, 4, 16384)])
+def test_ipfb_other_filters_match_oracle(prec, tol, N, p, b):
+    # one-pass (b <= 512) and three-pass (four-step) column stages; the
+    # threshold drops about a fifth of the eigenvalues; nu varies with f
+    print(f"case filters prec={prec} N={N} p={p} b={b}", flush=True)
+    from oracle import ipfb_oracle as Ox
+    w = Ox.window_sinc_hamming(p, N)
+    x = I.gaussian_timestream(N * b, 900 + b)
+    y = Ox.pfb_forward(x, w, N, p)
+    plan = ipfb.Plan(N, p, w, b, prec)
+    cdt = torch.complex128 if prec == ipfb.F64 else torch.complex64
+    yt = torch.from_numpy(y).to(cdt).cuda()
+    d = Ox.row_inverse(yt.cpu().numpy().astype(np.complex128), N)
+    W = Ox.column_spectra(w, N, p, b)
+    # a threshold in a clear gap between eigenvalue magnitudes (about the 20 %
+    # point), so that both sides drop the same eigenvalues
+    a = np.unique(np.round(np.abs(W).ravel(), 9))
+    i = len(a) // 5
+    while a[i + 1] - a[i] < 1e-6 * a[i]:
+        i += 1
+    tau = float(0.5 * (a[i] + a[i + 1]))
+    f = np.arange(b // 2 + 1)
+    nu = 0.005 + 0.05 * np.cos(np.pi * f / b) ** 2
+    nu_full = np.concatenate([nu, nu[1:b // 2][::-1]])
+    cases = [(ipfb.FILTER_THRESHOLD, tau, None, True, "threshold", tau),
+             (ipfb.FILTER_NU, 0.0, nu, True, "psd", 0.0), (ipfb.FILTER_NU, 0.0, nu, False, "psd", 0.0),
+             (ipfb.FILTER_WIENER, 0.2, None, True, None, 0.2)]
+    for kind, param, nv, norm, okind, oparam in cases:
+        nut = None if nv is None else torch.from_numpy(nv).cuda()
+        got = ipfb.wiener_filter(plan, yt, None, kind, param, nut, normalise=norm).cpu().numpy().astype(np.float64)
+        if okind is None:
+            ref = Ox.column_inverse(d, w, N, p, oparam, norm).reshape(-1)
+        else:
+            ref = Ox.column_inverse_filter(d, w, N, p, okind, oparam, nu_full, norm).reshape(-1)
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        assert err < (tol if kind != ipfb.FILTER_THRESHOLD else 10 * tol), (kind, norm, err)
