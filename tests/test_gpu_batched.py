@@ -181,3 +181,47 @@ def test_batched_autotuner_and_cache(tmp_path, monkeypatch):
     doc = json.loads(cache.read_text())
     assert len(doc["entries"]) == 3
     assert doc["entries"][key]["l1"] == 4
+
+
+def test_batched_full_workload_sampled_columns():
+    # the benchmarked configuration itself: 256 streams, nblock ~ U[1024, 32768]
+    # (seed 4), lblock 4096, 4-bit, one graph launch with autotuned shapes;
+    # sampled columns of four streams (the shortest, the longest, a prime
+    # length, one more) against the oracle, whose column inverse is exact per
+    # column (sub-filter paths are independent)
+    import math
+    N, p, phi = 4096, 4, 0.1
+    nbl = [int(b) for b in I.batched_nblocks(256, 1024, 32768, 4)]
+    print(f"case batched full workload: {sum(nbl) * N} samples", flush=True)
+    w = O.window_sinc_hamming(p, N)
+    specs, scales, outs = [], [], []
+    for s_, b in enumerate(nbl):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(4000 + s_)
+        x = torch.randn(b * N, generator=g, device="cuda", dtype=torch.float32)
+        plan = ipfb.Plan(N, p, w, b, ipfb.F32)
+        pk, sc = ipfb.quantize_c4(plan, ipfb.pfb_forward(plan, x), 2.5)
+        specs.append(pk)
+        scales.append(sc)
+        outs.append(torch.empty(b * N, dtype=torch.float32, device="cuda"))
+        del x, plan
+    bp = ipfb.BatchedPlan(N, p, w, nbl, ipfb.F32)
+    shapes = bp.tune()
+    print(f"tuned shapes {shapes}", flush=True)
+    ipfb.wiener_batched(bp, specs, scales, phi, x_outs=outs)
+    torch.cuda.synchronize()
+    isprime = lambda v: v > 1 and all(v % q for q in range(2, int(math.isqrt(v)) + 1))
+    pick = [int(np.argmin(nbl)), int(np.argmax(nbl)), next(i for i, b in enumerate(nbl) if isprime(b)), 17]
+    cols = np.array([0, 1, 1023, 2047, 2048, 2049, 4094, 4095])
+    wsub = w.reshape(p, N)[:, cols].reshape(-1)
+    for s_ in pick:
+        b = nbl[s_]
+        qr, qi = O.unpack_c4(specs[s_].cpu().numpy())
+        d = O.row_inverse(O.dequantize(qr, qi, scales[s_].cpu().numpy()), N)
+        ref = O.column_inverse(d[:, cols], wsub, len(cols), p, phi)
+        got = outs[s_].view(b, N)[:, torch.from_numpy(cols).cuda()].cpu().numpy().astype(np.float64)
+        err = _rel(got, ref)
+        print(f"stream {s_} b={b}: sampled columns rel RMS {err:.2e}", flush=True)
+        assert err < 1e-5
+    del outs, specs, scales, bp
+    torch.cuda.empty_cache()
