@@ -241,12 +241,14 @@ def batched_form(torch, ipfb, inputs, nstreams):
                        "dtype": "f32"}}
 
 
-def streaming_form(torch, ipfb, nframes=65536, chunk=16384, halo=256):
+def streaming_form(torch, ipfb, nframes=65536, chunk=8192, halo=256):
     """Linear-boundary streaming inverse: one stream of nframes = 65536 frames
     (lblock 4096, ntap 4: 2^28 samples), white noise seed 6, the linear PFB's
     nframes - 3 spectra (the first spectra of the circular PFB over the same
-    frames), 4-bit; windows of 16384 frames with a 256-frame halo, phi = 0.1,
-    FP32. Inputs made on the GPU by the library's forward PFB and quantiser."""
+    frames), 4-bit; windows of 8192 frames (134 MB: one window stays in the
+    256 MB last-level cache through its column passes) with a 256-frame halo,
+    phi = 0.1, FP32. Inputs made on the GPU by the library's forward PFB and
+    quantiser."""
     N, p, phi = 4096, 4, 0.1
     w = ipfb.window_sinc_hamming(p, N)
     g = torch.Generator(device="cuda")
