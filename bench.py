@@ -235,7 +235,7 @@ def batched_form(torch, ipfb, inputs, nstreams):
             "samples": S, "power_of_two_streams": npow2, "graph": True,
             "s_per_step_default_shapes": sec_default, "tune_s": tune_s,
             "shapes": {f"2^{m}": {"default": list(default_shapes[m]), "tuned": list(shapes[m])} for m in shapes},
-            "shape_fields": ["l1", "mb", "kb", "pchunk", "fuse"],
+            "shape_fields": ["l1", "mb", "kb", "pchunk", "fuse", "nat"],
             "hbm_GBps": alg / sec / 1e9, "hbm_roofline_frac": alg / sec / 1e9 / HBM_PEAK_GBPS,
             "config": {"lblock": N, "ntap": p, "nblock": "U[1024, 32768], seed 4", "phi": phi,
                        "dtype": "f32"}}

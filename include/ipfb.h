@@ -253,22 +253,27 @@ int ipfb_wiener_batched(ipfb_bplan plan, int infmt, const void* const* spec, con
 
 /* Shape of the Bluestein column path for the streams whose convolution length
  * is M = 2^log2m (M the least power of two >= 2 nblock - 1, for nblock not a
- * power of two): shape = {l1, mb, kb, pchunk, fuse}: the four-step split
- * M = 2^l1 * 2^(log2m - l1) (1 <= l1 <= 8, 1 <= log2m - l1 <= 8), the
+ * power of two): shape = {l1, mb, kb, pchunk, fuse, nat}: the four-step
+ * split M = 2^l1 * 2^(log2m - l1) (1 <= l1 <= 8, 1 <= log2m - l1 <= 8), the
  * column-tile width mb and the row-tile height kb of the FFT passes (8, 16 or
- * 32), the column pairs per launch group (0: all lblock/2 at once), and
- * fuse = 1 to run the inverse of the first chirp convolution, the gain and
- * the forward transform of the second as one pass (0: three passes).
+ * 32), the column pairs per launch group (0: all lblock/2 at once), fuse = 1
+ * to run the inverse of the first chirp convolution, the gain and the forward
+ * transform of the second as one pass (0: three passes), and nat = 1 for the
+ * path that works in place on the frame matrix in its natural layout, in
+ * tiles of 128 bytes of column pairs (16 pairs FP32, 8 FP64; no transposes;
+ * always fused; mb, kb and fuse unused; pchunk counts tiles per launch
+ * group).
  * Every valid shape gives the same result up to rounding; they differ in
  * speed only. Where M1 or M2 is below 32 the tile width 16 is used whatever
- * mb or kb says. The default is {ceil(log2m/2), 16, 16, 0, 1}. get: IPFB_EINVAL if
+ * mb or kb says. The default is {ceil(log2m/2), 16, 16, 0, 1, 0}. get: IPFB_EINVAL if
  * the plan has no stream of that length. set: IPFB_EINVAL for an invalid
  * shape; it waits for the device to go idle (it re-lays the chirp filter
  * spectra for a new split), so it must not overlap a batched call. */
-int ipfb_batched_get_shape(ipfb_bplan plan, int log2m, int shape[5]);
-int ipfb_batched_set_shape(ipfb_bplan plan, int log2m, const int shape[5]);
+int ipfb_batched_get_shape(ipfb_bplan plan, int log2m, int shape[6]);
+int ipfb_batched_set_shape(ipfb_bplan plan, int log2m, const int shape[6]);
 /* Autotuner of the batched form: for each convolution length of the plan, a
- * coordinate search ((fuse, mb) jointly, then l1, kb, pchunk) times the column
+ * coordinate search (transposed path: (fuse, mb) jointly, then l1, kb,
+ * pchunk; natural-layout path: l1, then pchunk) times the column
  * path of the longest stream of that length on the plan's own scratch buffers
  * (three timed runs after a warm-up, best kept) and installs the fastest
  * shape. cache_path (NULL: the IPFB_TUNE_CACHE environment variable; neither:

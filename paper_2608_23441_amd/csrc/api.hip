@@ -1093,6 +1093,7 @@ int tune_load(ipfb_bplan p, const std::string& path) {
     c.kb = it->second.kb;
     c.pchunk = it->second.pchunk;
     c.fuse = it->second.fuse;
+    c.nat = it->second.nat;
     if (!blu_cfg_valid(kv.first, c)) continue;  // stale entry: keep the current shape
     int st = blu_apply_cfg(p, kv.first, c);
     if (st) return st;
@@ -1101,7 +1102,9 @@ int tune_load(ipfb_bplan p, const std::string& path) {
 }
 
 // Best of three timed runs (after one warm-up) of the Bluestein column path
-// for stream length b under shape cfg, on the plan's own buffers.
+// for stream length b under shape cfg, on the plan's own buffers: from the
+// rows' output to the result in time order (the transposed path's two
+// transposes included).
 int blu_time(ipfb_bplan p, int64_t b, const BluCfg& cfg, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
              double* us) {
   BluTables& bt = p->blu[b];
@@ -1114,9 +1117,16 @@ int blu_time(ipfb_bplan p, int64_t b, const BluCfg& cfg, hipStream_t st, hipEven
   double best = 1e300;
   for (int r = 0; r < 4; ++r) {
     hipError_t e = hipEventRecord(e0, st);
-    if (e == hipSuccess)
-      e = launch_blu_columns(p->prec, p->f1, p->f0, p->Tm, p->f0, p->f1, bt.chirp, bt.Crow, bt.twb64, b, bt.log2m,
-                             cfg, p->lblock, p->ntap, p->win64, 0.1, 1, tw4, st);
+    if (e == hipSuccess && cfg.nat) {
+      e = launch_blu_nat(p->prec, p->f0, p->Tm, bt.chirp, bt.Crow, bt.twb64, b, bt.log2m, cfg, p->lblock, p->ntap,
+                         p->win64, 0.1, 1, tw4, st);
+    } else if (e == hipSuccess) {  // with the two transposes this path needs
+      e = launch_transpose(p->prec, p->f0, p->f1, b, p->lblock, st);
+      if (e == hipSuccess)
+        e = launch_blu_columns(p->prec, p->f1, p->f0, p->Tm, p->f0, p->f1, bt.chirp, bt.Crow, bt.twb64, b, bt.log2m,
+                               cfg, p->lblock, p->ntap, p->win64, 0.1, 1, tw4, st);
+      if (e == hipSuccess) e = launch_transpose(p->prec, p->f0, p->f1, p->lblock, b, st);
+    }
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
@@ -1131,9 +1141,10 @@ int blu_time(ipfb_bplan p, int64_t b, const BluCfg& cfg, hipStream_t st, hipEven
   return IPFB_OK;
 }
 
-// Coordinate search per convolution length: fused or not jointly with the
-// column tile, then the split, the row tile and the pairs per launch group;
-// each stage keeps the fastest.
+// Coordinate search per convolution length: for the transposed path, fused or
+// not jointly with the column tile, then the split, the row tile and the pairs
+// per launch group; for the natural-layout path, the split and the tiles per
+// launch group; each stage keeps the fastest, and the fastest overall wins.
 int tune_length(ipfb_bplan p, int log2m, BluCfg* out, double* out_us) {
   int64_t b = 0;  // the longest stream of this length stands for all of them
   for (auto& kv : p->blu)
@@ -1189,6 +1200,39 @@ int tune_length(ipfb_bplan p, int log2m, BluCfg* out, double* out_us) {
     c.pchunk = pc;
     trial(c);
   }
+  // the natural-layout path, searched on its own (its best may lose to the
+  // transposed path's): the split, then tiles per launch group
+  const int ntiles = (p->lblock / 2 + blu_nat_tile_pairs(p->prec) - 1) / blu_nat_tile_pairs(p->prec);
+  BluCfg nbest = blu_cfg_default(log2m);
+  nbest.nat = 1;
+  double nbest_us = 1e300;
+  auto ntrial = [&](BluCfg c) {
+    if (st2 || !blu_cfg_valid(log2m, c)) return;
+    double us = 0.0;
+    st2 = blu_time(p, b, c, st, e0, e1, &us);
+    if (st2) return;
+    if (us < nbest_us) {
+      nbest = c;
+      nbest_us = us;
+    }
+    if (us < best_us) {
+      best = c;
+      best_us = us;
+    }
+  };
+  const BluCfg nstart = nbest;
+  for (int l1 : {d, d - 1, d + 1}) {
+    BluCfg c = nstart;
+    c.l1 = l1;
+    ntrial(c);
+  }
+  const BluCfg nsplit = nbest;
+  for (int pc : {32, 16, 8}) {
+    if (pc >= ntiles) continue;
+    BluCfg c = nsplit;
+    c.pchunk = pc;
+    ntrial(c);
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (st2) return st2;
@@ -1206,9 +1250,11 @@ hipError_t enqueue_batched(ipfb_bplan p, int infmt, const void* const* spec, con
   for (int s = 0; s < p->nstreams && e == hipSuccess; ++s) {
     const int64_t b = p->nblock[s];
     const BluTables& bt = p->blu[b];
-    // power of two: rows straight into the output, columns in place there;
-    // otherwise rows into f0 for the transposed Bluestein path
-    void* rows_out = bt.log2m == 0 ? xo[s] : p->f0;
+    // power of two, or the natural-layout Bluestein path: rows straight into
+    // the output, columns in place there; otherwise rows into f0 for the
+    // transposed Bluestein path
+    const bool in_place = bt.log2m == 0 || p->bcfg[bt.log2m].nat;
+    void* rows_out = in_place ? xo[s] : p->f0;
     e = hipErrorNotSupported;
     if (infmt == IPFB_IN_C4) e = launch_row_c4(p->prec, p->log2n, spec[s], sc[s], rows_out, b, p->twN, st);
     if (e == hipErrorNotSupported) {
@@ -1224,12 +1270,17 @@ hipError_t enqueue_batched(ipfb_bplan p, int infmt, const void* const* spec, con
                                   bt.twb64, st);
       continue;
     }
-    // Bluestein: d -> d_T in f1; Z in f0, A in f1 (d_T consumed by then), x_T in f0
-    e = launch_transpose(p->prec, p->f0, p->f1, b, N, st);
-    if (e != hipSuccess) break;
     const BluCfg& cfg = p->bcfg[bt.log2m];
     const void* tw4[4];
     blu_tw4(p, bt.log2m, cfg.l1, tw4);
+    if (cfg.nat) {
+      e = launch_blu_nat(p->prec, xo[s], p->Tm, bt.chirp, bt.Crow, bt.twb64, b, bt.log2m, cfg, N, p->ntap, p->win64,
+                         phi, normalise, tw4, st);
+      continue;
+    }
+    // Bluestein: d -> d_T in f1; Z in f0, A in f1 (d_T consumed by then), x_T in f0
+    e = launch_transpose(p->prec, p->f0, p->f1, b, N, st);
+    if (e != hipSuccess) break;
     e = launch_blu_columns(p->prec, p->f1, p->f0, p->Tm, p->f0, p->f1, bt.chirp, bt.Crow, bt.twb64, b, bt.log2m, cfg,
                            N, p->ntap, p->win64, phi, normalise, tw4, st);
     if (e == hipSuccess) e = launch_transpose(p->prec, p->f0, xo[s], N, b, st);  // x_T -> x (time order)
@@ -1284,8 +1335,12 @@ int ipfb_batched_plan_create(ipfb_bplan* out, int lblock, int ntap, const double
   const size_t fb = (size_t)maxb * lblock * esize(prec);
   if (!st) st = balloc(p, &p->f0, fb);
   if (!st) st = balloc(p, &p->f1, fb);
-  if (!st && maxlog2m > 0)
-    st = balloc(p, &p->Tm, (size_t)((lblock + 1) / 2) * ((size_t)1 << maxlog2m) * 2 * esize(prec));
+  if (!st && maxlog2m > 0) {  // whole tiles of column pairs cover at least (lblock + 1) / 2 pairs
+    const int tp = blu_nat_tile_pairs(prec);
+    const size_t pairs = (size_t)((lblock / 2 + tp - 1) / tp) * tp;
+    const size_t np2 = pairs > (size_t)((lblock + 1) / 2) ? pairs : (size_t)((lblock + 1) / 2);
+    st = balloc(p, &p->Tm, np2 * ((size_t)1 << maxlog2m) * 2 * esize(prec));
+  }
   (void)M;
   // shapes tuned earlier for this device and problem
   const char* cache = getenv("IPFB_TUNE_CACHE");
@@ -1314,7 +1369,7 @@ int ipfb_batched_plan_destroy(ipfb_bplan p) {
   return ok();
 }
 
-int ipfb_batched_get_shape(ipfb_bplan p, int log2m, int shape[5]) {
+int ipfb_batched_get_shape(ipfb_bplan p, int log2m, int shape[6]) {
   if (!p || !shape) return fail(IPFB_EINVAL, "NULL argument");
   auto it = p->bcfg.find(log2m);
   if (it == p->bcfg.end()) return fail(IPFB_EINVAL, "the plan has no stream of convolution length 2^%d", log2m);
@@ -1323,10 +1378,11 @@ int ipfb_batched_get_shape(ipfb_bplan p, int log2m, int shape[5]) {
   shape[2] = it->second.kb;
   shape[3] = it->second.pchunk;
   shape[4] = it->second.fuse;
+  shape[5] = it->second.nat;
   return ok();
 }
 
-int ipfb_batched_set_shape(ipfb_bplan p, int log2m, const int shape[5]) {
+int ipfb_batched_set_shape(ipfb_bplan p, int log2m, const int shape[6]) {
   if (!p || !shape) return fail(IPFB_EINVAL, "NULL argument");
   if (!p->bcfg.count(log2m)) return fail(IPFB_EINVAL, "the plan has no stream of convolution length 2^%d", log2m);
   BluCfg c;
@@ -1335,6 +1391,7 @@ int ipfb_batched_set_shape(ipfb_bplan p, int log2m, const int shape[5]) {
   c.kb = shape[2];
   c.pchunk = shape[3];
   c.fuse = shape[4];
+  c.nat = shape[5];
   DeviceGuard g(p->dev);
   int st = blu_apply_cfg(p, log2m, c);
   return st ? st : ok();
@@ -1377,6 +1434,7 @@ int ipfb_batched_tune(ipfb_bplan p, const char* cache_path, int force) {
       c.kb = it->second.kb;
       c.pchunk = it->second.pchunk;
       c.fuse = it->second.fuse;
+      c.nat = it->second.nat;
       us = it->second.us;
     }
     if (it == have.end() || !blu_cfg_valid(log2m, c)) {
@@ -1388,6 +1446,7 @@ int ipfb_batched_tune(ipfb_bplan p, const char* cache_path, int force) {
       t.kb = c.kb;
       t.pchunk = c.pchunk;
       t.fuse = c.fuse;
+      t.nat = c.nat;
       t.us = us;
       fresh[key] = t;
     }

@@ -433,6 +433,192 @@ __global__ __launch_bounds__((BluMidCfg<LOG2M1, H>::NT)) void k_blu_mid(
   }
 }
 
+// ---- natural layout ----------------------------------------------------------
+// The same convolutions computed in place on the frame matrix d[j][n] (as
+// the rows left it): a tile of TP adjacent column pairs (128 bytes of every
+// frame) is the unit of work, and the scratch of a launch group of tiles is
+// laid out T[tile][k1][j2][q] (q the pair within the tile), so every access
+// is a 128-byte run and no transpose is needed:
+//   A  (tile, j2): d[j1 M2 + j2][tile] conj(c_j) -> M1-point FFT over j1 -> twiddle
+//   B  (tile, k1): M2-point FFT over j2, times the filter spectrum (shared by
+//                  the tile's pairs), inverse FFT, conjugate twiddle
+//   M  (tile, column j2 and its partner): inverse over k1, gain, forward over j1
+//   A' (tile, j2): inverse FFT over k1 -> c_j / (M b) -> d[j][tile] = x
+template <typename T, int LOG2M>
+struct BnCfg {
+  static constexpr int TP = 128 / (int)sizeof(cx<T>);
+  static constexpr int L = 1 << LOG2M;
+  static constexpr int LS = lds_len(L);
+  static constexpr int EPT = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int cl(int v) { return v < 64 ? 64 : (v > 1024 ? 1024 : v); }
+  static constexpr int NT = cl(TP * L / EPT);       // one sequence set of TP pairs
+  static constexpr int NT2 = cl(2 * TP * L / EPT);  // two columns' sets (the middle pass)
+};
+
+template <typename T, int LOG2M1>
+__global__ __launch_bounds__((BnCfg<T, LOG2M1>::NT)) void k_bn_A(const cx<T>* __restrict__ x,
+                                                                   cx<T>* __restrict__ Tm,
+                                                                   const cx<T>* __restrict__ chirp, int64_t b,
+                                                                   int M2, int np, int t0, int ntc, BluTw tw) {
+  using Cfg = BnCfg<T, LOG2M1>;
+  constexpr int TP = Cfg::TP, M1 = Cfg::L, LS = Cfg::LS, NT = Cfg::NT;
+  __shared__ cx<T> s[TP * LS];
+  __shared__ cx<T> tlo[256], thi[256];
+  const int M = M1 * M2;
+  blu_tw_lds<T, NT>(tlo, thi, tw, M);
+  const int tl = blockIdx.x % ntc, j2 = blockIdx.x / ntc;
+  const int p0 = (t0 + tl) * TP;
+  for (int e = threadIdx.x; e < TP * M1; e += NT) {
+    const int q = e % TP, j1 = e / TP;
+    const int64_t j = (int64_t)j1 * M2 + j2;
+    cx<T> v = mk<T>(T(0), T(0));
+    if (j < b && p0 + q < np) v = cmulc(x[j * np + p0 + q], chirp[j]);
+    s[q * LS + pidx(j1)] = v;
+  }
+  __syncthreads();
+  lds_fft<T, M1, NT, TP, -1>(s, LS, reinterpret_cast<const cx<T>*>(tw.tM1), 1);
+  cx<T>* tp = Tm + (int64_t)tl * M * TP;
+  for (int e = threadIdx.x; e < TP * M1; e += NT) {
+    const int q = e % TP, k1 = e / TP;
+    tp[((int64_t)k1 * M2 + j2) * TP + q] = cmul(s[q * LS + pidx(k1)], blu_twM(tlo, thi, j2 * k1));
+  }
+}
+
+template <typename T, int LOG2M2>
+__global__ __launch_bounds__((BnCfg<T, LOG2M2>::NT)) void k_bn_B(cx<T>* __restrict__ Tm,
+                                                                   const cx<T>* __restrict__ Crow, int conjC,
+                                                                   int M1, int ntc, BluTw tw) {
+  using Cfg = BnCfg<T, LOG2M2>;
+  constexpr int TP = Cfg::TP, M2 = Cfg::L, LS = Cfg::LS, NT = Cfg::NT;
+  __shared__ cx<T> s[TP * LS];
+  __shared__ cx<T> tlo[256], thi[256];
+  const int M = M1 * M2;
+  blu_tw_lds<T, NT>(tlo, thi, tw, M);
+  const int tl = blockIdx.x % ntc, k1 = blockIdx.x / ntc;
+  cx<T>* tp = Tm + (int64_t)tl * M * TP + (int64_t)k1 * M2 * TP;  // row k1: [j2][q], contiguous
+  for (int e = threadIdx.x; e < TP * M2; e += NT) s[(e % TP) * LS + pidx(e / TP)] = tp[e];
+  __syncthreads();
+  const cx<T>* tM2 = reinterpret_cast<const cx<T>*>(tw.tM2);
+  lds_fft<T, M2, NT, TP, -1>(s, LS, tM2, 1);
+  for (int e = threadIdx.x; e < TP * M2; e += NT) {  // times C[k1 + M1 k2], the same for every pair
+    const int q = e % TP, k2 = e / TP;
+    cx<T> h = Crow[(int64_t)k1 * M2 + k2];
+    if (conjC) h.y = -h.y;
+    s[q * LS + pidx(k2)] = cmul(s[q * LS + pidx(k2)], h);
+  }
+  __syncthreads();
+  lds_fft<T, M2, NT, TP, +1>(s, LS, tM2, 1);
+  for (int e = threadIdx.x; e < TP * M2; e += NT) {
+    const int q = e % TP, j2 = e / TP;
+    tp[e] = cmulc(s[q * LS + pidx(j2)], blu_twM(tlo, thi, j2 * k1));
+  }
+}
+
+// Middle pass on one column u and its partner (r - u) mod M2 (see k_blu_mid),
+// for the TP pairs of a tile; slot 0 holds column u, slot 1 its partner.
+template <typename T, int LOG2M1, bool TAP4>
+__global__ __launch_bounds__((BnCfg<T, LOG2M1>::NT2)) void k_bn_mid(
+    cx<T>* __restrict__ Tm, const cx<T>* __restrict__ chirp, const cx<double>* __restrict__ twb64, int64_t b,
+    int M2, int np, int t0, int ntc, BluGain g, BluTw tw) {
+  using Cfg = BnCfg<T, LOG2M1>;
+  constexpr int TP = Cfg::TP, M1 = Cfg::L, LS = Cfg::LS, NT = Cfg::NT2, C = 2 * TP;
+  __shared__ cx<T> s[C * LS];
+  __shared__ cx<T> tlo[256], thi[256];
+  const int M = M1 * M2;
+  blu_tw_lds<T, NT>(tlo, thi, tw, M);
+  const int qb = (int)(b / M2), r = (int)(b - (int64_t)qb * M2);
+  const int tl = blockIdx.x % ntc, t = blockIdx.x / ntc;
+  const int p0 = (t0 + tl) * TP;
+  const int u = (((r + 1) / 2) + t) & (M2 - 1);
+  int l = (r - u) & (M2 - 1);
+  const bool own = (l == u);  // u is its own partner
+  if (own) l = -1;
+  cx<T>* tp = Tm + (int64_t)tl * M * TP;
+  for (int e = threadIdx.x; e < C * M1; e += NT) {
+    const int q = e % TP, rest = e / TP, sl = rest & 1, k1 = rest >> 1;
+    const int j2 = sl ? l : u;
+    s[(sl * TP + q) * LS + pidx(k1)] = (j2 >= 0) ? tp[((int64_t)k1 * M2 + j2) * TP + q] : mk<T>(T(0), T(0));
+  }
+  __syncthreads();
+  lds_fft<T, M1, NT, C, +1>(s, LS, reinterpret_cast<const cx<T>*>(tw.tM1), 1);
+  const double invM = 1.0 / (double)M;
+#pragma unroll 1
+  for (int e = threadIdx.x; e < C * M1; e += NT) {
+    const int q = e % TP, rest = e / TP, sl = rest & 1, j1 = rest >> 1;
+    const int j2 = sl ? l : u;
+    if (j2 < 0) continue;
+    cx<T>* sj = s + (sl * TP + q) * LS + pidx(j1);
+    const int64_t j = (int64_t)j1 * M2 + j2;
+    if (j >= b || p0 + q >= np) {
+      *sj = mk<T>(T(0), T(0));
+      continue;
+    }
+    const int64_t jm = (j == 0) ? 0 : b - j;
+    if (jm < j) continue;  // the partner's thread does this pair
+    cx<T>* sm = sj;
+    if (jm != j) sm = s + ((own ? sl : 1 - sl) * TP + q) * LS + pidx(qb - j1 - (j2 > r ? 1 : 0));
+    const int n = 2 * (p0 + q);
+    const bool has1 = n + 1 < g.N;
+    const cx<T> cj = chirp[j], cm = chirp[jm];
+    const cx<double> c = mk<double>(cj.x, cj.y), cmd = mk<double>(cm.x, cm.y);
+    const cx<T> v = *sj, w = *sm;
+    const cx<double> Zk = cmulc(mk<double>(v.x * invM, v.y * invM), c);
+    const cx<double> Zm = cmulc(mk<double>(w.x * invM, w.y * invM), cmd);
+    const cx<double> X1 = mk<double>(0.5 * (Zk.x + Zm.x), 0.5 * (Zk.y - Zm.y));
+    const cx<double> X2 = mk<double>(0.5 * (Zk.y + Zm.y), -0.5 * (Zk.x - Zm.x));
+    cx<double> Ga, Gc;
+    if constexpr (TAP4) {
+      blu_gain_pair4(g, n, has1, twb64[j], Ga, Gc);
+    } else {
+      Ga = blu_gain(g, n, twb64, j);
+      Gc = has1 ? blu_gain(g, n + 1, twb64, j) : mk<double>(0.0, 0.0);
+    }
+    const cx<double> Y1 = cmul(Ga, X1);
+    const cx<double> Y2 = has1 ? cmul(Gc, X2) : mk<double>(0.0, 0.0);
+    const cx<double> oj = cmul(mk<double>(Y1.x - Y2.y, Y1.y + Y2.x), c);
+    *sj = mk<T>(T(oj.x), T(oj.y));
+    if (jm != j) {
+      const cx<double> om = cmul(mk<double>(Y1.x + Y2.y, -Y1.y + Y2.x), cmd);
+      *sm = mk<T>(T(om.x), T(om.y));
+    }
+  }
+  __syncthreads();
+  lds_fft<T, M1, NT, C, -1>(s, LS, reinterpret_cast<const cx<T>*>(tw.tM1), 1);
+  for (int e = threadIdx.x; e < C * M1; e += NT) {
+    const int q = e % TP, rest = e / TP, sl = rest & 1, k1 = rest >> 1;
+    const int j2 = sl ? l : u;
+    if (j2 < 0) continue;
+    tp[((int64_t)k1 * M2 + j2) * TP + q] = cmul(s[(sl * TP + q) * LS + pidx(k1)], blu_twM(tlo, thi, j2 * k1));
+  }
+}
+
+template <typename T, int LOG2M1>
+__global__ __launch_bounds__((BnCfg<T, LOG2M1>::NT)) void k_bn_Ainv(const cx<T>* __restrict__ Tm,
+                                                                      cx<T>* __restrict__ x,
+                                                                      const cx<T>* __restrict__ chirp, int64_t b,
+                                                                      int M2, int np, int t0, int ntc, BluTw tw) {
+  using Cfg = BnCfg<T, LOG2M1>;
+  constexpr int TP = Cfg::TP, M1 = Cfg::L, LS = Cfg::LS, NT = Cfg::NT;
+  __shared__ cx<T> s[TP * LS];
+  const int M = M1 * M2;
+  const int tl = blockIdx.x % ntc, j2 = blockIdx.x / ntc;
+  const int p0 = (t0 + tl) * TP;
+  const cx<T>* tp = Tm + (int64_t)tl * M * TP;
+  for (int e = threadIdx.x; e < TP * M1; e += NT) {
+    const int q = e % TP, k1 = e / TP;
+    s[q * LS + pidx(k1)] = tp[((int64_t)k1 * M2 + j2) * TP + q];
+  }
+  __syncthreads();
+  lds_fft<T, M1, NT, TP, +1>(s, LS, reinterpret_cast<const cx<T>*>(tw.tM1), 1);
+  const T sc = T(1.0 / ((double)M * (double)b));
+  for (int e = threadIdx.x; e < TP * M1; e += NT) {
+    const int q = e % TP, j1 = e / TP;
+    const int64_t j = (int64_t)j1 * M2 + j2;
+    if (j >= b || p0 + q >= np) continue;
+    x[j * np + p0 + q] = cmul(scale(s[q * LS + pidx(j1)], sc), chirp[j]);
+  }
+}
+
 // ---- launchers ---------------------------------------------------------------
 // Tile widths other than 16 exist for M1, M2 >= 2^kBluTileMinLog2 only.
 constexpr int kBluTileMinLog2 = 5;
@@ -573,6 +759,78 @@ static hipError_t blu_mid_pass(int mb, void* Tm, const void* chirp, const double
   }
 }
 
+// ---- natural-layout launchers
+template <typename T, int L1>
+static hipError_t launch_bn_A_t(const void* x, void* Tm, const void* chirp, int64_t b, int M2, int np, int t0, int ntc,
+                                const BluTw& tw, hipStream_t st) {
+  k_bn_A<T, L1><<<dim3((unsigned)(ntc * M2)), BnCfg<T, L1>::NT, 0, st>>>((const cx<T>*)x, (cx<T>*)Tm,
+                                                                         (const cx<T>*)chirp, b, M2, np, t0, ntc, tw);
+  return hipGetLastError();
+}
+template <typename T, int L2>
+static hipError_t launch_bn_B_t(void* Tm, const void* Crow, int conjC, int M1, int ntc, const BluTw& tw,
+                                hipStream_t st) {
+  k_bn_B<T, L2><<<dim3((unsigned)(ntc * M1)), BnCfg<T, L2>::NT, 0, st>>>((cx<T>*)Tm, (const cx<T>*)Crow, conjC, M1,
+                                                                         ntc, tw);
+  return hipGetLastError();
+}
+template <typename T, int L1>
+static hipError_t launch_bn_mid_t(void* Tm, const void* chirp, const double* twb64, int64_t b, int M2, int np, int t0,
+                                  int ntc, const BluGain& g, const BluTw& tw, hipStream_t st) {
+  const int r = (int)(b % M2);
+  const int npc = (r & 1) ? M2 / 2 : M2 / 2 + 1;
+  const dim3 grid((unsigned)(ntc * npc));
+  if (g.ntap == 4)
+    k_bn_mid<T, L1, true><<<grid, BnCfg<T, L1>::NT2, 0, st>>>((cx<T>*)Tm, (const cx<T>*)chirp,
+                                                              (const cx<double>*)twb64, b, M2, np, t0, ntc, g, tw);
+  else
+    k_bn_mid<T, L1, false><<<grid, BnCfg<T, L1>::NT2, 0, st>>>((cx<T>*)Tm, (const cx<T>*)chirp,
+                                                               (const cx<double>*)twb64, b, M2, np, t0, ntc, g, tw);
+  return hipGetLastError();
+}
+template <typename T, int L1>
+static hipError_t launch_bn_Ainv_t(const void* Tm, void* x, const void* chirp, int64_t b, int M2, int np, int t0,
+                                   int ntc, const BluTw& tw, hipStream_t st) {
+  k_bn_Ainv<T, L1><<<dim3((unsigned)(ntc * M2)), BnCfg<T, L1>::NT, 0, st>>>((const cx<T>*)Tm, (cx<T>*)x,
+                                                                            (const cx<T>*)chirp, b, M2, np, t0, ntc,
+                                                                            tw);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t blu_nat_t(void* x, void* Tm, const void* chirp, const void* Crow, const double* twb64, int64_t b,
+                            int log2m, const BluCfg& cfg, int N, const BluGain& g, const BluTw& tw, hipStream_t st) {
+  constexpr int TP = BnCfg<T, 1>::TP;
+  const int l1 = cfg.l1, l2 = log2m - cfg.l1;
+  const int M1 = 1 << l1, M2 = 1 << l2;
+  const int np = N / 2, nt = (np + TP - 1) / TP;
+  const int ch = (cfg.pchunk > 0 && cfg.pchunk < nt) ? cfg.pchunk : nt;
+  hipError_t e = hipSuccess;
+  for (int t0 = 0; t0 < nt && e == hipSuccess; t0 += ch) {
+    const int ntc = nt - t0 < ch ? nt - t0 : ch;
+#define CALL(L) e = launch_bn_A_t<T, L>(x, Tm, chirp, b, M2, np, t0, ntc, tw, st); break;
+    BLU_L_SWITCH(l1, CALL)
+#undef CALL
+    if (e != hipSuccess) break;
+#define CALL(L) e = launch_bn_B_t<T, L>(Tm, Crow, 0, M1, ntc, tw, st); break;
+    BLU_L_SWITCH(l2, CALL)
+#undef CALL
+    if (e != hipSuccess) break;
+#define CALL(L) e = launch_bn_mid_t<T, L>(Tm, chirp, twb64, b, M2, np, t0, ntc, g, tw, st); break;
+    BLU_L_SWITCH(l1, CALL)
+#undef CALL
+    if (e != hipSuccess) break;
+#define CALL(L) e = launch_bn_B_t<T, L>(Tm, Crow, 1, M1, ntc, tw, st); break;
+    BLU_L_SWITCH(l2, CALL)
+#undef CALL
+    if (e != hipSuccess) break;
+#define CALL(L) e = launch_bn_Ainv_t<T, L>(Tm, x, chirp, b, M2, np, t0, ntc, tw, st); break;
+    BLU_L_SWITCH(l1, CALL)
+#undef CALL
+  }
+  return e;
+}
+
 bool blu_cfg_valid(int log2m, const BluCfg& c) {
   const int l2 = log2m - c.l1;
   if (log2m < 2 || log2m > kBluMaxLog2M) return false;
@@ -580,6 +838,7 @@ bool blu_cfg_valid(int log2m, const BluCfg& c) {
   if (c.mb != 8 && c.mb != 16 && c.mb != 32) return false;
   if (c.kb != 8 && c.kb != 16 && c.kb != 32) return false;
   if (c.fuse != 0 && c.fuse != 1) return false;
+  if (c.nat != 0 && c.nat != 1) return false;
   return c.pchunk >= 0;
 }
 
@@ -590,6 +849,7 @@ BluCfg blu_cfg_default(int log2m) {
   c.kb = 16;
   c.pchunk = 0;
   c.fuse = 1;
+  c.nat = 0;
   return c;
 }
 
@@ -631,6 +891,24 @@ static hipError_t blu_columns_t(const void* dT, void* xT, void* Tm, void* Z, voi
       e = blu_step<T>(step, 1, A, xT, Tm, chirp, Crow, 1, b, log2m, cfg, N, p0, np, tw, st);
   }
   return e;
+}
+
+int blu_nat_tile_pairs(int prec) { return prec == F32 ? BnCfg<float, 1>::TP : BnCfg<double, 1>::TP; }
+
+hipError_t launch_blu_nat(int prec, void* x, void* Tm, const void* chirp, const void* Crow, const double* twb64,
+                          int64_t b, int log2m, const BluCfg& cfg, int N, int ntap, const double* win64, double phi,
+                          int normalise, const void* const tw4[4], hipStream_t st) {
+  if (!blu_cfg_valid(log2m, cfg) || (N & 1)) return hipErrorInvalidValue;
+  BluTw tw{tw4[0], tw4[1], tw4[2], tw4[3]};
+  BluGain g;
+  g.win = win64;
+  g.N = N;
+  g.ntap = ntap;
+  g.phi2 = phi * phi;
+  g.gnorm = normalise ? 1.0 + phi * phi : 1.0;
+  g.naive = (phi == 0.0);
+  if (prec == F32) return blu_nat_t<float>(x, Tm, chirp, Crow, twb64, b, log2m, cfg, N, g, tw, st);
+  return blu_nat_t<double>(x, Tm, chirp, Crow, twb64, b, log2m, cfg, N, g, tw, st);
 }
 
 hipError_t launch_blu_columns(int prec, const void* dT, void* xT, void* Tm, void* Z, void* A, const void* chirp,

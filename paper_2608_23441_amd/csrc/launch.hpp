@@ -100,8 +100,10 @@ constexpr int kCgParts = 1024;
 // mb, kb in {8, 16, 32}, pairs per launch group (0: all), fuse = 1: the
 // inverse of the first convolution, the gain and the forward of the second in
 // one pass over the scratch (0: three kernels through Z and A).
+// nat = 1: the natural-layout path (in place on d[b][N], tiles of column
+// pairs, always fused; mb, kb and fuse unused, pchunk counts tiles).
 struct BluCfg {
-  int l1 = 0, mb = 16, kb = 16, pchunk = 0, fuse = 1;
+  int l1 = 0, mb = 16, kb = 16, pchunk = 0, fuse = 1, nat = 0;
 };
 bool blu_cfg_valid(int log2m, const BluCfg& c);
 BluCfg blu_cfg_default(int log2m);
@@ -113,6 +115,13 @@ BluCfg blu_cfg_default(int log2m);
 // [M1][M2] complex = FFT_M of the symmetric chirp filter in row layout for
 // the split cfg.l1; twb64 [b] double complex e^{-2 pi i m/b};
 // tw4 = {tM1 [M1], tM2 [M2], tLo [256], tHi [max(1, M/256)]}.
+// The Bluestein column stage in place on the natural layout x[b][N] (the
+// rows' output, overwritten with the result); Tm: scratch of
+// min(pchunk, tiles) * tile_pairs * 2^log2m complex, tiles = ceil(N/2 / tile_pairs).
+int blu_nat_tile_pairs(int prec);
+hipError_t launch_blu_nat(int prec, void* x, void* Tm, const void* chirp, const void* Crow, const double* twb64,
+                          int64_t b, int log2m, const BluCfg& cfg, int N, int ntap, const double* win64, double phi,
+                          int normalise, const void* const tw4[4], hipStream_t st);
 hipError_t launch_blu_columns(int prec, const void* dT, void* xT, void* Tm, void* Z, void* A, const void* chirp,
                               const void* Crow, const double* twb64, int64_t b, int log2m, const BluCfg& cfg,
                               int N, int ntap, const double* win64, double phi, int normalise,

@@ -83,13 +83,14 @@ struct Reader {
       std::string k;
       if (!str(k) || !eat(':')) return ok = false;
       double v = 0.0;
-      if (k == "l1" || k == "mb" || k == "kb" || k == "pchunk" || k == "fuse" || k == "us") {
+      if (k == "l1" || k == "mb" || k == "kb" || k == "pchunk" || k == "fuse" || k == "nat" || k == "us") {
         if (!num(v)) return false;
         if (k == "l1") t.l1 = (int)v;
         if (k == "mb") t.mb = (int)v;
         if (k == "kb") t.kb = (int)v;
         if (k == "pchunk") t.pchunk = (int)v;
         if (k == "fuse") t.fuse = (int)v;
+        if (k == "nat") t.nat = (int)v;
         if (k == "us") t.us = v;
       } else if (!skip()) {
         return false;
@@ -157,8 +158,9 @@ bool tune_cache_write(const std::string& path, const std::map<std::string, TuneE
         k.push_back(c);
       }
       char buf[160];
-      snprintf(buf, sizeof(buf), "{\"l1\": %d, \"mb\": %d, \"kb\": %d, \"pchunk\": %d, \"fuse\": %d, \"us\": %.3f}",
-               kv.second.l1, kv.second.mb, kv.second.kb, kv.second.pchunk, kv.second.fuse, kv.second.us);
+      snprintf(buf, sizeof(buf),
+               "{\"l1\": %d, \"mb\": %d, \"kb\": %d, \"pchunk\": %d, \"fuse\": %d, \"nat\": %d, \"us\": %.3f}",
+               kv.second.l1, kv.second.mb, kv.second.kb, kv.second.pchunk, kv.second.fuse, kv.second.nat, kv.second.us);
       f << (first ? "\n  \"" : ",\n  \"") << k << "\": " << buf;
       first = false;
     }

@@ -1,7 +1,7 @@
 // Autotuner cache of the batched plan: a JSON file holding, per key, the
 // chosen shape of the Bluestein column path and its measured time.
 //   {"version": 1, "entries": {"<key>": {"l1": 8, "mb": 16, "kb": 16,
-//                                        "pchunk": 0, "fuse": 1, "us": 1234.5}, ...}}
+//                                        "pchunk": 0, "fuse": 1, "nat": 0, "us": 1234.5}, ...}}
 // The key names the device and the problem ("gfx950:256cu|f32|N4096|T4|m16").
 // Host code only.
 #pragma once
@@ -11,7 +11,7 @@
 namespace ipfb {
 
 struct TuneEntry {
-  int l1 = 0, mb = 16, kb = 16, pchunk = 0, fuse = 1;  // fuse: 1 when the file has none
+  int l1 = 0, mb = 16, kb = 16, pchunk = 0, fuse = 1, nat = 0;  // fuse 1, nat 0 when the file has none
   double us = 0.0;
 };
 

@@ -397,13 +397,13 @@ class BatchedPlan:
         return sorted(out)
 
     def get_shape(self, log2m: int):
-        """(l1, mb, kb, pchunk, fuse) used for convolution length 2^log2m."""
-        a = (ctypes.c_int * 5)()
+        """(l1, mb, kb, pchunk, fuse, nat) used for convolution length 2^log2m."""
+        a = (ctypes.c_int * 6)()
         _check(lib().ipfb_batched_get_shape(self._h, int(log2m), a))
         return tuple(a)
 
     def set_shape(self, log2m: int, shape):
-        a = (ctypes.c_int * 5)(*[int(v) for v in shape])
+        a = (ctypes.c_int * 6)(*[int(v) for v in shape])
         _check(lib().ipfb_batched_set_shape(self._h, int(log2m), a))
 
     def tune(self, cache_path=None, force: bool = False):

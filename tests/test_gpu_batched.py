@@ -119,30 +119,33 @@ def test_batched_every_shape_matches_oracle(prec, tol):
     assert bp.conv_lengths() == [7, 10, 12]
     for m in bp.conv_lengths():
         d = (m + 1) // 2
-        assert bp.get_shape(m) == (d, 16, 16, 0, 1)
+        assert bp.get_shape(m) == (d, 16, 16, 0, 1, 0)
         shapes = []
         for fuse in (1, 0):
-            shapes += [(l1, 16, 16, 0, fuse) for l1 in range(max(1, m - 8), min(8, m - 1) + 1)]
-            shapes += [(d, 8, 16, 0, fuse), (d, 32, 16, 0, fuse), (d, 16, 8, 0, fuse), (d, 16, 32, 0, fuse),
-                       (d, 8, 32, 5, fuse), (d, 32, 8, 7, fuse)]
+            shapes += [(l1, 16, 16, 0, fuse, 0) for l1 in range(max(1, m - 8), min(8, m - 1) + 1)]
+            shapes += [(d, 8, 16, 0, fuse, 0), (d, 32, 16, 0, fuse, 0), (d, 16, 8, 0, fuse, 0),
+                       (d, 16, 32, 0, fuse, 0), (d, 8, 32, 5, fuse, 0), (d, 32, 8, 7, fuse, 0)]
+        # natural layout: every split, one tile per launch group (ragged: 32 pairs = 2 or 4 tiles)
+        shapes += [(l1, 16, 16, 0, 1, 1) for l1 in range(max(1, m - 8), min(8, m - 1) + 1)]
+        shapes += [(d, 16, 16, 1, 1, 1)]
         for sh in shapes:
             bp.set_shape(m, sh)
             assert bp.get_shape(m) == sh
             _check_streams(bp, data, nblocks, w, N, p, tol, (m, sh))
-        bp.set_shape(m, (d, 16, 16, 0, 1))
+        bp.set_shape(m, (d, 16, 16, 0, 1, 0))
 
 
 def test_batched_shape_rejects_invalid():
     N, p = 64, 4
     w = O.window_sinc_hamming(p, N)
     bp = ipfb.BatchedPlan(N, p, w, [300], ipfb.F32)
-    for bad in [(9, 16, 16, 0, 1), (1, 16, 16, 0, 1), (5, 12, 16, 0, 1), (5, 16, 64, 0, 1), (5, 16, 16, -1, 1),
-                (5, 16, 16, 0, 2)]:
+    for bad in [(9, 16, 16, 0, 1, 0), (1, 16, 16, 0, 1, 0), (5, 12, 16, 0, 1, 0), (5, 16, 64, 0, 1, 0),
+                (5, 16, 16, -1, 1, 0), (5, 16, 16, 0, 2, 0), (5, 16, 16, 0, 1, 2)]:
         with pytest.raises(ipfb.IpfbError):
             bp.set_shape(10, bad)
     with pytest.raises(ipfb.IpfbError):
         bp.get_shape(11)  # no stream of that length
-    assert bp.get_shape(10) == (5, 16, 16, 0, 1)
+    assert bp.get_shape(10) == (5, 16, 16, 0, 1, 0)
 
 
 def test_batched_autotuner_and_cache(tmp_path, monkeypatch):
@@ -160,7 +163,7 @@ def test_batched_autotuner_and_cache(tmp_path, monkeypatch):
     assert len(keys) == 3 and all("|f32|N256|T4|m" in k for k in keys)
     for k, e in doc["entries"].items():
         m = int(k.rsplit("|m", 1)[1])
-        assert (e["l1"], e["mb"], e["kb"], e["pchunk"], e["fuse"]) == tuned[m]
+        assert (e["l1"], e["mb"], e["kb"], e["pchunk"], e["fuse"], e["nat"]) == tuned[m]
         assert e["us"] > 0
     _check_streams(bp, data, nblocks, w, N, p, 1e-5, "tuned")
     # a plan created with the cache in the environment installs the same shapes
@@ -173,8 +176,8 @@ def test_batched_autotuner_and_cache(tmp_path, monkeypatch):
     cache.write_text('{ "entries" : { "%s" : { "note": "manual", "l1" : 4, "mb": 32, "kb": 8, "pchunk": 3, '
                      '"us": 1.0 } }, "version": 1 }' % key)
     bp3 = ipfb.BatchedPlan(N, p, w, nblocks, ipfb.F32)
-    assert bp3.get_shape(11) == (4, 32, 8, 3, 1)  # no "fuse" field: fused
-    assert bp3.get_shape(10) == (5, 16, 16, 0, 1)  # no entry: default
+    assert bp3.get_shape(11) == (4, 32, 8, 3, 1, 0)  # no "fuse" or "nat" field: fused, transposed
+    assert bp3.get_shape(10) == (5, 16, 16, 0, 1, 0)  # no entry: default
     _check_streams(bp3, data, nblocks, w, N, p, 1e-5, "hand-edited")
     # tune with the env cache: the entry found is kept, the missing ones are timed and merged
     bp3.tune()
