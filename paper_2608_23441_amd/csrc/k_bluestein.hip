@@ -449,10 +449,11 @@ struct BnCfg {
   static constexpr int TP = 128 / (int)sizeof(cx<T>);
   static constexpr int L = 1 << LOG2M;
   static constexpr int LS = lds_len(L);
-  static constexpr int EPT = sizeof(T) == 4 ? 16 : 8;
   static constexpr int cl(int v) { return v < 64 ? 64 : (v > 1024 ? 1024 : v); }
-  static constexpr int NT = cl(TP * L / EPT);       // one sequence set of TP pairs
-  static constexpr int NT2 = cl(2 * TP * L / EPT);  // two columns' sets (the middle pass)
+  // 8 elements per thread in the FFT passes; 16 in the middle pass, whose
+  // FP64 gain work favours fewer, fuller threads
+  static constexpr int NT = cl(TP * L / 8);        // one sequence set of TP pairs
+  static constexpr int NT2 = cl(2 * TP * L / 16);  // two columns' sets (the middle pass)
 };
 
 template <typename T, int LOG2M1>
