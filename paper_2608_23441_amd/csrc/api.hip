@@ -655,11 +655,11 @@ int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale
     if (e == hipSuccess) e = launch_cg_normal(p->prec, xT, qT, p->cg_autoc, maskT, lam, p->ntap, b, S, p->cg_part, st);
     if (e == hipSuccess) e = launch_cg_resid(p->prec, rhsT, qT, rT, S, p->cg_part, st);
     if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 2, p->cg_sc, resid_norms, 0, st);
+    // z0 = M^-1 r0 with the partial sums of r0 . z0 formed on the way out
     if (e == hipSuccess)
       e = launch_col_wiener(p->prec, p->log2b, rT, zT, p->lblock, p->ntap, p->win64, phi_precond, 1, p->twB,
-                            p->twB64, st, 1);
+                            p->twB64, st, 1, p->cg_part);
     if (e == hipSuccess) e = launch_cg_p(p->prec, pT, zT, p->cg_sc, 0, S, st);
-    if (e == hipSuccess) e = launch_cg_dot(p->prec, rT, zT, S, p->cg_part, st);
     if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 0, p->cg_sc, nullptr, 0, st);
   }
   for (int k = 1; k <= iters && e == hipSuccess; ++k) {
@@ -670,8 +670,7 @@ int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale
     if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 2, p->cg_sc, resid_norms, k, st);
     if (e == hipSuccess)
       e = launch_col_wiener(p->prec, p->log2b, rT, zT, p->lblock, p->ntap, p->win64, phi_precond, 1, p->twB,
-                            p->twB64, st, 1);
-    if (e == hipSuccess) e = launch_cg_dot(p->prec, rT, zT, S, p->cg_part, st);
+                            p->twB64, st, 1, p->cg_part);
     if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 3, p->cg_sc, nullptr, 0, st);
     if (e == hipSuccess) e = launch_cg_p(p->prec, pT, zT, p->cg_sc, 1, S, st);
   }

@@ -111,11 +111,13 @@ __device__ __forceinline__ void gain_pair4(const GainArgs& ga, int n, int k, con
 template <typename T, int LOG2B>
 __global__ __launch_bounds__((ColCfg<T, LOG2B>::NT), (ColCfg<T, LOG2B>::WPE)) void k_col_wiener(
     const T* __restrict__ dT, T* __restrict__ xT, GainArgs ga, const cx<T>* __restrict__ twB,
-    const cx<double>* __restrict__ twB64) {
+    const cx<double>* __restrict__ twB64, double* __restrict__ part, int nparts) {
   using Cfg = ColCfg<T, LOG2B>;
   constexpr int B = 1 << LOG2B, H = Cfg::H, C = Cfg::C, LS = Cfg::LS, NT = Cfg::NT;
   constexpr int HP = H / 2 + 1;
-  __shared__ cx<T> s[C * LS];
+  // the FFT tile, also the dot product's reduction buffer (NT doubles) afterwards
+  constexpr int SRED = (NT * (int)sizeof(double) + (int)sizeof(cx<T>) - 1) / (int)sizeof(cx<T>);
+  __shared__ cx<T> s[C * LS > SRED ? C * LS : SRED];
   const int tid = threadIdx.x;
   const int N = ga.lblock;
   const int n0 = blockIdx.x * C;
@@ -176,29 +178,51 @@ __global__ __launch_bounds__((ColCfg<T, LOG2B>::NT), (ColCfg<T, LOG2B>::WPE)) vo
   __syncthreads();
   lds_fft<T, H, NT, C, +1>(s, LS, twB, 2);
 
+  double acc = 0.0;
   for (int e = tid; e < H * C; e += NT) {
     const int c = e / H, m = e % H;
     const int n = n0 + c;
-    if (n < N) reinterpret_cast<cx<T>*>(xT + (int64_t)n * B)[m] = s[c * LS + pidx(m)];
+    if (n >= N) continue;
+    const cx<T> v = s[c * LS + pidx(m)];
+    reinterpret_cast<cx<T>*>(xT + (int64_t)n * B)[m] = v;
+    if (part) {  // the dot product input . output of these columns (the CG's r . z)
+      const cx<T> a = reinterpret_cast<const cx<T>*>(dT + (int64_t)n * B)[m];
+      acc += (double)a.x * (double)v.x + (double)a.y * (double)v.y;
+    }
+  }
+  if (part) {  // fixed-order sum over the workgroup in the (now free) LDS
+    double* red = reinterpret_cast<double*>(s);
+    __syncthreads();
+    red[tid] = acc;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0) part[blockIdx.x] = red[0];
+    if (blockIdx.x == 0)  // the slots no workgroup of this launch fills
+      for (int i = (int)gridDim.x + tid; i < nparts; i += NT) part[i] = 0.0;
   }
 }
 
 template <typename T, int LOG2B>
 static hipError_t launch_col_t(const void* d, void* xo, const GainArgs& ga, const void* twB,
-                               const double* twB64, hipStream_t st) {
+                               const double* twB64, hipStream_t st, double* part) {
   using Cfg = ColCfg<T, LOG2B>;
+  static_assert((Cfg::NT & (Cfg::NT - 1)) == 0, "the dot product's tree needs a power-of-two workgroup");
   const int nwg = (ga.lblock + Cfg::C - 1) / Cfg::C;
+  if (part && nwg > kCgParts) return hipErrorInvalidValue;
   k_col_wiener<T, LOG2B><<<dim3(nwg), dim3(Cfg::NT), 0, st>>>(
-      (const T*)d, (T*)xo, ga, (const cx<T>*)twB, (const cx<double>*)twB64);
+      (const T*)d, (T*)xo, ga, (const cx<T>*)twB, (const cx<double>*)twB64, part, kCgParts);
   return hipGetLastError();
 }
 
 #define COL_CASE(T, L) \
-  case L: return launch_col_t<T, L>(d, xo, ga, twB, twB64, st);
+  case L: return launch_col_t<T, L>(d, xo, ga, twB, twB64, st, part);
 
 hipError_t launch_col_wiener(int prec, int log2b, const void* d, void* xo, int lblock, int ntap,
                              const double* win64, double phi, int normalise, const void* twB,
-                             const double* twB64, hipStream_t st, int precond) {
+                             const double* twB64, hipStream_t st, int precond, double* part) {
   GainArgs ga;
   ga.win = win64;
   ga.lblock = lblock;

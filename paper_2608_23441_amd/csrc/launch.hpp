@@ -55,10 +55,12 @@ hipError_t launch_row_c4(int prec, int log2n, const void* in, const float* chan_
 // Column stage on the transposed frame matrix: per column n (contiguous in
 // d_T[n][0..b)), x_T[n] = F^-1[ G_n F d_T[n] ] with the FP64 gain.
 // precond = 1 applies the real gain 1/(|W_n|^2 + phi^2) instead (the inverse
-// of A^T A + phi^2 I, used as the CG preconditioner).
+// of A^T A + phi^2 I, used as the CG preconditioner). part != NULL: also the
+// partial sums of d . xo, one per workgroup, in part[0, kCgParts) (unused
+// slots zeroed; needs at most kCgParts workgroups).
 hipError_t launch_col_wiener(int prec, int log2b, const void* d, void* xo, int lblock, int ntap,
                              const double* win64, double phi, int normalise, const void* twB,
-                             const double* twB64, hipStream_t st, int precond = 0);
+                             const double* twB64, hipStream_t st, int precond = 0, double* part = nullptr);
 
 // The same column stage on the natural layout z = d[b][N] (read as N/2
 // complex pairs per frame), in place: on return z holds x[b][N] in time

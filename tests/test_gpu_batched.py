@@ -107,12 +107,13 @@ def _check_streams(bp, data, nblocks, w, N, p, tol, what):
         assert err < tol, (what, b, err)
 
 
-@pytest.mark.parametrize("prec,tol", [(ipfb.F64, 1e-11), (ipfb.F32, 1e-5)])
-def test_batched_every_shape_matches_oracle(prec, tol):
-    # every split, both non-default tile widths and ragged launch groups
-    N, p = 64, 4
+@pytest.mark.parametrize("prec,tol,p", [(ipfb.F64, 1e-11, 4), (ipfb.F32, 1e-5, 4), (ipfb.F64, 1e-11, 5)])
+def test_batched_every_shape_matches_oracle(prec, tol, p):
+    # every split, both non-default tile widths and ragged launch groups; 5
+    # taps take the generic gain code of every path
+    N = 64
     nblocks = [37, 300, 1031]  # convolution lengths 2^7, 2^10, 2^12
-    print(f"case batched shapes prec={prec}", flush=True)
+    print(f"case batched shapes prec={prec} ntap={p}", flush=True)
     w, data = _streams(N, p, nblocks, 4300)
     bp = ipfb.BatchedPlan(N, p, w, nblocks, prec)
     bp.use_graph(False)
