@@ -598,6 +598,28 @@ int ipfb_wiener_stream(ipfb_splan sp, int infmt, const void* spec, const float* 
   return launched(e, "ipfb_wiener_stream");
 }
 
+}  // extern "C"
+
+namespace {
+
+// z = M^-1 r (the CG preconditioner) and the partial sums of r . z in
+// p->cg_part: formed by the column kernel itself where its workgroups fit the
+// partial-sum slots, else by a separate dot-product pass.
+hipError_t precond_dot(ipfb_plan p, const void* rT, void* zT, double phi_precond, int64_t S, hipStream_t st) {
+  hipError_t e = launch_col_wiener(p->prec, p->log2b, rT, zT, p->lblock, p->ntap, p->win64, phi_precond, 1, p->twB,
+                                   p->twB64, st, 1, p->cg_part);
+  if (e != hipErrorNotSupported) return e;
+  hipGetLastError();
+  e = launch_col_wiener(p->prec, p->log2b, rT, zT, p->lblock, p->ntap, p->win64, phi_precond, 1, p->twB, p->twB64,
+                        st, 1);
+  if (e == hipSuccess) e = launch_cg_dot(p->prec, rT, zT, S, p->cg_part, st);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
 int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, const uint8_t* mask,
                const void* prior, double lam, double phi_x0, double phi_precond, int iters, const void* x_init,
                void* x_out, double* resid_norms, void* stream) {
@@ -656,9 +678,7 @@ int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale
     if (e == hipSuccess) e = launch_cg_resid(p->prec, rhsT, qT, rT, S, p->cg_part, st);
     if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 2, p->cg_sc, resid_norms, 0, st);
     // z0 = M^-1 r0 with the partial sums of r0 . z0 formed on the way out
-    if (e == hipSuccess)
-      e = launch_col_wiener(p->prec, p->log2b, rT, zT, p->lblock, p->ntap, p->win64, phi_precond, 1, p->twB,
-                            p->twB64, st, 1, p->cg_part);
+    if (e == hipSuccess) e = precond_dot(p, rT, zT, phi_precond, S, st);
     if (e == hipSuccess) e = launch_cg_p(p->prec, pT, zT, p->cg_sc, 0, S, st);
     if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 0, p->cg_sc, nullptr, 0, st);
   }
@@ -668,9 +688,7 @@ int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale
     if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 1, p->cg_sc, nullptr, 0, st);
     if (e == hipSuccess) e = launch_cg_xr(p->prec, xT, rT, pT, qT, p->cg_sc, S, p->cg_part, st);
     if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 2, p->cg_sc, resid_norms, k, st);
-    if (e == hipSuccess)
-      e = launch_col_wiener(p->prec, p->log2b, rT, zT, p->lblock, p->ntap, p->win64, phi_precond, 1, p->twB,
-                            p->twB64, st, 1, p->cg_part);
+    if (e == hipSuccess) e = precond_dot(p, rT, zT, phi_precond, S, st);
     if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 3, p->cg_sc, nullptr, 0, st);
     if (e == hipSuccess) e = launch_cg_p(p->prec, pT, zT, p->cg_sc, 1, S, st);
   }

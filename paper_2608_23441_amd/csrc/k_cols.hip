@@ -211,7 +211,7 @@ static hipError_t launch_col_t(const void* d, void* xo, const GainArgs& ga, cons
   using Cfg = ColCfg<T, LOG2B>;
   static_assert((Cfg::NT & (Cfg::NT - 1)) == 0, "the dot product's tree needs a power-of-two workgroup");
   const int nwg = (ga.lblock + Cfg::C - 1) / Cfg::C;
-  if (part && nwg > kCgParts) return hipErrorInvalidValue;
+  if (part && nwg > kCgParts) return hipErrorNotSupported;  // more workgroups than partial-sum slots
   k_col_wiener<T, LOG2B><<<dim3(nwg), dim3(Cfg::NT), 0, st>>>(
       (const T*)d, (T*)xo, ga, (const cx<T>*)twB, (const cx<double>*)twB64, part, kCgParts);
   return hipGetLastError();

@@ -57,7 +57,8 @@ hipError_t launch_row_c4(int prec, int log2n, const void* in, const float* chan_
 // precond = 1 applies the real gain 1/(|W_n|^2 + phi^2) instead (the inverse
 // of A^T A + phi^2 I, used as the CG preconditioner). part != NULL: also the
 // partial sums of d . xo, one per workgroup, in part[0, kCgParts) (unused
-// slots zeroed; needs at most kCgParts workgroups).
+// slots zeroed; hipErrorNotSupported, launching nothing, where the stage
+// needs more than kCgParts workgroups).
 hipError_t launch_col_wiener(int prec, int log2b, const void* d, void* xo, int lblock, int ntap,
                              const double* win64, double phi, int normalise, const void* twB,
                              const double* twB64, hipStream_t st, int precond = 0, double* part = nullptr);

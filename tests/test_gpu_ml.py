@@ -165,3 +165,17 @@ def test_ml_cg_reads_no_workspace_before_writing_it(prec):
     dt = torch.float64 if prec == ipfb.F64 else torch.float32
     xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(mask.astype(np.uint8)), _dev(x).to(dt), 1.0, 0.1, 0.1, 3)
     assert np.all(np.isfinite(_host(xg))) and np.all(np.isfinite(_host(ng)))
+
+
+def test_ml_cg_long_columns_take_the_separate_dot_product():
+    # 2^14 frames in FP64: the column kernel runs one column per workgroup,
+    # 2048 workgroups, more than the partial-sum slots, so r.z is its own pass
+    N, p, b, iters = 2048, 4, 16384, 2
+    print(f"case ml_cg separate dot N={N} b={b}", flush=True)
+    w, x, packed, s, mask, d = _ml_case(N, p, b, 340)
+    x0 = O.column_inverse(d, w, N, p, 0.1).reshape(-1)
+    ref_x, ref_n = O.ml_pcg(d, w, N, p, mask, x, 1.0, 0.1, iters, x0)
+    plan = ipfb.Plan(N, p, w, b, ipfb.F64)
+    xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(mask.astype(np.uint8)), _dev(x), 1.0, 0.1, 0.1, iters)
+    assert np.max(np.abs(_host(ng) - ref_n) / ref_n) < 1e-9
+    assert _rel(_host(xg), ref_x) < 1e-9
