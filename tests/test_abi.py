@@ -76,3 +76,26 @@ def test_calls_reject_null_plan_and_pointers():
     assert L.ipfb_quantize_c4(None, None, 2.5, None, None, None) == ipfb.EINVAL
     assert L.ipfb_plan_destroy(None) == ipfb.EINVAL
     assert L.ipfb_window_sinc_hamming(None, 4, 16) == ipfb.EINVAL
+
+
+def test_new_entry_points_reject_bad_arguments_before_any_device_call():
+    L = ipfb.lib()
+    i4 = (ctypes.c_int * 6)(5, 16, 16, 0, 1, 0)
+    # batched shapes and tuner, streaming, filters, diagnostics, structured mask
+    assert L.ipfb_batched_get_shape(None, 10, i4) == ipfb.EINVAL
+    assert L.ipfb_batched_set_shape(None, 10, i4) == ipfb.EINVAL
+    assert L.ipfb_batched_tune(None, None, 0) == ipfb.EINVAL
+    assert L.ipfb_stream_plan_destroy(None) == ipfb.EINVAL
+    assert L.ipfb_wiener_stream(None, 0, None, None, 10, 0.1, 1, None, None) == ipfb.EINVAL
+    assert L.ipfb_wiener_filter(None, 0, None, None, 1, 0.1, None, 1, None, None) == ipfb.EINVAL
+    assert L.ipfb_delta_analytic(None, 16, 0.1, 0.0, None, None) == ipfb.EINVAL
+    assert L.ipfb_autospectrum_error(None, None, None, None, None) == ipfb.EINVAL
+    assert L.ipfb_mask_structured(None, 4, 8, None, None) == ipfb.EINVAL
+    w = np.ones(4 * 64)
+    h = ctypes.c_void_p()
+    for chunk, halo, prec in [(100, 8, 0), (64, 31, 0), (2, 0, 0), (64, -1, 0), (1 << 16, 8, 0), (1 << 15, 8, 1),
+                              (64, 8, 5)]:
+        st = L.ipfb_stream_plan_create(ctypes.byref(h), 64, 4, w.ctypes.data, chunk, halo, prec)
+        assert st == ipfb.EINVAL and not h.value, (chunk, halo, prec)
+        assert len(L.ipfb_last_error()) > 0
+    assert L.ipfb_stream_plan_create(None, 64, 4, w.ctypes.data, 64, 8, 0) == ipfb.EINVAL
