@@ -124,19 +124,23 @@ template <int LOG2P1>
 struct Lf1rCfg {
   static constexpr int P1 = 1 << LOG2P1;
   static constexpr int MB = 8;  // 64-byte runs: what the register budget allows
-  static constexpr int NT = 1024;
+  // P1 = 512: 512 threads of 8 elements, a 512-point FFT in three radix-8
+  // passes and room (two waves per SIMD) for the ring and window slice in
+  // registers; shorter rows keep 1024 threads
+  static constexpr int NT = LOG2P1 == 9 ? 512 : 1024;
   static constexpr int EPT = (P1 * MB) / NT;
   static constexpr int LS = lds_len(P1);
 };
 
 template <int LOG2P1>
-__global__ __launch_bounds__(1024) void k_lf1r(const cx<float>* __restrict__ x, cx<float>* __restrict__ tmp,
+__global__ __launch_bounds__(Lf1rCfg<LOG2P1>::NT) void k_lf1r(const cx<float>* __restrict__ x,
+                                                               cx<float>* __restrict__ tmp,
                                                int64_t nblock, const cx<float>* __restrict__ win,
                                                LfTw<float> tw, int M, int P2, int nr, int frange) {
   using Cfg = Lf1rCfg<LOG2P1>;
   constexpr int P1 = Cfg::P1, MB = Cfg::MB, NT = Cfg::NT, EPT = Cfg::EPT, LS = Cfg::LS;
   constexpr int NTAP = 4;
-  static_assert(EPT >= 1 && EPT <= 4, "register budget: 4 frames + 4 window taps of EPT elements");
+  static_assert(EPT >= 1 && EPT <= 8, "register budget: 4 frames + 4 window taps of EPT elements");
   __shared__ cx<float> s[MB * LS];
   // the twiddle tables live in LDS for the life of the workgroup: every FFT
   // pass and store then waits on LDS, not on global-memory latency
