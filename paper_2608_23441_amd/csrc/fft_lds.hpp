@@ -38,6 +38,15 @@ template <typename T>
 __device__ __forceinline__ cx<T> conj(cx<T> a) { return mk<T>(a.x, -a.y); }
 template <typename T>
 __device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+// Load of a value that this kernel reads once and does not write back: a
+// non-temporal load. Read streams loaded this way leave the last-level cache
+// to the lines the kernel writes, which the next kernel reads.
+template <typename T>
+__device__ __forceinline__ cx<T> ld_once(const cx<T>* p) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
+  return mk<T>(v.x, v.y);
+}
 // multiply by DIR*i  (DIR = -1: forward transform kernel e^{-i...}; +1 inverse)
 template <int DIR, typename T>
 __device__ __forceinline__ cx<T> mul_i(cx<T> a) {

@@ -48,6 +48,10 @@ constexpr int kGainWiener = 0, kGainThreshold = 1, kGainNu = 2;
 template <typename T>
 struct NatCfg {
   static constexpr int TP = 128 / (int)sizeof(cx<T>);  // pairs per tile: 128 bytes per frame
+  // pairs per workgroup of passes A and C: 512-byte runs per frame. When the
+  // frames are not in the last-level cache (pass A after the row stage), HBM
+  // serves the strided gather much faster in runs of 512 bytes than of 128
+  static constexpr int TPO = 4 * TP;
   static constexpr int EPT = sizeof(T) == 4 ? 16 : 8;  // complex elements per thread in the FFTs
   static constexpr int clampnt(int v) { return v < 64 ? 64 : (v > 1024 ? 1024 : v); }
 };
@@ -108,14 +112,15 @@ __device__ __forceinline__ void pair_gains_kind(const NatGain& ga, cx<double> Wa
 }
 
 // Passes A (DIR = -1) and C (DIR = +1): a b1-point FFT down the rows
-// b2 j1 + j2 of one tile, for one j2 per workgroup. All global loads of a
-// thread are issued before the first LDS write; the four-step twiddles of
-// pass A are gathered into LDS at the start.
+// b2 j1 + j2 of TPO pairs [pa + TPO g, ...) clipped to pe, for one j2 per
+// workgroup (ng groups g). All global loads of a thread are issued before the
+// first LDS write; the four-step twiddles of pass A are gathered into LDS at
+// the start.
 template <typename T, int LOG2B1, int LOG2B2, int DIR>
-__global__ __launch_bounds__((NatCfg<T>::clampnt(NatCfg<T>::TP * (1 << LOG2B1) / NatCfg<T>::EPT)), 4) void k_nat_outer(
-    cx<T>* __restrict__ z, int np, int t0, int ntile, const cx<T>* __restrict__ tw, cx<T>* __restrict__ out,
+__global__ __launch_bounds__((NatCfg<T>::clampnt(NatCfg<T>::TPO * (1 << LOG2B1) / NatCfg<T>::EPT)), 4) void k_nat_outer(
+    cx<T>* __restrict__ z, int np, int pa, int pe, int ng, const cx<T>* __restrict__ tw, cx<T>* __restrict__ out,
     int r0, int nr) {
-  constexpr int TP = NatCfg<T>::TP;
+  constexpr int TP = NatCfg<T>::TPO;
   constexpr int B1 = 1 << LOG2B1, B2 = 1 << LOG2B2, B = B1 * B2;
   constexpr int NT = NatCfg<T>::clampnt(TP * B1 / NatCfg<T>::EPT);
   constexpr int LS = lds_len(B1);
@@ -124,8 +129,8 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(NatCfg<T>::TP * (1 << LOG2B1) /
   __shared__ cx<T> tws[DIR < 0 ? B1 : 1];
   __shared__ cx<T> twf[B1];  // e^{-2 pi i m / b1}: the FFT's table, LDS-resident
   const int tid = threadIdx.x;
-  const int tile = blockIdx.x % ntile, j2 = blockIdx.x / ntile;
-  const int p0 = (t0 + tile) * TP;
+  const int g = blockIdx.x % ng, j2 = blockIdx.x / ng;
+  const int p0 = pa + g * TP;
   for (int m = tid; m < B1; m += NT) {
     twf[m] = tw[m * B2];
     if (DIR < 0) tws[m] = tw[j2 * m];  // e^{-2 pi i j2 k1 / b}
@@ -135,7 +140,7 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(NatCfg<T>::TP * (1 << LOG2B1) /
   for (int i = 0; i < IT; ++i) {
     const int e = tid + i * NT, q = e % TP, j1 = e / TP;
     v[i] = mk<T>(T(0), T(0));
-    if ((NE % NT == 0 || e < NE) && p0 + q < np) v[i] = z[(int64_t)(j1 * B2 + j2) * np + p0 + q];
+    if ((NE % NT == 0 || e < NE) && p0 + q < pe) v[i] = z[(int64_t)(j1 * B2 + j2) * np + p0 + q];
   }
 #pragma unroll
   for (int i = 0; i < IT; ++i) {
@@ -150,7 +155,7 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(NatCfg<T>::TP * (1 << LOG2B1) /
     if (NE % NT != 0 && e >= NE) continue;
     cx<T> u = s[q * LS + pidx(k1)];
     if (DIR < 0) u = cmul(u, tws[k1]);
-    if (p0 + q >= np) continue;
+    if (p0 + q >= pe) continue;
     const int row = k1 * B2 + j2;
     if (DIR > 0 && out) {  // only the frames [r0, r0 + nr), to out
       if (row >= r0 && row < r0 + nr) out[(int64_t)(row - r0) * np + p0 + q] = u;
@@ -383,16 +388,19 @@ static hipError_t launch_nat_t(int pass, void* zv, int lblock, int tile0, int nt
     launch_mid<T, 0, LOG2B>(kind, dim3(ntiles), dim3(NT), z, np, tile0, ntiles, ga, tw, tw64, st);
   } else {
     constexpr int L1 = LOG2B / 2, L2 = LOG2B - L1;
-    constexpr int NTO = Cfg::clampnt(Cfg::TP * (1 << L1) / Cfg::EPT);
+    constexpr int NTO = Cfg::clampnt(Cfg::TPO * (1 << L1) / Cfg::EPT);
     constexpr int NTM = Cfg::clampnt(2 * Cfg::TP * (1 << L2) / Cfg::EPT);
+    // passes A and C: the pairs of tiles [tile0, tile0 + ntiles) in groups of TPO
+    const int pa = tile0 * Cfg::TP;
+    const int pe = (tile0 + ntiles) * Cfg::TP < np ? (tile0 + ntiles) * Cfg::TP : np;
+    const int ng = (pe - pa + Cfg::TPO - 1) / Cfg::TPO;
     if (pass == 0)
-      k_nat_outer<T, L1, L2, -1><<<dim3(ntiles * (1 << L2)), dim3(NTO), 0, st>>>(z, np, tile0, ntiles, tw, nullptr,
-                                                                                  0, 0);
+      k_nat_outer<T, L1, L2, -1><<<dim3(ng * (1 << L2)), dim3(NTO), 0, st>>>(z, np, pa, pe, ng, tw, nullptr, 0, 0);
     if (pass == 1)
       launch_mid<T, L1, L2>(kind, dim3(ntiles * (1 << (L1 - 1))), dim3(NTM), z, np, tile0, ntiles, ga, tw, tw64, st);
     if (pass == 2)
-      k_nat_outer<T, L1, L2, +1><<<dim3(ntiles * (1 << L2)), dim3(NTO), 0, st>>>(z, np, tile0, ntiles, tw,
-                                                                                  (cx<T>*)out, r0, nr);
+      k_nat_outer<T, L1, L2, +1><<<dim3(ng * (1 << L2)), dim3(NTO), 0, st>>>(z, np, pa, pe, ng, tw, (cx<T>*)out,
+                                                                              r0, nr);
   }
   return hipGetLastError();
 }

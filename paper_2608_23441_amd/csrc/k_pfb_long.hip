@@ -273,7 +273,7 @@ __global__ __launch_bounds__((Lf2Cfg<T, LOG2P2>::NT)) void k_lf2(
       const int sl = e / P2, c = e % P2;
       const int half = sl / KB, q = sl % KB;
       pf[i] = mk<T>(T(0), T(0));
-      if (q < count) pf[i] = tj[(int64_t)row_of(half, q) * P2 + c];
+      if (q < count) pf[i] = ld_once(tj + (int64_t)row_of(half, q) * P2 + c);
     }
   };
   if (ja < jb) fetch(ja);

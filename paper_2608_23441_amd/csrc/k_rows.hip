@@ -133,7 +133,10 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
       pf[d] = 0u;
       if (idx < nd) {
         if (byte + 4 <= total) {
-          pf[d] = *reinterpret_cast<const unsigned int*>(in + byte);
+          // read once: a non-temporal load, so that the input stream does not
+          // push the frames this kernel writes out of the last-level cache
+          // (the column pass that follows reads them back from there)
+          pf[d] = __builtin_nontemporal_load(reinterpret_cast<const unsigned int*>(in + byte));
         } else {  // the array's last word may be partial: read its bytes one by one
           unsigned int w = 0u;
           for (int q = 0; q < 4 && byte + q < total; ++q) w |= (unsigned int)in[byte + q] << (8 * q);
