@@ -156,10 +156,13 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
     __syncthreads();
     if (j + gridDim.x < nrows) fetch(j + gridDim.x);  // in flight during the FFT
     const unsigned char* rb = reinterpret_cast<const unsigned char*>(raw) + (int)((j * (int64_t)(H + 1)) & 3);
+    // one dequantised pair (Y_k, Y_{H-k}) gives Z_k = a + i t and, since
+    // e^{+2 pi i (H-k)/N} = -conj e^{+2 pi i k/N}, Z_{H-k} = conj(a) + i conj(t)
+    constexpr int HH = H / 2;
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
+    for (int i = 0; i < (HH + NT) / NT; ++i) {
       const int k = tid + i * NT;
-      if (k >= H) continue;
+      if (k > HH) continue;
       const signed char bk = (signed char)rb[k], bm = (signed char)rb[H - k];
       const T fk = facs[k], fm = facs[H - k];
       cx<T> yk = mk<T>(T(bk >> 4) * fk, T((signed char)(bk << 4) >> 4) * fk);
@@ -171,6 +174,7 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
       const cx<T> a = yk + conj(ym);
       const cx<T> t = cmul(wt[k], yk - conj(ym));
       s[pidx(k)] = mk<T>(a.x - t.y, a.y + t.x);  // a + i t
+      if (k != 0 && k != HH) s[pidx(H - k)] = mk<T>(a.x + t.y, t.x - a.y);
     }
     __syncthreads();
     // the FFT's own twiddles stay in global memory (L2): an LDS copy would
