@@ -115,38 +115,39 @@ __global__ __launch_bounds__((Lf1Cfg<T, LOG2P1>::NT), 2) void k_lf1(
   }
 }
 
-// Pass 1, sliding form (FP32, 4 taps, P1 <= 512): one workgroup per column
-// block of 8 columns and a range of frames. The window slice and the four
+// Pass 1, sliding form (4 taps, P1 <= 512): one workgroup per column block
+// (64 bytes of columns: 8 in FP32, 4 in FP64) and a range of frames. The window slice and the four
 // frames of the sliding sum stay in registers (each input sample is loaded
 // once per workgroup, the window once), and the next frame is fetched while
 // the FFT of the current one runs.
-template <int LOG2P1>
+template <typename T, int LOG2P1>
 struct Lf1rCfg {
   static constexpr int P1 = 1 << LOG2P1;
-  static constexpr int MB = 8;  // 64-byte runs: what the register budget allows
-  // P1 = 512: 512 threads of 8 elements, a 512-point FFT in three radix-8
-  // passes and room (two waves per SIMD) for the ring and window slice in
-  // registers; shorter rows keep 1024 threads
-  static constexpr int NT = LOG2P1 == 9 ? 512 : 1024;
+  static constexpr int MB = 64 / (int)sizeof(cx<T>);  // 64-byte runs: what the register budget allows
+  // FP32, P1 = 512: 512 threads of 8 elements, a 512-point FFT in three
+  // radix-8 passes and room (two waves per SIMD) for the ring and window slice
+  // in registers; shorter FP32 rows keep 1024 threads. FP64: 512 threads,
+  // the same register budget at half the elements
+  static constexpr int NT = (sizeof(T) == 8 || LOG2P1 == 9) ? 512 : 1024;
   static constexpr int EPT = (P1 * MB) / NT;
   static constexpr int LS = lds_len(P1);
 };
 
-template <int LOG2P1>
-__global__ __launch_bounds__(Lf1rCfg<LOG2P1>::NT) void k_lf1r(const cx<float>* __restrict__ x,
-                                                               cx<float>* __restrict__ tmp,
-                                               int64_t nblock, const cx<float>* __restrict__ win,
-                                               LfTw<float> tw, int M, int P2, int nr, int frange) {
-  using Cfg = Lf1rCfg<LOG2P1>;
+template <typename T, int LOG2P1>
+__global__ __launch_bounds__((Lf1rCfg<T, LOG2P1>::NT)) void k_lf1r(const cx<T>* __restrict__ x,
+                                                                  cx<T>* __restrict__ tmp, int64_t nblock,
+                                                                  const cx<T>* __restrict__ win, LfTw<T> tw,
+                                                                  int M, int P2, int nr, int frange) {
+  using Cfg = Lf1rCfg<T, LOG2P1>;
   constexpr int P1 = Cfg::P1, MB = Cfg::MB, NT = Cfg::NT, EPT = Cfg::EPT, LS = Cfg::LS;
   constexpr int NTAP = 4;
   static_assert(EPT >= 1 && EPT <= 8, "register budget: 4 frames + 4 window taps of EPT elements");
-  __shared__ cx<float> s[MB * LS];
+  __shared__ cx<T> s[MB * LS];
   // the twiddle tables live in LDS for the life of the workgroup: every FFT
   // pass and store then waits on LDS, not on global-memory latency
   // M = P1 * P2 <= P1^2, so e^{-2 pi i 512 m / M} needs at most P1^2 / 512 entries
   constexpr int NHI = (P1 * P1) / 512 > 0 ? (P1 * P1) / 512 : 1;
-  __shared__ cx<float> tP1s[P1], tMlos[512], tMhis[NHI];
+  __shared__ cx<T> tP1s[P1], tMlos[512], tMhis[NHI];
   const int tid = threadIdx.x;
   const int lg = xcd_remap(blockIdx.x, (int)gridDim.x);
   const int cb = lg / nr, rg = lg % nr;
@@ -161,7 +162,7 @@ __global__ __launch_bounds__(Lf1rCfg<LOG2P1>::NT) void k_lf1r(const cx<float>* _
   constexpr int ASTEP = NT / MB;
   // frames wrap once at most (nblock >= NTAP): f < nblock + NTAP
   auto frame_off = [&](int64_t f) -> int64_t { return (f < nblock ? f : f - nblock) * (int64_t)M; };
-  cx<float> w[NTAP][EPT], ring[NTAP][EPT];
+  cx<T> w[NTAP][EPT], ring[NTAP][EPT];
 #pragma unroll
   for (int r = 0; r < NTAP; ++r) {
     const int64_t fo = frame_off(ja + r);
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(Lf1rCfg<LOG2P1>::NT) void k_lf1r(const cx<float>* _
   for (int64_t j = ja; j < jb; ++j) {
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      cx<float> acc = mk<float>(0.f, 0.f);
+      cx<T> acc = mk<T>(T(0), T(0));
 #pragma unroll
       for (int r = 0; r < NTAP; ++r) {
         acc.x += w[r][i].x * ring[r][i].x;
@@ -194,8 +195,8 @@ __global__ __launch_bounds__(Lf1rCfg<LOG2P1>::NT) void k_lf1r(const cx<float>* _
       for (int i = 0; i < EPT; ++i) ring[NTAP - 1][i] = x[fo + off0 + i * ASTEP * P2];
     }
     __syncthreads();
-    lds_fft<float, P1, NT, MB, -1>(s, LS, tP1s, 1);
-    cx<float>* tj = tmp + j * (int64_t)M;
+    lds_fft<T, P1, NT, MB, -1>(s, LS, tP1s, 1);
+    cx<T>* tj = tmp + j * (int64_t)M;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * NT;
@@ -364,17 +365,17 @@ static LfTw<T> lf_tables(const void* twS, int P1, int P2, int M) {
 template <typename T, int L1>
 static hipError_t launch_lf1_t(const void* x, void* tmp, int64_t nblock, int ntap, const void* winT,
                                const LfTw<T>& tw, int M, int P2, hipStream_t st) {
-  if constexpr (sizeof(T) == 4 && L1 <= 9) {
+  if constexpr (L1 <= 9) {
     if (ntap == 4 && nblock >= 4 && (M >> 9) <= ((1 << L1) * (1 << L1)) / 512) {
-      using Cr = Lf1rCfg<L1>;
+      using Cr = Lf1rCfg<T, L1>;
       const int ncb = P2 / Cr::MB;
       // about one workgroup per CU, each sliding over a range of frames
       int64_t nr = (256 + ncb - 1) / ncb;
       if (nr > nblock) nr = nblock;
       const int frange = (int)((nblock + nr - 1) / nr);
       nr = (nblock + frange - 1) / frange;
-      k_lf1r<L1><<<dim3((unsigned)(ncb * nr)), dim3(Cr::NT), 0, st>>>(
-          (const cx<float>*)x, (cx<float>*)tmp, nblock, (const cx<float>*)winT, tw, M, P2, (int)nr, frange);
+      k_lf1r<T, L1><<<dim3((unsigned)(ncb * nr)), dim3(Cr::NT), 0, st>>>(
+          (const cx<T>*)x, (cx<T>*)tmp, nblock, (const cx<T>*)winT, tw, M, P2, (int)nr, frange);
       return hipGetLastError();
     }
   }
