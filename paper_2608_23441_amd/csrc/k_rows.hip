@@ -101,7 +101,12 @@ struct RowPCfg {
   static constexpr int LS = lds_len(H);
   static constexpr int RAWW = (H + 1 + 3) / 4 + 2;  // words covering the run from its aligned start
   static constexpr int DPT = (RAWW + NT - 1) / NT;  // words fetched per thread
-  static constexpr int LDSB = LS * (int)sizeof(cx<T>) + (H + 1) * (int)sizeof(T) + H * (int)sizeof(cx<T>) + RAWW * 4;
+  // the pre-twiddles sit in LDS where that still fits the LDS budget with
+  // them (FP32); otherwise (FP64, long frames) they are read from the global
+  // table, which stays in L2
+  static constexpr int LDSB0 = LS * (int)sizeof(cx<T>) + (H + 1) * (int)sizeof(T) + RAWW * 4;
+  static constexpr bool WT_LDS = LDSB0 + H * (int)sizeof(cx<T>) <= 81920;
+  static constexpr int LDSB = LDSB0 + (WT_LDS ? H * (int)sizeof(cx<T>) : 0);
 };
 
 template <typename T, int LOG2N>
@@ -114,13 +119,14 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
   static_assert(H % NT == 0 || NT == 64, "frame must split over the threads");
   __shared__ cx<T> s[LS];
   __shared__ T facs[H + 1];
-  __shared__ cx<T> wt[H];  // e^{+2 pi i k / N}: pre-twiddles
+  __shared__ cx<T> wt[Cfg::WT_LDS ? H : 1];  // e^{+2 pi i k / N}: pre-twiddles
   __shared__ unsigned int raw[RAWW];
   const int tid = threadIdx.x;
   const int64_t total = nrows * (int64_t)(H + 1);
   // dequantisation factor 1/(s_k N), formed in FP64 from the stored FP32 scale
   for (int k = tid; k <= H; k += NT) facs[k] = T(1.0 / ((double)chan_scale[k] * (double)N));
-  for (int k = tid; k < H; k += NT) wt[k] = conj(twN[k]);
+  if constexpr (Cfg::WT_LDS)
+    for (int k = tid; k < H; k += NT) wt[k] = conj(twN[k]);
   unsigned int pf[DPT];
   auto fetch = [&](int64_t j) {
     const int64_t b0 = j * (int64_t)(H + 1);
@@ -172,7 +178,7 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
         ym.y = T(0);
       }
       const cx<T> a = yk + conj(ym);
-      const cx<T> t = cmul(wt[k], yk - conj(ym));
+      const cx<T> t = cmul(Cfg::WT_LDS ? wt[k] : conj(twN[k]), yk - conj(ym));
       s[pidx(k)] = mk<T>(a.x - t.y, a.y + t.x);  // a + i t
       if (k != 0 && k != HH) s[pidx(H - k)] = mk<T>(a.x + t.y, t.x - a.y);
     }

@@ -44,6 +44,7 @@ def _quantised_case(N, p, b, seed, levels=2.5):
 @pytest.mark.parametrize("N,p,b,phi", [
     (16, 4, 8, 0.1), (64, 4, 32, 0.1), (256, 4, 64, 0.0), (128, 3, 16, 0.3),
     (2048, 4, 128, 0.1), (4096, 4, 256, 0.1), (32, 4, 2048, 0.1), (8, 4, 4, 0.1),
+    (8192, 4, 32, 0.1),  # persistent row kernel with the pre-twiddles read from global memory (FP32)
 ])
 def test_ipfb_wiener_c4(prec, N, p, b, phi):
     print(f"case ipfb_wiener c4 prec={prec} N={N} p={p} b={b} phi={phi}", flush=True)
