@@ -116,10 +116,10 @@ __global__ __launch_bounds__((Lf1Cfg<T, LOG2P1>::NT), 2) void k_lf1(
 }
 
 // Pass 1, sliding form (4 taps, P1 <= 512): one workgroup per column block
-// (64 bytes of columns: 8 in FP32, 4 in FP64) and a range of frames. The window slice and the four
-// frames of the sliding sum stay in registers (each input sample is loaded
-// once per workgroup, the window once), and the next frame is fetched while
-// the FFT of the current one runs.
+// (64 bytes of columns: 8 in FP32, 4 in FP64) and a range of frames. The
+// window slice and the four frames of the sliding sum stay in registers (each
+// input sample is loaded once per workgroup, the window once), and the next
+// frame is fetched while the FFT of the current one runs.
 template <typename T, int LOG2P1>
 struct Lf1rCfg {
   static constexpr int P1 = 1 << LOG2P1;

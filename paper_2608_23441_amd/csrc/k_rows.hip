@@ -87,11 +87,11 @@ __global__ __launch_bounds__((RowCfg<T, LOG2N>::NT)) void k_row_irfft(
 }
 
 // Persistent form for 4-bit spectra: each workgroup inverts frames j, j + G,
-// j + 2G, ... (G = grid size). The per-channel factors and the pre-twiddles
-// e^{+2 pi i k/N} sit in LDS for the workgroup's life; a frame's packed
-// bytes (an unaligned run of N/2+1 bytes) arrive as aligned 4-byte words
-// staged through LDS, and the next frame's words are fetched into registers
-// while the current frame's FFT runs.
+// j + 2G, ... (G = grid size). The per-channel factors and (where they fit)
+// the pre-twiddles e^{+2 pi i k/N} sit in LDS for the workgroup's life; a
+// frame's packed bytes (an unaligned run of N/2+1 bytes) arrive as aligned
+// 4-byte words staged through LDS, and the next frame's words are fetched
+// into registers while the current frame's FFT runs.
 template <typename T, int LOG2N>
 struct RowPCfg {
   static constexpr int H = 1 << (LOG2N - 1);
