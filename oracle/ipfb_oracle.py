@@ -133,6 +133,18 @@ def unpack_c4(packed: np.ndarray):
     return hi.astype(np.int8), lo.astype(np.int8)
 
 
+def pack_ci8(qr: np.ndarray, qi: np.ndarray) -> np.ndarray:
+    """Two bytes per complex value, the real then the imaginary code, each an
+    8-bit two's complement integer: [..., 2] int8 (READING: the paper
+    quantises to 4 bits only; this is the finer format of the interface)."""
+    return np.stack([qr.astype(np.int8), qi.astype(np.int8)], axis=-1)
+
+
+def unpack_ci8(packed: np.ndarray):
+    """Inverse of pack_ci8."""
+    return packed[..., 0].astype(np.int8), packed[..., 1].astype(np.int8)
+
+
 def dequantize(qr: np.ndarray, qi: np.ndarray, scales_f32: np.ndarray) -> np.ndarray:
     """yhat = q / s_k with s_k read back from its float32 value."""
     s = np.asarray(scales_f32, dtype=np.float32).astype(np.float64)[None, :]
@@ -264,6 +276,14 @@ def ipfb_wiener(packed: np.ndarray, scales_f32: np.ndarray, window: np.ndarray,
                 lblock: int, ntap: int, phi: float, normalise: bool = True) -> np.ndarray:
     """Dequantise packed 4-bit spectra, then invert (steps a1..a5)."""
     qr, qi = unpack_c4(packed)
+    return ipfb_wiener_from_spectra(dequantize(qr, qi, scales_f32), window, lblock,
+                                    ntap, phi, normalise)
+
+
+def ipfb_wiener_ci8(packed: np.ndarray, scales_f32: np.ndarray, window: np.ndarray,
+                    lblock: int, ntap: int, phi: float, normalise: bool = True) -> np.ndarray:
+    """Dequantise 8-bit spectra ([nspec][N/2+1][2] int8), then invert (a1..a5)."""
+    qr, qi = unpack_ci8(packed)
     return ipfb_wiener_from_spectra(dequantize(qr, qi, scales_f32), window, lblock,
                                     ntap, phi, normalise)
 
