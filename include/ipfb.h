@@ -54,8 +54,13 @@ typedef enum { IPFB_F32 = 0, IPFB_F64 = 1 } ipfb_prec;
  *   imaginary part in the low nibble, each 4-bit two's complement in -7..7
  *   (Section 4.3's 15-level quantiser), with a per-channel float scale s_k:
  *   the spectrum is q / s_k.
- * IPFB_IN_CF32 / IPFB_IN_CF64: interleaved float / double complex. */
-typedef enum { IPFB_IN_C4 = 0, IPFB_IN_CF32 = 2, IPFB_IN_CF64 = 3 } ipfb_infmt;
+ * IPFB_IN_CI8: two bytes per complex value, the real then the imaginary
+ *   part, each an 8-bit two's complement code, with the same per-channel
+ *   scale: the spectrum is q / s_k (a finer quantiser than Section 4.3's).
+ * IPFB_IN_CF32 / IPFB_IN_CF64: interleaved float / double complex.
+ * chan_scale arguments below are required for the two quantised formats
+ * and ignored (may be NULL) for the float ones. */
+typedef enum { IPFB_IN_C4 = 0, IPFB_IN_CI8 = 1, IPFB_IN_CF32 = 2, IPFB_IN_CF64 = 3 } ipfb_infmt;
 
 typedef struct ipfb_plan_s* ipfb_plan;
 
@@ -77,8 +82,28 @@ int ipfb_window_sinc_hamming(double* out, int ntap, int lblock);
  * The plan allocates its tables and workspace on the current device. */
 int ipfb_plan_create(ipfb_plan* out, int lblock, int ntap, const double* window, int64_t nblock, int prec);
 int ipfb_plan_destroy(ipfb_plan plan);
-/* Device bytes the plan holds (tables + workspace). */
+/* Bytes of the plan's workspace: the frame buffers every call uses as
+ * scratch (the frame matrix d, its transposed copy where the column length
+ * is a power of two, the long-frame intermediate). This is the size
+ * ipfb_plan_set_workspace needs. */
 int ipfb_plan_workspace_size(ipfb_plan plan, size_t* bytes);
+/* Device bytes the plan holds itself: its tables, small buffers, scratch
+ * allocated on first use, and its workspace unless the caller provides it. */
+int ipfb_plan_device_bytes(ipfb_plan plan, size_t* bytes);
+/* Gives the plan a caller-owned workspace (Section 3's inverse needs d and
+ * the column-stage intermediate per call; this is where they live).
+ * dev: device memory on the plan's device, 256-byte aligned, at least
+ * ipfb_plan_workspace_size bytes (bytes: its size). The call waits for the
+ * device to finish queued work, releases the plan's own workspace and uses
+ * dev in every later call; its contents are scratch, not kept between calls.
+ * The caller keeps dev allocated, does not touch it while calls on the plan
+ * may run, and frees it only after ipfb_plan_destroy or after giving the plan
+ * another workspace. dev = NULL gives the plan a workspace of its own again
+ * (if that allocation fails the caller's stays in use). Scratch that some
+ * calls allocate on first use (the ML-CG vectors, the diagnostics, the
+ * Bluestein path of a non-power-of-two nblock) stays the plan's.
+ * Errors: IPFB_EINVAL (too small, misaligned, NULL plan), IPFB_ENOMEM. */
+int ipfb_plan_set_workspace(ipfb_plan plan, void* dev, size_t bytes);
 
 /* Forward PFB (Section 2.2 polyphase equation, Section 2.3 y = F S W x),
  * circular: y_j[k] = sum_n e^{-2 pi i nk/N} sum_r h[rN+n] x[((j+r) mod b)N + n].
@@ -101,7 +126,7 @@ int pfb_adjoint(ipfb_plan plan, const void* y, void* x, void* stream);
  * phi = 0 gives the plain division 1/conj(W_n), with eigenvalues at rounding
  * level (|W| <= 1e-12 sum_r |h[rN+n]|) truncated to zero.
  * spec: [nblock][lblock/2+1] in format infmt. chan_scale: device float
- * [lblock/2+1] for IPFB_IN_C4, ignored (may be NULL) otherwise.
+ * [lblock/2+1] for IPFB_IN_C4 and IPFB_IN_CI8, ignored (may be NULL) otherwise.
  * x_out: [nblock*lblock] real, time order. The imaginary parts of the DC and
  * Nyquist channels are ignored. The row stage writes the frame matrix into
  * x_out and the column stage transforms it there in place, so x_out must not
@@ -246,7 +271,7 @@ int ipfb_batched_workspace_size(ipfb_bplan plan, size_t* bytes);
  * format or normalisation change; on = 0: launch directly on the stream. */
 int ipfb_batched_use_graph(ipfb_bplan plan, int on);
 /* spec, chan_scale, x_out: host arrays [nstreams] of device pointers with the
- * per-stream layouts of ipfb_wiener (chan_scale ignored unless IPFB_IN_C4).
+ * per-stream layouts of ipfb_wiener (chan_scale ignored for the float formats).
  * normalise as in ipfb_wiener_ex. Asynchronous on stream (NULL = default). */
 int ipfb_wiener_batched(ipfb_bplan plan, int infmt, const void* const* spec, const float* const* chan_scale,
                         double phi, int normalise, void* const* x_out, void* stream);

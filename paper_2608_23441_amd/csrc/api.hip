@@ -108,11 +108,23 @@ struct ipfb_plan_s {
   // spectra of either, and the two autospectra
   void* diag = nullptr;
   size_t bytes = 0;
+  bool ws_ext = false;  // work, work2, tmp point into a caller-owned workspace
 };
 
 namespace {
 
 size_t esize(int prec) { return prec == IPFB_F32 ? sizeof(float) : sizeof(double); }
+
+// Input spectrum formats; the quantised ones carry per-channel scales.
+bool scaled_infmt(int f) { return f == IPFB_IN_C4 || f == IPFB_IN_CI8; }
+size_t infmt_bytes(int f) { return f == IPFB_IN_C4 ? 1 : f == IPFB_IN_CI8 ? 2 : f == IPFB_IN_CF32 ? 8 : 16; }
+int check_infmt(int infmt, const void* chan_scale) {
+  if (infmt != IPFB_IN_C4 && infmt != IPFB_IN_CI8 && infmt != IPFB_IN_CF32 && infmt != IPFB_IN_CF64)
+    return fail(IPFB_EINVAL, "unknown input format %d", infmt);
+  if (scaled_infmt(infmt) && !chan_scale)
+    return fail(IPFB_EINVAL, "chan_scale is required for the quantised formats (IPFB_IN_C4, IPFB_IN_CI8)");
+  return IPFB_OK;
+}
 
 int dev_alloc(ipfb_plan p, void** ptr, size_t bytes) {
   if (bytes == 0) bytes = 16;
@@ -148,11 +160,33 @@ void free_bplan(ipfb_bplan p);
 
 void free_plan(ipfb_plan p) {
   if (p->blu1) free_bplan(p->blu1);
-  void* ptrs[] = {p->win64, p->winT, p->twN, p->twB, p->twB64, p->work, p->work2, p->tmp, p->part, p->fac, p->twS,
+  void* ptrs[] = {p->win64, p->winT, p->twN, p->twB, p->twB64, p->part, p->fac, p->twS,
                   p->cg, p->cg_autoc, p->cg_part, p->cg_sc, p->diag};
   for (void* q : ptrs)
     if (q) hipFree(q);
+  if (!p->ws_ext) {
+    void* ws[] = {p->work, p->work2, p->tmp};
+    for (void* q : ws)
+      if (q) hipFree(q);
+  }
   delete p;
+}
+
+// The workspace a caller may provide: the plan's per-call frame buffers d
+// (work), its transposed copy (work2) and the long-frame intermediate (tmp),
+// each present or not with the plan's shape, at 256-byte-aligned offsets.
+// Returns the total; o_* receive the offsets (SIZE_MAX where absent).
+size_t ws_layout(ipfb_plan p, size_t* o_work, size_t* o_work2, size_t* o_tmp) {
+  const size_t fb = ((size_t)p->nblock * p->lblock * esize(p->prec) + 255) & ~size_t(255);
+  size_t off = 0;
+  auto take = [&](bool need, size_t* o) {
+    *o = need ? off : SIZE_MAX;
+    if (need) off += fb;
+  };
+  take(p->row_lds, o_work);
+  take(p->row_lds && p->col_lds, o_work2);
+  take(!p->row_lds, o_tmp);
+  return off;
 }
 
 struct DeviceGuard {
@@ -357,7 +391,62 @@ int ipfb_plan_destroy(ipfb_plan plan) {
 int ipfb_plan_workspace_size(ipfb_plan plan, size_t* bytes) {
   if (check_plan(plan)) return IPFB_EINVAL;
   if (!bytes) return fail(IPFB_EINVAL, "bytes is NULL");
+  size_t a, b, c;
+  *bytes = ws_layout(plan, &a, &b, &c);
+  return ok();
+}
+
+int ipfb_plan_device_bytes(ipfb_plan plan, size_t* bytes) {
+  if (check_plan(plan)) return IPFB_EINVAL;
+  if (!bytes) return fail(IPFB_EINVAL, "bytes is NULL");
   *bytes = plan->bytes;
+  return ok();
+}
+
+int ipfb_plan_set_workspace(ipfb_plan p, void* dev, size_t bytes) {
+  if (check_plan(p)) return IPFB_EINVAL;
+  size_t ow, ow2, ot;
+  const size_t need = ws_layout(p, &ow, &ow2, &ot);
+  if (dev && bytes < need)
+    return fail(IPFB_EINVAL, "workspace of %zu bytes is smaller than the %zu bytes the plan needs", bytes, need);
+  if (dev && ((uintptr_t)dev & 255)) return fail(IPFB_EINVAL, "workspace must be 256-byte aligned");
+  if (!dev && !p->ws_ext) return ok();  // the plan already owns its workspace
+  DeviceGuard g(p->dev);
+  void** bufs[3] = {&p->work, &p->work2, &p->tmp};
+  const size_t offs[3] = {ow, ow2, ot};
+  const size_t fbytes = (size_t)p->nblock * p->lblock * esize(p->prec);
+  void* next[3] = {nullptr, nullptr, nullptr};
+  if (dev) {
+    for (int i = 0; i < 3; ++i)
+      if (offs[i] != SIZE_MAX) next[i] = (char*)dev + offs[i];
+  } else {
+    // back to a workspace of the plan's own: allocate it before letting the
+    // caller's go, so that a failure leaves the plan as it was
+    for (int i = 0; i < 3; ++i) {
+      if (offs[i] == SIZE_MAX) continue;
+      const int st = dev_alloc(p, &next[i], fbytes);
+      if (st) {
+        for (int k = 0; k < i; ++k)
+          if (next[k]) {
+            hipFree(next[k]);
+            p->bytes -= fbytes;
+          }
+        return st;
+      }
+    }
+  }
+  // calls already queued may still use the current workspace
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return fail(IPFB_EHIP, "hipDeviceSynchronize: %s", hipGetErrorString(e));
+  if (!p->ws_ext) {
+    for (void** b : bufs)
+      if (*b) {
+        hipFree(*b);
+        p->bytes -= fbytes;
+      }
+  }
+  for (int i = 0; i < 3; ++i) *bufs[i] = next[i];
+  p->ws_ext = dev != nullptr;
   return ok();
 }
 
@@ -417,7 +506,7 @@ int wiener_lds(ipfb_plan p, int infmt, const void* spec, const float* chan_scale
     if (infmt == IPFB_IN_C4) e = launch_row_c4(p->prec, p->log2n, spec, chan_scale, x_out, p->nblock, p->twN, st);
     if (e == hipErrorNotSupported) {
       hipGetLastError();
-      if (infmt == IPFB_IN_C4) e = launch_dequant_factors(p->prec, chan_scale, p->lblock / 2 + 1, p->lblock, p->fac, st);
+      if (scaled_infmt(infmt)) e = launch_dequant_factors(p->prec, chan_scale, p->lblock / 2 + 1, p->lblock, p->fac, st);
       else e = hipSuccess;
       if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec, p->fac, x_out, p->nblock, p->twN, st);
     }
@@ -441,9 +530,7 @@ int ipfb_wiener_ex(ipfb_plan p, int infmt, const void* spec, const float* chan_s
                    void* x_out, void* stream) {
   if (check_plan(p)) return IPFB_EINVAL;
   if (!spec || !x_out) return fail(IPFB_EINVAL, "spec and x_out must be non-NULL device pointers");
-  if (infmt != IPFB_IN_C4 && infmt != IPFB_IN_CF32 && infmt != IPFB_IN_CF64)
-    return fail(IPFB_EINVAL, "unknown input format %d", infmt);
-  if (infmt == IPFB_IN_C4 && !chan_scale) return fail(IPFB_EINVAL, "chan_scale is required for IPFB_IN_C4");
+  if (check_infmt(infmt, chan_scale)) return IPFB_EINVAL;
   if (!(phi >= 0.0) || !std::isfinite(phi)) return fail(IPFB_EINVAL, "phi must be finite and >= 0");
   if (!p->row_lds)
     return fail(IPFB_EUNSUPPORTED, "ipfb_wiener supports lblock <= 2^%d for this precision", max_log2_row(p->prec));
@@ -473,9 +560,7 @@ int ipfb_wiener_filter(ipfb_plan p, int infmt, const void* spec, const float* ch
                        const double* nu, int normalise, void* x_out, void* stream) {
   if (check_plan(p)) return IPFB_EINVAL;
   if (!spec || !x_out) return fail(IPFB_EINVAL, "spec and x_out must be non-NULL device pointers");
-  if (infmt != IPFB_IN_C4 && infmt != IPFB_IN_CF32 && infmt != IPFB_IN_CF64)
-    return fail(IPFB_EINVAL, "unknown input format %d", infmt);
-  if (infmt == IPFB_IN_C4 && !chan_scale) return fail(IPFB_EINVAL, "chan_scale is required for IPFB_IN_C4");
+  if (check_infmt(infmt, chan_scale)) return IPFB_EINVAL;
   if (kind != IPFB_FILTER_WIENER && kind != IPFB_FILTER_THRESHOLD && kind != IPFB_FILTER_NU)
     return fail(IPFB_EINVAL, "unknown filter kind %d", kind);
   if (kind != IPFB_FILTER_NU && (!(param >= 0.0) || !std::isfinite(param)))
@@ -540,16 +625,14 @@ int ipfb_wiener_stream(ipfb_splan sp, int infmt, const void* spec, const float* 
   if (!sp) return fail(IPFB_EINVAL, "plan is NULL");
   ipfb_plan p = sp->inner;
   if (!spec || !x_out) return fail(IPFB_EINVAL, "spec and x_out must be non-NULL device pointers");
-  if (infmt != IPFB_IN_C4 && infmt != IPFB_IN_CF32 && infmt != IPFB_IN_CF64)
-    return fail(IPFB_EINVAL, "unknown input format %d", infmt);
-  if (infmt == IPFB_IN_C4 && !chan_scale) return fail(IPFB_EINVAL, "chan_scale is required for IPFB_IN_C4");
+  if (check_infmt(infmt, chan_scale)) return IPFB_EINVAL;
   if (!(phi >= 0.0) || !std::isfinite(phi)) return fail(IPFB_EINVAL, "phi must be finite and >= 0");
   if (nspec < 1) return fail(IPFB_EINVAL, "nspec must be >= 1");
   DeviceGuard g(p->dev);
   hipStream_t st = (hipStream_t)stream;
   const int N = p->lblock, K = N / 2 + 1;
   const size_t es = esize(p->prec), fb = (size_t)N * es;
-  const size_t inb = infmt == IPFB_IN_C4 ? 1 : (infmt == IPFB_IN_CF32 ? 8 : 16);
+  const size_t inb = infmt_bytes(infmt);
   const int64_t B = sp->chunk, h = sp->halo, m = B - (p->ntap - 1), L = m - 2 * h;
   const int64_t nframes = nspec + p->ntap - 1;
   char* work = (char*)p->work;
@@ -561,9 +644,10 @@ int ipfb_wiener_stream(ipfb_splan sp, int infmt, const void* spec, const float* 
     if (e == hipErrorNotSupported) {
       hipGetLastError();
       row_c4 = false;
-      e = launch_dequant_factors(p->prec, chan_scale, K, N, p->fac, st);
+      e = hipSuccess;
     }
   }
+  if (e == hipSuccess && !row_c4 && scaled_infmt(infmt)) e = launch_dequant_factors(p->prec, chan_scale, K, N, p->fac, st);
   // windows of the overlap-save reading: window c keeps output frames
   // [c L, c L + nkeep); it starts at spectrum s0 and holds nvalid spectra,
   // zero-extended to B frames
@@ -625,9 +709,7 @@ int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale
                void* x_out, double* resid_norms, void* stream) {
   if (check_plan(p)) return IPFB_EINVAL;
   if (!spec || !mask || !prior || !x_out) return fail(IPFB_EINVAL, "spec, mask, prior and x_out must be non-NULL");
-  if (infmt != IPFB_IN_C4 && infmt != IPFB_IN_CF32 && infmt != IPFB_IN_CF64)
-    return fail(IPFB_EINVAL, "unknown input format %d", infmt);
-  if (infmt == IPFB_IN_C4 && !chan_scale) return fail(IPFB_EINVAL, "chan_scale is required for IPFB_IN_C4");
+  if (check_infmt(infmt, chan_scale)) return IPFB_EINVAL;
   if (!(lam >= 0.0) || !std::isfinite(lam)) return fail(IPFB_EINVAL, "lambda must be finite and >= 0");
   if (!(phi_precond > 0.0) || !std::isfinite(phi_precond)) return fail(IPFB_EINVAL, "phi_precond must be > 0");
   if (!(phi_x0 >= 0.0) || !std::isfinite(phi_x0)) return fail(IPFB_EINVAL, "phi_x0 must be finite and >= 0");
@@ -658,7 +740,7 @@ int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale
   hipError_t e;
   {
     ProfScope ps("cg_setup", st);
-    if (infmt == IPFB_IN_C4) e = launch_dequant_factors(p->prec, chan_scale, p->lblock / 2 + 1, p->lblock, p->fac, st);
+    if (scaled_infmt(infmt)) e = launch_dequant_factors(p->prec, chan_scale, p->lblock / 2 + 1, p->lblock, p->fac, st);
     else e = hipSuccess;
     if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec, p->fac, p->work, b, p->twN, st);
     if (e == hipSuccess) e = launch_transpose(p->prec, p->work, dT, b, p->lblock, st);
@@ -1277,7 +1359,7 @@ hipError_t enqueue_batched(ipfb_bplan p, int infmt, const void* const* spec, con
     if (e == hipErrorNotSupported) {
       hipGetLastError();
       e = hipSuccess;
-      if (infmt == IPFB_IN_C4) e = launch_dequant_factors(p->prec, sc[s], K, N, p->fac, st);
+      if (scaled_infmt(infmt)) e = launch_dequant_factors(p->prec, sc[s], K, N, p->fac, st);
       if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec[s], p->fac, rows_out, b, p->twN, st);
     }
     if (e != hipSuccess) break;
@@ -1493,12 +1575,10 @@ int ipfb_wiener_batched(ipfb_bplan p, int infmt, const void* const* spec, const 
                         double phi, int normalise, void* const* x_out, void* stream) {
   if (!p) return fail(IPFB_EINVAL, "plan is NULL");
   if (!spec || !x_out) return fail(IPFB_EINVAL, "spec and x_out must be non-NULL host arrays of device pointers");
-  if (infmt != IPFB_IN_C4 && infmt != IPFB_IN_CF32 && infmt != IPFB_IN_CF64)
-    return fail(IPFB_EINVAL, "unknown input format %d", infmt);
-  if (infmt == IPFB_IN_C4 && !chan_scale) return fail(IPFB_EINVAL, "chan_scale is required for IPFB_IN_C4");
+  if (check_infmt(infmt, chan_scale)) return IPFB_EINVAL;
   if (!(phi >= 0.0) || !std::isfinite(phi)) return fail(IPFB_EINVAL, "phi must be finite and >= 0");
   for (int s = 0; s < p->nstreams; ++s) {
-    if (!spec[s] || !x_out[s] || (infmt == IPFB_IN_C4 && !chan_scale[s]))
+    if (!spec[s] || !x_out[s] || (scaled_infmt(infmt) && !chan_scale[s]))
       return fail(IPFB_EINVAL, "stream %d: NULL pointer", s);
   }
   DeviceGuard g(p->dev);

@@ -23,6 +23,10 @@ __device__ __forceinline__ cx<T> load_spec(const void* __restrict__ in, const T*
     const int im = (signed char)(b << 4) >> 4;        // low nibble, sign-extended
     const T f = fac[k];
     return mk<T>(T(re) * f, T(im) * f);
+  } else if constexpr (FMT == IN_CI8) {  // (re, im) as two signed bytes
+    const char2 q = reinterpret_cast<const char2*>(in)[idx];
+    const T f = fac[k];
+    return mk<T>(T((int)q.x) * f, T((int)q.y) * f);
   } else if constexpr (FMT == IN_CF32) {
     const cx<float> v = reinterpret_cast<const cx<float>*>(in)[idx];
     const T f = T(1.0 / (double)N);
@@ -207,6 +211,7 @@ static hipError_t launch_row_t(int fmt, const void* in, const void* fac, void* o
   const T* sc = reinterpret_cast<const T*>(fac);
   switch (fmt) {
     case IN_C4: k_row_irfft<T, LOG2N, IN_C4><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(in, sc, o, nrows, tw); break;
+    case IN_CI8: k_row_irfft<T, LOG2N, IN_CI8><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(in, sc, o, nrows, tw); break;
     case IN_CF32: k_row_irfft<T, LOG2N, IN_CF32><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(in, sc, o, nrows, tw); break;
     case IN_CF64: k_row_irfft<T, LOG2N, IN_CF64><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(in, sc, o, nrows, tw); break;
     default: k_row_irfft<T, LOG2N, IN_ADJ><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(in, sc, o, nrows, tw); break;

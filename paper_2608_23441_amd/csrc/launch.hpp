@@ -28,7 +28,7 @@ inline int resident_workgroups(K kernel, int nt) {
   return cache[slot];
 }
 // Input spectrum formats of the inverse (match the public header).
-enum InFmt { IN_C4 = 0, IN_CF32 = 2, IN_CF64 = 3, IN_ADJ = 100 };
+enum InFmt { IN_C4 = 0, IN_CI8 = 1, IN_CF32 = 2, IN_CF64 = 3, IN_ADJ = 100 };
 
 // Largest power-of-two lengths each LDS-resident kernel accepts.
 constexpr int kMaxLog2RowF32 = 15;  // N real = 2^15 -> 16384 complex, 128 KiB

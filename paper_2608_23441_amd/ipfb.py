@@ -16,13 +16,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libipfb.so")
 
 F32, F64 = 0, 1
-IN_C4, IN_CF32, IN_CF64 = 0, 2, 3
+IN_C4, IN_CI8, IN_CF32, IN_CF64 = 0, 1, 2, 3
 OK, EINVAL, EUNSUPPORTED, ENOMEM, EHIP = 0, -1, -2, -3, -4
 
 # Symbols the C ABI exports (include/ipfb.h).
 EXPORTS = (
     "ipfb_last_error", "ipfb_version", "ipfb_window_sinc_hamming", "ipfb_plan_create",
-    "ipfb_plan_destroy", "ipfb_plan_workspace_size", "pfb_forward", "pfb_adjoint", "ipfb_wiener",
+    "ipfb_plan_destroy", "ipfb_plan_workspace_size", "ipfb_plan_device_bytes", "ipfb_plan_set_workspace",
+    "pfb_forward", "pfb_adjoint", "ipfb_wiener",
     "ipfb_wiener_ex", "upchannelize", "ipfb_autospectrum", "ipfb_quantize_c4",
     "ipfb_profile_enable", "ipfb_profile_reset", "ipfb_profile_query", "ipfb_ml_cg",
     "ipfb_batched_plan_create", "ipfb_batched_plan_destroy", "ipfb_batched_workspace_size",
@@ -58,6 +59,8 @@ def lib():
         L.ipfb_plan_create.argtypes = [ctypes.POINTER(vp), i32, i32, vp, i64, i32]
         L.ipfb_plan_destroy.argtypes = [vp]
         L.ipfb_plan_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.ipfb_plan_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.ipfb_plan_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
         L.pfb_forward.argtypes = [vp, vp, vp, vp]
         L.pfb_adjoint.argtypes = [vp, vp, vp, vp]
         L.ipfb_wiener.argtypes = [vp, i32, vp, vp, dbl, vp, vp]
@@ -133,6 +136,7 @@ class Plan:
         _check(lib().ipfb_plan_create(ctypes.byref(h), self.lblock, self.ntap, w.ctypes.data,
                                       self.nblock, self.prec))
         self._h = h
+        self._ws = None
 
     @property
     def handle(self):
@@ -153,14 +157,34 @@ class Plan:
         return torch.complex64 if self.prec == F32 else torch.complex128
 
     def workspace_bytes(self) -> int:
+        """Size of the workspace set_workspace takes."""
         b = ctypes.c_size_t()
         _check(lib().ipfb_plan_workspace_size(self._h, ctypes.byref(b)))
         return b.value
+
+    def device_bytes(self) -> int:
+        """Device bytes the plan itself holds."""
+        b = ctypes.c_size_t()
+        _check(lib().ipfb_plan_device_bytes(self._h, ctypes.byref(b)))
+        return b.value
+
+    def set_workspace(self, buf=None):
+        """Give the plan a caller-owned workspace: a CUDA tensor of at least
+        workspace_bytes() bytes, 256-byte aligned, kept alive (and otherwise
+        unused) while the plan uses it; None returns the plan to its own."""
+        if buf is None:
+            _check(lib().ipfb_plan_set_workspace(self._h, None, 0))
+            self._ws = None
+            return
+        nbytes = buf.numel() * buf.element_size()
+        _check(lib().ipfb_plan_set_workspace(self._h, _ptr(buf, "workspace"), nbytes))
+        self._ws = buf  # the plan keeps a reference while it uses the memory
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             lib().ipfb_plan_destroy(self._h)
             self._h = None
+        self._ws = None  # a caller-provided workspace may go once the plan is gone
 
     def __del__(self):
         try:
@@ -199,23 +223,36 @@ def pfb_adjoint(plan: Plan, y, x=None, stream=None):
     return x
 
 
-def ipfb_wiener(plan: Plan, spec, chan_scale=None, phi: float = 0.1, x_out=None, normalise: bool = True,
-                stream=None):
-    """spec: uint8 [nblock, nchan] (4-bit packed, needs chan_scale float32 [nchan]),
-    complex64 or complex128 [nblock, nchan]."""
+def _spec_format(spec, nchan, chan_scale):
+    """Input format of a spectrum tensor and the number of complex values it
+    holds: uint8 (packed 4-bit, one byte per value), int8 (8-bit codes, two
+    bytes per value: real then imaginary), complex64 or complex128. The two
+    quantised formats need chan_scale, float32 [nchan]."""
     import torch
     if spec.dtype == torch.uint8:
-        fmt = IN_C4
-        if chan_scale is None or chan_scale.dtype != torch.float32 or chan_scale.numel() != plan.nchan:
-            raise ValueError("chan_scale: float32 [nchan] is required for packed 4-bit spectra")
+        fmt, n = IN_C4, spec.numel()
+    elif spec.dtype == torch.int8:
+        if spec.numel() % 2:
+            raise ValueError("int8 spectra hold (real, imaginary) pairs: an even number of bytes")
+        fmt, n = IN_CI8, spec.numel() // 2
     elif spec.dtype == torch.complex64:
-        fmt = IN_CF32
+        fmt, n = IN_CF32, spec.numel()
     elif spec.dtype == torch.complex128:
-        fmt = IN_CF64
+        fmt, n = IN_CF64, spec.numel()
     else:
-        raise ValueError("spec must be uint8 (packed 4-bit), complex64 or complex128")
-    if spec.numel() != plan.nblock * plan.nchan:
-        raise ValueError("spec must hold nblock * (lblock/2+1) values")
+        raise ValueError("spec must be uint8 (packed 4-bit), int8 (8-bit pairs), complex64 or complex128")
+    if fmt in (IN_C4, IN_CI8) and (chan_scale is None or chan_scale.dtype != torch.float32
+                                   or chan_scale.numel() != nchan):
+        raise ValueError("chan_scale: float32 [nchan] is required for quantised spectra")
+    return fmt, n
+
+
+def ipfb_wiener(plan: Plan, spec, chan_scale=None, phi: float = 0.1, x_out=None, normalise: bool = True,
+                stream=None):
+    """spec: uint8 [nblock, nchan] (4-bit packed) or int8 [nblock, nchan, 2]
+    (8-bit), both with chan_scale float32 [nchan]; or complex64 / complex128
+    [nblock, nchan]."""
+    fmt = _spec_fmt(plan, spec, chan_scale)
     if x_out is None:
         x_out = _empty((plan.nblock * plan.lblock,), plan.real_dtype)
     _check(lib().ipfb_wiener_ex(plan.handle, fmt, _ptr(spec, "spec"), _ptr(chan_scale, "chan_scale"),
@@ -240,19 +277,14 @@ def wiener_filter(plan: Plan, spec, chan_scale=None, kind: int = FILTER_WIENER, 
     return x_out
 
 
-def _spec_fmt(plan, spec, chan_scale):
+def _quantised_dtypes():
     import torch
-    if spec.dtype == torch.uint8:
-        if chan_scale is None or chan_scale.dtype != torch.float32 or chan_scale.numel() != plan.nchan:
-            raise ValueError("chan_scale: float32 [nchan] is required for packed 4-bit spectra")
-        fmt = IN_C4
-    elif spec.dtype == torch.complex64:
-        fmt = IN_CF32
-    elif spec.dtype == torch.complex128:
-        fmt = IN_CF64
-    else:
-        raise ValueError("spec must be uint8 (packed 4-bit), complex64 or complex128")
-    if spec.numel() != plan.nblock * plan.nchan:
+    return (torch.uint8, torch.int8)
+
+
+def _spec_fmt(plan, spec, chan_scale):
+    fmt, n = _spec_format(spec, plan.nchan, chan_scale)
+    if n != plan.nblock * plan.nchan:
         raise ValueError("spec must hold nblock * (lblock/2+1) values")
     return fmt
 
@@ -426,23 +458,22 @@ class BatchedPlan:
 
 def wiener_batched(bp: BatchedPlan, specs, chan_scales=None, phi: float = 0.1, x_outs=None,
                    normalise: bool = True, stream=None):
-    """specs: list of per-stream spectra (uint8 packed with chan_scales, or complex);
-    returns the list of per-stream timestreams."""
-    import torch
+    """specs: list of per-stream spectra (uint8 packed 4-bit or int8 8-bit,
+    with chan_scales; or complex); returns the list of per-stream timestreams."""
     ns = len(bp.nblocks)
     if len(specs) != ns:
         raise ValueError("one spectrum tensor per stream")
+    quantised = specs and specs[0].dtype in _quantised_dtypes()
+    if quantised and (chan_scales is None or len(chan_scales) != ns):
+        raise ValueError("quantised spectra need one float32 scale vector per stream")
     fmt = None
-    for s_, b in zip(specs, bp.nblocks):
-        f = IN_C4 if s_.dtype == torch.uint8 else IN_CF32 if s_.dtype == torch.complex64 else \
-            IN_CF64 if s_.dtype == torch.complex128 else None
-        if f is None or (fmt is not None and f != fmt):
-            raise ValueError("all streams need one spectrum dtype: uint8, complex64 or complex128")
+    for i, (s_, b) in enumerate(zip(specs, bp.nblocks)):
+        f, n = _spec_format(s_, bp.nchan, chan_scales[i] if quantised else None)
+        if fmt is not None and f != fmt:
+            raise ValueError("all streams need one spectrum dtype")
         fmt = f
-        if s_.numel() != b * bp.nchan:
+        if n != b * bp.nchan:
             raise ValueError("stream spectra must hold nblock * (lblock/2+1) values")
-    if fmt == IN_C4 and (chan_scales is None or len(chan_scales) != ns):
-        raise ValueError("packed 4-bit spectra need one float32 scale vector per stream")
     if x_outs is None:
         x_outs = [_empty((b * bp.lblock,), bp.real_dtype) for b in bp.nblocks]
     for x, b in zip(x_outs, bp.nblocks):
@@ -451,7 +482,7 @@ def wiener_batched(bp: BatchedPlan, specs, chan_scales=None, phi: float = 0.1, x
     P = ctypes.c_void_p * ns
     sp = P(*[_ptr(t, "spec").value for t in specs])
     xo = P(*[_ptr(t, "x_out").value for t in x_outs])
-    sc = P(*[_ptr(t, "chan_scale").value for t in chan_scales]) if fmt == IN_C4 else None
+    sc = P(*[_ptr(t, "chan_scale").value for t in chan_scales]) if fmt in (IN_C4, IN_CI8) else None
     _check(lib().ipfb_wiener_batched(bp._h, fmt, sp, sc, float(phi), int(bool(normalise)), xo, _stream(stream)))
     return x_outs
 
@@ -491,21 +522,15 @@ class StreamPlan:
 
 def wiener_stream(sp: StreamPlan, spec, chan_scale=None, phi: float = 0.1, x_out=None, normalise: bool = True,
                   stream=None):
-    """Streaming inverse of nspec linear-PFB spectra (uint8 [nspec][nchan] with
-    chan_scale, or complex [nspec][nchan]); returns (nspec + ntap - 1) * lblock samples."""
-    import torch
-    if spec.dtype == torch.uint8:
-        if chan_scale is None or chan_scale.dtype != torch.float32 or chan_scale.numel() != sp.nchan:
-            raise ValueError("chan_scale: float32 [nchan] is required for packed 4-bit spectra")
-        fmt = IN_C4
-    elif spec.dtype in (torch.complex64, torch.complex128):
-        fmt = IN_CF32 if spec.dtype == torch.complex64 else IN_CF64
+    """Streaming inverse of nspec linear-PFB spectra (uint8 [nspec][nchan] or
+    int8 [nspec][nchan][2] with chan_scale, or complex [nspec][nchan]); returns
+    (nspec + ntap - 1) * lblock samples."""
+    fmt, n = _spec_format(spec, sp.nchan, chan_scale)
+    if fmt not in (IN_C4, IN_CI8):
         chan_scale = None
-    else:
-        raise ValueError("spec must be uint8 (packed 4-bit), complex64 or complex128")
-    if spec.numel() % sp.nchan != 0 or spec.numel() == 0:
+    if n % sp.nchan != 0 or n == 0:
         raise ValueError("spec must hold nspec * (lblock/2+1) values")
-    nspec = spec.numel() // sp.nchan
+    nspec = n // sp.nchan
     nout = (nspec + sp.ntap - 1) * sp.lblock
     if x_out is None:
         x_out = _empty((nout,), sp.real_dtype)

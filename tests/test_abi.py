@@ -75,6 +75,9 @@ def test_calls_reject_null_plan_and_pointers():
     assert L.ipfb_autospectrum(None, None, None, None) == ipfb.EINVAL
     assert L.ipfb_quantize_c4(None, None, 2.5, None, None, None) == ipfb.EINVAL
     assert L.ipfb_plan_destroy(None) == ipfb.EINVAL
+    assert L.ipfb_plan_set_workspace(None, None, 0) == ipfb.EINVAL
+    assert L.ipfb_plan_device_bytes(None, None) == ipfb.EINVAL
+    assert L.ipfb_plan_workspace_size(None, None) == ipfb.EINVAL
     assert L.ipfb_window_sinc_hamming(None, 4, 16) == ipfb.EINVAL
 
 

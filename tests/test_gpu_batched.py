@@ -46,6 +46,26 @@ def test_batched_small_uneven(prec, tol):
             assert _rel(xo.cpu().numpy().astype(np.float64), ref) < (tol if phi > 0 else 50 * tol), (b, phi)
 
 
+@pytest.mark.parametrize("prec,tol", [(ipfb.F64, 1e-11), (ipfb.F32, 1e-5)])
+def test_batched_ci8_uneven(prec, tol):
+    N, p = 64, 4
+    nblocks = [12, 64, 129, 5, 1031]
+    print(f"case batched ci8 prec={prec}", flush=True)
+    w = O.window_sinc_hamming(p, N)
+    data = []
+    for s_, b in enumerate(nblocks):
+        y = O.pfb_forward(I.gaussian_timestream(N * b, 4100 + s_), w, N, p)
+        sc = O.channel_scales(y, levels_rms=40.0)
+        data.append((O.pack_ci8(*O.quantize(y, sc, qmax=127)), sc))
+    bp = ipfb.BatchedPlan(N, p, w, nblocks, prec)
+    outs = ipfb.wiener_batched(bp, [torch.from_numpy(pk).cuda() for pk, _ in data],
+                               [torch.from_numpy(sc).cuda() for _, sc in data], 0.1)
+    torch.cuda.synchronize()
+    for (pk, sc), b, xo in zip(data, nblocks, outs):
+        ref = O.ipfb_wiener_ci8(pk, sc, w, N, p, 0.1)
+        assert _rel(xo.cpu().numpy().astype(np.float64), ref) < tol, b
+
+
 def test_batched_production_lengths_fp32():
     # production frame length with Bluestein lengths up to M = 65536
     N, p = 4096, 4

@@ -60,6 +60,28 @@ def test_ml_cg_fp64_matches_oracle(N, b, iters):
         assert _rel(xg, dense) < 1e-6
 
 
+def test_ml_cg_ci8_matches_oracle():
+    N, p, b, iters = 256, 4, 64, 30
+    print("case ml_cg fp64 ci8", flush=True)
+    w = O.window_sinc_hamming(p, N)
+    x = I.gaussian_timestream(N * b, 310)
+    y = O.pfb_forward(x, w, N, p)
+    s = O.channel_scales(y, levels_rms=40.0)
+    qr, qi = O.quantize(y, s, qmax=127)
+    mask = I.random_mask(N * b, 0.1, 311)
+    d = O.row_inverse(O.dequantize(qr, qi, s), N)
+    x0 = O.column_inverse(d, w, N, p, 0.1).reshape(-1)
+    ref_x, ref_n = O.ml_pcg(d, w, N, p, mask, x, 1.0, 0.1, iters, x0)
+    plan = ipfb.Plan(N, p, w, b, ipfb.F64)
+    xg, ng = ipfb.ml_cg(plan, _dev(O.pack_ci8(qr, qi)), _dev(s), _dev(mask.astype(np.uint8)), _dev(x), 1.0, 0.1,
+                        0.1, iters)
+    xg, ng = _host(xg), _host(ng)
+    k = ref_n > 1e-4 * ref_n[0]
+    assert k.sum() >= 5
+    assert np.max(np.abs(ng[k] - ref_n[k]) / ref_n[k]) < 1e-6
+    assert _rel(xg, ref_x) < 1e-6
+
+
 def test_ml_cg_zero_iterations_is_wiener():
     N, p, b = 64, 4, 32
     w, x, packed, s, mask, d = _ml_case(N, p, b, 310)

@@ -55,6 +55,23 @@ def test_ipfb_wiener_c4(prec, N, p, b, phi):
     assert _rel(_host(out), ref) < TOL[prec]
 
 
+# 8-bit spectra (IPFB_IN_CI8): finer codes with the same per-channel scale;
+# power-of-two and Bluestein column lengths, the four-step and one-pass stages
+@pytest.mark.parametrize("prec", [ipfb.F64, ipfb.F32])
+@pytest.mark.parametrize("N,p,b,phi", [(64, 4, 32, 0.1), (4096, 4, 256, 0.1), (32, 4, 2048, 0.0),
+                                       (2048, 4, 128, 0.1), (64, 4, 100, 0.1)])
+def test_ipfb_wiener_ci8(prec, N, p, b, phi):
+    print(f"case ipfb_wiener ci8 prec={prec} N={N} p={p} b={b} phi={phi}", flush=True)
+    w = O.window_sinc_hamming(p, N)
+    y = O.pfb_forward(I.gaussian_timestream(N * b, 300 + N + b), w, N, p)
+    s = O.channel_scales(y, levels_rms=40.0)
+    packed = O.pack_ci8(*O.quantize(y, s, qmax=127))
+    ref = O.ipfb_wiener_ci8(packed, s, w, N, p, phi)
+    plan = ipfb.Plan(N, p, w, b, prec)
+    out = ipfb.ipfb_wiener(plan, _dev(packed), _dev(s), phi)
+    assert _rel(_host(out), ref) < TOL[prec]
+
+
 # The three-pass (four-step) column stage, b > 512: partial column tiles
 # (lblock/2 below the 16-pair tile), tap counts other than 4 (the generic gain
 # kernel), phi = 0 with the four-step, and the b1 x b2 splits 32x32 ... 128x256.

@@ -49,6 +49,22 @@ def test_stream_c4_matches_oracle(prec, tol, N, p, chunk, halo, nspec):
 
 
 @pytest.mark.parametrize("prec,tol", [(ipfb.F64, 1e-11), (ipfb.F32, 1e-5)])
+def test_stream_ci8_matches_oracle(prec, tol):
+    N, p, chunk, halo, nspec = 64, 4, 1024, 100, 3000
+    print(f"case stream ci8 prec={prec}", flush=True)
+    w = O.window_sinc_hamming(p, N)
+    y = _linear_spectra(N, p, nspec, 5200, w)
+    sc = O.channel_scales(y, levels_rms=40.0)
+    qr, qi = O.quantize(y, sc, qmax=127)
+    pk = O.pack_ci8(qr, qi)
+    ref = O.ipfb_stream_from_spectra(O.dequantize(qr, qi, sc), w, N, p, 0.1, chunk, halo)
+    sp = ipfb.StreamPlan(N, p, w, chunk, halo, prec)
+    out = ipfb.wiener_stream(sp, torch.from_numpy(pk).cuda(), torch.from_numpy(sc).cuda(), 0.1)
+    torch.cuda.synchronize()
+    assert _rel(out.cpu().numpy().astype(np.float64), ref) < tol
+
+
+@pytest.mark.parametrize("prec,tol", [(ipfb.F64, 1e-11), (ipfb.F32, 1e-5)])
 def test_stream_complex_input_and_phi_zero(prec, tol):
     N, p, chunk, halo, nspec = 64, 4, 1024, 64, 2500
     w = O.window_sinc_hamming(p, N)

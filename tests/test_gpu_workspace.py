@@ -1,0 +1,85 @@
+"""A caller-provided workspace (ipfb_plan_set_workspace): the same results,
+bit for bit, as the plan's own workspace, whatever the memory held before;
+sizes and alignment checked; and the way back to a workspace of the plan's own."""
+import numpy as np
+import pytest
+
+from oracle import ipfb_oracle as O
+from paper_2608_23441_amd import inputs as I
+from paper_2608_23441_amd import ipfb
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _case(N, p, b, seed):
+    w = O.window_sinc_hamming(p, N)
+    x = I.gaussian_timestream(N * b, seed)
+    y = O.pfb_forward(x, w, N, p)
+    s = O.channel_scales(y)
+    return w, x, O.pack_c4(*O.quantize(y, s)), s
+
+
+@pytest.mark.parametrize("prec", [ipfb.F64, ipfb.F32])
+@pytest.mark.parametrize("N,b", [(64, 256), (256, 4096), (128, 100)])
+def test_caller_workspace_matches_own_workspace(prec, N, b):
+    print(f"case workspace prec={prec} N={N} b={b}", flush=True)
+    p = 4
+    w, x, packed, s = _case(N, p, b, 600 + N + b)
+    pk, sc = _dev(packed), _dev(s)
+    own = ipfb.Plan(N, p, w, b, prec)
+    ref = ipfb.ipfb_wiener(own, pk, sc, 0.1).clone()
+    plan = ipfb.Plan(N, p, w, b, prec)
+    need = plan.workspace_bytes()
+    held = plan.device_bytes()
+    assert need > 0
+    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    assert ws.data_ptr() % 256 == 0
+    with pytest.raises(ipfb.IpfbError):
+        plan.set_workspace(ws[: need - 256])  # too small
+    with pytest.raises(ipfb.IpfbError):
+        plan.set_workspace(ws[1: need + 1])  # misaligned
+    plan.set_workspace(ws)
+    assert plan.device_bytes() <= held - need + 256 * 3
+    for fill in (0, 255):  # the workspace is scratch: what it held does not matter
+        ws.fill_(fill)
+        got = ipfb.ipfb_wiener(plan, pk, sc, 0.1)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), fill
+    if (b & (b - 1)) == 0:  # ML-CG also runs on the workspace (power-of-two b)
+        mask = _dev(I.random_mask(N * b, 0.1, 7).astype(np.uint8))
+        prior = _dev(x).to(ref.dtype)
+        xa, na = ipfb.ml_cg(own, pk, sc, mask, prior, 1.0, 0.1, 0.1, 5)
+        xb, nb = ipfb.ml_cg(plan, pk, sc, mask, prior, 1.0, 0.1, 0.1, 5)
+        torch.cuda.synchronize()
+        assert torch.equal(xa, xb) and torch.equal(na, nb)
+    lazy = plan.device_bytes() - (held - need)  # scratch allocated on first use (ML-CG), plan-owned
+    plan.set_workspace(None)  # back to a workspace of its own
+    ws.fill_(255)
+    got = ipfb.ipfb_wiener(plan, pk, sc, 0.1)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    assert plan.device_bytes() >= held and plan.device_bytes() <= held + lazy
+
+
+@pytest.mark.parametrize("prec", [ipfb.F64, ipfb.F32])
+def test_caller_workspace_long_frames(prec):
+    # long frames keep the four-step intermediate in the workspace
+    Nf, bf = 1 << 16, 8
+    print(f"case workspace long frames prec={prec}", flush=True)
+    wf = O.window_sinc_hamming(4, Nf)
+    dt = torch.float64 if prec == ipfb.F64 else torch.float32
+    x = _dev(I.gaussian_timestream(Nf * bf, 77)).to(dt)
+    own = ipfb.Plan(Nf, 4, wf, bf, prec)
+    Y0, A0 = ipfb.upchannelize(own, x)
+    plan = ipfb.Plan(Nf, 4, wf, bf, prec)
+    ws = torch.full((plan.workspace_bytes(),), 255, dtype=torch.uint8, device="cuda")
+    plan.set_workspace(ws)
+    Y1, A1 = ipfb.upchannelize(plan, x)
+    torch.cuda.synchronize()
+    assert torch.equal(Y0, Y1) and torch.equal(A0, A1)
