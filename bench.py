@@ -118,6 +118,55 @@ def time_steps(torch, step, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
+def copy_peak_GBps(torch, nbytes=1 << 30):
+    """A plain device copy (read + write of nbytes each), the practical HBM
+    ceiling the roofline fraction is also stated against."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / 10
+    del src, dst
+    return 2 * nbytes / sec / 1e9
+
+
+def small_config(torch, ipfb, inputs):
+    """The small configuration (N = 2048, p = 4, b = 128, phi = 0.1, x8
+    up-channelize): latency-bound, so its time per step (median of 20 after 3
+    warm-ups, each step synchronised) is what it reports, per precision."""
+    N, p, b, u, phi = 2048, 4, 128, 8, 0.1
+    Nf = N * u
+    _, w, packed, scales = make_inputs(torch, ipfb, inputs, N, p, b, 1, 0, 0, 0.0, 2.5)
+    wf = ipfb.window_sinc_hamming(4, Nf)
+    out = {"config": {"lblock": N, "ntap": p, "nblock": b, "phi": phi, "lblock_fine": Nf,
+                      "nblock_fine": (N * b) // Nf}}
+    for tag, prec in (("f64", ipfb.F64), ("f32", ipfb.F32)):
+        coarse = ipfb.Plan(N, p, w, b, prec)
+        fine = ipfb.Plan(Nf, 4, wf, (N * b) // Nf, prec)
+        xh = torch.empty(N * b, dtype=coarse.real_dtype, device="cuda")
+        Y = torch.empty(((N * b) // Nf, Nf // 2 + 1), dtype=fine.complex_dtype, device="cuda")
+        A = torch.empty(Nf // 2 + 1, dtype=torch.float64, device="cuda")
+        times = []
+        for i in range(23):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ipfb.ipfb_wiener(coarse, packed, scales, phi, x_out=xh)
+            ipfb.upchannelize(fine, xh, Y, A)
+            torch.cuda.synchronize()
+            if i >= 3:
+                times.append(time.perf_counter() - t0)
+        times.sort()
+        out[tag] = {"us_per_step_median": 1e6 * times[len(times) // 2], "us_per_step_min": 1e6 * times[0]}
+        del coarse, fine
+    return out
+
+
 def cpu_baseline(N, p, Nf, phi, frames, seed):
     """The FP64 numpy oracle on a bounded sample of the same workload: the
     same steps (dequantise, row inverse, column Wiener inverse, x64
@@ -350,6 +399,7 @@ def main():
     ap.add_argument("--batched-streams", type=int, default=256)
     ap.add_argument("--no-stream", action="store_true", help="skip timing the streaming (linear boundary) form")
     ap.add_argument("--no-sweep", action="store_true", help="skip the structured-prior sweep (Section 4.3)")
+    ap.add_argument("--no-small", action="store_true", help="skip the small configuration's latency")
     ap.add_argument("--probe-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -474,6 +524,12 @@ def main():
                             "hbm_GBps": sb64 / r64["sec_per_step"] / 1e9,
                             "per_kernel_us": {k: round(v["avg_us"], 2) for k, v in r64["per_kernel"].items()}}
         out["fp32_vs_fp64"] = agree
+    cp = copy_peak_GBps(torch)
+    out["copy_peak_GBps"] = cp
+    out["hbm_frac_of_copy_peak"] = out["hbm_GBps"] / cp
+    out["roofline"]["frac_of_copy_peak"] = achieved / cp
+    if not args.no_small:
+        out["small_config_latency"] = small_config(torch, ipfb, inputs)
     if not args.no_ml:
         out["ml_form"] = ml_form(torch, ipfb, inputs)
     if not args.no_batched:
