@@ -400,6 +400,7 @@ def main():
     ap.add_argument("--no-stream", action="store_true", help="skip timing the streaming (linear boundary) form")
     ap.add_argument("--no-sweep", action="store_true", help="skip the structured-prior sweep (Section 4.3)")
     ap.add_argument("--no-small", action="store_true", help="skip the small configuration's latency")
+    ap.add_argument("--no-copy-peak", action="store_true", help="skip timing the plain device copy")
     ap.add_argument("--probe-copy", action="store_true",
                     help="only run a plain 256 MiB device copy 5 times (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -524,10 +525,11 @@ def main():
                             "hbm_GBps": sb64 / r64["sec_per_step"] / 1e9,
                             "per_kernel_us": {k: round(v["avg_us"], 2) for k, v in r64["per_kernel"].items()}}
         out["fp32_vs_fp64"] = agree
-    cp = copy_peak_GBps(torch)
-    out["copy_peak_GBps"] = cp
-    out["hbm_frac_of_copy_peak"] = out["hbm_GBps"] / cp
-    out["roofline"]["frac_of_copy_peak"] = achieved / cp
+    if not args.no_copy_peak:
+        cp = copy_peak_GBps(torch)
+        out["copy_peak_GBps"] = cp
+        out["hbm_frac_of_copy_peak"] = out["hbm_GBps"] / cp
+        out["roofline"]["frac_of_copy_peak"] = achieved / cp
     if not args.no_small:
         out["small_config_latency"] = small_config(torch, ipfb, inputs)
     if not args.no_ml:
