@@ -154,8 +154,10 @@ __host__ __device__ constexpr int lds_len(int L) { return L + (L >> 4) + 1; }
 // ---- one Stockham pass ------------------------------------------------------
 // s: C sequences of length L at stride LS (>= lds_len(L)), element i of a
 // sequence at pidx(i). Ns: product of radices already done.
-// tw: table of exp(-2 pi i m / LT) with LT = L * twmul.
-template <typename T, int L, int R, int NT, int C, int DIR>
+// tw: table of exp(-2 pi i m / LT) with LT = L * twmul. FULLTW: the table
+// holds all LT entries and every w^{rk} is read from it (no products; for
+// kernels whose time goes to vector arithmetic rather than memory).
+template <typename T, int L, int R, int NT, int C, int DIR, bool FULLTW = false>
 __device__ __forceinline__ void stockham_pass(cx<T>* s, int LS, int Ns, const cx<T>* __restrict__ tw,
                                               int twmul) {
   constexpr int LR = L / R;
@@ -185,15 +187,20 @@ __device__ __forceinline__ void stockham_pass(cx<T>* s, int LS, int Ns, const cx
         // (power-of-two multiples of k): at most three products per twiddle
         const int step = (L / (Ns * R)) * twmul;
         cx<T> w[R];
-        w[1] = tw[k * step];
-        if constexpr (R > 2) w[2] = tw[2 * k * step];
-        if constexpr (R > 4) w[4] = tw[4 * k * step];
-        if constexpr (R > 8) w[8] = tw[8 * k * step];
+        if constexpr (FULLTW) {
 #pragma unroll
-        for (int r = 3; r < R; ++r) {
-          if ((r & (r - 1)) == 0) continue;
-          const int hi = 1 << (31 - __builtin_clz(r));  // highest power of two in r
-          w[r] = cmul(w[r - hi], w[hi]);
+          for (int r = 1; r < R; ++r) w[r] = tw[r * k * step];  // r k step < (R-1)/R LT
+        } else {
+          w[1] = tw[k * step];
+          if constexpr (R > 2) w[2] = tw[2 * k * step];
+          if constexpr (R > 4) w[4] = tw[4 * k * step];
+          if constexpr (R > 8) w[8] = tw[8 * k * step];
+#pragma unroll
+          for (int r = 3; r < R; ++r) {
+            if ((r & (r - 1)) == 0) continue;
+            const int hi = 1 << (31 - __builtin_clz(r));  // highest power of two in r
+            w[r] = cmul(w[r - hi], w[hi]);
+          }
         }
 #pragma unroll
         for (int r = 1; r < R; ++r) v[i][r] = (DIR < 0) ? cmul(v[i][r], w[r]) : cmulc(v[i][r], w[r]);
@@ -209,25 +216,25 @@ __device__ __forceinline__ void stockham_pass(cx<T>* s, int LS, int Ns, const cx
 }
 
 // Radix schedule: P passes of at most RMAXLOG bits each, bits spread evenly.
-template <typename T, int L, int NT, int C, int DIR, int RMAXLOG, int PASS, int NSLOG>
+template <typename T, int L, int NT, int C, int DIR, int RMAXLOG, int PASS, int NSLOG, bool FULLTW>
 __device__ __forceinline__ void stockham_rec(cx<T>* s, int LS, const cx<T>* __restrict__ tw, int twmul) {
   constexpr int E = ilog2c(L);
   constexpr int P = (E + RMAXLOG - 1) / RMAXLOG;
   if constexpr (PASS < P) {
     constexpr int bits = E / P + ((PASS < E % P) ? 1 : 0);
     constexpr int R = 1 << bits;
-    stockham_pass<T, L, R, NT, C, DIR>(s, LS, 1 << NSLOG, tw, twmul);
-    stockham_rec<T, L, NT, C, DIR, RMAXLOG, PASS + 1, NSLOG + bits>(s, LS, tw, twmul);
+    stockham_pass<T, L, R, NT, C, DIR, FULLTW>(s, LS, 1 << NSLOG, tw, twmul);
+    stockham_rec<T, L, NT, C, DIR, RMAXLOG, PASS + 1, NSLOG + bits, FULLTW>(s, LS, tw, twmul);
   }
 }
 
 // Full unnormalised transform, exp(DIR * 2 pi i jk / L). Ends with a barrier.
-template <typename T, int L, int NT, int C, int DIR>
+template <typename T, int L, int NT, int C, int DIR, bool FULLTW = false>
 __device__ __forceinline__ void lds_fft(cx<T>* s, int LS, const cx<T>* __restrict__ tw, int twmul) {
   if constexpr (L > 1) {
     constexpr int EPT = (L * C) / NT;  // elements per thread
     constexpr int RM = EPT >= 16 ? 4 : (EPT >= 8 ? 3 : (EPT >= 4 ? 2 : 1));
-    stockham_rec<T, L, NT, C, DIR, RM, 0, 0>(s, LS, tw, twmul);
+    stockham_rec<T, L, NT, C, DIR, RM, 0, 0, FULLTW>(s, LS, tw, twmul);
   }
 }
 

@@ -189,7 +189,7 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
     __syncthreads();
     // the FFT's own twiddles stay in global memory (L2): an LDS copy would
     // cost a workgroup per CU, which costs more than their latency
-    lds_fft<T, H, NT, 1, +1>(s, LS, twN, 2);
+    lds_fft<T, H, NT, 1, +1, true>(s, LS, twN, 2);  // twN: all N entries
     cx<T>* orow = reinterpret_cast<cx<T>*>(out + j * (int64_t)N);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
