@@ -157,9 +157,14 @@ __host__ __device__ constexpr int lds_len(int L) { return L + (L >> 4) + 1; }
 // tw: table of exp(-2 pi i m / LT) with LT = L * twmul. FULLTW: the table
 // holds all LT entries and every w^{rk} is read from it (no products; for
 // kernels whose time goes to vector arithmetic rather than memory).
-template <typename T, int L, int R, int NT, int C, int DIR, bool FULLTW = false>
-__device__ __forceinline__ void stockham_pass(cx<T>* s, int LS, int Ns, const cx<T>* __restrict__ tw,
-                                              int twmul) {
+//
+// L, R and Ns are powers of two, so an element's padded index splits into a
+// per-thread base plus a compile-time offset: the reads j + r L/R (j < L/R)
+// and the writes m R Ns + k + r Ns (k < Ns) never carry into another
+// 16-element block except through the r term, hence
+//   pidx(a + r S) = pidx(a) + r S + (r S >> 4)  for S = L/R and S = Ns.
+template <typename T, int L, int R, int NT, int C, int DIR, int Ns, bool FULLTW = false>
+__device__ __forceinline__ void stockham_pass(cx<T>* s, int LS, const cx<T>* __restrict__ tw, int twmul) {
   constexpr int LR = L / R;
   constexpr int NB = C * LR;
   constexpr int BPT = (NB + NT - 1) / NT;
@@ -170,9 +175,9 @@ __device__ __forceinline__ void stockham_pass(cx<T>* s, int LS, int Ns, const cx
     const int g = tid + i * NT;
     if ((NB % NT == 0) || g < NB) {
       const int c = g / LR, j = g % LR;
-      const cx<T>* src = s + c * LS;
+      const cx<T>* src = s + c * LS + pidx(j);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = src[pidx(j + r * LR)];
+      for (int r = 0; r < R; ++r) v[i][r] = src[r * LR + ((r * LR) >> 4)];
     }
   }
   __syncthreads();
@@ -182,7 +187,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* s, int LS, int Ns, const cx
     if ((NB % NT == 0) || g < NB) {
       const int c = g / LR, j = g % LR;
       const int k = j & (Ns - 1);
-      if (Ns > 1) {
+      if constexpr (Ns > 1) {
         // w^{rk} for r = 1..R-1 from the table entries for r = 1, 2, 4, 8
         // (power-of-two multiples of k): at most three products per twiddle
         const int step = (L / (Ns * R)) * twmul;
@@ -206,10 +211,9 @@ __device__ __forceinline__ void stockham_pass(cx<T>* s, int LS, int Ns, const cx
         for (int r = 1; r < R; ++r) v[i][r] = (DIR < 0) ? cmul(v[i][r], w[r]) : cmulc(v[i][r], w[r]);
       }
       dftR<R, DIR>(v[i]);
-      cx<T>* dst = s + c * LS;
-      const int base = (j - k) * R + k;
+      cx<T>* dst = s + c * LS + pidx((j - k) * R + k);
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[pidx(base + r * Ns)] = v[i][r];
+      for (int r = 0; r < R; ++r) dst[r * Ns + ((r * Ns) >> 4)] = v[i][r];
     }
   }
   __syncthreads();
@@ -223,7 +227,7 @@ __device__ __forceinline__ void stockham_rec(cx<T>* s, int LS, const cx<T>* __re
   if constexpr (PASS < P) {
     constexpr int bits = E / P + ((PASS < E % P) ? 1 : 0);
     constexpr int R = 1 << bits;
-    stockham_pass<T, L, R, NT, C, DIR, FULLTW>(s, LS, 1 << NSLOG, tw, twmul);
+    stockham_pass<T, L, R, NT, C, DIR, (1 << NSLOG), FULLTW>(s, LS, tw, twmul);
     stockham_rec<T, L, NT, C, DIR, RMAXLOG, PASS + 1, NSLOG + bits, FULLTW>(s, LS, tw, twmul);
   }
 }
