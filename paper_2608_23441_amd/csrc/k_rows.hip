@@ -23,10 +23,10 @@ __device__ __forceinline__ cx<T> load_spec(const void* __restrict__ in, const T*
     const int im = (signed char)(b << 4) >> 4;        // low nibble, sign-extended
     const T f = fac[k];
     return mk<T>(T(re) * f, T(im) * f);
-  } else if constexpr (FMT == IN_CI8) {  // (re, im) as two signed bytes
-    const char2 q = reinterpret_cast<const char2*>(in)[idx];
+  } else if constexpr (FMT == IN_CI8) {  // (re, im) as two signed bytes, any alignment
+    const signed char* q = reinterpret_cast<const signed char*>(in) + 2 * idx;
     const T f = fac[k];
-    return mk<T>(T((int)q.x) * f, T((int)q.y) * f);
+    return mk<T>(T((int)q[0]) * f, T((int)q[1]) * f);
   } else if constexpr (FMT == IN_CF32) {
     const cx<float> v = reinterpret_cast<const cx<float>*>(in)[idx];
     const T f = T(1.0 / (double)N);
