@@ -55,6 +55,24 @@ def test_ipfb_wiener_c4(prec, N, p, b, phi):
     assert _rel(_host(out), ref) < TOL[prec]
 
 
+# The longest frames the inverse takes (lblock 2^15 in FP32, 2^14 in FP64),
+# and the error one frame length beyond them.
+@pytest.mark.parametrize("prec,N", [(ipfb.F32, 1 << 15), (ipfb.F64, 1 << 14)])
+def test_ipfb_wiener_longest_frames(prec, N):
+    p, b = 4, 16
+    print(f"case ipfb_wiener longest frames prec={prec} N={N}", flush=True)
+    w, x, y, packed, s = _quantised_case(N, p, b, 700)
+    ref = O.ipfb_wiener(packed, s, w, N, p, 0.1)
+    plan = ipfb.Plan(N, p, w, b, prec)
+    out = ipfb.ipfb_wiener(plan, _dev(packed), _dev(s), 0.1)
+    assert _rel(_host(out), ref) < TOL[prec]
+    big = ipfb.Plan(2 * N, p, O.window_sinc_hamming(p, 2 * N), b, prec)
+    with pytest.raises(ipfb.IpfbError) as err:
+        ipfb.ipfb_wiener(big, torch.zeros((b, N + 1), dtype=torch.uint8, device="cuda"),
+                         torch.ones(N + 1, dtype=torch.float32, device="cuda"), 0.1)
+    assert err.value.status == ipfb.EUNSUPPORTED
+
+
 # 8-bit spectra (IPFB_IN_CI8): finer codes with the same per-channel scale;
 # power-of-two and Bluestein column lengths, the four-step and one-pass stages
 @pytest.mark.parametrize("prec", [ipfb.F64, ipfb.F32])
