@@ -82,6 +82,22 @@ def test_ml_cg_ci8_matches_oracle():
     assert _rel(xg, ref_x) < 1e-6
 
 
+def test_ml_cg_bitwise_deterministic():
+    # the dot products reduce in a fixed order (wavefront butterflies, then
+    # wavefronts, then workgroups in index order): two runs agree bit for bit
+    N, p, b = 256, 4, 1024
+    print("case ml_cg determinism", flush=True)
+    w, x, packed, s, mask, d = _ml_case(N, p, b, 320)
+    plan = ipfb.Plan(N, p, w, b, ipfb.F32)
+    runs = []
+    for _ in range(2):
+        xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(mask.astype(np.uint8)),
+                            _dev(x).to(torch.float32), 1.0, 0.1, 0.1, 20)
+        runs.append((_host(xg).copy(), _host(ng).copy()))
+    assert np.array_equal(runs[0][0].view(np.uint8), runs[1][0].view(np.uint8))
+    assert np.array_equal(runs[0][1].view(np.uint8), runs[1][1].view(np.uint8))
+
+
 def test_ml_cg_zero_iterations_is_wiener():
     N, p, b = 64, 4, 32
     w, x, packed, s, mask, d = _ml_case(N, p, b, 310)
