@@ -12,37 +12,12 @@
 // memory: no host round trip inside the iteration loop.
 #include "fft_lds.hpp"
 #include "launch.hpp"
+#include "reduce.hpp"
 
 namespace ipfb {
 
 constexpr int kCgNWG = 1024;  // workgroups of the element-wise kernels (fixed: deterministic sums)
 constexpr int kCgNT = 256;
-
-// Sum over the 64 lanes of a wavefront: a butterfly of cross-lane exchanges.
-// Each step adds the same two partials on both lanes of a pair (in swapped
-// order, which IEEE addition does not distinguish), so every lane ends with
-// the same total.
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Sum over a workgroup of NT threads: wavefront sums, then the NT/64 of them
-// in wavefront order, so the result does not depend on timing. sh holds at
-// least NT/64 doubles. Every thread returns the total.
-template <int NT>
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-  static_assert(NT % 64 == 0, "whole wavefronts");
-  v = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int w = 0; w < NT / 64; ++w) t += sh[w];
-  __syncthreads();  // the caller may write sh again
-  return t;
-}
 
 // c_n[t] for t in [-(p-1), p-1], stored autoc[n * (2p-1) + t + p - 1], FP64
 __global__ __launch_bounds__(256) void k_cg_autocorr(const double* __restrict__ win, int N, int ntap,

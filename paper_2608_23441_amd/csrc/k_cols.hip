@@ -16,6 +16,7 @@
 // so no N x b table ever touches HBM.
 #include "fft_lds.hpp"
 #include "launch.hpp"
+#include "reduce.hpp"
 
 namespace ipfb {
 
@@ -190,16 +191,11 @@ __global__ __launch_bounds__((ColCfg<T, LOG2B>::NT), (ColCfg<T, LOG2B>::WPE)) vo
       acc += (double)a.x * (double)v.x + (double)a.y * (double)v.y;
     }
   }
-  if (part) {  // fixed-order sum over the workgroup in the (now free) LDS
+  if (part) {  // fixed-order sum over the workgroup, through the (now free) LDS
     double* red = reinterpret_cast<double*>(s);
     __syncthreads();
-    red[tid] = acc;
-    __syncthreads();
-    for (int w = NT / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    if (tid == 0) part[blockIdx.x] = red[0];
+    const double tot = block_sum<NT>(acc, red);
+    if (tid == 0) part[blockIdx.x] = tot;
     if (blockIdx.x == 0)  // the slots no workgroup of this launch fills
       for (int i = (int)gridDim.x + tid; i < nparts; i += NT) part[i] = 0.0;
   }

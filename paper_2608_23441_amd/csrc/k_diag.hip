@@ -3,6 +3,7 @@
 // timestreams) or predicted for white input from the sub-filter responses.
 #include "fft_lds.hpp"
 #include "launch.hpp"
+#include "reduce.hpp"
 
 namespace ipfb {
 
@@ -40,7 +41,7 @@ hipError_t launch_ratio(const double* num, const double* den, double* out, int n
 // W_n(f) = sum_r h[rN + n] e^{-2 pi i r f}, mode 0 (Wiener):
 // 1 - (1/N) sum_n |W_n|^2 / (|W_n|^2 + phi^2); mode 1 (naive):
 // (inv_snr / N) sum_n 1 / |W_n|^2. One workgroup per frequency; each thread
-// sums its columns in order, then a fixed-order tree over the workgroup.
+// sums its columns in order, then a fixed-order sum over the workgroup.
 __global__ __launch_bounds__(256) void k_delta_analytic(const double* __restrict__ win, int N, int ntap,
                                                         int64_t nfreq, double phi2, int mode, double inv_snr,
                                                         double* __restrict__ out) {
@@ -64,14 +65,9 @@ __global__ __launch_bounds__(256) void k_delta_analytic(const double* __restrict
     const double a2 = wr * wr + wi * wi;
     acc += (mode == 0) ? a2 / (a2 + phi2) : 1.0 / a2;
   }
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
+  const double tot = block_sum<256>(acc, red);
   if (threadIdx.x == 0) {
-    const double mean = red[0] / (double)N;
+    const double mean = tot / (double)N;
     out[k] = (mode == 0) ? 1.0 - mean : inv_snr * mean;
   }
 }
