@@ -406,9 +406,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(streams and columns shard without communication; see the design notes).",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path. Independent streams "
+              "would shard over GPUs without communication, one long stream with one all-to-all of the "
+              "frame matrix between the row and column stages.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
