@@ -142,7 +142,9 @@ __global__ __launch_bounds__((Lf1rCfg<T, LOG2P1>::NT)) void k_lf1r(const cx<T>* 
   constexpr int P1 = Cfg::P1, MB = Cfg::MB, NT = Cfg::NT, EPT = Cfg::EPT, LS = Cfg::LS;
   constexpr int NTAP = 4;
   static_assert(EPT >= 1 && EPT <= 8, "register budget: 4 frames + 4 window taps of EPT elements");
-  __shared__ cx<T> s[MB * LS];
+  // two frame buffers, alternating by frame: the next frame's sums go to the
+  // other buffer while slower threads still read this one for their stores
+  __shared__ cx<T> sbuf[2 * MB * LS];
   // the twiddle tables live in LDS for the life of the workgroup: every FFT
   // pass and store then waits on LDS, not on global-memory latency
   // M = P1 * P2 <= P1^2, so e^{-2 pi i 512 m / M} needs at most P1^2 / 512 entries
@@ -173,6 +175,7 @@ __global__ __launch_bounds__((Lf1rCfg<T, LOG2P1>::NT)) void k_lf1r(const cx<T>* 
     }
   }
   for (int64_t j = ja; j < jb; ++j) {
+    cx<T>* s = sbuf + ((j - ja) & 1) * (MB * LS);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       cx<T> acc = mk<T>(T(0), T(0));
@@ -204,7 +207,9 @@ __global__ __launch_bounds__((Lf1rCfg<T, LOG2P1>::NT)) void k_lf1r(const cx<T>* 
       const int c = c0 + mb;
       tj[(int64_t)k1 * P2 + c] = cmul(s[mb * LS + pidx(k1)], tw2(tMlos, tMhis, c * k1));
     }
-    __syncthreads();  // the next sums overwrite s
+    // no barrier: frame j + 1 writes the other buffer, and frame j + 2 writes
+    // this one only after the barriers of frame j + 1, which every thread
+    // reaches after its reads above
   }
 }
 
