@@ -311,6 +311,26 @@ def test_fault_injection_reports_errors(monkeypatch):
 
 # ---- other eigenvalue filters ------------------------------------------------
 @pytest.mark.parametrize("prec,tol", [(ipfb.F64, 1e-11), (ipfb.F32, 1e-5)])
+def test_filter_with_8bit_spectra(prec, tol):
+    # the filter entry point dequantises 8-bit codes like the Wiener one
+    N, p, b = 64, 4, 4096
+    print(f"case filter ci8 prec={prec}", flush=True)
+    w = O.window_sinc_hamming(p, N)
+    y = O.pfb_forward(I.gaussian_timestream(N * b, 950), w, N, p)
+    sc = O.channel_scales(y, levels_rms=40.0)
+    qr, qi = O.quantize(y, sc, qmax=127)
+    d = O.row_inverse(O.dequantize(qr, qi, sc), N)
+    f = np.arange(b // 2 + 1)
+    nu = 0.01 + 0.04 * np.sin(np.pi * f / b) ** 2
+    nu_full = np.concatenate([nu, nu[1:b // 2][::-1]])
+    ref = O.column_inverse_filter(d, w, N, p, "psd", 0.0, nu_full, True).reshape(-1)
+    plan = ipfb.Plan(N, p, w, b, prec)
+    got = ipfb.wiener_filter(plan, _dev(O.pack_ci8(qr, qi)), _dev(sc), ipfb.FILTER_NU, 0.0, _dev(nu))
+    assert _rel(_host(got).astype(np.float64), ref) < tol
+
+
+
+@pytest.mark.parametrize("prec,tol", [(ipfb.F64, 1e-11), (ipfb.F32, 1e-5)])
 @pytest.mark.parametrize("N,p,b", [(64, 4, 256), (128, 4, 4096), (64, 3, 1024), (32, 4, 16384)])
 def test_ipfb_other_filters_match_oracle(prec, tol, N, p, b):
     # one-pass (b <= 512) and three-pass (four-step) column stages; the
