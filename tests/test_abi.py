@@ -21,6 +21,19 @@ def _header_functions():
     return sorted(set(names))
 
 
+@pytest.mark.parametrize("lang,std", [("c", "-std=c99"), ("c++", "-std=c++11")])
+def test_header_is_plain_c_and_cxx(lang, std):
+    # the boundary is a C ABI: the header alone compiles as C and as C++
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc" if lang == "c" else "g++")
+    if cc is None:
+        pytest.skip("no host compiler")
+    r = subprocess.run([cc, "-fsyntax-only", "-Wall", "-Wextra", "-Werror", "-x", lang, std,
+                        os.path.join(ROOT, "include", "ipfb.h")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def test_library_exports_every_header_symbol():
     L = ipfb.lib()
     names = _header_functions()
