@@ -206,7 +206,7 @@ def ml_form(torch, ipfb, inputs):
     N, p, b, iters = 2048, 4, 8192, 100
     S = N * b
     x, w, packed, scales = make_inputs(torch, ipfb, inputs, N, p, b, 5, 0, 0, 0.0, 2.5)
-    mask = torch.from_numpy(inputs.random_mask(S, 0.1, 505).astype("uint8")).cuda()
+    mask = ipfb.mask_pack(torch.from_numpy(inputs.random_mask(S, 0.1, 505).astype("uint8")).cuda())
     prior = torch.from_numpy(x.astype("float32")).cuda()
     plan = ipfb.Plan(N, p, w, b, ipfb.F32)
     xo = torch.empty(S, dtype=torch.float32, device="cuda")
@@ -224,10 +224,11 @@ def ml_form(torch, ipfb, inputs):
     it_ms, it_n = ipfb.profile_query("cg_iter")
     ipfb.profile_reset()
     nrm = norms.cpu().numpy()
-    # per-iteration compulsory traffic (FP32 vectors): H p (read p, write q) 8 B,
-    # x/r update (read x, p, r, q; write x, r) 24 B, z = M^-1 r (read r, write z)
-    # 8 B, r.z (read r, z) 8 B, p update (read z, p; write p) 12 B -> 60 B/sample
-    it_bytes = 60.0 * S
+    # per-iteration compulsory traffic (FP32 vectors): H p (read p and the
+    # 1-bit mask, write q) 8.125 B, x/r update (read x, p, r, q; write x, r)
+    # 24 B, z = M^-1 r with r.z formed on the way out (read r, write z) 8 B,
+    # p update (read z, p; write p) 12 B -> 52.125 B/sample
+    it_bytes = 52.125 * S
     it_us = 1e3 * it_ms / max(it_n, 1)
     return {"value": S / sec, "unit": "samples/s", "ms_per_solve": sec * 1e3, "iterations": iters,
             "config": {"lblock": N, "ntap": p, "nblock": b, "mask_fraction": 0.1, "lambda": 1.0, "phi": 0.1},
@@ -380,7 +381,8 @@ def structured_sweep(torch, ipfb, betas=(0.01, 0.03, 0.05, 0.10), iters=25):
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         dmax, dmed = worst(xm)
-        out[f"cg_beta_{beta:.2f}"] = {"saved_paths": L, "saved_fraction": float(mask.float().mean()),
+        out[f"cg_beta_{beta:.2f}"] = {"saved_paths": L,
+                                      "saved_fraction": float(len(range(0, b, R)) * L) / float(N * b),
                                       "delta_max": dmax, "delta_median": dmed, "solve_s": sec,
                                       "samples_per_s": N * b / sec}
     return out

@@ -144,13 +144,16 @@ int ipfb_wiener_ex(ipfb_plan plan, int infmt, const void* spec, const float* cha
  * G = H / conj(W) at no extra cost). As ipfb_wiener_ex, with the gain
  *   IPFB_FILTER_WIENER:    the Wiener filter with phi = param;
  *   IPFB_FILTER_THRESHOLD: H = 1 where |W_n(f)| >= param, else 0 (the
- *                          truncated pseudo-inverse);
+ *                          truncated pseudo-inverse); param > 0;
  *   IPFB_FILTER_NU:        the general Wiener filter S/(S+N) with a
  *                          noise-to-signal ratio per frequency,
  *                          H = |W|^2 (1 + nu_f) / (|W|^2 + nu_f) (the
  *                          (1 + nu_f) factor dropped with normalise = 0);
  *                          nu: device double [nblock/2 + 1], nu_f >= 0 for
- *                          f = 0 .. nblock/2 (nu_{b-f} is taken as nu_f).
+ *                          f = 0 .. nblock/2 (nu_{b-f} is taken as nu_f);
+ *                          where |W|^2 + nu_f <= (1e-12 sum_r |h[rN+n]|)^2
+ *                          (nu_f = 0 at an exact zero of W) the gain is 0,
+ *                          the naive inverse's truncation.
  * Power-of-two nblock only (the LDS column path); param is ignored for
  * IPFB_FILTER_NU and nu for the others. */
 enum { IPFB_FILTER_WIENER = 0, IPFB_FILTER_THRESHOLD = 1, IPFB_FILTER_NU = 2 };
@@ -201,17 +204,21 @@ int upchannelize(ipfb_plan fine, const void* x, void* y_fine, double* autospec, 
  * conjugate gradient on (A^T A + lambda D) x = A^T d + lambda D prior
  * (the CG method the paper cites), with the preconditioner
  * F^dagger diag(1/(|W_n|^2 + phi_precond^2)) F per column.
- * spec/chan_scale/infmt as for ipfb_wiener. mask: device uint8 [S] in time
- * order (S = nblock*lblock), nonzero where the timestream sample is saved.
- * prior: device [S] real (plan precision), read where mask != 0.
+ * spec/chan_scale/infmt as for ipfb_wiener. mask: device bitmask of
+ * ceil(S/32) 32-bit words, S = nblock*lblock, in time order: sample
+ * e = j*lblock + n is saved when bit (e mod 32) of word e/32 is 1 (least
+ * significant bit first; bits past S are ignored). ipfb_mask_pack builds it
+ * from one byte per sample.
+ * prior: device [S] real (plan precision), read where the mask bit is 1.
  * x_init: NULL to start from the Wiener solution with phi_x0 (the paper's
  * initial guess), else a device [S] real starting point. Runs exactly iters
  * iterations (no early exit; an exactly converged system stops moving).
  * x_out: device [S] real, time order. resid_norms: NULL or device double
  * [iters+1] receiving |r_k|_2 (FP64 sums). Vectors are FP32 for F32 plans,
  * dot products and norms FP64. The first call on a plan allocates the
- * workspace (8 vectors of S reals); later calls allocate nothing. */
-int ipfb_ml_cg(ipfb_plan plan, int infmt, const void* spec, const float* chan_scale, const uint8_t* mask,
+ * workspace (7 vectors of S reals and the mask bits transposed to the
+ * column layout); later calls allocate nothing. */
+int ipfb_ml_cg(ipfb_plan plan, int infmt, const void* spec, const float* chan_scale, const uint32_t* mask,
                const void* prior, double lambda, double phi_x0, double phi_precond, int iters,
                const void* x_init, void* x_out, double* resid_norms, void* stream);
 
@@ -219,12 +226,17 @@ int ipfb_ml_cg(ipfb_plan plan, int infmt, const void* spec, const float* chan_sc
 int ipfb_autospectrum(ipfb_plan plan, const void* y, double* autospec, void* stream);
 
 /* Prior mask of the sample-saving strategy (Section 4.2.2): every R-th
- * sample of the L sub-filter paths around the frame centre, i.e.
- * mask[j*lblock + n] = 1 for j = 0 mod R and lblock/2 - L/2 <= n <
- * lblock/2 + L/2, else 0; the saved fraction is beta = L/(R lblock) when R
- * divides nblock. mask: device uint8 [nblock*lblock] (ipfb_ml_cg's layout).
- * L even, 0 <= L <= lblock; R >= 1. */
-int ipfb_mask_structured(ipfb_plan plan, int R, int L, uint8_t* mask, void* stream);
+ * sample of the L sub-filter paths around the frame centre, i.e. sample
+ * e = j*lblock + n is saved for j = 0 mod R and lblock/2 - L/2 <= n <
+ * lblock/2 + L/2; the saved fraction is beta = L/(R lblock) when R divides
+ * nblock. mask: device uint32 [ceil(nblock*lblock/32)], ipfb_ml_cg's bitmask
+ * layout. L even, 0 <= L <= lblock; R >= 1. */
+int ipfb_mask_structured(ipfb_plan plan, int R, int L, uint32_t* mask, void* stream);
+
+/* Packs a byte-per-sample mask (device uint8 [nsamples], nonzero = saved)
+ * into ipfb_ml_cg's bitmask (device uint32 [ceil(nsamples/32)]) on the
+ * current device. nsamples = 0 enqueues nothing. */
+int ipfb_mask_pack(const uint8_t* mask, int64_t nsamples, uint32_t* bits, void* stream);
 
 /* Appendix B diagnostics. delta(f) = <|X(f) - Xhat(f)|^2> / <|X(f)|^2>, the
  * relative error of the power spectrum.

@@ -227,7 +227,7 @@ def column_inverse(d: np.ndarray, window: np.ndarray, lblock: int, ntap: int,
 
 
 def filter_gain(W: np.ndarray, kind: str, param: float = 0.0, nu: np.ndarray | None = None,
-                normalise: bool = True) -> np.ndarray:
+                normalise: bool = True, tapsum: np.ndarray | None = None) -> np.ndarray:
     """Other eigenvalue filters (Section 4.1: the circulant form gives the
     eigenspectrum W_n(f), so any filter H_n(f) applies as G = H / conj(W)).
 
@@ -237,7 +237,9 @@ def filter_gain(W: np.ndarray, kind: str, param: float = 0.0, nu: np.ndarray | N
     per frequency, nu[f] = N(f)/S(f) (an array of length b, read as
     nu[min(f, b - f)]), H = |W|^2 (1 + nu) / (|W|^2 + nu), the (1 + nu) factor
     dropped with normalise=False; a constant nu = phi^2 is the Wiener filter.
-    W: [b, N]; returns G [b, N].
+    READING (as the naive inverse's truncation, Section 4.2.2): where
+    |W|^2 + nu <= (1e-12 tapsum)^2, e.g. nu = 0 at an exact zero of W, G = 0.
+    W: [b, N]; tapsum: [N] sum_r |h[rN+n]| (default max |W|); returns G [b, N].
     """
     W = np.asarray(W, dtype=np.complex128)
     b = W.shape[0]
@@ -251,7 +253,12 @@ def filter_gain(W: np.ndarray, kind: str, param: float = 0.0, nu: np.ndarray | N
         f = np.arange(b)
         v = np.asarray(nu, dtype=np.float64)[np.minimum(f, b - f) % b][:, None]
         c = (1.0 + v) if normalise else 1.0
-        return W * c / (a2 + v)
+        den = a2 + v
+        bound = np.abs(W).max() if tapsum is None else np.broadcast_to(tapsum, W.shape)
+        ok = den > (1e-12 * bound) ** 2
+        G = np.zeros_like(W)
+        G[ok] = (W * c)[ok] / den[ok]
+        return G
     raise ValueError(kind)
 
 
@@ -261,7 +268,8 @@ def column_inverse_filter(d: np.ndarray, window: np.ndarray, lblock: int, ntap: 
     """xhat_n = F^dagger[ G_n . F d_n ] with a filter_gain eigenvalue filter."""
     d = np.asarray(d, dtype=np.float64)
     W = column_spectra(window, lblock, ntap, d.shape[0])
-    G = filter_gain(W, kind, param, nu, normalise)
+    tapsum = np.sum(np.abs(np.asarray(window, dtype=np.float64).reshape(ntap, lblock)), axis=0)
+    G = filter_gain(W, kind, param, nu, normalise, tapsum=tapsum[None, :])
     return np.fft.ifft(G * np.fft.fft(d, axis=0), axis=0).real
 
 
@@ -490,11 +498,13 @@ def ml_normal_apply(x, window, lblock, ntap, mask2d, lam):
     return sw_adjoint(sw_apply(x, window, lblock, ntap), window, lblock, ntap) + lam * mask2d * x
 
 
-def ml_preconditioner(r, window, lblock, ntap, phi):
+def ml_preconditioner(r, window, lblock, ntap, phi, W=None):
     """M^{-1} r = F^dagger[ F r_n / (|W_n|^2 + phi^2) ] per column: the inverse of
-    A^T A + phi^2 I, which is diagonal in the Fourier basis (Section 3.1)."""
+    A^T A + phi^2 I, which is diagonal in the Fourier basis (Section 3.1).
+    W: column_spectra(window, lblock, ntap, b) if the caller already holds it."""
     b = r.shape[0]
-    W = column_spectra(window, lblock, ntap, b)
+    if W is None:
+        W = column_spectra(window, lblock, ntap, b)
     return np.fft.ifft(np.fft.fft(r, axis=0) / (np.abs(W) ** 2 + phi * phi), axis=0).real
 
 
@@ -515,7 +525,8 @@ def ml_pcg(d: np.ndarray, window: np.ndarray, lblock: int, ntap: int,
     x = np.array(x0, dtype=np.float64).reshape(-1, N)
     rhs = sw_adjoint(d, window, lblock, ntap) + lam * m2 * pr
     r = rhs - ml_normal_apply(x, window, lblock, ntap, m2, lam)
-    z = ml_preconditioner(r, window, lblock, ntap, phi_precond)
+    W = column_spectra(window, lblock, ntap, d.shape[0])  # the same in every iteration
+    z = ml_preconditioner(r, window, lblock, ntap, phi_precond, W)
     pdir = z.copy()
     rho = float(np.sum(r * z))
     norms = [float(np.sqrt(np.sum(r * r)))]
@@ -526,7 +537,7 @@ def ml_pcg(d: np.ndarray, window: np.ndarray, lblock: int, ntap: int,
         alpha = rho / pq if pq != 0.0 else 0.0
         x = x + alpha * pdir
         r = r - alpha * q
-        z = ml_preconditioner(r, window, lblock, ntap, phi_precond)
+        z = ml_preconditioner(r, window, lblock, ntap, phi_precond, W)
         rho_new = float(np.sum(r * z))
         beta = rho_new / rho if rho != 0.0 else 0.0
         rho = rho_new

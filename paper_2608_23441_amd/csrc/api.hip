@@ -94,14 +94,12 @@ struct ipfb_plan_s {
   void* tmp = nullptr;   // four-step intermediate of long frames: nblock*lblock/2 complex
   double* part = nullptr;
   void* fac = nullptr;   // per-channel dequantisation factors 1/(s_k N)
-  // maximum-likelihood CG workspace (allocated on first use): 8 vectors in the
-  // transposed layout, the column autocorrelations, partial sums, scalars
+  // maximum-likelihood CG workspace (allocated on first use): 7 vectors in the
+  // transposed layout, the mask bits, the column autocorrelations, partial
+  // sums, scalars
   void* cg = nullptr;
   // nblock not a power of two: a one-stream batched plan runs the Bluestein column path
   ipfb_bplan_s* blu1 = nullptr;
-  double* cg_autoc = nullptr;
-  double* cg_part = nullptr;
-  double* cg_sc = nullptr;
   int jchunk = 1, nchunks = 1;
   int fchunk = 1, nfchunks = 1;  // long frames: frames per power-sum chunk
   // Appendix B diagnostics (allocated on first use): x_true - x_hat, the
@@ -161,7 +159,7 @@ void free_bplan(ipfb_bplan p);
 void free_plan(ipfb_plan p) {
   if (p->blu1) free_bplan(p->blu1);
   void* ptrs[] = {p->win64, p->winT, p->twN, p->twB, p->twB64, p->part, p->fac, p->twS,
-                  p->cg, p->cg_autoc, p->cg_part, p->cg_sc, p->diag};
+                  p->cg, p->diag};
   for (void* q : ptrs)
     if (q) hipFree(q);
   if (!p->ws_ext) {
@@ -563,8 +561,11 @@ int ipfb_wiener_filter(ipfb_plan p, int infmt, const void* spec, const float* ch
   if (check_infmt(infmt, chan_scale)) return IPFB_EINVAL;
   if (kind != IPFB_FILTER_WIENER && kind != IPFB_FILTER_THRESHOLD && kind != IPFB_FILTER_NU)
     return fail(IPFB_EINVAL, "unknown filter kind %d", kind);
-  if (kind != IPFB_FILTER_NU && (!(param >= 0.0) || !std::isfinite(param)))
-    return fail(IPFB_EINVAL, "param must be finite and >= 0");
+  if (kind == IPFB_FILTER_WIENER && (!(param >= 0.0) || !std::isfinite(param)))
+    return fail(IPFB_EINVAL, "param (phi) must be finite and >= 0");
+  if (kind == IPFB_FILTER_THRESHOLD && (!(param > 0.0) || !std::isfinite(param)))
+    return fail(IPFB_EINVAL, "param (the threshold) must be finite and > 0: a zero threshold keeps the zero "
+                             "eigenvalues");
   if (kind == IPFB_FILTER_NU && !nu) return fail(IPFB_EINVAL, "the noise-to-signal filter needs nu");
   if (!p->row_lds || !p->col_lds)
     return fail(IPFB_EUNSUPPORTED, "ipfb_wiener_filter needs a power-of-two nblock <= 2^%d and lblock <= 2^%d",
@@ -687,26 +688,60 @@ int ipfb_wiener_stream(ipfb_splan sp, int infmt, const void* spec, const float* 
 namespace {
 
 // z = M^-1 r (the CG preconditioner) and the partial sums of r . z in
-// p->cg_part: formed by the column kernel itself where its workgroups fit the
+// part: formed by the column kernel itself where its workgroups fit the
 // partial-sum slots, else by a separate dot-product pass.
-hipError_t precond_dot(ipfb_plan p, const void* rT, void* zT, double phi_precond, int64_t S, hipStream_t st) {
+hipError_t precond_dot(ipfb_plan p, const void* rT, void* zT, double phi_precond, int64_t S, double* part,
+                       hipStream_t st) {
   hipError_t e = launch_col_wiener(p->prec, p->log2b, rT, zT, p->lblock, p->ntap, p->win64, phi_precond, 1, p->twB,
-                                   p->twB64, st, 1, p->cg_part);
+                                   p->twB64, st, 1, part);
   if (e != hipErrorNotSupported) return e;
   hipGetLastError();
   e = launch_col_wiener(p->prec, p->log2b, rT, zT, p->lblock, p->ntap, p->win64, phi_precond, 1, p->twB, p->twB64,
                         st, 1);
-  if (e == hipSuccess) e = launch_cg_dot(p->prec, rT, zT, S, p->cg_part, st);
+  if (e == hipSuccess) e = launch_cg_dot(p->prec, rT, zT, S, part, st);
   return e;
 }
 
-}  // namespace
+// The CG buffers of one solve: seven vectors in the transposed layout, the
+// mask bits in the same layout, the column autocorrelations, the partial sums
+// and the scalars.
+struct CgBufs {
+  void *xT, *rT, *zT, *pT, *qT, *rhsT, *priorT;
+  uint32_t* maskT;
+  double *autoc, *part, *sc;
+};
 
-extern "C" {
+size_t cg_mask_bytes(ipfb_plan p) {
+  return (size_t)p->lblock * (size_t)((p->nblock + 31) / 32) * sizeof(uint32_t);
+}
 
-int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, const uint8_t* mask,
-               const void* prior, double lam, double phi_x0, double phi_precond, int iters, const void* x_init,
-               void* x_out, double* resid_norms, void* stream) {
+// Lays the CG buffers out from base: 7 vectors, the mask bits, then (256-byte
+// aligned) the autocorrelations, partial sums and scalars. Returns the bytes.
+size_t cg_layout(ipfb_plan p, char* base, CgBufs* o) {
+  const size_t vb = (size_t)p->lblock * (size_t)p->nblock * esize(p->prec);
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  size_t off = 7 * vb;
+  const size_t om = off;
+  off = up(off + cg_mask_bytes(p));
+  const size_t oa = off;
+  off = up(off + (size_t)p->lblock * (2 * p->ntap - 1) * sizeof(double));
+  const size_t op = off;
+  off = up(off + kCgParts * sizeof(double));
+  const size_t os = off;
+  off += 8 * sizeof(double);
+  if (o) {
+    void** v[7] = {&o->xT, &o->rT, &o->zT, &o->pT, &o->qT, &o->rhsT, &o->priorT};
+    for (int i = 0; i < 7; ++i) *v[i] = base + i * vb;
+    o->maskT = (uint32_t*)(base + om);
+    o->autoc = (double*)(base + oa);
+    o->part = (double*)(base + op);
+    o->sc = (double*)(base + os);
+  }
+  return off;
+}
+
+int ml_cg_check(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, const uint32_t* mask,
+                const void* prior, double lam, double phi_x0, double phi_precond, int iters, void* x_out) {
   if (check_plan(p)) return IPFB_EINVAL;
   if (!spec || !mask || !prior || !x_out) return fail(IPFB_EINVAL, "spec, mask, prior and x_out must be non-NULL");
   if (check_infmt(infmt, chan_scale)) return IPFB_EINVAL;
@@ -716,26 +751,15 @@ int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale
   if (iters < 0) return fail(IPFB_EINVAL, "iters must be >= 0");
   if (!p->row_lds || !p->col_lds)
     return fail(IPFB_EUNSUPPORTED, "ipfb_ml_cg needs a plan that supports ipfb_wiener");
-  DeviceGuard g(p->dev);
-  hipStream_t st = (hipStream_t)stream;
+  return IPFB_OK;
+}
+
+// Enqueues the whole solve on st with the buffers in c (the plan's frame
+// buffers work and work2 hold d and its transpose).
+hipError_t ml_cg_enqueue(ipfb_plan p, const CgBufs& c, int infmt, const void* spec, const float* chan_scale,
+                         const uint32_t* mask, const void* prior, double lam, double phi_x0, double phi_precond,
+                         int iters, const void* x_init, void* x_out, double* resid_norms, hipStream_t st) {
   const int64_t b = p->nblock, S = (int64_t)p->lblock * b;
-  const size_t vb = (size_t)S * esize(p->prec);
-  if (!p->cg) {
-    int s2 = dev_alloc(p, &p->cg, 8 * vb);
-    if (!s2) s2 = dev_alloc(p, (void**)&p->cg_autoc, (size_t)p->lblock * (2 * p->ntap - 1) * sizeof(double));
-    if (!s2) s2 = dev_alloc(p, (void**)&p->cg_part, kCgParts * sizeof(double));
-    if (!s2) s2 = dev_alloc(p, (void**)&p->cg_sc, 8 * sizeof(double));
-    if (s2) return s2;
-  }
-  char* base = (char*)p->cg;
-  void* xT = base;
-  void* rT = base + vb;
-  void* zT = base + 2 * vb;
-  void* pT = base + 3 * vb;
-  void* qT = base + 4 * vb;
-  void* rhsT = base + 5 * vb;
-  void* maskT = base + 6 * vb;
-  void* priorT = base + 7 * vb;
   void* dT = p->work2;
   hipError_t e;
   {
@@ -744,41 +768,60 @@ int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale
     else e = hipSuccess;
     if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec, p->fac, p->work, b, p->twN, st);
     if (e == hipSuccess) e = launch_transpose(p->prec, p->work, dT, b, p->lblock, st);
-    if (e == hipSuccess) e = launch_mask_to_T(p->prec, mask, qT, S, st);
-    if (e == hipSuccess) e = launch_transpose(p->prec, qT, maskT, b, p->lblock, st);
-    if (e == hipSuccess) e = launch_transpose(p->prec, prior, priorT, b, p->lblock, st);
-    if (e == hipSuccess) e = launch_cg_autocorr(p->win64, p->lblock, p->ntap, p->cg_autoc, st);
+    if (e == hipSuccess) e = launch_maskbits_transpose(mask, p->lblock, b, c.maskT, st);
+    if (e == hipSuccess) e = launch_transpose(p->prec, prior, c.priorT, b, p->lblock, st);
+    if (e == hipSuccess) e = launch_cg_autocorr(p->win64, p->lblock, p->ntap, c.autoc, st);
     if (e == hipSuccess)
-      e = launch_cg_rhs(p->prec, dT, rhsT, p->win64, maskT, priorT, lam, p->lblock, p->ntap, b, S, st);
+      e = launch_cg_rhs(p->prec, dT, c.rhsT, p->win64, c.maskT, c.priorT, lam, p->lblock, p->ntap, b, S, st);
     if (e == hipSuccess) {
-      if (x_init) e = launch_transpose(p->prec, x_init, xT, b, p->lblock, st);
-      else e = launch_col_wiener(p->prec, p->log2b, dT, xT, p->lblock, p->ntap, p->win64, phi_x0, 1, p->twB,
+      if (x_init) e = launch_transpose(p->prec, x_init, c.xT, b, p->lblock, st);
+      else e = launch_col_wiener(p->prec, p->log2b, dT, c.xT, p->lblock, p->ntap, p->win64, phi_x0, 1, p->twB,
                                  p->twB64, st);
     }
     // r0 = rhs - H x0, z0 = M^-1 r0, p0 = z0, rho0 = r0.z0
-    if (e == hipSuccess) e = launch_cg_normal(p->prec, xT, qT, p->cg_autoc, maskT, lam, p->ntap, b, S, p->cg_part, st);
-    if (e == hipSuccess) e = launch_cg_resid(p->prec, rhsT, qT, rT, S, p->cg_part, st);
-    if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 2, p->cg_sc, resid_norms, 0, st);
+    if (e == hipSuccess) e = launch_cg_normal(p->prec, c.xT, c.qT, c.autoc, c.maskT, lam, p->ntap, b, S, c.part, st);
+    if (e == hipSuccess) e = launch_cg_resid(p->prec, c.rhsT, c.qT, c.rT, S, c.part, st);
+    if (e == hipSuccess) e = launch_cg_scalar(c.part, 2, c.sc, resid_norms, 0, st);
     // z0 = M^-1 r0 with the partial sums of r0 . z0 formed on the way out
-    if (e == hipSuccess) e = precond_dot(p, rT, zT, phi_precond, S, st);
-    if (e == hipSuccess) e = launch_cg_p(p->prec, pT, zT, p->cg_sc, 0, S, st);
-    if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 0, p->cg_sc, nullptr, 0, st);
+    if (e == hipSuccess) e = precond_dot(p, c.rT, c.zT, phi_precond, S, c.part, st);
+    if (e == hipSuccess) e = launch_cg_p(p->prec, c.pT, c.zT, c.sc, 0, S, st);
+    if (e == hipSuccess) e = launch_cg_scalar(c.part, 0, c.sc, nullptr, 0, st);
   }
   for (int k = 1; k <= iters && e == hipSuccess; ++k) {
     ProfScope ps("cg_iter", st);
-    e = launch_cg_normal(p->prec, pT, qT, p->cg_autoc, maskT, lam, p->ntap, b, S, p->cg_part, st);
-    if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 1, p->cg_sc, nullptr, 0, st);
-    if (e == hipSuccess) e = launch_cg_xr(p->prec, xT, rT, pT, qT, p->cg_sc, S, p->cg_part, st);
-    if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 2, p->cg_sc, resid_norms, k, st);
-    if (e == hipSuccess) e = precond_dot(p, rT, zT, phi_precond, S, st);
-    if (e == hipSuccess) e = launch_cg_scalar(p->cg_part, 3, p->cg_sc, nullptr, 0, st);
-    if (e == hipSuccess) e = launch_cg_p(p->prec, pT, zT, p->cg_sc, 1, S, st);
+    e = launch_cg_normal(p->prec, c.pT, c.qT, c.autoc, c.maskT, lam, p->ntap, b, S, c.part, st);
+    if (e == hipSuccess) e = launch_cg_scalar(c.part, 1, c.sc, nullptr, 0, st);
+    if (e == hipSuccess) e = launch_cg_xr(p->prec, c.xT, c.rT, c.pT, c.qT, c.sc, S, c.part, st);
+    if (e == hipSuccess) e = launch_cg_scalar(c.part, 2, c.sc, resid_norms, k, st);
+    if (e == hipSuccess) e = precond_dot(p, c.rT, c.zT, phi_precond, S, c.part, st);
+    if (e == hipSuccess) e = launch_cg_scalar(c.part, 3, c.sc, nullptr, 0, st);
+    if (e == hipSuccess) e = launch_cg_p(p->prec, c.pT, c.zT, c.sc, 1, S, st);
   }
   if (e == hipSuccess) {
     ProfScope ps("cg_out", st);
-    e = launch_transpose(p->prec, xT, x_out, p->lblock, b, st);
+    e = launch_transpose(p->prec, c.xT, x_out, p->lblock, b, st);
   }
-  return launched(e, "ipfb_ml_cg");
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, const uint32_t* mask,
+               const void* prior, double lam, double phi_x0, double phi_precond, int iters, const void* x_init,
+               void* x_out, double* resid_norms, void* stream) {
+  if (int s = ml_cg_check(p, infmt, spec, chan_scale, mask, prior, lam, phi_x0, phi_precond, iters, x_out))
+    return s;
+  DeviceGuard g(p->dev);
+  if (!p->cg) {
+    if (int s2 = dev_alloc(p, &p->cg, cg_layout(p, nullptr, nullptr))) return s2;
+  }
+  CgBufs c;
+  cg_layout(p, (char*)p->cg, &c);
+  return launched(ml_cg_enqueue(p, c, infmt, spec, chan_scale, mask, prior, lam, phi_x0, phi_precond, iters, x_init,
+                                x_out, resid_norms, (hipStream_t)stream),
+                  "ipfb_ml_cg");
 }
 
 int ipfb_autospectrum(ipfb_plan p, const void* y, double* autospec, void* stream) {
@@ -825,7 +868,7 @@ int upchannelize(ipfb_plan fine, const void* x, void* y_fine, double* autospec, 
   return ok();
 }
 
-int ipfb_mask_structured(ipfb_plan p, int R, int L, uint8_t* mask, void* stream) {
+int ipfb_mask_structured(ipfb_plan p, int R, int L, uint32_t* mask, void* stream) {
   if (check_plan(p)) return IPFB_EINVAL;
   if (!mask) return fail(IPFB_EINVAL, "mask must be a non-NULL device pointer");
   if (R < 1) return fail(IPFB_EINVAL, "R must be >= 1");
@@ -833,6 +876,12 @@ int ipfb_mask_structured(ipfb_plan p, int R, int L, uint8_t* mask, void* stream)
   DeviceGuard g(p->dev);
   return launched(launch_mask_structured(mask, p->lblock, p->nblock, R, L, (hipStream_t)stream),
                   "ipfb_mask_structured");
+}
+
+int ipfb_mask_pack(const uint8_t* mask, int64_t nsamples, uint32_t* bits, void* stream) {
+  if (nsamples < 0) return fail(IPFB_EINVAL, "nsamples must be >= 0");
+  if (nsamples > 0 && (!mask || !bits)) return fail(IPFB_EINVAL, "mask and bits must be non-NULL device pointers");
+  return launched(launch_mask_pack(mask, nsamples, bits, (hipStream_t)stream), "ipfb_mask_pack");
 }
 
 int ipfb_delta_analytic(ipfb_plan p, int64_t nfreq, double phi, double snr, double* out, void* stream) {

@@ -7,6 +7,9 @@
 // frame j), so A^T A is a (2p-1)-tap circulant stencil along contiguous rows:
 //   (A^T A x)_n[i] = sum_{t=-(p-1)}^{p-1} c_n[t] x_n[(i+t) mod b],
 //   c_n[t] = sum_r h[rN+n] h[(r+t)N+n]  (autocorrelation of the column taps).
+// The prior mask D is one bit per sample, kept in the transposed layout as
+// rows of bw = ceil(b/32) 32-bit words (bit j of row n is frame j of path n),
+// so the stencil reads 1/8 byte per element for it.
 // Dot products and norms accumulate in FP64 per workgroup and are summed in a
 // fixed order by one workgroup, which also updates the CG scalars in device
 // memory: no host round trip inside the iteration loop.
@@ -18,6 +21,11 @@ namespace ipfb {
 
 constexpr int kCgNWG = 1024;  // workgroups of the element-wise kernels (fixed: deterministic sums)
 constexpr int kCgNT = 256;
+
+// bit j of row n of the transposed mask
+__device__ __forceinline__ unsigned mask_bit(const uint32_t* __restrict__ mb, int64_t bw, int64_t n, int64_t j) {
+  return (mb[n * bw + (j >> 5)] >> (j & 31)) & 1u;
+}
 
 // c_n[t] for t in [-(p-1), p-1], stored autoc[n * (2p-1) + t + p - 1], FP64
 __global__ __launch_bounds__(256) void k_cg_autocorr(const double* __restrict__ win, int N, int ntap,
@@ -39,9 +47,9 @@ __global__ __launch_bounds__(256) void k_cg_autocorr(const double* __restrict__ 
 // q = (A^T A + lam D) p ; partial sums of p.q
 template <typename T>
 __global__ __launch_bounds__(kCgNT) void k_cg_normal(const T* __restrict__ p, T* __restrict__ q,
-                                                     const double* __restrict__ autoc, const T* __restrict__ mask,
-                                                     double lam, int ntap, int64_t b, int64_t S,
-                                                     double* __restrict__ part) {
+                                                     const double* __restrict__ autoc,
+                                                     const uint32_t* __restrict__ mbits, int64_t bw, double lam,
+                                                     int ntap, int64_t b, int64_t S, double* __restrict__ part) {
   __shared__ double sh[kCgNT];
   const int nt = 2 * ntap - 1;
   double acc = 0.0;
@@ -57,7 +65,7 @@ __global__ __launch_bounds__(kCgNT) void k_cg_normal(const T* __restrict__ p, T*
       v += c[t] * (double)row[k];
     }
     const double pe = (double)p[e];
-    v += lam * (double)mask[e] * pe;
+    if (mask_bit(mbits, bw, n, i)) v += lam * pe;
     const T vt = T(v);
     q[e] = vt;
     acc += pe * (double)vt;
@@ -92,8 +100,9 @@ __device__ __forceinline__ void cg_stage_row(const T* __restrict__ row, T* tile,
 template <typename T>
 __global__ __launch_bounds__(kCgNT) void k_cg_normal_rows(const T* __restrict__ p, T* __restrict__ q,
                                                           const double* __restrict__ autoc,
-                                                          const T* __restrict__ mask, double lam, int ntap, int64_t b,
-                                                          int64_t nrows, double* __restrict__ part) {
+                                                          const uint32_t* __restrict__ mbits, int64_t bw, double lam,
+                                                          int ntap, int64_t b, int64_t nrows,
+                                                          double* __restrict__ part) {
   constexpr int EPT = kCgCH / kCgNT;
   __shared__ double sh[kCgNT];
   __shared__ double tile[kCgCH + 2 * kCgHMAX];  // widened once when staged
@@ -102,17 +111,17 @@ __global__ __launch_bounds__(kCgNT) void k_cg_normal_rows(const T* __restrict__ 
   const int h = ntap - 1, nt = 2 * ntap - 1;
   const int64_t nch = (b + kCgCH - 1) / kCgCH;
   const int64_t nw = nrows * nch;
-  T pm[EPT], mm[EPT], ph = T(0);
+  T pm[EPT], ph = T(0);
+  unsigned mm[EPT];
   auto fetch = [&](int64_t w) {
     const int64_t n = w / nch, c0 = (w - n * nch) * kCgCH;
     const int len = (int)((b - c0) < kCgCH ? (b - c0) : kCgCH);
     const T* row = p + n * b;
-    const T* mrow = mask + n * b;
 #pragma unroll
     for (int k = 0; k < EPT; ++k) {
       const int i = tid + k * kCgNT;
       pm[k] = i < len ? row[c0 + i] : T(0);
-      mm[k] = i < len ? mrow[c0 + i] : T(0);
+      mm[k] = i < len ? mask_bit(mbits, bw, n, c0 + i) : 0u;
     }
     if (tid < 2 * h) {  // halo: h elements before the chunk, h after, wrapped at the row ends
       int64_t pos = tid < h ? c0 - h + tid : c0 + len + (tid - h);
@@ -134,7 +143,7 @@ __global__ __launch_bounds__(kCgNT) void k_cg_normal_rows(const T* __restrict__ 
     for (int k = 0; k < EPT; ++k) {
       const int i = tid + k * kCgNT;
       if (i < len) tile[h + i] = (double)pm[k];
-      lm[k] = lam * (double)mm[k];
+      lm[k] = mm[k] ? lam : 0.0;
     }
     if (tid < 2 * h) tile[tid < h ? tid : len + tid] = (double)ph;
     for (int t = tid; t < nt; t += kCgNT) cs[t] = autoc[n * nt + t];
@@ -161,7 +170,8 @@ __global__ __launch_bounds__(kCgNT) void k_cg_normal_rows(const T* __restrict__ 
 // rhs = A^T d + lam D prior
 template <typename T>
 __global__ __launch_bounds__(kCgNT) void k_cg_rhs_rows(const T* __restrict__ d, T* __restrict__ rhs,
-                                                       const double* __restrict__ win, const T* __restrict__ mask,
+                                                       const double* __restrict__ win,
+                                                       const uint32_t* __restrict__ mbits, int64_t bw,
                                                        const T* __restrict__ prior, double lam, int N, int ntap,
                                                        int64_t b, int64_t nrows) {
   __shared__ T tile[kCgCH + 2 * kCgHMAX];
@@ -179,7 +189,7 @@ __global__ __launch_bounds__(kCgNT) void k_cg_rhs_rows(const T* __restrict__ d, 
         double v = 0.0;
         for (int r = 0; r < ntap; ++r) v += hs[r] * (double)tile[i + h - r];  // d_n[(i - r) mod b]
         const int64_t e = n * b + c0 + i;
-        v += lam * (double)mask[e] * (double)prior[e];
+        if (mask_bit(mbits, bw, n, c0 + i)) v += lam * (double)prior[e];
         rhs[e] = T(v);
       }
       __syncthreads();
@@ -190,7 +200,8 @@ __global__ __launch_bounds__(kCgNT) void k_cg_rhs_rows(const T* __restrict__ d, 
 // rhs = A^T d + lam D prior : (A^T d)_n[i] = sum_r h[rN+n] d_n[(i-r) mod b]
 template <typename T>
 __global__ __launch_bounds__(kCgNT) void k_cg_rhs(const T* __restrict__ d, T* __restrict__ rhs,
-                                                  const double* __restrict__ win, const T* __restrict__ mask,
+                                                  const double* __restrict__ win,
+                                                  const uint32_t* __restrict__ mbits, int64_t bw,
                                                   const T* __restrict__ prior, double lam, int N, int ntap,
                                                   int64_t b, int64_t S) {
   for (int64_t e = (int64_t)blockIdx.x * kCgNT + threadIdx.x; e < S; e += (int64_t)gridDim.x * kCgNT) {
@@ -202,7 +213,7 @@ __global__ __launch_bounds__(kCgNT) void k_cg_rhs(const T* __restrict__ d, T* __
       if (k < 0) k += b;
       v += win[(int64_t)r * N + n] * (double)row[k];
     }
-    v += lam * (double)mask[e] * (double)prior[e];
+    if (mask_bit(mbits, bw, n, i)) v += lam * (double)prior[e];
     rhs[e] = T(v);
   }
 }
@@ -294,12 +305,26 @@ __global__ __launch_bounds__(kCgNWG) void k_cg_scalar(const double* __restrict__
   }
 }
 
-// elementwise helpers used at set-up: out = (T) in for a byte mask
-template <typename T>
-__global__ __launch_bounds__(kCgNT) void k_mask_to_T(const uint8_t* __restrict__ m, T* __restrict__ out,
-                                                     int64_t S) {
-  for (int64_t e = (int64_t)blockIdx.x * kCgNT + threadIdx.x; e < S; e += (int64_t)gridDim.x * kCgNT)
-    out[e] = m[e] ? T(1) : T(0);
+// Set-up: the caller's time-order bitmask (bit e of word e/32 is sample
+// e = j N + n) to the transposed rows of bw words (bit j of row n). One
+// thread per output word; the 64 lanes of a wavefront take 64 neighbouring
+// paths of one word column, so each of their 32 reads touches at most two
+// input words.
+__global__ __launch_bounds__(kCgNT) void k_maskbits_transpose(const uint32_t* __restrict__ in, int N, int64_t b,
+                                                              int64_t bw, uint32_t* __restrict__ out) {
+  const int64_t total = (int64_t)N * bw;
+  for (int64_t t = (int64_t)blockIdx.x * kCgNT + threadIdx.x; t < total; t += (int64_t)gridDim.x * kCgNT) {
+    const int64_t jw = t / N;
+    const int n = (int)(t - jw * N);
+    const int64_t j0 = jw * 32;
+    const int nb = (b - j0) < 32 ? (int)(b - j0) : 32;
+    uint32_t w = 0;
+    for (int k = 0; k < nb; ++k) {
+      const int64_t e = (j0 + k) * N + n;
+      w |= ((in[e >> 5] >> (e & 31)) & 1u) << k;
+    }
+    out[(int64_t)n * bw + jw] = w;
+  }
 }
 
 #define CG_DISPATCH(prec, call) \
@@ -318,24 +343,26 @@ hipError_t launch_cg_autocorr(const double* win64, int N, int ntap, double* auto
   return hipGetLastError();
 }
 
-hipError_t launch_cg_normal(int prec, const void* p, void* q, const double* autoc, const void* mask, double lam,
-                            int ntap, int64_t b, int64_t S, double* part, hipStream_t st) {
+hipError_t launch_cg_normal(int prec, const void* p, void* q, const double* autoc, const uint32_t* mbits,
+                            double lam, int ntap, int64_t b, int64_t S, double* part, hipStream_t st) {
+  const int64_t bw = (b + 31) / 32;
   if (ntap - 1 <= kCgHMAX && b > 0)
-    CG_DISPATCH(prec, (k_cg_normal_rows<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)p, (T*)q, autoc, (const T*)mask, lam,
+    CG_DISPATCH(prec, (k_cg_normal_rows<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)p, (T*)q, autoc, mbits, bw, lam,
                                                                    ntap, b, S / b, part)));
   else
-    CG_DISPATCH(prec, (k_cg_normal<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)p, (T*)q, autoc, (const T*)mask, lam,
-                                                              ntap, b, S, part)));
+    CG_DISPATCH(prec, (k_cg_normal<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)p, (T*)q, autoc, mbits, bw, lam, ntap,
+                                                              b, S, part)));
   return hipGetLastError();
 }
 
-hipError_t launch_cg_rhs(int prec, const void* d, void* rhs, const double* win64, const void* mask,
+hipError_t launch_cg_rhs(int prec, const void* d, void* rhs, const double* win64, const uint32_t* mbits,
                          const void* prior, double lam, int N, int ntap, int64_t b, int64_t S, hipStream_t st) {
+  const int64_t bw = (b + 31) / 32;
   if (ntap - 1 <= kCgHMAX && b > 0)
-    CG_DISPATCH(prec, (k_cg_rhs_rows<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)d, (T*)rhs, win64, (const T*)mask,
+    CG_DISPATCH(prec, (k_cg_rhs_rows<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)d, (T*)rhs, win64, mbits, bw,
                                                                 (const T*)prior, lam, N, ntap, b, S / b)));
   else
-    CG_DISPATCH(prec, (k_cg_rhs<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)d, (T*)rhs, win64, (const T*)mask,
+    CG_DISPATCH(prec, (k_cg_rhs<T><<<kCgNWG, kCgNT, 0, st>>>((const T*)d, (T*)rhs, win64, mbits, bw,
                                                              (const T*)prior, lam, N, ntap, b, S)));
   return hipGetLastError();
 }
@@ -368,8 +395,8 @@ hipError_t launch_cg_scalar(const double* part, int mode, double* sc, double* re
   return hipGetLastError();
 }
 
-hipError_t launch_mask_to_T(int prec, const uint8_t* m, void* out, int64_t S, hipStream_t st) {
-  CG_DISPATCH(prec, (k_mask_to_T<T><<<kCgNWG, kCgNT, 0, st>>>(m, (T*)out, S)));
+hipError_t launch_maskbits_transpose(const uint32_t* in, int N, int64_t b, uint32_t* out, hipStream_t st) {
+  k_maskbits_transpose<<<kCgNWG, kCgNT, 0, st>>>(in, N, b, (b + 31) / 32, out);
   return hipGetLastError();
 }
 

@@ -92,10 +92,12 @@ __device__ __forceinline__ void pair_gains(const NatGain& ga, cx<double> Wa, cx<
 
 // The other filters at frequency f in [0, b/2] (the same gain for both paths' formula):
 // threshold: G = W / |W|^2 / b where |W|^2 >= tau^2, else 0;
-// noise-to-signal: G = W c / (|W|^2 + nu_f) / b, c = 1 + nu_f or 1.
+// noise-to-signal: G = W c / (|W|^2 + nu_f) / b, c = 1 + nu_f or 1, set to 0
+// where |W|^2 + nu_f is at rounding level against the squared tap magnitude
+// sum (wsa, wsc), as the naive inverse truncates (nu_f = 0 at a zero of W).
 template <int GK>
 __device__ __forceinline__ void pair_gains_kind(const NatGain& ga, cx<double> Wa, cx<double> Wc, int f,
-                                                cx<double>& Ga, cx<double>& Gc) {
+                                                double wsa, double wsc, cx<double>& Ga, cx<double>& Gc) {
   const double aa = Wa.x * Wa.x + Wa.y * Wa.y, ac = Wc.x * Wc.x + Wc.y * Wc.y;
   double sa, sc;
   if constexpr (GK == kGainThreshold) {
@@ -104,8 +106,9 @@ __device__ __forceinline__ void pair_gains_kind(const NatGain& ga, cx<double> Wa
   } else {
     const double v = ga.nu[f];
     const double c = (ga.norm ? 1.0 + v : 1.0) * ga.gnorm;
-    sa = c / (aa + v);
-    sc = c / (ac + v);
+    const double da = aa + v, dc = ac + v;
+    sa = (da <= 1e-24 * wsa * wsa) ? 0.0 : c / da;
+    sc = (dc <= 1e-24 * wsc * wsc) ? 0.0 : c / dc;
   }
   Ga = mk<double>(Wa.x * sa, Wa.y * sa);
   Gc = mk<double>(Wc.x * sc, Wc.y * sc);
@@ -234,7 +237,7 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * N
     hc[r] = (NTAP > 0 && valid) ? ga.win[(int64_t)r * N + nc] : 0.0;
   }
   double wsa = 0.0, wsc = 0.0;
-  if (ga.naive && valid) {
+  if ((ga.naive || GK == kGainNu) && valid) {
     for (int r = 0; r < ga.ntap; ++r) {
       wsa += fabs(ga.win[(int64_t)r * N + na]);
       wsc += fabs(ga.win[(int64_t)r * N + nc]);
@@ -261,7 +264,7 @@ __global__ __launch_bounds__((NatCfg<T>::clampnt(((1 << LOG2B1) > 1 ? 2 : 1) * N
       // the item's frequency: row k1 of its set (b1/2 for the second set of
       // kk = 0) plus b1 k2, folded to [0, b/2] (the filter is even in f)
       const int f = ((NS == 2 && kk == 0 && sk == 1) ? B1 / 2 : ka) + B1 * k2;
-      pair_gains_kind<GK>(ga, Wa, Wc, f <= B - f ? f : B - f, Ga, Gc);
+      pair_gains_kind<GK>(ga, Wa, Wc, f <= B - f ? f : B - f, wsa, wsc, Ga, Gc);
     }
   };
   // FP32 form with 4 taps: the first NPRE gains of this thread are formed

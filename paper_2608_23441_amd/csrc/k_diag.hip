@@ -81,24 +81,59 @@ hipError_t launch_delta_analytic(const double* win64, int N, int ntap, int64_t n
   return hipGetLastError();
 }
 
-// mask[j N + n] = 1 for j = 0 mod R and n0 <= n < n1, else 0
-__global__ __launch_bounds__(256) void k_mask_structured(uint8_t* __restrict__ mask, int N, int64_t S, int R, int n0,
+// Bitmasks are built a wavefront at a time: lane l of the wavefront that
+// starts at sample e0 (a multiple of 64) decides sample e0 + l, the ballot
+// gathers the 64 decisions, and lanes 0 and 32 store the two 32-bit words
+// (bits past the last sample are 0).
+__device__ __forceinline__ void store_ballot(bool bit, int64_t e0, int64_t nwords, uint32_t* __restrict__ bits) {
+  const unsigned long long m = __ballot(bit);
+  const int lane = threadIdx.x & 63;
+  const int64_t w = (e0 >> 5) + (lane >> 5);
+  if ((lane & 31) == 0 && w < nwords) bits[w] = (uint32_t)(lane ? (m >> 32) : m);
+}
+
+// bit e = j N + n set for j = 0 mod R and n0 <= n < n1
+__global__ __launch_bounds__(256) void k_mask_structured(uint32_t* __restrict__ bits, int N, int64_t S, int R, int n0,
                                                          int n1) {
-  const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < S; i += stride) {
-    const int64_t j = i / N;
-    const int n = (int)(i - j * N);
-    mask[i] = (j % R == 0 && n >= n0 && n < n1) ? 1 : 0;
+  const int64_t nwords = (S + 31) / 32;
+  const int64_t span = (int64_t)gridDim.x * 256;
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < S; base += span) {  // uniform per workgroup
+    const int64_t i = base + threadIdx.x;
+    bool bit = false;
+    if (i < S) {
+      const int64_t j = i / N;
+      const int n = (int)(i - j * N);
+      bit = j % R == 0 && n >= n0 && n < n1;
+    }
+    store_ballot(bit, base + (threadIdx.x & ~63), nwords, bits);
   }
 }
 
-hipError_t launch_mask_structured(uint8_t* mask, int N, int64_t nblock, int R, int L, hipStream_t st) {
+hipError_t launch_mask_structured(uint32_t* bits, int N, int64_t nblock, int R, int L, hipStream_t st) {
   const int64_t S = (int64_t)N * nblock;
   if (S <= 0) return hipSuccess;
   int64_t blocks = (S + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   const int n0 = N / 2 - L / 2;
-  k_mask_structured<<<dim3((unsigned)blocks), 256, 0, st>>>(mask, N, S, R, n0, n0 + L);
+  k_mask_structured<<<dim3((unsigned)blocks), 256, 0, st>>>(bits, N, S, R, n0, n0 + L);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_mask_pack(const uint8_t* __restrict__ mask, int64_t S,
+                                                   uint32_t* __restrict__ bits) {
+  const int64_t nwords = (S + 31) / 32;
+  const int64_t span = (int64_t)gridDim.x * 256;
+  for (int64_t base = (int64_t)blockIdx.x * 256; base < S; base += span) {
+    const int64_t i = base + threadIdx.x;
+    store_ballot(i < S && mask[i] != 0, base + (threadIdx.x & ~63), nwords, bits);
+  }
+}
+
+hipError_t launch_mask_pack(const uint8_t* mask, int64_t S, uint32_t* bits, hipStream_t st) {
+  if (S <= 0) return hipSuccess;
+  int64_t blocks = (S + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  k_mask_pack<<<dim3((unsigned)blocks), 256, 0, st>>>(mask, S, bits);
   return hipGetLastError();
 }
 

@@ -129,8 +129,10 @@ __global__ __launch_bounds__(256) void k_power_partial(const cx<T>* __restrict__
   part[(int64_t)c * nchan + k] = acc;
 }
 
-__global__ __launch_bounds__(256) void k_power_final(const double* __restrict__ part, int nchunks, int nchan,
-                                                     double mult, double* __restrict__ out) {
+// out may alias part's first row (the quantiser's scales reuse it): thread k
+// reads only column k and writes out[k] after its last read, so no restrict.
+__global__ __launch_bounds__(256) void k_power_final(const double* part, int nchunks, int nchan, double mult,
+                                                     double* out) {
   const int k = blockIdx.x * 256 + threadIdx.x;
   if (k >= nchan) return;
   double acc = 0.0;

@@ -83,9 +83,10 @@ hipError_t launch_col_wiener_nat(int prec, int log2b, int pass, void* z, int lbl
 
 // Maximum-likelihood CG pieces (vectors in the transposed layout [N][b]).
 hipError_t launch_cg_autocorr(const double* win64, int N, int ntap, double* autoc, hipStream_t st);
-hipError_t launch_cg_normal(int prec, const void* p, void* q, const double* autoc, const void* mask, double lam,
-                            int ntap, int64_t b, int64_t S, double* part, hipStream_t st);
-hipError_t launch_cg_rhs(int prec, const void* d, void* rhs, const double* win64, const void* mask,
+// mbits: the prior mask transposed to rows of ceil(b/32) words (bit j of row n)
+hipError_t launch_cg_normal(int prec, const void* p, void* q, const double* autoc, const uint32_t* mbits,
+                            double lam, int ntap, int64_t b, int64_t S, double* part, hipStream_t st);
+hipError_t launch_cg_rhs(int prec, const void* d, void* rhs, const double* win64, const uint32_t* mbits,
                          const void* prior, double lam, int N, int ntap, int64_t b, int64_t S, hipStream_t st);
 hipError_t launch_cg_resid(int prec, const void* rhs, const void* q, void* r, int64_t S, double* part,
                            hipStream_t st);
@@ -95,7 +96,8 @@ hipError_t launch_cg_xr(int prec, void* x, void* r, const void* p, const void* q
 hipError_t launch_cg_p(int prec, void* p, const void* z, const double* sc, int use_beta, int64_t S,
                        hipStream_t st);
 hipError_t launch_cg_scalar(const double* part, int mode, double* sc, double* resid, int k, hipStream_t st);
-hipError_t launch_mask_to_T(int prec, const uint8_t* m, void* out, int64_t S, hipStream_t st);
+// time-order bitmask (bit e = sample j N + n) -> transposed rows of ceil(b/32) words
+hipError_t launch_maskbits_transpose(const uint32_t* in, int N, int64_t b, uint32_t* out, hipStream_t st);
 constexpr int kCgParts = 1024;
 
 // Tunable shape of the Bluestein column path for one convolution length
@@ -157,8 +159,11 @@ hipError_t launch_ratio(const double* num, const double* den, double* out, int n
 hipError_t launch_delta_analytic(const double* win64, int N, int ntap, int64_t nfreq, double phi, double snr,
                                  double* out, hipStream_t st);
 
-// the structured prior mask: 1 at frames j = 0 mod R of paths [N/2 - L/2, N/2 + L/2)
-hipError_t launch_mask_structured(uint8_t* mask, int N, int64_t nblock, int R, int L, hipStream_t st);
+// the structured prior mask as a time-order bitmask of ceil(S/32) words: bit
+// e = j N + n set at frames j = 0 mod R of paths [N/2 - L/2, N/2 + L/2)
+hipError_t launch_mask_structured(uint32_t* bits, int N, int64_t nblock, int R, int L, hipStream_t st);
+// one byte per sample (nonzero = saved) -> time-order bitmask of ceil(S/32) words
+hipError_t launch_mask_pack(const uint8_t* mask, int64_t S, uint32_t* bits, hipStream_t st);
 
 // bytes zero bytes at p (a kernel, so that it may sit in a captured graph)
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);

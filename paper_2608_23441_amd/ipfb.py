@@ -30,7 +30,7 @@ EXPORTS = (
     "ipfb_batched_use_graph", "ipfb_wiener_batched", "ipfb_batched_get_shape",
     "ipfb_batched_set_shape", "ipfb_batched_tune", "ipfb_stream_plan_create", "ipfb_stream_plan_destroy",
     "ipfb_wiener_stream", "ipfb_delta_analytic", "ipfb_autospectrum_error", "ipfb_mask_structured",
-    "ipfb_wiener_filter",
+    "ipfb_wiener_filter", "ipfb_mask_pack",
 )
 FILTER_WIENER, FILTER_THRESHOLD, FILTER_NU = 0, 1, 2
 
@@ -83,6 +83,7 @@ def lib():
         L.ipfb_delta_analytic.argtypes = [vp, i64, dbl, dbl, vp, vp]
         L.ipfb_autospectrum_error.argtypes = [vp, vp, vp, vp, vp]
         L.ipfb_mask_structured.argtypes = [vp, i32, i32, vp, vp]
+        L.ipfb_mask_pack.argtypes = [vp, i64, vp, vp]
         L.ipfb_wiener_filter.argtypes = [vp, i32, vp, vp, i32, dbl, vp, i32, vp, vp]
         L.ipfb_profile_enable.argtypes = [i32]
         L.ipfb_profile_reset.argtypes = []
@@ -292,13 +293,14 @@ def _spec_fmt(plan, spec, chan_scale):
 def ml_cg(plan: Plan, spec, chan_scale, mask, prior, lam: float = 1.0, phi_x0: float = 0.1,
           phi_precond: float = 0.1, iters: int = 100, x_init=None, x_out=None, resid=True, stream=None):
     """Maximum-likelihood reconstruction with a time-domain prior (PCG).
-    mask: uint8 [S] (time order); prior: real [S] in the plan precision.
-    Returns (x, residual norms [iters+1] float64 or None)."""
+    mask: the bitmask of ceil(S/32) 32-bit words (int32 tensor; see
+    mask_pack), bit e for time-order sample e; prior: real [S] in the plan
+    precision. Returns (x, residual norms [iters+1] float64 or None)."""
     import torch
     fmt = _spec_fmt(plan, spec, chan_scale)
     S = plan.nblock * plan.lblock
-    if mask.dtype != torch.uint8 or mask.numel() != S:
-        raise ValueError("mask: uint8 [nblock*lblock]")
+    if mask.dtype != torch.int32 or mask.numel() != (S + 31) // 32:
+        raise ValueError("mask: int32 [ceil(nblock*lblock/32)] bitmask words")
     if x_out is None:
         x_out = _empty((S,), plan.real_dtype)
     norms = _empty((iters + 1,), torch.float64) if resid else None
@@ -341,11 +343,29 @@ def quantize_c4(plan: Plan, y, levels_rms: float = 2.5, stream=None):
 
 
 def mask_structured(plan: Plan, R: int, L: int, out=None, stream=None):
-    """The structured prior mask (uint8 [nblock * lblock] on the GPU)."""
+    """The structured prior mask as ml_cg's bitmask (int32 [ceil(S/32)] words on the GPU)."""
     import torch
+    nw = (plan.nblock * plan.lblock + 31) // 32
     if out is None:
-        out = _empty((plan.nblock * plan.lblock,), torch.uint8)
+        out = _empty((nw,), torch.int32)
+    if out.dtype != torch.int32 or out.numel() != nw:
+        raise ValueError("out: int32 [ceil(nblock*lblock/32)]")
     _check(lib().ipfb_mask_structured(plan.handle, int(R), int(L), _ptr(out, "mask"), _stream(stream)))
+    return out
+
+
+def mask_pack(mask, out=None, stream=None):
+    """Byte-per-sample mask (uint8 or bool [S] on the GPU, nonzero = saved) to
+    ml_cg's bitmask (int32 [ceil(S/32)] words)."""
+    import torch
+    if mask.dtype not in (torch.uint8, torch.bool):
+        raise ValueError("mask: uint8 or bool")
+    S = mask.numel()
+    if out is None:
+        out = _empty(((S + 31) // 32,), torch.int32)
+    if out.dtype != torch.int32 or out.numel() != (S + 31) // 32:
+        raise ValueError("out: int32 [ceil(S/32)]")
+    _check(lib().ipfb_mask_pack(_ptr(mask, "mask"), int(S), _ptr(out, "bits"), _stream(stream)))
     return out
 
 

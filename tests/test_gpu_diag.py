@@ -7,6 +7,7 @@ import pytest
 from oracle import ipfb_oracle as O
 from paper_2608_23441_amd import inputs as I
 from paper_2608_23441_amd import ipfb
+from maskbits import pack_bits, unpack_bits
 
 pytestmark = pytest.mark.gpu
 
@@ -59,8 +60,22 @@ def test_autospectrum_error_matches_oracle(prec, tol, Nf, bf):
                                      (16, 5, 1, 16), (16, 4, 2, 0)])
 def test_mask_structured_matches_oracle(N, b, R, L):
     plan = ipfb.Plan(N, 4, O.window_sinc_hamming(4, N), b, ipfb.F32)
-    got = _host(ipfb.mask_structured(plan, R, L))
-    assert np.array_equal(got, O.structured_mask(N, b, R, L))
+    words = _host(ipfb.mask_structured(plan, R, L))
+    assert words.size == (N * b + 31) // 32
+    assert np.array_equal(unpack_bits(words, N * b), O.structured_mask(N, b, R, L).astype(bool))
+    # bits past the last sample are zero
+    assert np.array_equal(words, pack_bits(O.structured_mask(N, b, R, L)))
+
+
+# The byte-to-bit packer: ragged lengths (not a multiple of 32 or 64), a
+# whole-wavefront length, one sample, and a length past one grid sweep.
+@pytest.mark.parametrize("S", [1, 31, 33, 64, 100, 4097, 8192 * 256 + 77])
+def test_mask_pack_bit_exact(S):
+    m = I.random_mask(S, 0.3, 40 + S % 1000)
+    words = _host(ipfb.mask_pack(_dev(m.astype(np.uint8))))
+    assert np.array_equal(words, pack_bits(m))
+    words_b = _host(ipfb.mask_pack(_dev(m)))  # bool input, same bytes
+    assert np.array_equal(words_b, words)
 
 
 @pytest.mark.parametrize("prec,tol", [(ipfb.F64, 1e-6), (ipfb.F32, 2e-4)])

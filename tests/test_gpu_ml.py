@@ -6,6 +6,7 @@ import pytest
 from oracle import ipfb_oracle as O
 from paper_2608_23441_amd import inputs as I
 from paper_2608_23441_amd import ipfb
+from maskbits import pack_bits
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +47,7 @@ def test_ml_cg_fp64_matches_oracle(N, b, iters):
     x0 = O.column_inverse(d, w, N, p, 0.1).reshape(-1)
     ref_x, ref_n = O.ml_pcg(d, w, N, p, mask, x, 1.0, 0.1, iters, x0)
     plan = ipfb.Plan(N, p, w, b, ipfb.F64)
-    xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(mask.astype(np.uint8)), _dev(x), 1.0, 0.1, 0.1, iters)
+    xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(pack_bits(mask)), _dev(x), 1.0, 0.1, 0.1, iters)
     xg, ng = _host(xg), _host(ng)
     # residual histories agree while the residual is well above rounding
     # (once |r_k| nears 1e-7 |r_0| CG's rounding, which differs in summation
@@ -73,7 +74,7 @@ def test_ml_cg_ci8_matches_oracle():
     x0 = O.column_inverse(d, w, N, p, 0.1).reshape(-1)
     ref_x, ref_n = O.ml_pcg(d, w, N, p, mask, x, 1.0, 0.1, iters, x0)
     plan = ipfb.Plan(N, p, w, b, ipfb.F64)
-    xg, ng = ipfb.ml_cg(plan, _dev(O.pack_ci8(qr, qi)), _dev(s), _dev(mask.astype(np.uint8)), _dev(x), 1.0, 0.1,
+    xg, ng = ipfb.ml_cg(plan, _dev(O.pack_ci8(qr, qi)), _dev(s), _dev(pack_bits(mask)), _dev(x), 1.0, 0.1,
                         0.1, iters)
     xg, ng = _host(xg), _host(ng)
     k = ref_n > 1e-4 * ref_n[0]
@@ -91,7 +92,7 @@ def test_ml_cg_bitwise_deterministic():
     plan = ipfb.Plan(N, p, w, b, ipfb.F32)
     runs = []
     for _ in range(2):
-        xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(mask.astype(np.uint8)),
+        xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(pack_bits(mask)),
                             _dev(x).to(torch.float32), 1.0, 0.1, 0.1, 20)
         runs.append((_host(xg).copy(), _host(ng).copy()))
     assert np.array_equal(runs[0][0].view(np.uint8), runs[1][0].view(np.uint8))
@@ -102,7 +103,7 @@ def test_ml_cg_zero_iterations_is_wiener():
     N, p, b = 64, 4, 32
     w, x, packed, s, mask, d = _ml_case(N, p, b, 310)
     plan = ipfb.Plan(N, p, w, b, ipfb.F64)
-    xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(mask.astype(np.uint8)), _dev(x), 1.0, 0.1, 0.1, 0)
+    xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(pack_bits(mask)), _dev(x), 1.0, 0.1, 0.1, 0)
     xw = ipfb.ipfb_wiener(plan, _dev(packed), _dev(s), 0.1)
     # the same Wiener estimate through two column-stage layouts: equal up to
     # FP64 rounding order
@@ -119,7 +120,7 @@ def test_ml_cg_toy_model_one_saved_sample():
     mask = np.zeros(N * b, dtype=np.uint8)
     mask[3 * N + N // 2] = 1
     plan = ipfb.Plan(N, p, w, b, ipfb.F64)
-    xg, ng = ipfb.ml_cg(plan, _dev(y), None, _dev(mask), _dev(x), 1.0, 0.1, 0.1, 80)
+    xg, ng = ipfb.ml_cg(plan, _dev(y), None, _dev(pack_bits(mask)), _dev(x), 1.0, 0.1, 0.1, 80)
     assert np.abs(_host(xg) - x).max() < 1e-8
 
 
@@ -132,7 +133,7 @@ def test_ml_cg_fp32_form():
     x0 = O.column_inverse(d, w, N, p, 0.1).reshape(-1)
     ref_x, ref_n = O.ml_pcg(d, w, N, p, mask, x, 1.0, 0.1, iters, x0)
     plan = ipfb.Plan(N, p, w, b, ipfb.F32)
-    xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(mask.astype(np.uint8)),
+    xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(pack_bits(mask)),
                         _dev(x.astype(np.float32)), 1.0, 0.1, 0.1, iters)
     xg, ng = _host(xg), _host(ng)
     err = _rel(xg.astype(np.float64), ref_x)
@@ -149,9 +150,9 @@ def test_ml_cg_rejects_bad_arguments():
     w, x, packed, s, mask, d = _ml_case(N, p, b, 330)
     plan = ipfb.Plan(N, p, w, b, ipfb.F64)
     with pytest.raises(ipfb.IpfbError):
-        ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(mask.astype(np.uint8)), _dev(x), 1.0, 0.1, 0.0, 5)
+        ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(pack_bits(mask)), _dev(x), 1.0, 0.1, 0.0, 5)
     with pytest.raises(ipfb.IpfbError):
-        ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(mask.astype(np.uint8)), _dev(x), -1.0, 0.1, 0.1, 5)
+        ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(pack_bits(mask)), _dev(x), -1.0, 0.1, 0.1, 5)
 
 
 # --- F3: autograd through the forward PFB ------------------------------------------
@@ -201,7 +202,7 @@ def test_ml_cg_reads_no_workspace_before_writing_it(prec):
     torch.cuda.empty_cache()
     plan = ipfb.Plan(N, p, w, b, prec)
     dt = torch.float64 if prec == ipfb.F64 else torch.float32
-    xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(mask.astype(np.uint8)), _dev(x).to(dt), 1.0, 0.1, 0.1, 3)
+    xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(pack_bits(mask)), _dev(x).to(dt), 1.0, 0.1, 0.1, 3)
     assert np.all(np.isfinite(_host(xg))) and np.all(np.isfinite(_host(ng)))
 
 
@@ -214,6 +215,6 @@ def test_ml_cg_long_columns_take_the_separate_dot_product():
     x0 = O.column_inverse(d, w, N, p, 0.1).reshape(-1)
     ref_x, ref_n = O.ml_pcg(d, w, N, p, mask, x, 1.0, 0.1, iters, x0)
     plan = ipfb.Plan(N, p, w, b, ipfb.F64)
-    xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(mask.astype(np.uint8)), _dev(x), 1.0, 0.1, 0.1, iters)
+    xg, ng = ipfb.ml_cg(plan, _dev(packed), _dev(s), _dev(pack_bits(mask)), _dev(x), 1.0, 0.1, 0.1, iters)
     assert np.max(np.abs(_host(ng) - ref_n) / ref_n) < 1e-9
     assert _rel(_host(xg), ref_x) < 1e-9

@@ -1,0 +1,62 @@
+"""The ML form at the workload's own shape: lblock 2048, ntap 4, nblock 8192
+(2^24 samples), 4-bit spectra, a random 10 % prior mask, FP32 vectors with
+FP64 dots and norms, 100 PCG iterations from the Wiener solution with the
+Wiener preconditioner (Section 4.2). The FP64 oracle needs minutes for this
+solve, so its run is stored by tests/golden/make_ml_pcg_workload.py (residual
+norms of every iteration, |x_100| and x_100 at 1024 seeded positions); the
+inputs are regenerated here from the same seeds.
+
+FP32 and FP64 CG trajectories part once the FP32 residual reaches its
+rounding floor, so the residual histories are compared while the oracle's
+residual is above 1e-4 |r_0| and x_100 against the oracle's x_100."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from maskbits import pack_bits
+from oracle import ipfb_oracle as O
+from paper_2608_23441_amd import inputs as I
+from paper_2608_23441_amd import ipfb
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+
+GOLD_PATH = os.path.join(os.path.dirname(__file__), "golden", "ml_pcg_workload.json")
+
+
+def test_ml_cg_workload_shape_against_stored_oracle():
+    GOLD = json.load(open(GOLD_PATH))
+    N, p, b, iters, phi = GOLD["lblock"], GOLD["ntap"], GOLD["nblock"], GOLD["iters"], GOLD["phi"]
+    S = N * b
+    print(f"case ml_cg workload N={N} b={b} iters={iters} f32", flush=True)
+    w = O.window_sinc_hamming(p, N)
+    x = I.gaussian_timestream(S, GOLD["signal_seed"])
+    y = O.pfb_forward(x, w, N, p)
+    s = O.channel_scales(y, GOLD["levels_rms"])
+    packed = O.pack_c4(*O.quantize(y, s))
+    del y
+    mask = I.random_mask(S, GOLD["mask_fraction"], GOLD["mask_seed"])
+    plan = ipfb.Plan(N, p, w, b, ipfb.F32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    xg, ng = ipfb.ml_cg(plan, dev(packed), dev(s), dev(pack_bits(mask)), dev(x.astype(np.float32)),
+                        GOLD["lambda"], phi, phi, iters)
+    torch.cuda.synchronize()
+    xg = xg.cpu().numpy().astype(np.float64)
+    ng = ng.cpu().numpy()
+    ref_n = np.asarray(GOLD["resid_norms"])
+    idx = np.asarray(GOLD["sample_idx"])
+    ref_x = np.asarray(GOLD["x_samples"])
+    k = ref_n > 1e-4 * ref_n[0]
+    e_hist = float(np.max(np.abs(ng[k] - ref_n[k]) / ref_n[k]))
+    e_x = float(np.linalg.norm(xg[idx] - ref_x) / np.linalg.norm(ref_x))
+    e_norm = abs(float(np.linalg.norm(xg)) - GOLD["x_norm"]) / GOLD["x_norm"]
+    print(f"residual history (first {int(k.sum())} iterations) max rel {e_hist:.3e}; "
+          f"x_100 at {idx.size} samples rel RMS {e_x:.3e}; |x_100| rel {e_norm:.3e}; "
+          f"|r_100| gpu {ng[-1]:.3e} oracle {ref_n[-1]:.3e}", flush=True)
+    assert int(k.sum()) >= 10
+    assert e_hist < 1e-3
+    assert e_x < 1e-4 and e_norm < 1e-5
+    assert ng[-1] < 1e-5 * ng[0]

@@ -7,12 +7,15 @@ import pytest
 from oracle import ipfb_oracle as O
 from paper_2608_23441_amd import inputs as I
 from paper_2608_23441_amd import ipfb
+from parity_metrics import worst_column_rel
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
 TOL = {ipfb.F64: 1e-12, ipfb.F32: 1e-5}
+# worst single sub-filter path (column of the frame matrix)
+TOL_COL = {ipfb.F64: 1e-11, ipfb.F32: 1e-4}
 
 
 def _rel(a, b):
@@ -51,8 +54,11 @@ def test_ipfb_wiener_c4(prec, N, p, b, phi):
     w, x, y, packed, s = _quantised_case(N, p, b, 100 + N + b)
     ref = O.ipfb_wiener(packed, s, w, N, p, phi)
     plan = ipfb.Plan(N, p, w, b, prec)
-    out = ipfb.ipfb_wiener(plan, _dev(packed), _dev(s), phi)
-    assert _rel(_host(out), ref) < TOL[prec]
+    out = _host(ipfb.ipfb_wiener(plan, _dev(packed), _dev(s), phi))
+    ec, nc = worst_column_rel(out.astype(np.float64), ref, N)
+    print(f"rel RMS {_rel(out, ref):.3e}, worst path {ec:.3e} at n={nc}", flush=True)
+    assert _rel(out, ref) < TOL[prec]
+    assert ec < TOL_COL[prec]
 
 
 # The longest frames the inverse takes (lblock 2^15 in FP32, 2^14 in FP64),
@@ -367,3 +373,29 @@ def test_ipfb_other_filters_match_oracle(prec, tol, N, p, b):
             ref = Ox.column_inverse_filter(d, w, N, p, okind, oparam, nu_full, norm).reshape(-1)
         err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         assert err < (tol if kind != ipfb.FILTER_THRESHOLD else 10 * tol), (kind, norm, err)
+
+
+# nu = 0 at every frequency with Appendix A's exactly symmetric window: the
+# eigenvalue of path N/2 at f = b/2 is exactly zero; the filter drops it as the
+# naive inverse does (finite output equal to the oracle's), and a zero
+# threshold, which would keep it, is rejected before anything runs.
+@pytest.mark.parametrize("prec,tol", [(ipfb.F64, 1e-11), (ipfb.F32, 1e-5)])
+@pytest.mark.parametrize("b", [64, 1024])
+def test_filter_zero_nu_at_an_exact_zero_eigenvalue(prec, tol, b):
+    N, p = 64, 4
+    print(f"case filter nu=0 symmetric window prec={prec} b={b}", flush=True)
+    w = O.window_symmetric_hann(p, N)
+    assert abs(O.column_spectra(w, N, p, b)[b // 2, N // 2]) < 1e-14
+    y = I.complex_block((b, N // 2 + 1), 960 + b)
+    d = O.row_inverse(y, N)
+    ref = O.column_inverse_filter(d, w, N, p, "psd", 0.0, np.zeros(b), True).reshape(-1)
+    plan = ipfb.Plan(N, p, w, b, prec)
+    cdt = torch.complex128 if prec == ipfb.F64 else torch.complex64
+    yt = torch.from_numpy(y).to(cdt).cuda()
+    got = _host(ipfb.wiener_filter(plan, yt, None, ipfb.FILTER_NU, 0.0,
+                                   torch.zeros(b // 2 + 1, dtype=torch.float64, device="cuda")))
+    assert np.all(np.isfinite(got))
+    assert _rel(got.astype(np.float64), ref) < tol
+    with pytest.raises(ipfb.IpfbError) as err:
+        ipfb.wiener_filter(plan, yt, None, ipfb.FILTER_THRESHOLD, 0.0, None)
+    assert err.value.status == ipfb.EINVAL

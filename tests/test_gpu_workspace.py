@@ -7,6 +7,7 @@ import pytest
 from oracle import ipfb_oracle as O
 from paper_2608_23441_amd import inputs as I
 from paper_2608_23441_amd import ipfb
+from maskbits import pack_bits
 
 pytestmark = pytest.mark.gpu
 
@@ -52,7 +53,7 @@ def test_caller_workspace_matches_own_workspace(prec, N, b):
         torch.cuda.synchronize()
         assert torch.equal(got, ref), fill
     if (b & (b - 1)) == 0:  # ML-CG also runs on the workspace (power-of-two b)
-        mask = _dev(I.random_mask(N * b, 0.1, 7).astype(np.uint8))
+        mask = _dev(pack_bits(I.random_mask(N * b, 0.1, 7)))
         prior = _dev(x).to(ref.dtype)
         xa, na = ipfb.ml_cg(own, pk, sc, mask, prior, 1.0, 0.1, 0.1, 5)
         xb, nb = ipfb.ml_cg(plan, pk, sc, mask, prior, 1.0, 0.1, 0.1, 5)

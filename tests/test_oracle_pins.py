@@ -553,3 +553,18 @@ def test_psd_filter_is_a_dense_map_solve_and_reduces_to_wiener():
         assert np.abs(got[:, n] - ref).max() < 1e-10
     const = O.column_inverse_filter(d, w, N, p, "psd", nu=np.full(b, 0.09))
     assert np.abs(const - O.column_inverse(d, w, N, p, 0.3)).max() < 1e-12
+
+
+# --- the noise-to-signal filter at nu = 0 is the truncated naive inverse -------
+@pytest.mark.parametrize("window", ["sinc_hamming", "symmetric_hann"])
+def test_psd_filter_with_zero_nu_is_the_naive_inverse(window):
+    # with nu = 0 the filter is H = 1, i.e. G = 1/conj(W) (Section 3.1), and an
+    # exact zero eigenvalue (Appendix A's symmetric window, path N/2 at f = b/2)
+    # is dropped as the naive inverse drops it, not divided by
+    N, p, b = 16, 4, 8
+    w = getattr(O, "window_" + window)(p, N)
+    d = np.random.default_rng(33).standard_normal((b, N))
+    got = O.column_inverse_filter(d, w, N, p, "psd", nu=np.zeros(b))
+    ref = O.column_inverse(d, w, N, p, 0.0)
+    assert np.all(np.isfinite(got))
+    assert np.abs(got - ref).max() < 1e-12 * np.abs(ref).max()
