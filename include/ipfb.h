@@ -222,6 +222,24 @@ int ipfb_ml_cg(ipfb_plan plan, int infmt, const void* spec, const float* chan_sc
                const void* prior, double lambda, double phi_x0, double phi_precond, int iters,
                const void* x_init, void* x_out, double* resid_norms, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve
+ * of ipfb_ml_cg, with the same arguments and the same results, whose CG
+ * buffers live in a static device array of 64 MiB per device instead of a
+ * workspace allocated by the plan. It calls no allocator (the plan, created
+ * beforehand, keeps its own tables and frame buffers). The solve must fit the
+ * array: 7 vectors of S reals, the mask bits and small tables, i.e. S up to
+ * 2^21 samples for F32 plans and 2^20 for F64 plans at power-of-two shapes;
+ * larger plans return IPFB_EUNSUPPORTED with the sizes in the message. Every
+ * call on one device shares that device's array and leaves its contents
+ * behind (nothing in it needs to start at zero: every buffer is written
+ * before it is read), so calls that overlap on one device, from other
+ * streams or threads, race and must be serialised by the caller. The first
+ * call on a device looks up the array's address there (no allocation). */
+int ipfb_ml_cg_noalloc(ipfb_plan plan, int infmt, const void* spec, const float* chan_scale, const uint32_t* mask,
+                       const void* prior, double lambda, double phi_x0, double phi_precond, int iters,
+                       const void* x_init, void* x_out, double* resid_norms, void* stream);
+
 /* Autospectrum alone: autospec[k] = (1/nspec) sum_j |y_jk|^2 (double). */
 int ipfb_autospectrum(ipfb_plan plan, const void* y, double* autospec, void* stream);
 

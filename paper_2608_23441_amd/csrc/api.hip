@@ -804,6 +804,36 @@ hipError_t ml_cg_enqueue(ipfb_plan p, const CgBufs& c, int infmt, const void* sp
   return e;
 }
 
+// ---- the entry point for callers that cannot allocate ------------------------
+// One file-scope device array holds every buffer of ipfb_ml_cg_noalloc's
+// solve. Each device the library runs on has its own copy at its own address,
+// found once per device with hipGetSymbolAddress; host code uses only those
+// addresses, never the array's name (which on the host is a stand-in, not a
+// device address).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of the scratch array (dev must be current).
+int scratch_ptr(int dev, char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(IPFB_EUNSUPPORTED, "device %d beyond the scratch table", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      hipGetLastError();
+      return fail(IPFB_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = (char*)g_scratch_ptr[dev];
+  return IPFB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -822,6 +852,28 @@ int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale
   return launched(ml_cg_enqueue(p, c, infmt, spec, chan_scale, mask, prior, lam, phi_x0, phi_precond, iters, x_init,
                                 x_out, resid_norms, (hipStream_t)stream),
                   "ipfb_ml_cg");
+}
+
+int ipfb_ml_cg_noalloc(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, const uint32_t* mask,
+                       const void* prior, double lam, double phi_x0, double phi_precond, int iters,
+                       const void* x_init, void* x_out, double* resid_norms, void* stream) {
+  if (int s = ml_cg_check(p, infmt, spec, chan_scale, mask, prior, lam, phi_x0, phi_precond, iters, x_out))
+    return s;
+  const size_t need = cg_layout(p, nullptr, nullptr);
+  if (need > kNoAllocScratchBytes)
+    return fail(IPFB_EUNSUPPORTED,
+                "ipfb_ml_cg_noalloc: this plan's solve needs %zu bytes of scratch, more than the %zu available "
+                "(at most about %zu samples in this precision); use ipfb_ml_cg",
+                need, kNoAllocScratchBytes,
+                kNoAllocScratchBytes / (7 * esize(p->prec) + 1));
+  DeviceGuard g(p->dev);
+  char* base = nullptr;
+  if (int s = scratch_ptr(p->dev, &base)) return s;
+  CgBufs c;
+  cg_layout(p, base, &c);
+  return launched(ml_cg_enqueue(p, c, infmt, spec, chan_scale, mask, prior, lam, phi_x0, phi_precond, iters, x_init,
+                                x_out, resid_norms, (hipStream_t)stream),
+                  "ipfb_ml_cg_noalloc");
 }
 
 int ipfb_autospectrum(ipfb_plan p, const void* y, double* autospec, void* stream) {

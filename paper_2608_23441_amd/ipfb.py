@@ -30,7 +30,7 @@ EXPORTS = (
     "ipfb_batched_use_graph", "ipfb_wiener_batched", "ipfb_batched_get_shape",
     "ipfb_batched_set_shape", "ipfb_batched_tune", "ipfb_stream_plan_create", "ipfb_stream_plan_destroy",
     "ipfb_wiener_stream", "ipfb_delta_analytic", "ipfb_autospectrum_error", "ipfb_mask_structured",
-    "ipfb_wiener_filter", "ipfb_mask_pack",
+    "ipfb_wiener_filter", "ipfb_mask_pack", "ipfb_ml_cg_noalloc",
 )
 FILTER_WIENER, FILTER_THRESHOLD, FILTER_NU = 0, 1, 2
 
@@ -69,6 +69,7 @@ def lib():
         L.ipfb_autospectrum.argtypes = [vp, vp, vp, vp]
         L.ipfb_quantize_c4.argtypes = [vp, vp, dbl, vp, vp, vp]
         L.ipfb_ml_cg.argtypes = [vp, i32, vp, vp, vp, vp, dbl, dbl, dbl, i32, vp, vp, vp, vp]
+        L.ipfb_ml_cg_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, dbl, dbl, dbl, i32, vp, vp, vp, vp]
         L.ipfb_batched_plan_create.argtypes = [ctypes.POINTER(vp), i32, i32, vp, i32, vp, i32]
         L.ipfb_batched_plan_destroy.argtypes = [vp]
         L.ipfb_batched_workspace_size.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
