@@ -23,11 +23,13 @@
  *  - Real arrays are float (IPFB_F32 plans) or double (IPFB_F64 plans);
  *    complex arrays are pairs of the same type.
  *  - Lengths: lblock is a power of two >= 4. Inverse: lblock <= 32768 (F32)
- *    / 16384 (F64); nblock any integer in [2, 32768] (powers of two up to
- *    2^15 (F32) / 2^14 (F64) use the LDS column kernel, other lengths the
- *    Bluestein column path, set up on the first call). Forward PFB /
- *    up-channelization: lblock up to 2^20, any nblock >= 1. ML-CG: nblock a
- *    power of two within the LDS column limits.
+ *    / 16384 (F64). With ntap = 4 and phi >= 1e-3 the recursive column stage
+ *    takes any nblock >= 1 (ipfb_plan_set_column_method); otherwise nblock
+ *    is an integer in [2, 32768] (powers of two up to 2^15 (F32) / 2^14
+ *    (F64) use the LDS column kernel, other lengths the Bluestein column
+ *    path, set up on the first call). Forward PFB / up-channelization:
+ *    lblock up to 2^20, any nblock >= 1. ML-CG: nblock a power of two within
+ *    the LDS column limits.
  */
 #ifndef IPFB_H
 #define IPFB_H
@@ -104,6 +106,26 @@ int ipfb_plan_device_bytes(ipfb_plan plan, size_t* bytes);
  * Bluestein path of a non-power-of-two nblock) stays the plan's.
  * Errors: IPFB_EINVAL (too small, misaligned, NULL plan), IPFB_ENOMEM. */
 int ipfb_plan_set_workspace(ipfb_plan plan, void* dev, size_t bytes);
+
+/* How ipfb_wiener / ipfb_wiener_ex run the column stage (Section 3.1's
+ * per-column circulant inverse with the Section 4.1 Wiener gain):
+ * IPFB_COLS_FFT: b-point column FFTs, the FP64 gain, inverse FFTs (the
+ *   paper's formulation);
+ * IPFB_COLS_RECURSIVE: the same linear map as two recursions along the frames.
+ *   The gain W_n (1+phi^2)/(|W_n|^2+phi^2) is a rational function of
+ *   e^{-2 pi i f/b}; factoring |W_n|^2 + phi^2 = K Q(z) Q(1/z) with Q's roots
+ *   inside the unit circle splits it into a causal filter W_n/Q (forward in
+ *   the frame index) and an anti-causal all-pole filter 1/Q(1/z) (backward),
+ *   run over the periodic sequence of nblock frames with exact periodic
+ *   states (one read of the frames to find them, one to apply), any nblock;
+ *   taken where ntap = 4 and phi >= 1e-3, the FFT form otherwise;
+ * IPFB_COLS_AUTO (default): the recursive form where it applies, except for
+ *   power-of-two nblock <= 512 (whose one-pass FFT stage is cheaper).
+ * Both give the same result up to rounding. IPFB_EUNSUPPORTED for
+ * IPFB_COLS_RECURSIVE on a plan whose tap count or frame length has no
+ * recursive kernel. */
+enum { IPFB_COLS_AUTO = 0, IPFB_COLS_FFT = 1, IPFB_COLS_RECURSIVE = 2 };
+int ipfb_plan_set_column_method(ipfb_plan plan, int method);
 
 /* Forward PFB (Section 2.2 polyphase equation, Section 2.3 y = F S W x),
  * circular: y_j[k] = sum_n e^{-2 pi i nk/N} sum_r h[rN+n] x[((j+r) mod b)N + n].

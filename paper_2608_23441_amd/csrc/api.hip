@@ -105,6 +105,12 @@ struct ipfb_plan_s {
   // Appendix B diagnostics (allocated on first use): x_true - x_hat, the
   // spectra of either, and the two autospectra
   void* diag = nullptr;
+  // recursive column stage: per-column coefficients for the phi last set up
+  // (NaN: none yet) and the per-segment states
+  double* iir_coef = nullptr;
+  void* iir_zs = nullptr;
+  double iir_phi = NAN;
+  int col_method = IPFB_COLS_AUTO;
   size_t bytes = 0;
   bool ws_ext = false;  // work, work2, tmp point into a caller-owned workspace
 };
@@ -159,7 +165,7 @@ void free_bplan(ipfb_bplan p);
 void free_plan(ipfb_plan p) {
   if (p->blu1) free_bplan(p->blu1);
   void* ptrs[] = {p->win64, p->winT, p->twN, p->twB, p->twB64, p->part, p->fac, p->twS,
-                  p->cg, p->diag};
+                  p->cg, p->diag, p->iir_coef, p->iir_zs};
   for (void* q : ptrs)
     if (q) hipFree(q);
   if (!p->ws_ext) {
@@ -336,6 +342,12 @@ int ipfb_plan_create(ipfb_plan* out, int lblock, int ntap, const double* window,
   if (!st && p->row_lds) st = dev_alloc(p, &p->work, frames_bytes);
   if (!st && p->row_lds && p->col_lds) st = dev_alloc(p, &p->work2, frames_bytes);
   if (!st && p->row_lds) st = dev_alloc(p, &p->fac, (size_t)(lblock / 2 + 1) * esize(prec));
+  const int iseg = prec == IPFB_F32 ? kIirSegF32 : kIirSegF64;
+  const int64_t nseg = (nblock + iseg - 1) / iseg;
+  if (!st && p->row_lds && iir_coef_stride(ntap) > 0 && nseg <= kIirMaxSeg) {  // the recursive column stage's buffers
+    st = dev_alloc(p, (void**)&p->iir_coef, (size_t)lblock * iir_coef_stride(ntap) * sizeof(double));
+    if (!st) st = dev_alloc(p, &p->iir_zs, (size_t)nseg * lblock * 2 * (ntap - 1) * esize(prec));
+  }
   if (!st && !p->row_lds) st = dev_alloc(p, &p->tmp, (size_t)nblock * lblock * esize(prec));
   if (!st && !p->row_lds) {
     // long frames: M = lblock/2-point complex FFTs, M = P1 * P2
@@ -398,6 +410,17 @@ int ipfb_plan_device_bytes(ipfb_plan plan, size_t* bytes) {
   if (check_plan(plan)) return IPFB_EINVAL;
   if (!bytes) return fail(IPFB_EINVAL, "bytes is NULL");
   *bytes = plan->bytes;
+  return ok();
+}
+
+int ipfb_plan_set_column_method(ipfb_plan p, int method) {
+  if (check_plan(p)) return IPFB_EINVAL;
+  if (method != IPFB_COLS_AUTO && method != IPFB_COLS_FFT && method != IPFB_COLS_RECURSIVE)
+    return fail(IPFB_EINVAL, "unknown column method %d", method);
+  if (method == IPFB_COLS_RECURSIVE && !p->iir_coef)
+    return fail(IPFB_EUNSUPPORTED, "the recursive column stage needs ntap = 4 and lblock <= 2^%d (ntap %d)",
+                max_log2_row(p->prec), p->ntap);
+  p->col_method = method;
   return ok();
 }
 
@@ -491,24 +514,28 @@ int pfb_adjoint(ipfb_plan p, const void* y, void* x, void* stream) {
 
 namespace {
 
+// Row stage into x_out: d [b][N].
+hipError_t rows_into(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, void* x_out,
+                     hipStream_t st) {
+  ProfScope ps("ipfb_rows", st);
+  hipError_t e = hipErrorNotSupported;
+  if (infmt == IPFB_IN_C4) e = launch_row_c4(p->prec, p->log2n, spec, chan_scale, x_out, p->nblock, p->twN, st);
+  if (e == hipErrorNotSupported) {
+    hipGetLastError();
+    if (scaled_infmt(infmt)) e = launch_dequant_factors(p->prec, chan_scale, p->lblock / 2 + 1, p->lblock, p->fac, st);
+    else e = hipSuccess;
+    if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec, p->fac, x_out, p->nblock, p->twN, st);
+  }
+  return e;
+}
+
 // Row stage into x_out, then the column stage in place there (power-of-two
 // nblock); kind/param/nu select the eigenvalue filter of the gain pass.
 int wiener_lds(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, int kind, double param,
                const double* nu, int normalise, void* x_out, void* stream) {
   DeviceGuard g(p->dev);
   hipStream_t st = (hipStream_t)stream;
-  hipError_t e;
-  {
-    ProfScope ps("ipfb_rows", st);
-    e = hipErrorNotSupported;
-    if (infmt == IPFB_IN_C4) e = launch_row_c4(p->prec, p->log2n, spec, chan_scale, x_out, p->nblock, p->twN, st);
-    if (e == hipErrorNotSupported) {
-      hipGetLastError();
-      if (scaled_infmt(infmt)) e = launch_dequant_factors(p->prec, chan_scale, p->lblock / 2 + 1, p->lblock, p->fac, st);
-      else e = hipSuccess;
-      if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec, p->fac, x_out, p->nblock, p->twN, st);
-    }
-  }
+  hipError_t e = rows_into(p, infmt, spec, chan_scale, x_out, st);
   // column stage in place on x_out: d [b][N] -> x [b][N]
   static const char* const pass_names[3] = {"ipfb_cols_fwd", "ipfb_cols_gain", "ipfb_cols_inv"};
   for (int pass = 0; pass < 3 && e == hipSuccess; ++pass) {
@@ -516,6 +543,38 @@ int wiener_lds(ipfb_plan p, int infmt, const void* spec, const float* chan_scale
     ProfScope ps(pass_names[pass], st);
     e = launch_col_wiener_nat(p->prec, p->log2b, pass, x_out, p->lblock, p->ntap, p->win64, param, normalise, p->twB,
                               p->twB64, st, 0, -1, nullptr, 0, 0, kind, nu);
+  }
+  return launched(e, "ipfb_wiener");
+}
+
+// Whether the Wiener inverse with this phi takes the recursive column stage.
+// It needs a tap count with a kernel and phi >= kIirMinPhi (poles of the
+// factorisation comfortably inside the unit circle); by default it is taken
+// for every nblock except the powers of two up to 512, whose one-pass FFT
+// stage reads and writes the frames once.
+constexpr double kIirMinPhi = 1e-3;
+bool use_recursive(ipfb_plan p, double phi) {
+  if (!p->iir_coef || !(phi >= kIirMinPhi) || p->col_method == IPFB_COLS_FFT) return false;
+  const int seg = p->prec == IPFB_F32 ? kIirSegF32 : kIirSegF64;
+  if ((p->nblock + seg - 1) / seg > kIirMaxSeg) return false;
+  if (p->col_method == IPFB_COLS_RECURSIVE) return true;
+  return !(p->col_lds && p->log2b <= 9);
+}
+
+int wiener_recursive(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, double phi, int normalise,
+                     void* x_out, void* stream) {
+  DeviceGuard g(p->dev);
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = rows_into(p, infmt, spec, chan_scale, x_out, st);
+  static const char* const names[4] = {"ipfb_cols_rec_setup", "ipfb_cols_rec_pass1", "ipfb_cols_rec_carry",
+                                       "ipfb_cols_rec_pass2"};
+  const double gnorm = normalise ? 1.0 + phi * phi : 1.0;
+  // the coefficients depend on phi only (and the plan): set up again only when it changes
+  for (int stage = (phi == p->iir_phi) ? kIirPass1 : kIirSetup; stage <= kIirApply && e == hipSuccess; ++stage) {
+    ProfScope ps(names[stage], st);
+    e = launch_col_iir(stage, p->prec, x_out, p->lblock, p->ntap, p->nblock, p->win64, phi, gnorm, p->iir_coef,
+                       p->iir_zs, st);
+    if (stage == kIirSetup) p->iir_phi = e == hipSuccess ? phi : NAN;
   }
   return launched(e, "ipfb_wiener");
 }
@@ -532,6 +591,7 @@ int ipfb_wiener_ex(ipfb_plan p, int infmt, const void* spec, const float* chan_s
   if (!(phi >= 0.0) || !std::isfinite(phi)) return fail(IPFB_EINVAL, "phi must be finite and >= 0");
   if (!p->row_lds)
     return fail(IPFB_EUNSUPPORTED, "ipfb_wiener supports lblock <= 2^%d for this precision", max_log2_row(p->prec));
+  if (use_recursive(p, phi)) return wiener_recursive(p, infmt, spec, chan_scale, phi, normalise, x_out, stream);
   if (!p->col_lds) {
     if (p->nblock < 2 || p->nblock > 32768)
       return fail(IPFB_EUNSUPPORTED, "ipfb_wiener supports nblock in [2, 32768] (got %lld)", (long long)p->nblock);

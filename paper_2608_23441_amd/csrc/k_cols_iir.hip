@@ -1,0 +1,645 @@
+// Column stage of the circulant Wiener inverse as two recursions along the
+// frames (Section 3.1 decorrelation with the Section 4.1 Wiener weights; the
+// Tikhonov form of Appendix C).
+//
+// For sub-filter path n, with zeta = e^{-2 pi i f / b}, the column spectrum is
+// the polynomial W(zeta) = sum_{r<p} h_r zeta^r (h_r = h[rN+n]) and
+//   |W|^2 + phi^2 = P(zeta) = c'_0 + sum_{t=1}^{p-1} c_t (zeta^t + zeta^-t),
+// c_t = sum_r h_r h_{r+t}, c'_0 = c_0 + phi^2. P > 0 on the unit circle, so
+// it factors as P = K Q(zeta) Q(1/zeta), Q(zeta) = prod_i (1 - r_i zeta) =
+// 1 - sum_i a_i zeta^i, |r_i| < 1 (the roots of P inside the unit circle).
+// The gain G = W (1+phi^2)/P, sampled at the b-th roots of unity, is the
+// eigenvalue sequence of the circulant matrix that periodises the impulse
+// response of kappa W(zeta)/(Q(zeta) Q(1/zeta)), kappa = (1+phi^2)/K. So,
+// over the periodic sequence of b frames,
+//   y = the causal ARMA filter W/Q applied to d      (forward in j),
+//   v = the anti-causal all-pole filter 1/Q(1/zeta) on y (backward in j),
+//   xhat = kappa v
+// is the same linear map as F^dagger G F, with O(p) operations per sample.
+//
+// Frames split into segments of L. Pass 1 runs both recursions from zero
+// state over each segment and keeps only their end states; a scan per column
+// turns them into the exact periodic states entering every segment (the
+// circular boundary solved through (I - A^b)^-1); pass 2 reruns the
+// recursions from those states and writes xhat over d in place. The states
+// are FP64 in both precisions.
+//
+// The factorisation runs on the device, one thread per column: the
+// palindromic P reduces to a degree-(p-1) polynomial R in x = zeta + 1/zeta;
+// its roots are found in u = 1/x (the reversed polynomial, whose leading
+// coefficient P(zeta = i) >= phi^2 never vanishes) by Aberth-Ehrlich
+// iteration, and r solves r + 1/r = 1/u inside the unit circle.
+#include "fft_lds.hpp"
+#include "launch.hpp"
+
+namespace ipfb {
+
+// Per-column coefficient block (FP64), M = p - 1 poles:
+//   h[M+1] numerator taps, a[M] with Q = 1 - sum a_i zeta^i, 1/K,
+//   then eight M x M matrices: A^L, A^{L'} (causal state over a segment and
+//   over the last segment of L' frames), B^L, B^{L'} (the same for the
+//   anti-causal state), N_L, N_{L'} (the anti-causal left-end state produced
+//   by the causal state entering the segment), (I - A^b)^-1, (I - B^b)^-1.
+template <int M>
+struct IirLayout {
+  static constexpr int H = 0, A = M + 1, IK = 2 * M + 1, MAT = 2 * M + 2;
+  static constexpr int AL = MAT, ALL = MAT + M * M, BL = MAT + 2 * M * M, BLL = MAT + 3 * M * M;
+  static constexpr int NL = MAT + 4 * M * M, NLL = MAT + 5 * M * M, IA = MAT + 6 * M * M, IB = MAT + 7 * M * M;
+  static constexpr int STRIDE = MAT + 8 * M * M;
+};
+
+int iir_coef_stride(int ntap) {
+  switch (ntap) {
+    case 4: return IirLayout<3>::STRIDE;
+    default: return 0;
+  }
+}
+
+// ---- small dense helpers (M x M, row major, FP64) ---------------------------
+template <int M>
+__device__ void mat_mul(const double* a, const double* b, double* c) {
+  double t[M * M];
+  for (int i = 0; i < M; ++i)
+    for (int j = 0; j < M; ++j) {
+      double s = 0.0;
+      for (int k = 0; k < M; ++k) s += a[i * M + k] * b[k * M + j];
+      t[i * M + j] = s;
+    }
+  for (int i = 0; i < M * M; ++i) c[i] = t[i];
+}
+
+template <int M>
+__device__ void mat_pow(const double* a, int64_t e, double* out) {
+  double base[M * M], r[M * M];
+  for (int i = 0; i < M * M; ++i) {
+    base[i] = a[i];
+    r[i] = (i % (M + 1) == 0) ? 1.0 : 0.0;
+  }
+  while (e > 0) {
+    if (e & 1) mat_mul<M>(r, base, r);
+    e >>= 1;
+    if (e) mat_mul<M>(base, base, base);
+  }
+  for (int i = 0; i < M * M; ++i) out[i] = r[i];
+}
+
+// out = (I - a)^-1 by Gauss-Jordan with partial pivoting
+template <int M>
+__device__ void inv_i_minus(const double* a, double* out) {
+  double m[M * M], v[M * M];
+  for (int i = 0; i < M * M; ++i) {
+    const double id = (i % (M + 1) == 0) ? 1.0 : 0.0;
+    m[i] = id - a[i];
+    v[i] = id;
+  }
+  for (int c = 0; c < M; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < M; ++r)
+      if (fabs(m[r * M + c]) > fabs(m[piv * M + c])) piv = r;
+    if (piv != c)
+      for (int k = 0; k < M; ++k) {
+        double t = m[c * M + k];
+        m[c * M + k] = m[piv * M + k];
+        m[piv * M + k] = t;
+        t = v[c * M + k];
+        v[c * M + k] = v[piv * M + k];
+        v[piv * M + k] = t;
+      }
+    const double d = 1.0 / m[c * M + c];
+    for (int k = 0; k < M; ++k) {
+      m[c * M + k] *= d;
+      v[c * M + k] *= d;
+    }
+    for (int r = 0; r < M; ++r) {
+      if (r == c) continue;
+      const double f = m[r * M + c];
+      for (int k = 0; k < M; ++k) {
+        m[r * M + k] -= f * m[c * M + k];
+        v[r * M + k] -= f * v[c * M + k];
+      }
+    }
+  }
+  for (int i = 0; i < M * M; ++i) out[i] = v[i];
+}
+
+__device__ __forceinline__ cx<double> cdiv(cx<double> a, cx<double> b) {
+  const double s = 1.0 / (b.x * b.x + b.y * b.y);
+  return mk<double>((a.x * b.x + a.y * b.y) * s, (a.y * b.x - a.x * b.y) * s);
+}
+
+__device__ __forceinline__ cx<double> csqrt(cx<double> z) {
+  const double r = sqrt(sqrt(z.x * z.x + z.y * z.y));
+  const double t = 0.5 * atan2(z.y, z.x);
+  return mk<double>(r * cos(t), r * sin(t));
+}
+
+// Roots of sum_{k=0}^{D} c[k] u^k (c[D] != 0) by Aberth-Ehrlich iteration.
+template <int D>
+__device__ void aberth(const double* c, cx<double>* z) {
+  // starting points on a circle of the roots' geometric-mean radius
+  const double rad = pow(fabs(c[0] / c[D]) + 1e-300, 1.0 / D) + 1e-3;
+  for (int k = 0; k < D; ++k) {
+    const double th = 6.283185307179586 * k / D + 0.4;
+    z[k] = mk<double>(rad * cos(th), rad * sin(th));
+  }
+  for (int it = 0; it < 200; ++it) {
+    double moved = 0.0, size = 0.0;
+    for (int k = 0; k < D; ++k) {
+      cx<double> pv = mk<double>(c[D], 0.0), dv = mk<double>(0.0, 0.0);
+      for (int j = D - 1; j >= 0; --j) {
+        dv = cmul(dv, z[k]) + pv;
+        pv = cmul(pv, z[k]) + mk<double>(c[j], 0.0);
+      }
+      if (pv.x == 0.0 && pv.y == 0.0) continue;
+      const cx<double> ratio = cdiv(pv, dv);
+      cx<double> s = mk<double>(0.0, 0.0);
+      for (int j = 0; j < D; ++j)
+        if (j != k) s = s + cdiv(mk<double>(1.0, 0.0), z[k] - z[j]);
+      const cx<double> w = cdiv(ratio, mk<double>(1.0, 0.0) - cmul(ratio, s));
+      z[k] = z[k] - w;
+      moved = fmax(moved, sqrt(w.x * w.x + w.y * w.y));
+      size = fmax(size, sqrt(z[k].x * z[k].x + z[k].y * z[k].y));
+    }
+    if (moved <= 1e-17 * fmax(size, 1e-300)) break;
+  }
+}
+
+// One thread per column: the factorisation and the segment matrices for
+// segments of L frames (the last one L' = b - (nseg - 1) L frames).
+template <int M>
+__global__ __launch_bounds__(64) void k_iir_setup(const double* __restrict__ win, int N, double phi, int64_t b,
+                                                   int L, double* __restrict__ coef) {
+  using Ly = IirLayout<M>;
+  const int n = blockIdx.x * 64 + threadIdx.x;
+  if (n >= N) return;
+  double* cf = coef + (int64_t)n * Ly::STRIDE;
+  double h[M + 1];
+  for (int r = 0; r <= M; ++r) h[r] = win[(int64_t)r * N + n];
+  double c[M + 1];
+  for (int t = 0; t <= M; ++t) {
+    double s = 0.0;
+    for (int r = 0; r + t <= M; ++r) s += h[r] * h[r + t];
+    c[t] = s;
+  }
+  c[0] += phi * phi;
+  // R(x) = c'_0 + sum_t c_t V_t(x), V_t(x) = zeta^t + zeta^-t: V_1 = x,
+  // V_2 = x^2 - 2, V_t = x V_{t-1} - V_{t-2}
+  double R[M + 1], vm2[M + 1], vm1[M + 1], vt[M + 1];
+  for (int k = 0; k <= M; ++k) R[k] = vm2[k] = vm1[k] = 0.0;
+  R[0] = c[0];
+  vm2[0] = 2.0;  // V_0 (unused in the sum: c'_0 enters once)
+  vm1[1] = 1.0;  // V_1
+  for (int t = 1; t <= M; ++t) {
+    if (t >= 2) {
+      for (int k = 0; k <= M; ++k) vt[k] = (k > 0 ? vm1[k - 1] : 0.0) - vm2[k];
+      for (int k = 0; k <= M; ++k) {
+        vm2[k] = vm1[k];
+        vm1[k] = vt[k];
+      }
+    }
+    for (int k = 0; k <= M; ++k) R[k] += c[t] * vm1[k];
+  }
+  // roots in u = 1/x: the reversed polynomial, leading coefficient R[0] = P(i) > 0
+  double rev[M + 1];
+  for (int k = 0; k <= M; ++k) rev[k] = R[M - k];
+  cx<double> u[M];
+  aberth<M>(rev, u);
+  // r with r + 1/r = 1/u and |r| < 1: r = 2u / (1 +- sqrt(1 - 4u^2))
+  cx<double> q[M + 1];  // Q(zeta) coefficients, q[0] = 1
+  q[0] = mk<double>(1.0, 0.0);
+  for (int k = 1; k <= M; ++k) q[k] = mk<double>(0.0, 0.0);
+  cx<double> q1 = mk<double>(1.0, 0.0);
+  for (int i = 0; i < M; ++i) {
+    const cx<double> u2 = cmul(u[i], u[i]);
+    const cx<double> s = csqrt(mk<double>(1.0 - 4.0 * u2.x, -4.0 * u2.y));
+    const cx<double> dp = mk<double>(1.0 + s.x, s.y), dm = mk<double>(1.0 - s.x, -s.y);
+    const cx<double> den = (dp.x * dp.x + dp.y * dp.y >= dm.x * dm.x + dm.y * dm.y) ? dp : dm;
+    const cx<double> r = cdiv(scale(u[i], 2.0), den);
+    for (int k = i + 1; k >= 1; --k) q[k] = q[k] - cmul(r, q[k - 1]);  // times (1 - r zeta)
+    q1 = cmul(q1, mk<double>(1.0 - r.x, -r.y));
+  }
+  double a[M];
+  for (int i = 0; i < M; ++i) a[i] = -q[i + 1].x;
+  double hs = 0.0;
+  for (int r = 0; r <= M; ++r) hs += h[r];
+  const double P1 = hs * hs + phi * phi;
+  const double Q1 = q1.x;  // real: the roots come in conjugate pairs
+  const double invK = Q1 * Q1 / P1;
+  for (int r = 0; r <= M; ++r) cf[Ly::H + r] = h[r];
+  for (int i = 0; i < M; ++i) cf[Ly::A + i] = a[i];
+  cf[Ly::IK] = invK;
+  // causal state (transposed direct form II, zero input): y = s_0,
+  // s_i <- a_{i+1} y + s_{i+1}; anti-causal state (v_j, ..., v_{j+M-1}) one
+  // frame to the left: v_{j-1} = sum_i a_{i+1} v_{j+i}
+  double A[M * M], B[M * M];
+  for (int i = 0; i < M * M; ++i) A[i] = B[i] = 0.0;
+  for (int i = 0; i < M; ++i) {
+    A[i * M + 0] = a[i];
+    if (i + 1 < M) A[i * M + i + 1] = 1.0;
+    B[0 * M + i] = a[i];
+    if (i >= 1) B[i * M + i - 1] = 1.0;
+  }
+  const int64_t nseg = (b + L - 1) / L;
+  const int Ll = (int)(b - (nseg - 1) * L);
+  double t1[M * M];
+  mat_pow<M>(A, L, cf + Ly::AL);
+  mat_pow<M>(A, Ll, cf + Ly::ALL);
+  mat_pow<M>(B, L, cf + Ly::BL);
+  mat_pow<M>(B, Ll, cf + Ly::BLL);
+  mat_pow<M>(A, b, t1);
+  inv_i_minus<M>(t1, cf + Ly::IA);
+  mat_pow<M>(B, b, t1);
+  inv_i_minus<M>(t1, cf + Ly::IB);
+  // N[t][i] = sum_{k=t}^{len-1} g[k-t] (e_0^T A^k)_i, g the all-pole impulse
+  // response (g_0 = 1, g_k = sum_i a_i g_{k-i}), for len = L and L'
+  for (int pass = 0; pass < 2; ++pass) {
+    const int len = pass ? Ll : L;
+    double* Nm = cf + (pass ? Ly::NLL : Ly::NL);
+    for (int i = 0; i < M * M; ++i) Nm[i] = 0.0;
+    double row[M], gr[M];
+    for (int i = 0; i < M; ++i) row[i] = gr[i] = 0.0;
+    row[0] = 1.0;
+    for (int k = 0; k < len; ++k) {
+      double gk = (k == 0) ? 1.0 : 0.0;
+      for (int i = 0; i < M; ++i) gk += a[i] * gr[i];
+      for (int i = M - 1; i > 0; --i) gr[i] = gr[i - 1];
+      gr[0] = gk;  // gr[t] = g_{k-t}
+      for (int t = 0; t < M; ++t)
+        for (int i = 0; i < M; ++i) Nm[t * M + i] += gr[t] * row[i];
+      double nr[M];
+      for (int j = 0; j < M; ++j) {
+        double s = 0.0;
+        for (int i = 0; i < M; ++i) s += row[i] * A[i * M + j];
+        nr[j] = s;
+      }
+      for (int j = 0; j < M; ++j) row[j] = nr[j];
+    }
+  }
+}
+
+// Frames of one column are streamed in chunks of kIirChunk, the next chunk
+// fetched while the current one is used.
+constexpr int kIirChunk = 16;
+
+template <typename T>
+__device__ __forceinline__ void load_chunk(const T* __restrict__ p, int64_t N, int k0, int Ls, T* v) {
+#pragma unroll
+  for (int k = 0; k < kIirChunk; ++k) v[k] = (k0 + k < Ls) ? p[(int64_t)(k0 + k) * N] : T(0);
+}
+
+// Pass 1: per (column, segment), both recursions from zero state: the causal
+// state leaving the segment and the anti-causal left-end state
+// (v_{j0}, ..., v_{j0+M-1}) = sum_{k>=t} g_{k-t} y_k. zs[(s N + n) 2M + .].
+// Segments are taken last first, the reverse of the order the row stage
+// wrote its frames in, so the most recently written ones (still in the
+// last-level cache) are read first.
+template <typename T, int M, int L>
+__global__ __launch_bounds__(256) void k_iir_zs(const T* __restrict__ d, int N, int64_t b,
+                                                 const double* __restrict__ coef, T* __restrict__ zs) {
+  using Ly = IirLayout<M>;
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  const int64_t s = (int64_t)gridDim.y - 1 - blockIdx.y;
+  if (n >= N) return;
+  const int64_t j0 = s * L;
+  const int Ls = (int)((b - j0) < L ? (b - j0) : L);
+  const double* cf = coef + (int64_t)n * Ly::STRIDE;
+  double h[M + 1], a[M];
+  for (int r = 0; r <= M; ++r) h[r] = cf[Ly::H + r];
+  for (int i = 0; i < M; ++i) a[i] = cf[Ly::A + i];
+  const T* pd = d + j0 * (int64_t)N + n;
+  double st[M], za[M], gr[M];
+  for (int i = 0; i < M; ++i) st[i] = za[i] = gr[i] = 0.0;
+  T cur[kIirChunk], nxt[kIirChunk];
+  load_chunk(pd, N, 0, Ls, cur);
+  const int nch = (Ls + kIirChunk - 1) / kIirChunk;
+#pragma unroll 1
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) load_chunk(pd, N, (c + 1) * kIirChunk, Ls, nxt);
+#pragma unroll
+    for (int kk = 0; kk < kIirChunk; ++kk) {
+      const int k = c * kIirChunk + kk;
+      if (k < Ls) {
+        const double x = (double)cur[kk];
+        const double y = h[0] * x + st[0];
+#pragma unroll
+        for (int i = 0; i < M; ++i) st[i] = h[i + 1] * x + a[i] * y + (i + 1 < M ? st[i + 1] : 0.0);
+        double gk = (k == 0) ? 1.0 : 0.0;
+#pragma unroll
+        for (int i = 0; i < M; ++i) gk += a[i] * gr[i];
+#pragma unroll
+        for (int i = M - 1; i > 0; --i) gr[i] = gr[i - 1];
+        gr[0] = gk;  // gr[t] = g_{k-t}
+#pragma unroll
+        for (int t = 0; t < M; ++t) za[t] += gr[t] * y;
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < kIirChunk; ++kk) cur[kk] = nxt[kk];
+  }
+  T* o = zs + (s * N + n) * (2 * M);
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    o[i] = T(st[i]);
+    o[M + i] = T(za[i]);
+  }
+}
+
+template <int M>
+__device__ __forceinline__ void matvec_add(const double* m, const double* x, const double* add, double* out) {
+  double t[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    double s = add[i];
+#pragma unroll
+    for (int j = 0; j < M; ++j) s += m[i * M + j] * x[j];
+    t[i] = s;
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) out[i] = t[i];
+}
+
+constexpr int kIirCarryQ = 4;  // segments per lane held in registers by the carry scan
+
+// The carry scan moves 3x3 affine maps X -> P X + Y across the lanes of a
+// wavefront with cross-lane exchanges.
+template <int M>
+__device__ __forceinline__ void shfl_map(const double* P, const double* Y, double* Po, double* Yo, int delta,
+                                         bool up) {
+#pragma unroll
+  for (int i = 0; i < M * M; ++i) Po[i] = up ? __shfl_up(P[i], delta, 64) : __shfl_down(P[i], delta, 64);
+#pragma unroll
+  for (int i = 0; i < M; ++i) Yo[i] = up ? __shfl_up(Y[i], delta, 64) : __shfl_down(Y[i], delta, 64);
+}
+
+template <int M>
+__device__ __forceinline__ void set_identity(double* P, double* Y) {
+#pragma unroll
+  for (int i = 0; i < M * M; ++i) P[i] = (i % (M + 1) == 0) ? 1.0 : 0.0;
+#pragma unroll
+  for (int i = 0; i < M; ++i) Y[i] = 0.0;
+}
+
+// Per column (one wavefront): the periodic states entering every segment,
+// written over the pass-1 results: zs[s] = (causal state entering segment s,
+// anti-causal state entering it from the right). Lane l takes the
+// contiguous segments [l q, (l+1) q), q = ceil(nseg / 64): it composes its
+// segments' affine maps, an inclusive scan of the maps across the lanes
+// (Hillis-Steele) gives every lane its entering state, and the lanes then
+// walk their segments. Causal: S_{s+1} = A^{len_s} S_s + zc_s, periodic
+// S_0 = (I - A^b)^-1 (scan of all). Anti-causal, right to left:
+// F_s = B^{len_s} F_{s+1} + c_s, c_s = za_s + N_{len_s} S_s, periodic
+// F_0 = (I - B^b)^-1 (scan of all); segment s receives V_s = F_{s+1}.
+// A lane's states (q <= QR segments) are loaded once into registers and
+// stored once; longer streams (QR = 0) re-read them for each phase.
+template <typename T, int M, int QR>
+__global__ __launch_bounds__(256) void k_iir_carry(int N, int64_t nseg, const double* __restrict__ coef,
+                                                   T* __restrict__ zs) {
+  using Ly = IirLayout<M>;
+  constexpr int QA = QR > 0 ? QR : 1;
+  constexpr int NMAT = 8 * M * M;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int n = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);
+  // the column's eight segment matrices, staged in LDS once (read back as
+  // wavefront-wide broadcasts in the dependent steps below)
+  __shared__ double smat[4][NMAT];
+  for (int i = lane; i < NMAT; i += 64) smat[wv][i] = n < N ? coef[(int64_t)n * Ly::STRIDE + Ly::MAT + i] : 0.0;
+  __syncthreads();
+  if (n >= N) return;  // the whole wavefront
+  const double* cf = smat[wv] - Ly::MAT;  // indexed with the Ly offsets
+  const int64_t stride = (int64_t)N * 2 * M;
+  T* z = zs + (int64_t)n * 2 * M;
+  const int64_t q = (nseg + 63) / 64;
+  const int64_t a0 = lane * q < nseg ? lane * q : nseg;
+  const int64_t a1 = a0 + q < nseg ? a0 + q : nseg;
+  const int cnt = (int)(a1 - a0);
+  // the lane's states in registers (QR > 0): zc then za of each segment
+  T r_zc[QA][M], r_za[QA][M];
+  if constexpr (QR > 0) {
+#pragma unroll
+    for (int k = 0; k < QR; ++k)
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        r_zc[k][i] = k < cnt ? z[(a0 + k) * stride + i] : T(0);
+        r_za[k][i] = k < cnt ? z[(a0 + k) * stride + M + i] : T(0);
+      }
+  }
+  auto get = [&](int k, int i, bool za) -> double {
+    if constexpr (QR > 0) return (double)(za ? r_za[k][i] : r_zc[k][i]);
+    else return (double)z[(a0 + k) * stride + (za ? M : 0) + i];
+  };
+  auto put = [&](int k, int i, bool za, double v) {
+    if constexpr (QR > 0) {
+      if (za) r_za[k][i] = T(v);
+      else r_zc[k][i] = T(v);
+    } else {
+      z[(a0 + k) * stride + (za ? M : 0) + i] = T(v);
+    }
+  };
+  const double zero[M] = {};
+  double P[M * M], Y[M], Po[M * M], Yo[M];
+  // ---- causal: local composition, then the scan
+  set_identity<M>(P, Y);
+#pragma unroll
+  for (int k = 0; k < (QR > 0 ? QR : 1); ++k) {
+    for (int kk = (QR > 0 ? k : 0); kk < (QR > 0 ? k + 1 : cnt); ++kk) {
+      if (kk >= cnt) break;
+      const double* As = cf + (a0 + kk + 1 < nseg ? Ly::AL : Ly::ALL);
+      double zc[M];
+      for (int i = 0; i < M; ++i) zc[i] = get(kk, i, false);
+      matvec_add<M>(As, Y, zc, Y);
+      mat_mul<M>(As, P, P);
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    shfl_map<M>(P, Y, Po, Yo, d, true);
+    if (lane >= d) {  // (P, Y) after (Po, Yo): X -> P (Po X + Yo) + Y
+      matvec_add<M>(P, Yo, Y, Y);
+      mat_mul<M>(P, Po, P);
+    }
+  }
+  double Tt[M], S0[M], S[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) Tt[i] = __shfl(Y[i], 63, 64);
+  matvec_add<M>(cf + Ly::IA, Tt, zero, S0);
+  shfl_map<M>(P, Y, Po, Yo, 1, true);  // exclusive: the lanes to the left
+  if (lane == 0) set_identity<M>(Po, Yo);
+  matvec_add<M>(Po, S0, Yo, S);
+#pragma unroll
+  for (int k = 0; k < (QR > 0 ? QR : 1); ++k) {
+    for (int kk = (QR > 0 ? k : 0); kk < (QR > 0 ? k + 1 : cnt); ++kk) {
+      if (kk >= cnt) break;
+      const bool last = a0 + kk + 1 == nseg;
+      double zc[M], c[M];
+      for (int i = 0; i < M; ++i) {
+        zc[i] = get(kk, i, false);
+        c[i] = get(kk, i, true);
+      }
+      matvec_add<M>(cf + (last ? Ly::NLL : Ly::NL), S, c, c);
+      for (int i = 0; i < M; ++i) {
+        put(kk, i, false, S[i]);
+        put(kk, i, true, c[i]);
+      }
+      matvec_add<M>(cf + (last ? Ly::ALL : Ly::AL), S, zc, S);
+    }
+  }
+  // ---- anti-causal: local composition right to left, then the suffix scan
+  set_identity<M>(P, Y);
+#pragma unroll
+  for (int k = (QR > 0 ? QR : 1) - 1; k >= 0; --k) {
+    for (int kk = (QR > 0 ? k : cnt - 1); kk >= (QR > 0 ? k : 0); --kk) {
+      if (kk >= cnt) continue;
+      const double* Bs = cf + (a0 + kk + 1 < nseg ? Ly::BL : Ly::BLL);
+      double c[M];
+      for (int i = 0; i < M; ++i) c[i] = get(kk, i, true);
+      matvec_add<M>(Bs, Y, c, Y);
+      mat_mul<M>(Bs, P, P);
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    shfl_map<M>(P, Y, Po, Yo, d, false);
+    if (lane + d < 64) {  // (P, Y) before (Po, Yo) on the right: X -> P (Po X + Yo) + Y
+      matvec_add<M>(P, Yo, Y, Y);
+      mat_mul<M>(P, Po, P);
+    }
+  }
+  double Ut[M], F0[M], F[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) Ut[i] = __shfl(Y[i], 0, 64);
+  matvec_add<M>(cf + Ly::IB, Ut, zero, F0);
+  shfl_map<M>(P, Y, Po, Yo, 1, false);  // the lanes to the right
+  if (lane == 63) set_identity<M>(Po, Yo);
+  matvec_add<M>(Po, F0, Yo, F);
+#pragma unroll
+  for (int k = (QR > 0 ? QR : 1) - 1; k >= 0; --k) {
+    for (int kk = (QR > 0 ? k : cnt - 1); kk >= (QR > 0 ? k : 0); --kk) {
+      if (kk >= cnt) continue;
+      double c[M];
+      for (int i = 0; i < M; ++i) c[i] = get(kk, i, true);
+      for (int i = 0; i < M; ++i) put(kk, i, true, F[i]);  // V_s = F_{s+1}
+      matvec_add<M>(cf + (a0 + kk + 1 < nseg ? Ly::BL : Ly::BLL), F, c, F);
+    }
+  }
+  if constexpr (QR > 0) {
+#pragma unroll
+    for (int k = 0; k < QR; ++k)
+      if (k < cnt)
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          z[(a0 + k) * stride + i] = r_zc[k][i];
+          z[(a0 + k) * stride + M + i] = r_za[k][i];
+        }
+  }
+}
+
+// Pass 2: per (column, segment), the causal ARMA from its entering state,
+// its outputs kept in LDS (each thread its own column: no barriers), then
+// the anti-causal recursion backwards from the right-hand state; xhat =
+// gain * v written over d. One wavefront of 64 columns per workgroup.
+template <typename T, int M, int L>
+__global__ __launch_bounds__(64) void k_iir_apply(T* __restrict__ x, int N, int64_t b,
+                                                   const double* __restrict__ coef, const T* __restrict__ zs,
+                                                   double gnorm) {
+  using Ly = IirLayout<M>;
+  __shared__ T ys[L * 64];
+  const int tid = threadIdx.x;
+  const int n = blockIdx.x * 64 + tid;
+  const int64_t s = blockIdx.y;
+  if (n >= N) return;
+  const int64_t j0 = s * L;
+  const int Ls = (int)((b - j0) < L ? (b - j0) : L);
+  const double* cf = coef + (int64_t)n * Ly::STRIDE;
+  double h[M + 1], a[M], st[M], v[M];
+  for (int r = 0; r <= M; ++r) h[r] = cf[Ly::H + r];
+  for (int i = 0; i < M; ++i) a[i] = cf[Ly::A + i];
+  const double g = gnorm * cf[Ly::IK];
+  const T* zz = zs + (s * N + n) * (2 * M);
+  for (int i = 0; i < M; ++i) {
+    st[i] = (double)zz[i];
+    v[i] = (double)zz[M + i];
+  }
+  T* px = x + j0 * (int64_t)N + n;
+  T cur[kIirChunk], nxt[kIirChunk];
+  load_chunk(px, N, 0, Ls, cur);
+  const int nch = (Ls + kIirChunk - 1) / kIirChunk;
+#pragma unroll 1
+  for (int c = 0; c < nch; ++c) {
+    if (c + 1 < nch) load_chunk(px, N, (c + 1) * kIirChunk, Ls, nxt);
+#pragma unroll
+    for (int kk = 0; kk < kIirChunk; ++kk) {
+      const int k = c * kIirChunk + kk;
+      if (k < Ls) {
+        const double xin = (double)cur[kk];
+        const double y = h[0] * xin + st[0];
+#pragma unroll
+        for (int i = 0; i < M; ++i) st[i] = h[i + 1] * xin + a[i] * y + (i + 1 < M ? st[i + 1] : 0.0);
+        ys[k * 64 + tid] = T(y);
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < kIirChunk; ++kk) cur[kk] = nxt[kk];
+  }
+#pragma unroll 4
+  for (int k = Ls - 1; k >= 0; --k) {
+    double w = (double)ys[k * 64 + tid];
+#pragma unroll
+    for (int i = 0; i < M; ++i) w += a[i] * v[i];
+#pragma unroll
+    for (int i = M - 1; i > 0; --i) v[i] = v[i - 1];
+    v[0] = w;
+    px[(int64_t)k * N] = T(g * w);
+  }
+}
+
+template <int M>
+static hipError_t launch_iir_m(int stage, int prec, void* x, int N, int64_t b, const double* win64, double phi,
+                               double gnorm, double* coef, void* zs, hipStream_t st) {
+  const int L = prec == F32 ? kIirSegF32 : kIirSegF64;
+  const int64_t nseg = (b + L - 1) / L;
+  if (nseg > kIirMaxSeg) return hipErrorNotSupported;  // segments run along the grid's y dimension
+  const dim3 gcol((unsigned)((N + 63) / 64));
+  const dim3 grid((unsigned)((N + 255) / 256), (unsigned)nseg);
+  const dim3 grid64((unsigned)((N + 63) / 64), (unsigned)nseg);
+  switch (stage) {
+    case kIirSetup:
+      k_iir_setup<M><<<gcol, 64, 0, st>>>(win64, N, phi, b, L, coef);
+      break;
+    case kIirPass1:
+      if (prec == F32) k_iir_zs<float, M, kIirSegF32><<<grid, 256, 0, st>>>((const float*)x, N, b, coef, (float*)zs);
+      else k_iir_zs<double, M, kIirSegF64><<<grid, 256, 0, st>>>((const double*)x, N, b, coef, (double*)zs);
+      break;
+    case kIirCarry:
+      {
+        const dim3 g4((unsigned)((N + 3) / 4));  // one wavefront per column
+        const bool regs = nseg <= 64 * kIirCarryQ;
+        if (prec == F32) {
+          if (regs) k_iir_carry<float, M, kIirCarryQ><<<g4, 256, 0, st>>>(N, nseg, coef, (float*)zs);
+          else k_iir_carry<float, M, 0><<<g4, 256, 0, st>>>(N, nseg, coef, (float*)zs);
+        } else {
+          if (regs) k_iir_carry<double, M, kIirCarryQ><<<g4, 256, 0, st>>>(N, nseg, coef, (double*)zs);
+          else k_iir_carry<double, M, 0><<<g4, 256, 0, st>>>(N, nseg, coef, (double*)zs);
+        }
+      }
+      break;
+    default:
+      if (prec == F32)
+        k_iir_apply<float, M, kIirSegF32><<<grid64, 64, 0, st>>>((float*)x, N, b, coef, (const float*)zs, gnorm);
+      else
+        k_iir_apply<double, M, kIirSegF64><<<grid64, 64, 0, st>>>((double*)x, N, b, coef, (const double*)zs, gnorm);
+      break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_col_iir(int stage, int prec, void* x, int N, int ntap, int64_t b, const double* win64, double phi,
+                          double gnorm, double* coef, void* zs, hipStream_t st) {
+  if (b < 1 || N < 1) return hipSuccess;
+  switch (ntap) {
+    case 4: return launch_iir_m<3>(stage, prec, x, N, b, win64, phi, gnorm, coef, zs, st);
+    default: return hipErrorNotSupported;
+  }
+}
+
+}  // namespace ipfb

@@ -52,6 +52,23 @@ hipError_t launch_dequant_factors(int prec, const float* chan_scale, int nchan, 
 hipError_t launch_row_c4(int prec, int log2n, const void* in, const float* chan_scale, void* out, int64_t nrows,
                          const void* twN, hipStream_t st);
 
+// Column stage as two recursions along the frames (the spectral
+// factorisation of |W_n|^2 + phi^2 into causal and anti-causal parts), in
+// place on the frame matrix x [b][N]: rows of frames, segments of
+// kIirSeg{F32,F64} frames, one launch per stage: kIirSetup computes the
+// per-column coefficients for this phi into coef (N * iir_coef_stride(ntap)
+// doubles), kIirPass1 the segments' zero-state end states into zs
+// (ceil(b / seg) * N * 2 (ntap - 1) values of the plan precision), kIirCarry
+// the periodic states entering each segment (over zs), kIirApply the two
+// recursions from those states, writing xhat over x. hipErrorNotSupported
+// (nothing launched) for tap counts without a kernel.
+constexpr int kIirSegF32 = 64, kIirSegF64 = 64;
+constexpr int64_t kIirMaxSeg = 65535;  // segments per column
+int iir_coef_stride(int ntap);
+enum { kIirSetup = 0, kIirPass1 = 1, kIirCarry = 2, kIirApply = 3 };
+hipError_t launch_col_iir(int stage, int prec, void* x, int N, int ntap, int64_t b, const double* win64, double phi,
+                          double gnorm, double* coef, void* zs, hipStream_t st);
+
 // Column stage on the transposed frame matrix: per column n (contiguous in
 // d_T[n][0..b)), x_T[n] = F^-1[ G_n F d_T[n] ] with the FP64 gain.
 // precond = 1 applies the real gain 1/(|W_n|^2 + phi^2) instead (the inverse

@@ -39,11 +39,15 @@ def _rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 
+@pytest.mark.parametrize("method", [ipfb.COLS_AUTO, ipfb.COLS_FFT])
 @pytest.mark.parametrize("prec,tol_x,tol_A,tol_col", [(ipfb.F32, 1e-5, 1e-4, 1e-4), (ipfb.F64, 1e-12, 1e-10, 1e-11)])
-def test_production_size_parity(production_case, prec, tol_x, tol_A, tol_col):
+def test_production_size_parity(production_case, prec, tol_x, tol_A, tol_col, method):
+    # AUTO is the recursive column stage here (the benchmark's launch
+    # configuration); COLS_FFT the three-pass FFT stage
     c = production_case
-    print(f"case full-size prec={prec}", flush=True)
+    print(f"case full-size prec={prec} method={method}", flush=True)
     coarse = ipfb.Plan(N, P, c["w"], B, prec)
+    coarse.set_column_method(method)
     fine = ipfb.Plan(c["Nf"], 4, c["wf"], (N * B) // c["Nf"], prec)
     xh = ipfb.ipfb_wiener(coarse, torch.from_numpy(c["packed"]).cuda(), torch.from_numpy(c["s"]).cuda(), PHI)
     Y, A = ipfb.upchannelize(fine, xh)

@@ -105,13 +105,18 @@ def test_ipfb_wiener_ci8(prec, N, p, b, phi):
     (ipfb.F64, 16, 4, 8192, 0.0), (ipfb.F32, 64, 4, 2048, 0.0),
     (ipfb.F32, 32, 4, 32768, 0.1), (ipfb.F64, 256, 4, 16384, 0.1),
 ])
-def test_ipfb_wiener_four_step_columns(prec, N, p, b, phi):
-    print(f"case ipfb_wiener four-step prec={prec} N={N} p={p} b={b} phi={phi}", flush=True)
+@pytest.mark.parametrize("method", [ipfb.COLS_FFT, ipfb.COLS_AUTO])
+def test_ipfb_wiener_four_step_columns(prec, N, p, b, phi, method):
+    # COLS_FFT forces the three-pass FFT stage; AUTO takes the recursive stage
+    # where it applies (4 taps, phi > 0)
+    print(f"case ipfb_wiener four-step prec={prec} N={N} p={p} b={b} phi={phi} method={method}", flush=True)
     w, x, y, packed, s = _quantised_case(N, p, b, 300 + N + b)
     ref = O.ipfb_wiener(packed, s, w, N, p, phi)
     plan = ipfb.Plan(N, p, w, b, prec)
-    out = ipfb.ipfb_wiener(plan, _dev(packed), _dev(s), phi)
-    assert _rel(_host(out), ref) < TOL[prec]
+    plan.set_column_method(method)
+    out = _host(ipfb.ipfb_wiener(plan, _dev(packed), _dev(s), phi))
+    assert _rel(out, ref) < TOL[prec]
+    assert worst_column_rel(out.astype(np.float64), ref, N)[0] < TOL_COL[prec]
 
 
 @pytest.mark.parametrize("prec,fmt", [(ipfb.F64, "c128"), (ipfb.F32, "c64"), (ipfb.F64, "c64"),
@@ -268,12 +273,18 @@ def test_bitwise_deterministic():
 
 
 def test_runtime_errors_reported():
+    # 40000 frames: past the FFT column stages (Bluestein up to 32768); the
+    # recursive stage takes them for phi > 0, phi = 0 is rejected
     N, p = 64, 4
     w = O.window_sinc_hamming(p, N)
-    plan = ipfb.Plan(N, p, w, 40000, ipfb.F32)  # inverse limited to nblock <= 32768
-    y = torch.zeros((40000, N // 2 + 1), dtype=torch.complex64, device="cuda")
+    plan = ipfb.Plan(N, p, w, 40000, ipfb.F32)
+    yh = I.complex_block((40000, N // 2 + 1), 41)
+    y = torch.from_numpy(yh.astype(np.complex64)).cuda()
+    out = _host(ipfb.ipfb_wiener(plan, y, None, 0.1))
+    ref = O.ipfb_wiener_from_spectra(yh.astype(np.complex64).astype(np.complex128), w, N, p, 0.1)
+    assert _rel(out, ref) < TOL[ipfb.F32]
     with pytest.raises(ipfb.IpfbError) as e:
-        ipfb.ipfb_wiener(plan, y, None, 0.1)
+        ipfb.ipfb_wiener(plan, y, None, 0.0)
     assert e.value.status == ipfb.EUNSUPPORTED
     with pytest.raises(ipfb.IpfbError):
         ipfb.ipfb_wiener(plan, y, None, -1.0)
