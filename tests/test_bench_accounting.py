@@ -27,15 +27,38 @@ def test_step_bytes_fp32_and_fp64():
     assert bench.step_bytes(N, B, NF, BF, 8) / MB == pytest.approx(2726, abs=2)
 
 
-@pytest.mark.parametrize("name,mb", [("ipfb_rows", 302.0), ("ipfb_cols_fwd", 536.9), ("ipfb_cols_gain", 536.9),
-                                     ("ipfb_cols_inv", 536.9), ("pfb_fwd_long_p1", 541.1),
-                                     ("pfb_fwd_long_p2", 536.9)])
-def test_kernel_bytes_production_fp32(name, mb):
+# each kernel's share of the compulsory bytes (intermediate round trips at
+# zero), for the recursive column stage and for the three-pass FFT stage
+@pytest.mark.parametrize("name,mb", [("ipfb_rows", 302.0), ("ipfb_cols_rec_pass1", 268.4),
+                                     ("ipfb_cols_rec_carry", 0.0), ("ipfb_cols_rec_pass2", 268.4),
+                                     ("ipfb_cols_fwd", 268.4), ("ipfb_cols_gain", 0.0), ("ipfb_cols_inv", 268.4),
+                                     ("pfb_fwd_long_p1", 272.6), ("pfb_fwd_long_p2", 268.4),
+                                     ("autospec_final", 0.0)])
+def test_compulsory_share_production_fp32(name, mb):
     assert bench.kernel_bytes(name, N, B, NF, BF, 4) / MB == pytest.approx(mb, abs=0.1)
 
 
-def test_unpriced_kernel_has_no_bytes():
-    assert bench.kernel_bytes("autospec_final", N, B, NF, BF, 4) is None
+def test_compulsory_shares_sum_to_the_step():
+    rec = ["ipfb_rows", "ipfb_cols_rec_setup", "ipfb_cols_rec_pass1", "ipfb_cols_rec_carry", "ipfb_cols_rec_pass2",
+           "pfb_fwd_long_p1", "pfb_fwd_long_p2", "autospec_final"]
+    fft = ["ipfb_rows", "ipfb_cols_fwd", "ipfb_cols_gain", "ipfb_cols_inv", "pfb_fwd_long_p1", "pfb_fwd_long_p2"]
+    for names in (rec, fft):
+        for esz in (4, 8):
+            assert sum(bench.kernel_bytes(k, N, B, NF, BF, esz) for k in names) == bench.step_bytes(N, B, NF, BF, esz)
+    # the one-pass FFT stage (nblock <= 512) takes both shares in its one kernel
+    n, b = 2048, 128
+    one = ["ipfb_rows", "ipfb_cols_gain"]
+    assert sum(bench.kernel_bytes(k, n, b, 16384, 16, 4, one_pass=True) for k in one) == \
+        bench.kernel_bytes("ipfb_rows", n, b, 16384, 16, 4) + 2 * n * b * 4
+
+
+# what each kernel moves by its design: the intermediates show up here
+@pytest.mark.parametrize("name,mb", [("ipfb_cols_fwd", 536.9), ("ipfb_cols_gain", 536.9), ("ipfb_cols_inv", 536.9),
+                                     ("ipfb_cols_rec_pass1", 268.4 + 25.2), ("ipfb_cols_rec_carry", 50.3),
+                                     ("ipfb_cols_rec_pass2", 536.9 + 25.2), ("pfb_fwd_long_p1", 541.1),
+                                     ("pfb_fwd_long_p2", 536.9)])
+def test_moved_bytes_production_fp32(name, mb):
+    assert bench.kernel_bytes(name, N, B, NF, BF, 4, "moved") / MB == pytest.approx(mb, abs=0.1)
 
 
 def test_source_digest_is_stable_hex():
