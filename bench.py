@@ -334,23 +334,47 @@ def batched_form(torch, ipfb, inputs, nstreams):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / steps
 
+    # the default: the recursive column stage over every stream at once
+    sec = timed()
+    # per-kernel times from one step launched directly (events are not
+    # recorded inside a replayed graph)
+    bp.use_graph(False)
+    ipfb.wiener_batched(bp, specs, scales, phi, x_outs=outs)
+    torch.cuda.synchronize()
+    ipfb.profile_reset()
+    ipfb.profile_enable(True)
+    ipfb.wiener_batched(bp, specs, scales, phi, x_outs=outs)
+    torch.cuda.synchronize()
+    ipfb.profile_enable(False)
+    bp.use_graph(True)
+    per_kernel = {}
+    for k in ("batched_rows", "batched_cols_rec_pass1", "batched_cols_rec_carry", "batched_cols_rec_pass2"):
+        ms, n = ipfb.profile_query(k)
+        if n:
+            per_kernel[k] = round(1e3 * ms / n, 1)
+    ipfb.profile_reset()
+    # beside it: the per-stream FFT path (Bluestein columns), default shapes, then the autotuner's
+    bp.set_column_method(ipfb.COLS_FFT)
     default_shapes = {m: bp.get_shape(m) for m in bp.conv_lengths()}
-    sec_default = timed()
+    sec_fft_default = timed()
     # autotuner: shapes from IPFB_TUNE_CACHE when it names a cache holding them, else timed now
     t0 = time.perf_counter()
     shapes = bp.tune()
     tune_s = time.perf_counter() - t0
-    sec = timed()
+    sec_fft = timed()
     S = sum(b * N for b in nbl)
     npow2 = sum(1 for b in nbl if b & (b - 1) == 0)
     # compulsory traffic of the inverse (packed input, one d round trip, xhat out): 12.5 B/sample
     alg = sum(b * (N // 2 + 1) + 4 * (N // 2 + 1) for b in nbl) + 12 * S
     return {"value": S / sec, "unit": "samples/s", "s_per_step": sec, "steps": steps, "streams": len(nbl),
-            "samples": S, "power_of_two_streams": npow2, "graph": True,
-            "s_per_step_default_shapes": sec_default, "tune_s": tune_s,
-            "shapes": {f"2^{m}": {"default": list(default_shapes[m]), "tuned": list(shapes[m])} for m in shapes},
-            "shape_fields": ["l1", "mb", "kb", "pchunk", "fuse", "nat"],
+            "samples": S, "power_of_two_streams": npow2, "graph": True, "column_stage": "recursive",
+            "per_kernel_ms": per_kernel,
             "hbm_GBps": alg / sec / 1e9, "hbm_roofline_frac": alg / sec / 1e9 / HBM_PEAK_GBPS,
+            "fft_path": {"value": S / sec_fft, "s_per_step": sec_fft, "s_per_step_default_shapes": sec_fft_default,
+                         "tune_s": tune_s,
+                         "shapes": {f"2^{m}": {"default": list(default_shapes[m]), "tuned": list(shapes[m])}
+                                    for m in shapes},
+                         "shape_fields": ["l1", "mb", "kb", "pchunk", "fuse", "nat"]},
             "config": {"lblock": N, "ntap": p, "nblock": "U[1024, 32768], seed 4", "phi": phi,
                        "dtype": "f32"}}
 

@@ -322,6 +322,16 @@ int ipfb_batched_workspace_size(ipfb_bplan plan, size_t* bytes);
  * launches, captured on the first call and again whenever the pointers, phi,
  * format or normalisation change; on = 0: launch directly on the stream. */
 int ipfb_batched_use_graph(ipfb_bplan plan, int on);
+/* The column stage of the batched form, as ipfb_plan_set_column_method for
+ * one stream: IPFB_COLS_AUTO (default) and IPFB_COLS_RECURSIVE take the
+ * recursive stage where it applies (ntap = 4, phi >= 1e-3), then for all
+ * streams at once: one kernel for the rows of every stream (4-bit spectra),
+ * and one launch per recursive pass over the segments of every stream;
+ * IPFB_COLS_FFT keeps the per-stream FFT / Bluestein path. The first call
+ * with a new phi sets the coefficients up (outside the graph); a call with
+ * other pointers than the last waits for the stream and rewrites the plan's
+ * stream tables. IPFB_EUNSUPPORTED for IPFB_COLS_RECURSIVE with ntap != 4. */
+int ipfb_batched_set_column_method(ipfb_bplan plan, int method);
 /* spec, chan_scale, x_out: host arrays [nstreams] of device pointers with the
  * per-stream layouts of ipfb_wiener (chan_scale ignored for the float formats).
  * normalise as in ipfb_wiener_ex. Asynchronous on stream (NULL = default). */

@@ -108,6 +108,7 @@ struct ipfb_plan_s {
   // recursive column stage: per-column coefficients for the phi last set up
   // (NaN: none yet) and the per-segment states
   double* iir_coef = nullptr;
+  double* iir_scoef = nullptr;
   void* iir_zs = nullptr;
   double iir_phi = NAN;
   int col_method = IPFB_COLS_AUTO;
@@ -165,7 +166,7 @@ void free_bplan(ipfb_bplan p);
 void free_plan(ipfb_plan p) {
   if (p->blu1) free_bplan(p->blu1);
   void* ptrs[] = {p->win64, p->winT, p->twN, p->twB, p->twB64, p->part, p->fac, p->twS,
-                  p->cg, p->diag, p->iir_coef, p->iir_zs};
+                  p->cg, p->diag, p->iir_coef, p->iir_scoef, p->iir_zs};
   for (void* q : ptrs)
     if (q) hipFree(q);
   if (!p->ws_ext) {
@@ -344,8 +345,9 @@ int ipfb_plan_create(ipfb_plan* out, int lblock, int ntap, const double* window,
   if (!st && p->row_lds) st = dev_alloc(p, &p->fac, (size_t)(lblock / 2 + 1) * esize(prec));
   const int iseg = prec == IPFB_F32 ? kIirSegF32 : kIirSegF64;
   const int64_t nseg = (nblock + iseg - 1) / iseg;
-  if (!st && p->row_lds && iir_coef_stride(ntap) > 0 && nseg <= kIirMaxSeg) {  // the recursive column stage's buffers
+  if (!st && p->row_lds && iir_coef_stride(ntap) > 0) {  // the recursive column stage's buffers
     st = dev_alloc(p, (void**)&p->iir_coef, (size_t)lblock * iir_coef_stride(ntap) * sizeof(double));
+    if (!st) st = dev_alloc(p, (void**)&p->iir_scoef, (size_t)lblock * iir_stream_stride(ntap) * sizeof(double));
     if (!st) st = dev_alloc(p, &p->iir_zs, (size_t)nseg * lblock * 2 * (ntap - 1) * esize(prec));
   }
   if (!st && !p->row_lds) st = dev_alloc(p, &p->tmp, (size_t)nblock * lblock * esize(prec));
@@ -555,8 +557,6 @@ int wiener_lds(ipfb_plan p, int infmt, const void* spec, const float* chan_scale
 constexpr double kIirMinPhi = 1e-3;
 bool use_recursive(ipfb_plan p, double phi) {
   if (!p->iir_coef || !(phi >= kIirMinPhi) || p->col_method == IPFB_COLS_FFT) return false;
-  const int seg = p->prec == IPFB_F32 ? kIirSegF32 : kIirSegF64;
-  if ((p->nblock + seg - 1) / seg > kIirMaxSeg) return false;
   if (p->col_method == IPFB_COLS_RECURSIVE) return true;
   return !(p->col_lds && p->log2b <= 9);
 }
@@ -566,15 +566,18 @@ int wiener_recursive(ipfb_plan p, int infmt, const void* spec, const float* chan
   DeviceGuard g(p->dev);
   hipStream_t st = (hipStream_t)stream;
   hipError_t e = rows_into(p, infmt, spec, chan_scale, x_out, st);
-  static const char* const names[4] = {"ipfb_cols_rec_setup", "ipfb_cols_rec_pass1", "ipfb_cols_rec_carry",
-                                       "ipfb_cols_rec_pass2"};
+  static const char* const names[5] = {"ipfb_cols_rec_setup", "ipfb_cols_rec_setup", "ipfb_cols_rec_pass1",
+                                       "ipfb_cols_rec_carry", "ipfb_cols_rec_pass2"};
   const double gnorm = normalise ? 1.0 + phi * phi : 1.0;
+  const int seg = p->prec == IPFB_F32 ? kIirSegF32 : kIirSegF64;
+  const int64_t nseg = (p->nblock + seg - 1) / seg;
+  const IirStream one = {x_out, p->nblock, 0};
   // the coefficients depend on phi only (and the plan): set up again only when it changes
   for (int stage = (phi == p->iir_phi) ? kIirPass1 : kIirSetup; stage <= kIirApply && e == hipSuccess; ++stage) {
     ProfScope ps(names[stage], st);
-    e = launch_col_iir(stage, p->prec, x_out, p->lblock, p->ntap, p->nblock, p->win64, phi, gnorm, p->iir_coef,
-                       p->iir_zs, st);
-    if (stage == kIirSetup) p->iir_phi = e == hipSuccess ? phi : NAN;
+    e = launch_col_iir(stage, p->prec, one, nullptr, 1, nseg, nseg, p->lblock, p->ntap, p->win64, phi, gnorm,
+                       p->iir_coef, p->iir_scoef, p->iir_zs, st);
+    if (stage <= kIirSetupLen) p->iir_phi = e == hipSuccess ? phi : NAN;
   }
   return launched(e, "ipfb_wiener");
 }
@@ -1156,6 +1159,19 @@ struct ipfb_bplan_s {
   hipGraphExec_t exec = nullptr;
   std::vector<uintptr_t> key;
   bool use_graph = true;
+  // recursive column stage over all streams at once (4 taps): per-column and
+  // per-(stream, column) coefficients, segment states of all streams, and the
+  // device tables the multi-stream kernels read (rewritten when the caller's
+  // pointers change)
+  int col_method = IPFB_COLS_AUTO;
+  double* rec_coef = nullptr;
+  double* rec_scoef = nullptr;
+  void* rec_zs = nullptr;
+  IirStream* rec_tab = nullptr;
+  RowStream* row_tab = nullptr;
+  int64_t rec_nsegt = 0, rec_maxnseg = 0, rec_frames = 0;
+  double rec_phi = NAN;
+  std::vector<uintptr_t> rec_key;
 };
 
 namespace {
@@ -1548,6 +1564,75 @@ hipError_t enqueue_batched(ipfb_bplan p, int infmt, const void* const* spec, con
   return e;
 }
 
+// The recursive column stage over every stream: rows of all streams (one
+// multi-stream kernel for 4-bit spectra, else one launch per stream), then
+// the segment passes of all streams together. The device tables must hold
+// this call's pointers, and the coefficients this phi.
+bool batched_recursive(ipfb_bplan p, double phi) {
+  if (!p->rec_coef || !(phi >= kIirMinPhi) || p->col_method == IPFB_COLS_FFT) return false;
+  return true;
+}
+
+hipError_t enqueue_batched_recursive(ipfb_bplan p, int infmt, const void* const* spec, const float* const* sc,
+                                     double phi, int normalise, void* const* xo, hipStream_t st) {
+  const int N = p->lblock;
+  hipError_t e;
+  {
+    ProfScope ps("batched_rows", st);
+    e = hipErrorNotSupported;
+    if (infmt == IPFB_IN_C4)
+      e = launch_row_c4(p->prec, p->log2n, nullptr, nullptr, nullptr, p->rec_frames, p->twN, st, p->row_tab,
+                        p->nstreams);
+    if (e == hipErrorNotSupported) {  // other formats and frame lengths: one launch per stream
+      hipGetLastError();
+      e = hipSuccess;
+      for (int s = 0; s < p->nstreams && e == hipSuccess; ++s) {
+        if (scaled_infmt(infmt)) e = launch_dequant_factors(p->prec, sc[s], N / 2 + 1, N, p->fac, st);
+        if (e == hipSuccess)
+          e = launch_row_irfft(p->prec, p->log2n, infmt, spec[s], p->fac, xo[s], p->nblock[s], p->twN, st);
+      }
+    }
+  }
+  static const char* const names[3] = {"batched_cols_rec_pass1", "batched_cols_rec_carry", "batched_cols_rec_pass2"};
+  const IirStream none = {nullptr, 0, 0};
+  for (int stage = kIirPass1; stage <= kIirApply && e == hipSuccess; ++stage) {
+    ProfScope ps(names[stage - kIirPass1], st);
+    e = launch_col_iir(stage, p->prec, none, p->rec_tab, p->nstreams, p->rec_nsegt, p->rec_maxnseg, N, p->ntap,
+                       p->win64, phi, normalise ? 1.0 + phi * phi : 1.0, p->rec_coef, p->rec_scoef, p->rec_zs, st);
+  }
+  return e;
+}
+
+// Rewrites the multi-stream tables for these pointers (waits for the stream
+// first: a graph launched earlier may still read them).
+int batched_tables(ipfb_bplan p, const void* const* spec, const float* const* sc, void* const* xo, hipStream_t st) {
+  std::vector<uintptr_t> key;
+  for (int s = 0; s < p->nstreams; ++s) {
+    key.push_back((uintptr_t)spec[s]);
+    key.push_back((uintptr_t)(sc ? sc[s] : nullptr));
+    key.push_back((uintptr_t)xo[s]);
+  }
+  if (key == p->rec_key) return IPFB_OK;
+  const int seg = p->prec == IPFB_F32 ? kIirSegF32 : kIirSegF64;
+  std::vector<IirStream> it(p->nstreams);
+  std::vector<RowStream> rt(p->nstreams);
+  int64_t g = 0, f = 0;
+  for (int s = 0; s < p->nstreams; ++s) {
+    it[s] = {xo[s], p->nblock[s], g};
+    rt[s] = {(const unsigned char*)spec[s], sc ? sc[s] : nullptr, xo[s], p->nblock[s], f};
+    g += (p->nblock[s] + seg - 1) / seg;
+    f += p->nblock[s];
+  }
+  if (hipStreamSynchronize(st) != hipSuccess ||
+      hipMemcpy(p->rec_tab, it.data(), it.size() * sizeof(IirStream), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->row_tab, rt.data(), rt.size() * sizeof(RowStream), hipMemcpyHostToDevice) != hipSuccess) {
+    hipGetLastError();
+    return fail(IPFB_EHIP, "writing the batched stream tables failed");
+  }
+  p->rec_key = key;
+  return IPFB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1602,6 +1687,24 @@ int ipfb_batched_plan_create(ipfb_bplan* out, int lblock, int ntap, const double
     st = balloc(p, &p->Tm, np2 * ((size_t)1 << maxlog2m) * 2 * esize(prec));
   }
   (void)M;
+  if (!st && iir_coef_stride(ntap) > 0) {  // the recursive column stage over all streams
+    const int seg = prec == IPFB_F32 ? kIirSegF32 : kIirSegF64;
+    for (int s = 0; s < nstreams; ++s) {
+      const int64_t ns = (nblock[s] + seg - 1) / seg;
+      p->rec_nsegt += ns;
+      p->rec_frames += nblock[s];
+      if (ns > p->rec_maxnseg) p->rec_maxnseg = ns;
+    }
+    st = balloc(p, (void**)&p->rec_coef, (size_t)lblock * iir_coef_stride(ntap) * sizeof(double));
+    if (!st) st = balloc(p, (void**)&p->rec_scoef, (size_t)nstreams * lblock * iir_stream_stride(ntap) * sizeof(double));
+    if (!st) st = balloc(p, &p->rec_zs, (size_t)p->rec_nsegt * lblock * 2 * (ntap - 1) * esize(prec));
+    if (!st) st = balloc(p, (void**)&p->rec_tab, (size_t)nstreams * sizeof(IirStream));
+    if (!st) st = balloc(p, (void**)&p->row_tab, (size_t)nstreams * sizeof(RowStream));
+    // prime the multi-stream row kernel's occupancy query outside any later graph capture
+    if (!st && launch_row_c4(prec, p->log2n, nullptr, nullptr, nullptr, 0, nullptr, nullptr, p->row_tab, 0) !=
+                   hipSuccess)
+      hipGetLastError();
+  }
   // shapes tuned earlier for this device and problem
   const char* cache = getenv("IPFB_TUNE_CACHE");
   if (!st && cache && *cache) st = tune_load(p, cache);
@@ -1726,6 +1829,16 @@ int ipfb_batched_workspace_size(ipfb_bplan p, size_t* bytes) {
   return ok();
 }
 
+int ipfb_batched_set_column_method(ipfb_bplan p, int method) {
+  if (!p) return fail(IPFB_EINVAL, "plan is NULL");
+  if (method != IPFB_COLS_AUTO && method != IPFB_COLS_FFT && method != IPFB_COLS_RECURSIVE)
+    return fail(IPFB_EINVAL, "unknown column method %d", method);
+  if (method == IPFB_COLS_RECURSIVE && !p->rec_coef)
+    return fail(IPFB_EUNSUPPORTED, "the recursive column stage needs ntap = 4 (ntap %d)", p->ntap);
+  p->col_method = method;
+  return ok();
+}
+
 int ipfb_batched_use_graph(ipfb_bplan p, int on) {
   if (!p) return fail(IPFB_EINVAL, "plan is NULL");
   p->use_graph = (on != 0);
@@ -1744,8 +1857,28 @@ int ipfb_wiener_batched(ipfb_bplan p, int infmt, const void* const* spec, const 
   }
   DeviceGuard g(p->dev);
   hipStream_t st = (hipStream_t)stream;
-  if (!p->use_graph) return launched(enqueue_batched(p, infmt, spec, chan_scale, phi, normalise, x_out, st), "ipfb_wiener_batched");
+  const bool rec = batched_recursive(p, phi);
+  if (rec) {
+    if (int s2 = batched_tables(p, spec, chan_scale, x_out, st)) return s2;
+    if (!(phi == p->rec_phi)) {  // the coefficients for this phi, outside the graph
+      const IirStream none = {nullptr, 0, 0};
+      hipError_t e = hipSuccess;
+      for (int stage = kIirSetup; stage <= kIirSetupLen && e == hipSuccess; ++stage) {
+        ProfScope ps("batched_cols_rec_setup", st);
+        e = launch_col_iir(stage, p->prec, none, p->rec_tab, p->nstreams, p->rec_nsegt, p->rec_maxnseg, p->lblock,
+                           p->ntap, p->win64, phi, 1.0, p->rec_coef, p->rec_scoef, p->rec_zs, st);
+      }
+      p->rec_phi = e == hipSuccess ? phi : NAN;
+      if (e != hipSuccess) return launched(e, "ipfb_wiener_batched");
+    }
+  }
+  auto enqueue = [&](hipStream_t s) {
+    return rec ? enqueue_batched_recursive(p, infmt, spec, chan_scale, phi, normalise, x_out, s)
+               : enqueue_batched(p, infmt, spec, chan_scale, phi, normalise, x_out, s);
+  };
+  if (!p->use_graph) return launched(enqueue(st), "ipfb_wiener_batched");
   std::vector<uintptr_t> key;
+  key.push_back((uintptr_t)rec);
   key.push_back((uintptr_t)infmt);
   key.push_back((uintptr_t)normalise);
   uint64_t phibits;
@@ -1763,7 +1896,7 @@ int ipfb_wiener_batched(ipfb_bplan p, int infmt, const void* const* spec, const 
     }
     hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return launched(e, "hipStreamBeginCapture");
-    hipError_t ee = enqueue_batched(p, infmt, spec, chan_scale, phi, normalise, x_out, p->cap);
+    hipError_t ee = enqueue(p->cap);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(p->cap, &graph);
     if (ee != hipSuccess) e = ee;

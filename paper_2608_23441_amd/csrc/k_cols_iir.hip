@@ -34,18 +34,23 @@
 
 namespace ipfb {
 
-// Per-column coefficient block (FP64), M = p - 1 poles:
+// Per-column coefficient block (FP64), M = p - 1 poles, shared by every
+// stream of the column's window and phi:
 //   h[M+1] numerator taps, a[M] with Q = 1 - sum a_i zeta^i, 1/K,
-//   then eight M x M matrices: A^L, A^{L'} (causal state over a segment and
-//   over the last segment of L' frames), B^L, B^{L'} (the same for the
-//   anti-causal state), N_L, N_{L'} (the anti-causal left-end state produced
-//   by the causal state entering the segment), (I - A^b)^-1, (I - B^b)^-1.
+//   A^L, B^L (the causal and anti-causal states carried over a full segment
+//   of L frames), N_L (the anti-causal left-end state produced by the causal
+//   state entering a full segment).
+// Per-(stream, column) block, for the stream's length b and its last
+// segment of L' = b - (nseg - 1) L frames:
+//   A^{L'}, B^{L'}, N_{L'}, (I - A^b)^-1, (I - B^b)^-1.
 template <int M>
 struct IirLayout {
   static constexpr int H = 0, A = M + 1, IK = 2 * M + 1, MAT = 2 * M + 2;
-  static constexpr int AL = MAT, ALL = MAT + M * M, BL = MAT + 2 * M * M, BLL = MAT + 3 * M * M;
-  static constexpr int NL = MAT + 4 * M * M, NLL = MAT + 5 * M * M, IA = MAT + 6 * M * M, IB = MAT + 7 * M * M;
-  static constexpr int STRIDE = MAT + 8 * M * M;
+  static constexpr int AL = MAT, BL = MAT + M * M, NL = MAT + 2 * M * M;
+  static constexpr int STRIDE = MAT + 3 * M * M;
+  // the per-stream block
+  static constexpr int ALL = 0, BLL = M * M, NLL = 2 * M * M, IA = 3 * M * M, IB = 4 * M * M;
+  static constexpr int SSTRIDE = 5 * M * M;
 };
 
 int iir_coef_stride(int ntap) {
@@ -53,6 +58,41 @@ int iir_coef_stride(int ntap) {
     case 4: return IirLayout<3>::STRIDE;
     default: return 0;
   }
+}
+
+int iir_stream_stride(int ntap) {
+  switch (ntap) {
+    case 4: return IirLayout<3>::SSTRIDE;
+    default: return 0;
+  }
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// The stream of global segment g (the same for the whole workgroup): the
+// last s with seg0[s] <= g, or the single stream passed by value when there
+// is no table. The fields come back as wavefront-uniform values.
+__device__ __forceinline__ IirStream iir_stream_of(int64_t g, const IirStream& one, const IirStream* __restrict__ tab,
+                                                   int nstreams) {
+  IirStream r = one;
+  if (nstreams > 1) {
+    int lo = 0, hi = nstreams - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tab[mid].seg0 <= g) lo = mid;
+      else hi = mid - 1;
+    }
+    r = tab[lo];
+  }
+  r.x = (void*)uniform64((int64_t)r.x);
+  r.b = uniform64(r.b);
+  r.seg0 = uniform64(r.seg0);
+  return r;
 }
 
 // ---- small dense helpers (M x M, row major, FP64) ---------------------------
@@ -164,11 +204,52 @@ __device__ void aberth(const double* c, cx<double>* z) {
   }
 }
 
-// One thread per column: the factorisation and the segment matrices for
-// segments of L frames (the last one L' = b - (nseg - 1) L frames).
+// The causal and anti-causal zero-input state steps from the poles'
+// polynomial: causal (transposed direct form II): y = s_0,
+// s_i <- a_{i+1} y + s_{i+1}; anti-causal state (v_j, ..., v_{j+M-1}) one
+// frame to the left: v_{j-1} = sum_i a_{i+1} v_{j+i}
 template <int M>
-__global__ __launch_bounds__(64) void k_iir_setup(const double* __restrict__ win, int N, double phi, int64_t b,
-                                                   int L, double* __restrict__ coef) {
+__device__ void iir_steps(const double* a, double* A, double* B) {
+  for (int i = 0; i < M * M; ++i) A[i] = B[i] = 0.0;
+  for (int i = 0; i < M; ++i) {
+    A[i * M + 0] = a[i];
+    if (i + 1 < M) A[i * M + i + 1] = 1.0;
+    B[0 * M + i] = a[i];
+    if (i >= 1) B[i * M + i - 1] = 1.0;
+  }
+}
+
+// N[t][i] = sum_{k=t}^{len-1} g[k-t] (e_0^T A^k)_i, g the all-pole impulse
+// response (g_0 = 1, g_k = sum_i a_i g_{k-i}): the anti-causal left-end state
+// that a causal state entering a segment of len frames produces
+template <int M>
+__device__ void iir_nmat(const double* a, const double* A, int len, double* Nm) {
+  for (int i = 0; i < M * M; ++i) Nm[i] = 0.0;
+  double row[M], gr[M];
+  for (int i = 0; i < M; ++i) row[i] = gr[i] = 0.0;
+  row[0] = 1.0;
+  for (int k = 0; k < len; ++k) {
+    double gk = (k == 0) ? 1.0 : 0.0;
+    for (int i = 0; i < M; ++i) gk += a[i] * gr[i];
+    for (int i = M - 1; i > 0; --i) gr[i] = gr[i - 1];
+    gr[0] = gk;  // gr[t] = g_{k-t}
+    for (int t = 0; t < M; ++t)
+      for (int i = 0; i < M; ++i) Nm[t * M + i] += gr[t] * row[i];
+    double nr[M];
+    for (int j = 0; j < M; ++j) {
+      double s = 0.0;
+      for (int i = 0; i < M; ++i) s += row[i] * A[i * M + j];
+      nr[j] = s;
+    }
+    for (int j = 0; j < M; ++j) row[j] = nr[j];
+  }
+}
+
+// One thread per column: the factorisation and the full-segment matrices
+// for segments of L frames.
+template <int M>
+__global__ __launch_bounds__(64) void k_iir_setup(const double* __restrict__ win, int N, double phi, int L,
+                                                   double* __restrict__ coef) {
   using Ly = IirLayout<M>;
   const int n = blockIdx.x * 64 + threadIdx.x;
   if (n >= N) return;
@@ -228,53 +309,39 @@ __global__ __launch_bounds__(64) void k_iir_setup(const double* __restrict__ win
   for (int r = 0; r <= M; ++r) cf[Ly::H + r] = h[r];
   for (int i = 0; i < M; ++i) cf[Ly::A + i] = a[i];
   cf[Ly::IK] = invK;
-  // causal state (transposed direct form II, zero input): y = s_0,
-  // s_i <- a_{i+1} y + s_{i+1}; anti-causal state (v_j, ..., v_{j+M-1}) one
-  // frame to the left: v_{j-1} = sum_i a_{i+1} v_{j+i}
   double A[M * M], B[M * M];
-  for (int i = 0; i < M * M; ++i) A[i] = B[i] = 0.0;
-  for (int i = 0; i < M; ++i) {
-    A[i * M + 0] = a[i];
-    if (i + 1 < M) A[i * M + i + 1] = 1.0;
-    B[0 * M + i] = a[i];
-    if (i >= 1) B[i * M + i - 1] = 1.0;
-  }
+  iir_steps<M>(a, A, B);
+  mat_pow<M>(A, L, cf + Ly::AL);
+  mat_pow<M>(B, L, cf + Ly::BL);
+  iir_nmat<M>(a, A, L, cf + Ly::NL);
+}
+
+// One thread per (stream, column): the matrices that depend on the stream's
+// length, for its last segment and its periodic boundary.
+template <int M>
+__global__ __launch_bounds__(64) void k_iir_setup_len(int N, int L, IirStream one, const IirStream* __restrict__ tab,
+                                                       int nstreams, const double* __restrict__ coef,
+                                                       double* __restrict__ scoef) {
+  using Ly = IirLayout<M>;
+  const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (t >= (int64_t)nstreams * N) return;
+  const int si = (int)(t / N), n = (int)(t - (int64_t)si * N);
+  const IirStream sd = nstreams <= 1 ? one : tab[si];
+  const double* cf = coef + (int64_t)n * Ly::STRIDE;
+  double* sc = scoef + t * Ly::SSTRIDE;
+  double a[M], A[M * M], B[M * M], t1[M * M];
+  for (int i = 0; i < M; ++i) a[i] = cf[Ly::A + i];
+  iir_steps<M>(a, A, B);
+  const int64_t b = sd.b;
   const int64_t nseg = (b + L - 1) / L;
   const int Ll = (int)(b - (nseg - 1) * L);
-  double t1[M * M];
-  mat_pow<M>(A, L, cf + Ly::AL);
-  mat_pow<M>(A, Ll, cf + Ly::ALL);
-  mat_pow<M>(B, L, cf + Ly::BL);
-  mat_pow<M>(B, Ll, cf + Ly::BLL);
+  mat_pow<M>(A, Ll, sc + Ly::ALL);
+  mat_pow<M>(B, Ll, sc + Ly::BLL);
+  iir_nmat<M>(a, A, Ll, sc + Ly::NLL);
   mat_pow<M>(A, b, t1);
-  inv_i_minus<M>(t1, cf + Ly::IA);
+  inv_i_minus<M>(t1, sc + Ly::IA);
   mat_pow<M>(B, b, t1);
-  inv_i_minus<M>(t1, cf + Ly::IB);
-  // N[t][i] = sum_{k=t}^{len-1} g[k-t] (e_0^T A^k)_i, g the all-pole impulse
-  // response (g_0 = 1, g_k = sum_i a_i g_{k-i}), for len = L and L'
-  for (int pass = 0; pass < 2; ++pass) {
-    const int len = pass ? Ll : L;
-    double* Nm = cf + (pass ? Ly::NLL : Ly::NL);
-    for (int i = 0; i < M * M; ++i) Nm[i] = 0.0;
-    double row[M], gr[M];
-    for (int i = 0; i < M; ++i) row[i] = gr[i] = 0.0;
-    row[0] = 1.0;
-    for (int k = 0; k < len; ++k) {
-      double gk = (k == 0) ? 1.0 : 0.0;
-      for (int i = 0; i < M; ++i) gk += a[i] * gr[i];
-      for (int i = M - 1; i > 0; --i) gr[i] = gr[i - 1];
-      gr[0] = gk;  // gr[t] = g_{k-t}
-      for (int t = 0; t < M; ++t)
-        for (int i = 0; i < M; ++i) Nm[t * M + i] += gr[t] * row[i];
-      double nr[M];
-      for (int j = 0; j < M; ++j) {
-        double s = 0.0;
-        for (int i = 0; i < M; ++i) s += row[i] * A[i * M + j];
-        nr[j] = s;
-      }
-      for (int j = 0; j < M; ++j) row[j] = nr[j];
-    }
-  }
+  inv_i_minus<M>(t1, sc + Ly::IB);
 }
 
 // Frames of one column are streamed in chunks of kIirChunk, the next chunk
@@ -289,24 +356,27 @@ __device__ __forceinline__ void load_chunk(const T* __restrict__ p, int64_t N, i
 
 // Pass 1: per (column, segment), both recursions from zero state: the causal
 // state leaving the segment and the anti-causal left-end state
-// (v_{j0}, ..., v_{j0+M-1}) = sum_{k>=t} g_{k-t} y_k. zs[(s N + n) 2M + .].
-// Segments are taken last first, the reverse of the order the row stage
-// wrote its frames in, so the most recently written ones (still in the
-// last-level cache) are read first.
+// (v_{j0}, ..., v_{j0+M-1}) = sum_{k>=t} g_{k-t} y_k. zs[(g N + n) 2M + .]
+// for global segment g (the segments of all streams, one after another).
+// Workgroup w takes segment g = nsegt - 1 - w / ntiles, last first: the
+// reverse of the order the row stage wrote its frames in, so the most
+// recently written ones (still in the last-level cache) are read first.
 template <typename T, int M, int L>
-__global__ __launch_bounds__(256) void k_iir_zs(const T* __restrict__ d, int N, int64_t b,
+__global__ __launch_bounds__(256) void k_iir_zs(int N, int ntiles, int64_t nsegt, IirStream one,
+                                                 const IirStream* __restrict__ tab, int nstreams,
                                                  const double* __restrict__ coef, T* __restrict__ zs) {
   using Ly = IirLayout<M>;
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  const int64_t s = (int64_t)gridDim.y - 1 - blockIdx.y;
+  const int64_t g = nsegt - 1 - (int64_t)__builtin_amdgcn_readfirstlane(blockIdx.x / ntiles);
+  const int n = (int)__builtin_amdgcn_readfirstlane(blockIdx.x % ntiles) * 256 + threadIdx.x;
   if (n >= N) return;
-  const int64_t j0 = s * L;
-  const int Ls = (int)((b - j0) < L ? (b - j0) : L);
+  const IirStream sd = iir_stream_of(g, one, tab, nstreams);
+  const int64_t j0 = (g - sd.seg0) * L;
+  const int Ls = (int)((sd.b - j0) < L ? (sd.b - j0) : L);
   const double* cf = coef + (int64_t)n * Ly::STRIDE;
   double h[M + 1], a[M];
   for (int r = 0; r <= M; ++r) h[r] = cf[Ly::H + r];
   for (int i = 0; i < M; ++i) a[i] = cf[Ly::A + i];
-  const T* pd = d + j0 * (int64_t)N + n;
+  const T* pd = (const T*)sd.x + j0 * (int64_t)N + n;
   double st[M], za[M], gr[M];
   for (int i = 0; i < M; ++i) st[i] = za[i] = gr[i] = 0.0;
   T cur[kIirChunk], nxt[kIirChunk];
@@ -336,7 +406,7 @@ __global__ __launch_bounds__(256) void k_iir_zs(const T* __restrict__ d, int N, 
 #pragma unroll
     for (int kk = 0; kk < kIirChunk; ++kk) cur[kk] = nxt[kk];
   }
-  T* o = zs + (s * N + n) * (2 * M);
+  T* o = zs + (g * N + n) * (2 * M);
 #pragma unroll
   for (int i = 0; i < M; ++i) {
     o[i] = T(st[i]);
@@ -392,23 +462,53 @@ __device__ __forceinline__ void set_identity(double* P, double* Y) {
 // A lane's states (q <= QR segments) are loaded once into registers and
 // stored once; longer streams (QR = 0) re-read them for each phase.
 template <typename T, int M, int QR>
-__global__ __launch_bounds__(256) void k_iir_carry(int N, int64_t nseg, const double* __restrict__ coef,
-                                                   T* __restrict__ zs) {
+__global__ __launch_bounds__(256) void k_iir_carry(int N, int L, IirStream one, const IirStream* __restrict__ tab,
+                                                   int nstreams, const double* __restrict__ coef,
+                                                   const double* __restrict__ scoef, T* __restrict__ zs) {
   using Ly = IirLayout<M>;
   constexpr int QA = QR > 0 ? QR : 1;
   constexpr int NMAT = 8 * M * M;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  const int n = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);
+  const int groups = (N + 3) / 4;
+  const int si = __builtin_amdgcn_readfirstlane(blockIdx.x / groups);  // the stream
+  const int n = __builtin_amdgcn_readfirstlane((blockIdx.x % groups) * 4 + wv);
   // the column's eight segment matrices, staged in LDS once (read back as
-  // wavefront-wide broadcasts in the dependent steps below)
+  // wavefront-wide broadcasts in the dependent steps below), in the order
+  // A^L, A^{L'}, B^L, B^{L'}, N_L, N_{L'}, (I - A^b)^-1, (I - B^b)^-1
   __shared__ double smat[4][NMAT];
-  for (int i = lane; i < NMAT; i += 64) smat[wv][i] = n < N ? coef[(int64_t)n * Ly::STRIDE + Ly::MAT + i] : 0.0;
+  constexpr int MM = M * M;
+  for (int i = lane; i < NMAT; i += 64) {
+    double v = 0.0;
+    if (n < N) {
+      const int m = i / MM, e = i - m * MM;
+      const double* cfm = coef + (int64_t)n * Ly::STRIDE;
+      const double* scm = scoef + ((int64_t)si * N + n) * Ly::SSTRIDE;
+      switch (m) {
+        case 0: v = cfm[Ly::AL + e]; break;
+        case 1: v = scm[Ly::ALL + e]; break;
+        case 2: v = cfm[Ly::BL + e]; break;
+        case 3: v = scm[Ly::BLL + e]; break;
+        case 4: v = cfm[Ly::NL + e]; break;
+        case 5: v = scm[Ly::NLL + e]; break;
+        case 6: v = scm[Ly::IA + e]; break;
+        default: v = scm[Ly::IB + e]; break;
+      }
+    }
+    smat[wv][i] = v;
+  }
   __syncthreads();
   if (n >= N) return;  // the whole wavefront
-  const double* cf = smat[wv] - Ly::MAT;  // indexed with the Ly offsets
+  struct {
+    int AL, ALL, BL, BLL, NL, NLL, IA, IB;
+  } constexpr Lo = {0, MM, 2 * MM, 3 * MM, 4 * MM, 5 * MM, 6 * MM, 7 * MM};
+  const double* cf = smat[wv];
+  IirStream sd = nstreams <= 1 ? one : tab[si];
+  sd.b = uniform64(sd.b);
+  sd.seg0 = uniform64(sd.seg0);
+  const int64_t nseg = (sd.b + L - 1) / L;
   const int64_t stride = (int64_t)N * 2 * M;
-  T* z = zs + (int64_t)n * 2 * M;
+  T* z = zs + (sd.seg0 * N + n) * 2 * M;
   const int64_t q = (nseg + 63) / 64;
   const int64_t a0 = lane * q < nseg ? lane * q : nseg;
   const int64_t a1 = a0 + q < nseg ? a0 + q : nseg;
@@ -444,7 +544,7 @@ __global__ __launch_bounds__(256) void k_iir_carry(int N, int64_t nseg, const do
   for (int k = 0; k < (QR > 0 ? QR : 1); ++k) {
     for (int kk = (QR > 0 ? k : 0); kk < (QR > 0 ? k + 1 : cnt); ++kk) {
       if (kk >= cnt) break;
-      const double* As = cf + (a0 + kk + 1 < nseg ? Ly::AL : Ly::ALL);
+      const double* As = cf + (a0 + kk + 1 < nseg ? Lo.AL : Lo.ALL);
       double zc[M];
       for (int i = 0; i < M; ++i) zc[i] = get(kk, i, false);
       matvec_add<M>(As, Y, zc, Y);
@@ -462,7 +562,7 @@ __global__ __launch_bounds__(256) void k_iir_carry(int N, int64_t nseg, const do
   double Tt[M], S0[M], S[M];
 #pragma unroll
   for (int i = 0; i < M; ++i) Tt[i] = __shfl(Y[i], 63, 64);
-  matvec_add<M>(cf + Ly::IA, Tt, zero, S0);
+  matvec_add<M>(cf + Lo.IA, Tt, zero, S0);
   shfl_map<M>(P, Y, Po, Yo, 1, true);  // exclusive: the lanes to the left
   if (lane == 0) set_identity<M>(Po, Yo);
   matvec_add<M>(Po, S0, Yo, S);
@@ -476,12 +576,12 @@ __global__ __launch_bounds__(256) void k_iir_carry(int N, int64_t nseg, const do
         zc[i] = get(kk, i, false);
         c[i] = get(kk, i, true);
       }
-      matvec_add<M>(cf + (last ? Ly::NLL : Ly::NL), S, c, c);
+      matvec_add<M>(cf + (last ? Lo.NLL : Lo.NL), S, c, c);
       for (int i = 0; i < M; ++i) {
         put(kk, i, false, S[i]);
         put(kk, i, true, c[i]);
       }
-      matvec_add<M>(cf + (last ? Ly::ALL : Ly::AL), S, zc, S);
+      matvec_add<M>(cf + (last ? Lo.ALL : Lo.AL), S, zc, S);
     }
   }
   // ---- anti-causal: local composition right to left, then the suffix scan
@@ -490,7 +590,7 @@ __global__ __launch_bounds__(256) void k_iir_carry(int N, int64_t nseg, const do
   for (int k = (QR > 0 ? QR : 1) - 1; k >= 0; --k) {
     for (int kk = (QR > 0 ? k : cnt - 1); kk >= (QR > 0 ? k : 0); --kk) {
       if (kk >= cnt) continue;
-      const double* Bs = cf + (a0 + kk + 1 < nseg ? Ly::BL : Ly::BLL);
+      const double* Bs = cf + (a0 + kk + 1 < nseg ? Lo.BL : Lo.BLL);
       double c[M];
       for (int i = 0; i < M; ++i) c[i] = get(kk, i, true);
       matvec_add<M>(Bs, Y, c, Y);
@@ -508,7 +608,7 @@ __global__ __launch_bounds__(256) void k_iir_carry(int N, int64_t nseg, const do
   double Ut[M], F0[M], F[M];
 #pragma unroll
   for (int i = 0; i < M; ++i) Ut[i] = __shfl(Y[i], 0, 64);
-  matvec_add<M>(cf + Ly::IB, Ut, zero, F0);
+  matvec_add<M>(cf + Lo.IB, Ut, zero, F0);
   shfl_map<M>(P, Y, Po, Yo, 1, false);  // the lanes to the right
   if (lane == 63) set_identity<M>(Po, Yo);
   matvec_add<M>(Po, F0, Yo, F);
@@ -519,7 +619,7 @@ __global__ __launch_bounds__(256) void k_iir_carry(int N, int64_t nseg, const do
       double c[M];
       for (int i = 0; i < M; ++i) c[i] = get(kk, i, true);
       for (int i = 0; i < M; ++i) put(kk, i, true, F[i]);  // V_s = F_{s+1}
-      matvec_add<M>(cf + (a0 + kk + 1 < nseg ? Ly::BL : Ly::BLL), F, c, F);
+      matvec_add<M>(cf + (a0 + kk + 1 < nseg ? Lo.BL : Lo.BLL), F, c, F);
     }
   }
   if constexpr (QR > 0) {
@@ -537,30 +637,32 @@ __global__ __launch_bounds__(256) void k_iir_carry(int N, int64_t nseg, const do
 // Pass 2: per (column, segment), the causal ARMA from its entering state,
 // its outputs kept in LDS (each thread its own column: no barriers), then
 // the anti-causal recursion backwards from the right-hand state; xhat =
-// gain * v written over d. One wavefront of 64 columns per workgroup.
+// gain * v written over d. One wavefront of 64 columns per workgroup;
+// workgroup w takes global segment w / ntiles.
 template <typename T, int M, int L>
-__global__ __launch_bounds__(64) void k_iir_apply(T* __restrict__ x, int N, int64_t b,
-                                                   const double* __restrict__ coef, const T* __restrict__ zs,
-                                                   double gnorm) {
+__global__ __launch_bounds__(64) void k_iir_apply(int N, int ntiles, IirStream one, const IirStream* __restrict__ tab,
+                                                   int nstreams, const double* __restrict__ coef,
+                                                   const T* __restrict__ zs, double gnorm) {
   using Ly = IirLayout<M>;
   __shared__ T ys[L * 64];
   const int tid = threadIdx.x;
-  const int n = blockIdx.x * 64 + tid;
-  const int64_t s = blockIdx.y;
+  const int64_t g = __builtin_amdgcn_readfirstlane(blockIdx.x / ntiles);
+  const int n = (int)__builtin_amdgcn_readfirstlane(blockIdx.x % ntiles) * 64 + tid;
   if (n >= N) return;
-  const int64_t j0 = s * L;
-  const int Ls = (int)((b - j0) < L ? (b - j0) : L);
+  const IirStream sd = iir_stream_of(g, one, tab, nstreams);
+  const int64_t j0 = (g - sd.seg0) * L;
+  const int Ls = (int)((sd.b - j0) < L ? (sd.b - j0) : L);
   const double* cf = coef + (int64_t)n * Ly::STRIDE;
   double h[M + 1], a[M], st[M], v[M];
   for (int r = 0; r <= M; ++r) h[r] = cf[Ly::H + r];
   for (int i = 0; i < M; ++i) a[i] = cf[Ly::A + i];
-  const double g = gnorm * cf[Ly::IK];
-  const T* zz = zs + (s * N + n) * (2 * M);
+  const double gn = gnorm * cf[Ly::IK];
+  const T* zz = zs + (g * N + n) * (2 * M);
   for (int i = 0; i < M; ++i) {
     st[i] = (double)zz[i];
     v[i] = (double)zz[M + i];
   }
-  T* px = x + j0 * (int64_t)N + n;
+  T* px = (T*)sd.x + j0 * (int64_t)N + n;
   T cur[kIirChunk], nxt[kIirChunk];
   load_chunk(px, N, 0, Ls, cur);
   const int nch = (Ls + kIirChunk - 1) / kIirChunk;
@@ -589,55 +691,68 @@ __global__ __launch_bounds__(64) void k_iir_apply(T* __restrict__ x, int N, int6
 #pragma unroll
     for (int i = M - 1; i > 0; --i) v[i] = v[i - 1];
     v[0] = w;
-    px[(int64_t)k * N] = T(g * w);
+    px[(int64_t)k * N] = T(gn * w);
   }
 }
 
 template <int M>
-static hipError_t launch_iir_m(int stage, int prec, void* x, int N, int64_t b, const double* win64, double phi,
-                               double gnorm, double* coef, void* zs, hipStream_t st) {
+static hipError_t launch_iir_m(int stage, int prec, const IirStream& one, const IirStream* tab, int nstreams,
+                               int64_t nsegt, int64_t max_nseg, int N, const double* win64, double phi,
+                               double gnorm, double* coef, double* scoef, void* zs, hipStream_t st) {
   const int L = prec == F32 ? kIirSegF32 : kIirSegF64;
-  const int64_t nseg = (b + L - 1) / L;
-  if (nseg > kIirMaxSeg) return hipErrorNotSupported;  // segments run along the grid's y dimension
-  const dim3 gcol((unsigned)((N + 63) / 64));
-  const dim3 grid((unsigned)((N + 255) / 256), (unsigned)nseg);
-  const dim3 grid64((unsigned)((N + 63) / 64), (unsigned)nseg);
+  const int t256 = (N + 255) / 256, t64 = (N + 63) / 64;
+  if (nsegt * t64 > 0x7fffffffLL) return hipErrorNotSupported;  // one-dimensional grids
   switch (stage) {
     case kIirSetup:
-      k_iir_setup<M><<<gcol, 64, 0, st>>>(win64, N, phi, b, L, coef);
+      k_iir_setup<M><<<dim3((unsigned)((N + 63) / 64)), 64, 0, st>>>(win64, N, phi, L, coef);
+      break;
+    case kIirSetupLen:
+      k_iir_setup_len<M><<<dim3((unsigned)(((int64_t)nstreams * N + 63) / 64)), 64, 0, st>>>(N, L, one, tab,
+                                                                                              nstreams, coef, scoef);
       break;
     case kIirPass1:
-      if (prec == F32) k_iir_zs<float, M, kIirSegF32><<<grid, 256, 0, st>>>((const float*)x, N, b, coef, (float*)zs);
-      else k_iir_zs<double, M, kIirSegF64><<<grid, 256, 0, st>>>((const double*)x, N, b, coef, (double*)zs);
+      if (prec == F32)
+        k_iir_zs<float, M, kIirSegF32><<<dim3((unsigned)(nsegt * t256)), 256, 0, st>>>(N, t256, nsegt, one, tab,
+                                                                                       nstreams, coef, (float*)zs);
+      else
+        k_iir_zs<double, M, kIirSegF64><<<dim3((unsigned)(nsegt * t256)), 256, 0, st>>>(N, t256, nsegt, one, tab,
+                                                                                        nstreams, coef, (double*)zs);
       break;
-    case kIirCarry:
-      {
-        const dim3 g4((unsigned)((N + 3) / 4));  // one wavefront per column
-        const bool regs = nseg <= 64 * kIirCarryQ;
-        if (prec == F32) {
-          if (regs) k_iir_carry<float, M, kIirCarryQ><<<g4, 256, 0, st>>>(N, nseg, coef, (float*)zs);
-          else k_iir_carry<float, M, 0><<<g4, 256, 0, st>>>(N, nseg, coef, (float*)zs);
-        } else {
-          if (regs) k_iir_carry<double, M, kIirCarryQ><<<g4, 256, 0, st>>>(N, nseg, coef, (double*)zs);
-          else k_iir_carry<double, M, 0><<<g4, 256, 0, st>>>(N, nseg, coef, (double*)zs);
-        }
+    case kIirCarry: {
+      const dim3 g4((unsigned)((int64_t)nstreams * ((N + 3) / 4)));  // one wavefront per (stream, column)
+#define CARRY(T, Q) k_iir_carry<T, M, Q><<<g4, 256, 0, st>>>(N, L, one, tab, nstreams, coef, scoef, (T*)zs)
+      if (prec == F32) {
+        if (max_nseg <= 64 * 4) CARRY(float, 4);
+        else if (max_nseg <= 64 * 8) CARRY(float, 8);
+        else CARRY(float, 0);
+      } else {
+        if (max_nseg <= 64 * 4) CARRY(double, 4);
+        else if (max_nseg <= 64 * 8) CARRY(double, 8);
+        else CARRY(double, 0);
       }
+#undef CARRY
       break;
+    }
     default:
       if (prec == F32)
-        k_iir_apply<float, M, kIirSegF32><<<grid64, 64, 0, st>>>((float*)x, N, b, coef, (const float*)zs, gnorm);
+        k_iir_apply<float, M, kIirSegF32><<<dim3((unsigned)(nsegt * t64)), 64, 0, st>>>(N, t64, one, tab, nstreams,
+                                                                                        coef, (const float*)zs, gnorm);
       else
-        k_iir_apply<double, M, kIirSegF64><<<grid64, 64, 0, st>>>((double*)x, N, b, coef, (const double*)zs, gnorm);
+        k_iir_apply<double, M, kIirSegF64><<<dim3((unsigned)(nsegt * t64)), 64, 0, st>>>(N, t64, one, tab, nstreams,
+                                                                                         coef, (const double*)zs, gnorm);
       break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_col_iir(int stage, int prec, void* x, int N, int ntap, int64_t b, const double* win64, double phi,
-                          double gnorm, double* coef, void* zs, hipStream_t st) {
-  if (b < 1 || N < 1) return hipSuccess;
+hipError_t launch_col_iir(int stage, int prec, const IirStream& one, const IirStream* tab, int nstreams,
+                          int64_t nsegt, int64_t max_nseg, int N, int ntap, const double* win64, double phi,
+                          double gnorm, double* coef, double* scoef, void* zs, hipStream_t st) {
+  if (N < 1 || nsegt < 1) return hipSuccess;
   switch (ntap) {
-    case 4: return launch_iir_m<3>(stage, prec, x, N, b, win64, phi, gnorm, coef, zs, st);
+    case 4:
+      return launch_iir_m<3>(stage, prec, one, tab, nstreams, nsegt, max_nseg, N, win64, phi, gnorm, coef, scoef, zs,
+                             st);
     default: return hipErrorNotSupported;
   }
 }

@@ -113,10 +113,25 @@ struct RowPCfg {
   static constexpr int LDSB = LDSB0 + (WT_LDS ? H * (int)sizeof(cx<T>) : 0);
 };
 
-template <typename T, int LOG2N>
+// The stream of global frame j: the last s with f0[s] <= j.
+__device__ __forceinline__ int row_stream_of(int64_t j, const RowStream* __restrict__ tab, int nstreams) {
+  int lo = 0, hi = nstreams - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].f0 <= j) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// MULTI: the frames of nstreams streams (tab: their spectra, scales,
+// outputs and first global frames), numbered one stream after another; the
+// per-channel factors are formed again whenever a workgroup moves to another
+// stream. Otherwise one stream (in, chan_scale, out, nrows).
+template <typename T, int LOG2N, bool MULTI>
 __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
-    const unsigned char* __restrict__ in, const float* __restrict__ chan_scale, T* __restrict__ out,
-    int64_t nrows, const cx<T>* __restrict__ twN) {
+    const unsigned char* __restrict__ in1, const float* __restrict__ scale1, T* __restrict__ out1,
+    int64_t nrows, const cx<T>* __restrict__ twN, const RowStream* __restrict__ tab, int nstreams) {
   using Cfg = RowPCfg<T, LOG2N>;
   constexpr int N = 1 << LOG2N, H = Cfg::H, NT = Cfg::NT, LS = Cfg::LS, EPT = Cfg::EPT;
   constexpr int RAWW = Cfg::RAWW, DPT = Cfg::DPT;
@@ -126,14 +141,26 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
   __shared__ cx<T> wt[Cfg::WT_LDS ? H : 1];  // e^{+2 pi i k / N}: pre-twiddles
   __shared__ unsigned int raw[RAWW];
   const int tid = threadIdx.x;
-  const int64_t total = nrows * (int64_t)(H + 1);
   // dequantisation factor 1/(s_k N), formed in FP64 from the stored FP32 scale
-  for (int k = tid; k <= H; k += NT) facs[k] = T(1.0 / ((double)chan_scale[k] * (double)N));
+  auto set_facs = [&](const float* sc) {
+    for (int k = tid; k <= H; k += NT) facs[k] = T(1.0 / ((double)sc[k] * (double)N));
+  };
+  if (!MULTI) set_facs(scale1);
   if constexpr (Cfg::WT_LDS)
     for (int k = tid; k < H; k += NT) wt[k] = conj(twN[k]);
   unsigned int pf[DPT];
+  int snext = 0;  // MULTI: the stream of the frame fetched last
   auto fetch = [&](int64_t j) {
-    const int64_t b0 = j * (int64_t)(H + 1);
+    const unsigned char* in = in1;
+    int64_t jl = j, rows = nrows;
+    if constexpr (MULTI) {
+      snext = row_stream_of(j, tab, nstreams);
+      in = tab[snext].spec;
+      jl = j - tab[snext].f0;
+      rows = tab[snext].b;
+    }
+    const int64_t total = rows * (int64_t)(H + 1);
+    const int64_t b0 = jl * (int64_t)(H + 1);
     const int64_t a0 = b0 & ~int64_t(3);
     const int nd = (int)((b0 + H + 1 - a0 + 3) >> 2);
 #pragma unroll
@@ -155,9 +182,16 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
       }
     }
   };
+  int scur = -1;
   int64_t j = blockIdx.x;
   if (j < nrows) fetch(j);
   for (; j < nrows; j += gridDim.x) {
+    const int sj = snext;
+    if (MULTI && sj != scur) {  // uniform: the whole workgroup moves to another stream
+      __syncthreads();          // the previous frame's factor reads are done
+      set_facs(tab[sj].scale);
+      scur = sj;
+    }
 #pragma unroll
     for (int d = 0; d < DPT; ++d) {
       const int idx = tid + d * NT;
@@ -165,7 +199,8 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
     }
     __syncthreads();
     if (j + gridDim.x < nrows) fetch(j + gridDim.x);  // in flight during the FFT
-    const unsigned char* rb = reinterpret_cast<const unsigned char*>(raw) + (int)((j * (int64_t)(H + 1)) & 3);
+    const int64_t jl = MULTI ? j - tab[sj].f0 : j;
+    const unsigned char* rb = reinterpret_cast<const unsigned char*>(raw) + (int)((jl * (int64_t)(H + 1)) & 3);
     // one dequantised pair (Y_k, Y_{H-k}) gives Z_k = a + i t and, since
     // e^{+2 pi i (H-k)/N} = -conj e^{+2 pi i k/N}, Z_{H-k} = conj(a) + i conj(t)
     constexpr int HH = H / 2;
@@ -190,7 +225,8 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
     // the FFT's own twiddles stay in global memory (L2): an LDS copy would
     // cost a workgroup per CU, which costs more than their latency
     lds_fft<T, H, NT, 1, +1, true>(s, LS, twN, 2);  // twN: all N entries
-    cx<T>* orow = reinterpret_cast<cx<T>*>(out + j * (int64_t)N);
+    T* out = MULTI ? (T*)tab[sj].out : out1;
+    cx<T>* orow = reinterpret_cast<cx<T>*>(out + jl * (int64_t)N);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int m = tid + i * NT;
@@ -242,14 +278,19 @@ hipError_t launch_row_irfft(int prec, int log2n, int fmt, const void* in, const 
 
 template <typename T, int LOG2N>
 static hipError_t launch_row_c4_t(const void* in, const float* chan_scale, void* out, int64_t nrows,
-                                  const void* twN, hipStream_t st) {
+                                  const void* twN, const RowStream* tab, int nstreams, hipStream_t st) {
   if constexpr (LOG2N >= 9 && RowPCfg<T, LOG2N>::LDSB <= 81920) {
     using Cp = RowPCfg<T, LOG2N>;
-    const int64_t res = resident_workgroups(k_row_c4p<T, LOG2N>, Cp::NT);  // (cached after the first call)
+    const int64_t res = tab ? resident_workgroups(k_row_c4p<T, LOG2N, true>, Cp::NT)
+                            : resident_workgroups(k_row_c4p<T, LOG2N, false>, Cp::NT);  // (cached after the first call)
     if (nrows == 0) return hipSuccess;
     const int64_t g = nrows < res ? nrows : res;
-    k_row_c4p<T, LOG2N><<<dim3((unsigned)g), dim3(Cp::NT), 0, st>>>(
-        (const unsigned char*)in, chan_scale, (T*)out, nrows, (const cx<T>*)twN);
+    if (tab)
+      k_row_c4p<T, LOG2N, true><<<dim3((unsigned)g), dim3(Cp::NT), 0, st>>>(
+          nullptr, nullptr, nullptr, nrows, (const cx<T>*)twN, tab, nstreams);
+    else
+      k_row_c4p<T, LOG2N, false><<<dim3((unsigned)g), dim3(Cp::NT), 0, st>>>(
+          (const unsigned char*)in, chan_scale, (T*)out, nrows, (const cx<T>*)twN, nullptr, 0);
     return hipGetLastError();
   } else {
     return hipErrorNotSupported;
@@ -257,10 +298,10 @@ static hipError_t launch_row_c4_t(const void* in, const float* chan_scale, void*
 }
 
 #define ROWC4_CASE(T, L) \
-  case L: return launch_row_c4_t<T, L>(in, chan_scale, out, nrows, twN, st);
+  case L: return launch_row_c4_t<T, L>(in, chan_scale, out, nrows, twN, tab, nstreams, st);
 
 hipError_t launch_row_c4(int prec, int log2n, const void* in, const float* chan_scale, void* out, int64_t nrows,
-                         const void* twN, hipStream_t st) {
+                         const void* twN, hipStream_t st, const RowStream* tab, int nstreams) {
   if (prec == F32) {
     switch (log2n) {
       ROWC4_CASE(float, 9) ROWC4_CASE(float, 10) ROWC4_CASE(float, 11) ROWC4_CASE(float, 12)

@@ -49,25 +49,45 @@ hipError_t launch_dequant_factors(int prec, const float* chan_scale, int nchan, 
 // no such kernel (then use launch_dequant_factors + launch_row_irfft).
 // nrows = 0 launches nothing (it primes the occupancy query, for callers that
 // later launch inside a graph capture).
+// tab != NULL: the frames of nstreams streams at once (nrows = their total;
+// in, chan_scale and out unused), numbered one stream after another.
+struct RowStream {
+  const unsigned char* spec;  // packed 4-bit spectra [b][N/2+1]
+  const float* scale;         // channel scales [N/2+1]
+  void* out;                  // frames [b][N]
+  int64_t b;                  // frame count
+  int64_t f0;                 // first global frame
+};
 hipError_t launch_row_c4(int prec, int log2n, const void* in, const float* chan_scale, void* out, int64_t nrows,
-                         const void* twN, hipStream_t st);
+                         const void* twN, hipStream_t st, const RowStream* tab = nullptr, int nstreams = 0);
 
 // Column stage as two recursions along the frames (the spectral
 // factorisation of |W_n|^2 + phi^2 into causal and anti-causal parts), in
-// place on the frame matrix x [b][N]: rows of frames, segments of
-// kIirSeg{F32,F64} frames, one launch per stage: kIirSetup computes the
-// per-column coefficients for this phi into coef (N * iir_coef_stride(ntap)
-// doubles), kIirPass1 the segments' zero-state end states into zs
-// (ceil(b / seg) * N * 2 (ntap - 1) values of the plan precision), kIirCarry
-// the periodic states entering each segment (over zs), kIirApply the two
-// recursions from those states, writing xhat over x. hipErrorNotSupported
-// (nothing launched) for tap counts without a kernel.
+// place on the frame matrices x [b][N] of one or many streams: segments of
+// kIirSeg{F32,F64} frames, numbered across the streams one after another
+// (stream s owns global segments [seg0, seg0 + ceil(b / seg))). One launch
+// per stage: kIirSetup computes the per-column coefficients for this phi
+// into coef (N * iir_coef_stride(ntap) doubles), kIirSetupLen the
+// per-(stream, column) matrices of each stream's length into scoef
+// (nstreams * N * iir_stream_stride(ntap) doubles), kIirPass1 the segments'
+// zero-state end states into zs (nsegt * N * 2 (ntap - 1) values of the plan
+// precision), kIirCarry the periodic states entering each segment (over
+// zs), kIirApply the two recursions from those states, writing xhat over x.
+// One stream: `one` describes it and tab is unused; several: tab is a device
+// array of nstreams entries. max_nseg: the most segments of any stream.
+// hipErrorNotSupported (nothing launched) for tap counts without a kernel.
 constexpr int kIirSegF32 = 64, kIirSegF64 = 64;
-constexpr int64_t kIirMaxSeg = 65535;  // segments per column
+struct IirStream {
+  void* x;       // the stream's frames [b][N], transformed in place
+  int64_t b;     // its frame count
+  int64_t seg0;  // its first global segment
+};
+enum { kIirSetup = 0, kIirSetupLen = 1, kIirPass1 = 2, kIirCarry = 3, kIirApply = 4 };
 int iir_coef_stride(int ntap);
-enum { kIirSetup = 0, kIirPass1 = 1, kIirCarry = 2, kIirApply = 3 };
-hipError_t launch_col_iir(int stage, int prec, void* x, int N, int ntap, int64_t b, const double* win64, double phi,
-                          double gnorm, double* coef, void* zs, hipStream_t st);
+int iir_stream_stride(int ntap);
+hipError_t launch_col_iir(int stage, int prec, const IirStream& one, const IirStream* tab, int nstreams,
+                          int64_t nsegt, int64_t max_nseg, int N, int ntap, const double* win64, double phi,
+                          double gnorm, double* coef, double* scoef, void* zs, hipStream_t st);
 
 // Column stage on the transposed frame matrix: per column n (contiguous in
 // d_T[n][0..b)), x_T[n] = F^-1[ G_n F d_T[n] ] with the FP64 gain.

@@ -31,6 +31,7 @@ EXPORTS = (
     "ipfb_batched_set_shape", "ipfb_batched_tune", "ipfb_stream_plan_create", "ipfb_stream_plan_destroy",
     "ipfb_wiener_stream", "ipfb_delta_analytic", "ipfb_autospectrum_error", "ipfb_mask_structured",
     "ipfb_wiener_filter", "ipfb_mask_pack", "ipfb_ml_cg_noalloc", "ipfb_plan_set_column_method",
+    "ipfb_batched_set_column_method",
 )
 COLS_AUTO, COLS_FFT, COLS_RECURSIVE = 0, 1, 2
 FILTER_WIENER, FILTER_THRESHOLD, FILTER_NU = 0, 1, 2
@@ -63,6 +64,7 @@ def lib():
         L.ipfb_plan_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
         L.ipfb_plan_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
         L.ipfb_plan_set_column_method.argtypes = [vp, i32]
+        L.ipfb_batched_set_column_method.argtypes = [vp, i32]
         L.pfb_forward.argtypes = [vp, vp, vp, vp]
         L.pfb_adjoint.argtypes = [vp, vp, vp, vp]
         L.ipfb_wiener.argtypes = [vp, i32, vp, vp, dbl, vp, vp]
@@ -433,6 +435,10 @@ class BatchedPlan:
     def real_dtype(self):
         import torch
         return torch.float32 if self.prec == F32 else torch.float64
+
+    def set_column_method(self, method: int):
+        """COLS_AUTO, COLS_FFT or COLS_RECURSIVE (see ipfb_batched_set_column_method)."""
+        _check(lib().ipfb_batched_set_column_method(self._h, int(method)))
 
     def use_graph(self, on: bool):
         _check(lib().ipfb_batched_use_graph(self._h, int(bool(on))))

@@ -1,6 +1,9 @@
 """GPU tests of the batched form: streams of uneven (arbitrary) nblock in one
-call, Bluestein column DFTs for lengths that are not powers of two, replayed
-from one captured HIP graph; every stream against the FP64 oracle."""
+call, replayed from one captured HIP graph; every stream against the FP64
+oracle. Two column stages: the recursive one over all streams at once (the
+default for 4 taps and phi > 0) and the per-stream FFT path with Bluestein
+column DFTs for lengths that are not powers of two (COLS_FFT; its shapes and
+autotuner are tested with it forced)."""
 import numpy as np
 import pytest
 
@@ -29,13 +32,15 @@ def _streams(N, p, nblocks, seed0):
     return w, out
 
 
+@pytest.mark.parametrize("method", [ipfb.COLS_AUTO, ipfb.COLS_FFT])
 @pytest.mark.parametrize("prec,tol", [(ipfb.F64, 1e-11), (ipfb.F32, 1e-5)])
-def test_batched_small_uneven(prec, tol):
+def test_batched_small_uneven(prec, tol, method):
     N, p = 64, 4
     nblocks = [12, 37, 64, 100, 129, 5, 3, 2, 16, 1031]
-    print(f"case batched small prec={prec}", flush=True)
+    print(f"case batched small prec={prec} method={method}", flush=True)
     w, data = _streams(N, p, nblocks, 4000)
     bp = ipfb.BatchedPlan(N, p, w, nblocks, prec)
+    bp.set_column_method(method)
     specs = [torch.from_numpy(pk).cuda() for pk, _ in data]
     scs = [torch.from_numpy(sc).cuda() for _, sc in data]
     for phi in (0.1, 0.0):
@@ -66,13 +71,16 @@ def test_batched_ci8_uneven(prec, tol):
         assert _rel(xo.cpu().numpy().astype(np.float64), ref) < tol, b
 
 
-def test_batched_production_lengths_fp32():
-    # production frame length with Bluestein lengths up to M = 65536
+@pytest.mark.parametrize("method", [ipfb.COLS_AUTO, ipfb.COLS_FFT])
+def test_batched_production_lengths_fp32(method):
+    # production frame length with Bluestein lengths up to M = 65536 (FFT),
+    # up to 257 segments of a stream (recursive)
     N, p = 4096, 4
     nblocks = [1031, 3000, 16385, 2048]
-    print("case batched production lengths", flush=True)
+    print(f"case batched production lengths method={method}", flush=True)
     w, data = _streams(N, p, nblocks, 4100)
     bp = ipfb.BatchedPlan(N, p, w, nblocks, ipfb.F32)
+    bp.set_column_method(method)
     outs = ipfb.wiener_batched(bp, [torch.from_numpy(pk).cuda() for pk, _ in data],
                                [torch.from_numpy(sc).cuda() for _, sc in data], 0.1)
     torch.cuda.synchronize()
@@ -83,7 +91,8 @@ def test_batched_production_lengths_fp32():
         assert err < 1e-5
 
 
-def test_batched_graph_replays_match_eager():
+@pytest.mark.parametrize("method", [ipfb.COLS_AUTO, ipfb.COLS_FFT])
+def test_batched_graph_replays_match_eager(method):
     N, p = 128, 4
     nblocks = [40, 64, 77, 300]
     w, data = _streams(N, p, nblocks, 4200)
@@ -91,8 +100,10 @@ def test_batched_graph_replays_match_eager():
     scs = [torch.from_numpy(sc).cuda() for _, sc in data]
     eager = ipfb.BatchedPlan(N, p, w, nblocks, ipfb.F32)
     eager.use_graph(False)
+    eager.set_column_method(method)
     ref = [t.cpu().numpy() for t in ipfb.wiener_batched(eager, specs, scs, 0.1)]
     bp = ipfb.BatchedPlan(N, p, w, nblocks, ipfb.F32)
+    bp.set_column_method(method)
     outs = [torch.empty(b * N, dtype=torch.float32, device="cuda") for b in nblocks]
     for rep in range(4):
         for o in outs:
@@ -137,6 +148,7 @@ def test_batched_every_shape_matches_oracle(prec, tol, p):
     w, data = _streams(N, p, nblocks, 4300)
     bp = ipfb.BatchedPlan(N, p, w, nblocks, prec)
     bp.use_graph(False)
+    bp.set_column_method(ipfb.COLS_FFT)
     assert bp.conv_lengths() == [7, 10, 12]
     for m in bp.conv_lengths():
         d = (m + 1) // 2
@@ -177,6 +189,7 @@ def test_batched_autotuner_and_cache(tmp_path, monkeypatch):
     w, data = _streams(N, p, nblocks, 4400)
     cache = tmp_path / "tune.json"
     bp = ipfb.BatchedPlan(N, p, w, nblocks, ipfb.F32)
+    bp.set_column_method(ipfb.COLS_FFT)
     tuned = bp.tune(str(cache))
     assert set(tuned) == {10, 11, 12}
     doc = json.loads(cache.read_text())
@@ -190,6 +203,7 @@ def test_batched_autotuner_and_cache(tmp_path, monkeypatch):
     # a plan created with the cache in the environment installs the same shapes
     monkeypatch.setenv("IPFB_TUNE_CACHE", str(cache))
     bp2 = ipfb.BatchedPlan(N, p, w, nblocks, ipfb.F32)
+    bp2.set_column_method(ipfb.COLS_FFT)
     assert {m: bp2.get_shape(m) for m in bp2.conv_lengths()} == tuned
     _check_streams(bp2, data, nblocks, w, N, p, 1e-5, "from cache")
     # a hand-edited entry (other spacing, extra field) is read as well
@@ -197,6 +211,7 @@ def test_batched_autotuner_and_cache(tmp_path, monkeypatch):
     cache.write_text('{ "entries" : { "%s" : { "note": "manual", "l1" : 4, "mb": 32, "kb": 8, "pchunk": 3, '
                      '"us": 1.0 } }, "version": 1 }' % key)
     bp3 = ipfb.BatchedPlan(N, p, w, nblocks, ipfb.F32)
+    bp3.set_column_method(ipfb.COLS_FFT)
     assert bp3.get_shape(11) == (4, 32, 8, 3, 1, 0)  # no "fuse" or "nat" field: fused, transposed
     assert bp3.get_shape(10) == (5, 16, 16, 0, 1, 0)  # no entry: default
     _check_streams(bp3, data, nblocks, w, N, p, 1e-5, "hand-edited")
@@ -207,7 +222,8 @@ def test_batched_autotuner_and_cache(tmp_path, monkeypatch):
     assert doc["entries"][key]["l1"] == 4
 
 
-def test_batched_full_workload_sampled_columns():
+@pytest.mark.parametrize("method", [ipfb.COLS_AUTO, ipfb.COLS_FFT])
+def test_batched_full_workload_sampled_columns(method):
     # the benchmarked configuration itself: 256 streams, nblock ~ U[1024, 32768]
     # (seed 4), lblock 4096, 4-bit, one graph launch with autotuned shapes;
     # sampled columns of four streams (the shortest, the longest, a prime
@@ -216,7 +232,7 @@ def test_batched_full_workload_sampled_columns():
     import math
     N, p, phi = 4096, 4, 0.1
     nbl = [int(b) for b in I.batched_nblocks(256, 1024, 32768, 4)]
-    print(f"case batched full workload: {sum(nbl) * N} samples", flush=True)
+    print(f"case batched full workload: {sum(nbl) * N} samples, method={method}", flush=True)
     w = O.window_sinc_hamming(p, N)
     specs, scales, outs = [], [], []
     for s_, b in enumerate(nbl):
@@ -230,8 +246,10 @@ def test_batched_full_workload_sampled_columns():
         outs.append(torch.empty(b * N, dtype=torch.float32, device="cuda"))
         del x, plan
     bp = ipfb.BatchedPlan(N, p, w, nbl, ipfb.F32)
-    shapes = bp.tune()
-    print(f"tuned shapes {shapes}", flush=True)
+    bp.set_column_method(method)
+    if method == ipfb.COLS_FFT:
+        shapes = bp.tune()
+        print(f"tuned shapes {shapes}", flush=True)
     ipfb.wiener_batched(bp, specs, scales, phi, x_outs=outs)
     torch.cuda.synchronize()
     isprime = lambda v: v > 1 and all(v % q for q in range(2, int(math.isqrt(v)) + 1))
@@ -249,3 +267,23 @@ def test_batched_full_workload_sampled_columns():
         assert err < 1e-5
     del outs, specs, scales, bp
     torch.cuda.empty_cache()
+
+
+def test_batched_recursive_equals_single_stream_plans():
+    # the multi-stream launches give each stream what its own plan gives
+    N, p = 256, 4
+    nblocks = [3, 64, 65, 1000, 4097]
+    print("case batched recursive vs single plans", flush=True)
+    w, data = _streams(N, p, nblocks, 4500)
+    specs = [torch.from_numpy(pk).cuda() for pk, _ in data]
+    scs = [torch.from_numpy(sc).cuda() for _, sc in data]
+    bp = ipfb.BatchedPlan(N, p, w, nblocks, ipfb.F64)
+    bp.set_column_method(ipfb.COLS_RECURSIVE)
+    for phi in (0.1, 0.3):
+        outs = ipfb.wiener_batched(bp, specs, scs, phi)
+        for b, sp, sc, o in zip(nblocks, specs, scs, outs):
+            plan = ipfb.Plan(N, p, w, b, ipfb.F64)
+            plan.set_column_method(ipfb.COLS_RECURSIVE)
+            single = ipfb.ipfb_wiener(plan, sp, sc, phi)
+            torch.cuda.synchronize()
+            assert _rel(o.cpu().numpy(), single.cpu().numpy()) < 1e-14, (b, phi)
