@@ -599,3 +599,88 @@ def analytic_delta(window, lblock, ntap, nfreq, phi=None, snr=None):
     if phi is None:
         return (1.0 / snr) * np.mean(1.0 / a2, axis=1)
     return 1.0 - np.mean(a2 / (a2 + phi * phi), axis=1)
+
+
+# ----------------------------------------------------------------------------
+# The alternative solvers of Appendix C (time complexity): a Tikhonov-
+# regularised solve of the linear sub-problem by banded Cholesky, and FIR
+# filtering with truncated decorrelation kernels.
+# ----------------------------------------------------------------------------
+
+
+def linear_subproblem(wn: np.ndarray, nblock: int) -> np.ndarray:
+    """W_n of the sub-filter equation (Section 2.3): the [b-p+1, b] Toeplitz
+    matrix with W[k][k+r] = w_n[r], built entry by entry."""
+    p = len(wn)
+    W = np.zeros((nblock - p + 1, nblock))
+    for k in range(nblock - p + 1):
+        for r in range(p):
+            W[k, k + r] = wn[r]
+    return W
+
+
+def tikhonov_banded(d_lin: np.ndarray, window: np.ndarray, lblock: int, ntap: int, phi: float,
+                    normalise: bool = True) -> np.ndarray:
+    """Per column, the Tikhonov-regularised solution of the linear sub-problem
+    d_n = W_n x_n (Appendix C: the Wiener machinery replicated by a
+    pseudo-inverse with Tikhonov regularisation, solved by banded Cholesky):
+    x_n = c (W_n^T W_n + phi^2 I)^{-1} W_n^T d_n, c = 1 + phi^2 (normalise)
+    or 1. d_lin: [b - p + 1, N] frames after the row inverse of a linear PFB;
+    returns [b, N]. W^T W + phi^2 I has bandwidth p - 1; scipy's banded
+    Cholesky solver (LAPACK pbsv) is the library step."""
+    from scipy.linalg import solveh_banded
+    d_lin = np.asarray(d_lin, dtype=np.float64)
+    nspec = d_lin.shape[0]
+    b = nspec + ntap - 1
+    H = np.asarray(window, dtype=np.float64).reshape(ntap, lblock)
+    c = (1.0 + phi * phi) if normalise else 1.0
+    x = np.zeros((b, lblock))
+    for n in range(lblock):
+        W = linear_subproblem(H[:, n], b)
+        A = W.T @ W + phi * phi * np.eye(b)
+        # lower banded storage: ab[t, i] = A[i + t, i]
+        ab = np.zeros((ntap, b))
+        for t in range(ntap):
+            ab[t, :b - t] = np.diagonal(A, -t)
+        x[:, n] = c * solveh_banded(ab, W.T @ d_lin[:, n], lower=True)
+    return x
+
+
+def fir_kernels(window: np.ndarray, lblock: int, ntap: int, nblock: int, phi: float, ltaps: int,
+                normalise: bool = True) -> np.ndarray:
+    """The decorrelation kernels of Section 3.1 / Appendix C, truncated to
+    ltaps (odd) lags: the circulant Wiener inverse's impulse response (its
+    output for d = a unit sample at frame 0), g_n[t] for the lags
+    t = c - T .. c + T, T = (ltaps-1)/2, taken mod b. READING: the kernels are
+    centred on c = p // 2, the delay of the window's main lobe (the sinc peaks
+    at sample M/2 = (p/2) N, so the inverse filters peak at lag p/2); the
+    paper does not say where its truncated kernels start. Returns [ltaps, N]."""
+    T = (ltaps - 1) // 2
+    delta = np.zeros((nblock, lblock))
+    delta[0] = 1.0
+    c = column_inverse(delta, window, lblock, ntap, phi, normalise)
+    return c[(np.arange(-T, T + 1) + ntap // 2) % nblock]
+
+
+def fir_apply(d: np.ndarray, g: np.ndarray, center: int) -> np.ndarray:
+    """x_n[j] = sum_t g_n[t] d_n[(j - t) mod b] over the kernels' lags
+    t = center - T .. center + T (FIR filtering of each sub-filter path with
+    its decorrelation kernel, Appendix C)."""
+    d = np.asarray(d, dtype=np.float64)
+    b = d.shape[0]
+    T = (g.shape[0] - 1) // 2
+    x = np.zeros_like(d)
+    j = np.arange(b)
+    for i, t in enumerate(range(center - T, center + T + 1)):
+        x += g[i][None, :] * d[(j - t) % b]
+    return x
+
+
+def ipfb_fir(packed: np.ndarray, scales_f32: np.ndarray, window: np.ndarray, lblock: int, ntap: int,
+             phi: float, ltaps: int, normalise: bool = True) -> np.ndarray:
+    """Dequantise 4-bit spectra, row inverse, FIR decorrelation with the
+    truncated kernels; returns x[j*N + n]."""
+    qr, qi = unpack_c4(packed)
+    d = row_inverse(dequantize(qr, qi, scales_f32), lblock)
+    g = fir_kernels(window, lblock, ntap, d.shape[0], phi, ltaps, normalise)
+    return fir_apply(d, g, ntap // 2).reshape(-1)
