@@ -422,6 +422,50 @@ def streaming_form(torch, ipfb, nframes=65536, chunk=8192, halo=256):
                        "halo": halo, "phi": phi, "dtype": "f32", "boundary": "linear"}}
 
 
+def alt_solvers(torch, ipfb, taps=(4, 8, 16), ltaps=(51, 101, 201), N=4096, b=16384, phi=0.1):
+    """Appendix C's cost comparison, measured: the circulant Wiener inverse
+    beside the Tikhonov solve of the linear sub-problems (banded Cholesky,
+    O(b p^2) per path) and FIR decorrelation with kernels truncated to L lags
+    (O(b L) per path), FP32, phi = 0.1, at p = 4, 8, 16 taps. Input: white
+    noise (torch seed 8), 2^26 samples (lblock 4096, nblock 16384), channelised
+    by the library's FP64 forward PFB and quantised to 4 bits (RMS 2.5 levels);
+    the Tikhonov solver takes the first nblock - p + 1 spectra (the ones that
+    do not wrap: a linear PFB's). Each solver's error is its relative RMS
+    difference from the original timestream (Tikhonov: over all frames, its
+    ends included); the FIR forms also against the circulant result."""
+    out = {"config": {"lblock": N, "nblock": b, "samples": N * b, "phi": phi, "dtype": "f32", "levels_rms": 2.5}}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(8)
+    x = torch.randn(N * b, generator=g, device="cuda", dtype=torch.float64)
+
+    def rel(a, ref):
+        return float(torch.linalg.vector_norm(a.double() - ref) / torch.linalg.vector_norm(ref))
+
+    for p in taps:
+        w = ipfb.window_sinc_hamming(p, N)
+        plan64 = ipfb.Plan(N, p, w, b, ipfb.F64)
+        pk, sc = ipfb.quantize_c4(plan64, ipfb.pfb_forward(plan64, x), 2.5)
+        plan64.close()
+        plan = ipfb.Plan(N, p, w, b, ipfb.F32)
+        xo = torch.empty(N * b, dtype=torch.float32, device="cuda")
+        r = {}
+        sec = time_steps(torch, lambda: ipfb.ipfb_wiener(plan, pk, sc, phi, x_out=xo), 10, 2)
+        xc = xo.clone()
+        r["circulant"] = {"s_per_call": sec, "samples_per_s": N * b / sec, "rel_err": rel(xc, x)}
+        pl = pk[:b - p + 1].contiguous()
+        sec = time_steps(torch, lambda: ipfb.tikhonov(plan, pl, sc, phi, x_out=xo), 3, 1)
+        r["tikhonov"] = {"s_per_call": sec, "samples_per_s": N * b / sec, "rel_err": rel(xo, x)}
+        for L in ltaps:
+            ipfb.fir(plan, pk, sc, phi, L, x_out=xo)  # makes the kernels (not timed)
+            sec = time_steps(torch, lambda: ipfb.fir(plan, pk, sc, phi, L, x_out=xo), 10, 2)
+            r[f"fir_L{L}"] = {"s_per_call": sec, "samples_per_s": N * b / sec, "rel_err": rel(xo, x),
+                              "rel_diff_vs_circulant": rel(xo, xc.double())}
+        out[f"p{p}"] = r
+        del pk, sc, pl, xo, xc
+        plan.close()
+    return out
+
+
 def structured_sweep(torch, ipfb, betas=(0.01, 0.03, 0.05, 0.10), iters=25):
     """Section 4.3's experiment on synthetic data: white noise (torch seed 7)
     through a 2048-channel 4-tap PFB (FP32 form), 4-bit at the 0.353 sigma
@@ -489,6 +533,7 @@ def main():
     ap.add_argument("--batched-streams", type=int, default=256)
     ap.add_argument("--no-stream", action="store_true", help="skip timing the streaming (linear boundary) form")
     ap.add_argument("--no-sweep", action="store_true", help="skip the structured-prior sweep (Section 4.3)")
+    ap.add_argument("--no-alt", action="store_true", help="skip timing the comparison solvers (Appendix C)")
     ap.add_argument("--no-small", action="store_true", help="skip the small configuration's latency")
     ap.add_argument("--no-copy-peak", action="store_true", help="skip timing the plain device copy")
     ap.add_argument("--probe-copy", action="store_true",
@@ -647,6 +692,8 @@ def main():
         out["streaming_form"] = streaming_form(torch, ipfb)
     if not args.no_sweep:
         out["structured_prior_sweep"] = structured_sweep(torch, ipfb)
+    if not args.no_alt:
+        out["alt_solvers"] = alt_solvers(torch, ipfb)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(N, p, Nf, phi, args.cpu_frames, 2)
     print(json.dumps(out), flush=True)

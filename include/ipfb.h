@@ -182,6 +182,37 @@ enum { IPFB_FILTER_WIENER = 0, IPFB_FILTER_THRESHOLD = 1, IPFB_FILTER_NU = 2 };
 int ipfb_wiener_filter(ipfb_plan plan, int infmt, const void* spec, const float* chan_scale, int kind, double param,
                        const double* nu, int normalise, void* x_out, void* stream);
 
+/* The comparison solvers of Appendix C (time complexity), beside the
+ * circulant inverse.
+ * ipfb_tikhonov: per sub-filter path, the Tikhonov-regularised solution of
+ * the LINEAR sub-problem d_n = W_n x_n of Section 2.3 (W_n the
+ * [nblock - ntap + 1, nblock] Toeplitz matrix of the path's taps, no
+ * circulant extension): x_n = c (W_n^T W_n + phi^2 I)^{-1} W_n^T d_n,
+ * c = 1 + phi^2 (normalise = 1) or 1, solved by banded Cholesky (bandwidth
+ * ntap - 1: O(nblock ntap^2) per path, sequential along the frames, the
+ * paths in parallel). spec: [nblock - ntap + 1][lblock/2+1] spectra of a
+ * linear (non-wrapping) PFB over nblock frames, in format infmt (chan_scale
+ * as for ipfb_wiener); x_out: [nblock * lblock] real, also used to hold the
+ * frames first. phi > 0; ntap in {2, 3, 4, 5, 8, 16}. The first call
+ * allocates (ntap + 1) * nblock * lblock doubles of workspace.
+ * ipfb_fir_kernels: the Wiener decorrelation kernels (the circulant inverse's
+ * response to a unit sample at frame 0) truncated to ltaps lags
+ * c - T .. c + T, c = ntap / 2 (the window's delay), T = (ltaps - 1)/2,
+ * taken modulo nblock: kernels [ltaps][lblock] real (plan precision), on the
+ * stream. ltaps odd, 1 <= ltaps <= 255, phi > 0. Needs a plan whose column
+ * stage runs in place (power-of-two nblock, or ntap = 4).
+ * ipfb_fir: the inverse with each path's decorrelation done by those
+ * truncated kernels (FIR filtering, O(nblock ltaps) per path):
+ * x_n[j] = sum_t g_n[t] d_n[(j - t) mod nblock]; spec, chan_scale, x_out as
+ * for ipfb_wiener. The kernels are made on the first call and again when
+ * phi, ltaps or normalise change (the first call allocates them:
+ * 255 * lblock reals). */
+int ipfb_tikhonov(ipfb_plan plan, int infmt, const void* spec, const float* chan_scale, double phi, int normalise,
+                  void* x_out, void* stream);
+int ipfb_fir_kernels(ipfb_plan plan, double phi, int ltaps, int normalise, void* kernels, void* stream);
+int ipfb_fir(ipfb_plan plan, int infmt, const void* spec, const float* chan_scale, double phi, int ltaps,
+             int normalise, void* x_out, void* stream);
+
 /* Linear boundary, streaming (Section 3.1: real data are not circulant; the
  * data are extended to b frames, and the circulant inverse corrupts only the
  * samples within a decorrelation-kernel width of the ends). Input: nspec

@@ -112,6 +112,13 @@ struct ipfb_plan_s {
   void* iir_zs = nullptr;
   double iir_phi = NAN;
   int col_method = IPFB_COLS_AUTO;
+  // Appendix C's comparison solvers (allocated on first use): the banded
+  // Cholesky workspace, and the truncated decorrelation kernels with the
+  // (phi, taps, normalisation) they were made for
+  double* tik_ws = nullptr;
+  void* fir_g = nullptr;
+  double fir_phi = NAN;
+  int fir_taps = 0, fir_norm = -1;
   size_t bytes = 0;
   bool ws_ext = false;  // work, work2, tmp point into a caller-owned workspace
 };
@@ -166,7 +173,8 @@ void free_bplan(ipfb_bplan p);
 void free_plan(ipfb_plan p) {
   if (p->blu1) free_bplan(p->blu1);
   void* ptrs[] = {p->win64, p->winT, p->twN, p->twB, p->twB64, p->part, p->fac, p->twS,
-                  p->cg, p->diag, p->iir_coef, p->iir_scoef, p->iir_zs};
+                  p->cg, p->diag, p->iir_coef, p->iir_scoef, p->iir_zs,
+                  p->tik_ws, p->fir_g};
   for (void* q : ptrs)
     if (q) hipFree(q);
   if (!p->ws_ext) {
@@ -640,6 +648,134 @@ int ipfb_wiener(ipfb_plan p, int infmt, const void* spec, const float* chan_scal
                 void* stream) {
   return ipfb_wiener_ex(p, infmt, spec, chan_scale, phi, 1, x_out, stream);
 }
+
+// ---- Appendix C's comparison solvers ---------------------------------------
+namespace {
+
+// The column stage alone, in place on the frame matrix buf [b][N]:
+// the recursive form where it applies, else the FFT form (power-of-two b).
+hipError_t cols_into(ipfb_plan p, void* buf, double phi, int normalise, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (use_recursive(p, phi)) {
+    const int seg = p->prec == IPFB_F32 ? kIirSegF32 : kIirSegF64;
+    const int64_t nseg = (p->nblock + seg - 1) / seg;
+    const IirStream one = {buf, p->nblock, 0};
+    const double gnorm = normalise ? 1.0 + phi * phi : 1.0;
+    for (int stage = (phi == p->iir_phi) ? kIirPass1 : kIirSetup; stage <= kIirApply && e == hipSuccess; ++stage) {
+      e = launch_col_iir(stage, p->prec, one, nullptr, 1, nseg, nseg, p->lblock, p->ntap, p->win64, phi, gnorm,
+                         p->iir_coef, p->iir_scoef, p->iir_zs, st);
+      if (stage <= kIirSetupLen) p->iir_phi = e == hipSuccess ? phi : NAN;
+    }
+    return e;
+  }
+  for (int pass = 0; pass < 3 && e == hipSuccess; ++pass) {
+    if (p->log2b <= 9 && pass != 1) continue;
+    e = launch_col_wiener_nat(p->prec, p->log2b, pass, buf, p->lblock, p->ntap, p->win64, phi, normalise, p->twB,
+                              p->twB64, st, 0, -1, nullptr, 0, 0, 0, nullptr);
+  }
+  return e;
+}
+
+int fir_check(ipfb_plan p, double phi, int ltaps) {
+  if (check_plan(p)) return IPFB_EINVAL;
+  if (!(phi > 0.0) || !std::isfinite(phi)) return fail(IPFB_EINVAL, "phi must be finite and > 0");
+  if (ltaps < 1 || !(ltaps & 1) || ltaps > kFirMaxTaps)
+    return fail(IPFB_EINVAL, "ltaps must be odd and in [1, %d] (got %d)", kFirMaxTaps, ltaps);
+  if (!p->row_lds || !(use_recursive(p, phi) || p->col_lds))
+    return fail(IPFB_EUNSUPPORTED, "the decorrelation kernels need a plan whose column stage runs in place (a "
+                                   "power-of-two nblock, or 4 taps)");
+  return IPFB_OK;
+}
+
+// The truncated kernels into g [ltaps][N] (the column stage applied to a unit
+// sample, through the plan's frame buffer).
+hipError_t fir_kernels_into(ipfb_plan p, double phi, int ltaps, int normalise, void* g, hipStream_t st) {
+  const int64_t c0 = p->ntap / 2 - (ltaps - 1) / 2;
+  hipError_t e = launch_fir_setup(p->prec, 0, p->work, nullptr, p->lblock, p->nblock, ltaps, c0, st);
+  if (e == hipSuccess) e = cols_into(p, p->work, phi, normalise, st);
+  if (e == hipSuccess) e = launch_fir_setup(p->prec, 1, p->work, g, p->lblock, p->nblock, ltaps, c0, st);
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ipfb_tikhonov(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, double phi, int normalise,
+                  void* x_out, void* stream) {
+  if (check_plan(p)) return IPFB_EINVAL;
+  if (!spec || !x_out) return fail(IPFB_EINVAL, "spec and x_out must be non-NULL device pointers");
+  if (check_infmt(infmt, chan_scale)) return IPFB_EINVAL;
+  if (!(phi > 0.0) || !std::isfinite(phi))
+    return fail(IPFB_EINVAL, "phi must be finite and > 0 (W^T W alone is singular: b unknowns, b - p + 1 equations)");
+  if (!p->row_lds) return fail(IPFB_EUNSUPPORTED, "lblock too large for the row stage");
+  if (p->nblock < p->ntap) return fail(IPFB_EINVAL, "nblock must be >= ntap (at least one spectrum)");
+  const int nt = p->ntap;
+  if (nt != 2 && nt != 3 && nt != 4 && nt != 5 && nt != 8 && nt != 16)
+    return fail(IPFB_EUNSUPPORTED, "the banded Cholesky solver takes ntap in {2, 3, 4, 5, 8, 16} (got %d)", nt);
+  DeviceGuard g(p->dev);
+  if (!p->tik_ws) {
+    if (int s2 = dev_alloc(p, (void**)&p->tik_ws, (size_t)(nt + 1) * p->nblock * p->lblock * sizeof(double)))
+      return s2;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t nspec = p->nblock - nt + 1;
+  hipError_t e;
+  {
+    ProfScope ps("tik_rows", st);
+    e = hipErrorNotSupported;
+    if (infmt == IPFB_IN_C4) e = launch_row_c4(p->prec, p->log2n, spec, chan_scale, x_out, nspec, p->twN, st);
+    if (e == hipErrorNotSupported) {
+      hipGetLastError();
+      if (scaled_infmt(infmt)) e = launch_dequant_factors(p->prec, chan_scale, p->lblock / 2 + 1, p->lblock, p->fac, st);
+      else e = hipSuccess;
+      if (e == hipSuccess) e = launch_row_irfft(p->prec, p->log2n, infmt, spec, p->fac, x_out, nspec, p->twN, st);
+    }
+  }
+  if (e == hipSuccess) {
+    ProfScope ps("tik_solve", st);
+    e = launch_tikhonov(p->prec, x_out, p->lblock, nt, p->nblock, p->win64, phi, normalise ? 1.0 + phi * phi : 1.0,
+                        p->tik_ws, st);
+  }
+  return launched(e, "ipfb_tikhonov");
+}
+
+int ipfb_fir_kernels(ipfb_plan p, double phi, int ltaps, int normalise, void* kernels, void* stream) {
+  if (int s = fir_check(p, phi, ltaps)) return s;
+  if (!kernels) return fail(IPFB_EINVAL, "kernels must be a non-NULL device pointer");
+  DeviceGuard g(p->dev);
+  return launched(fir_kernels_into(p, phi, ltaps, normalise, kernels, (hipStream_t)stream), "ipfb_fir_kernels");
+}
+
+int ipfb_fir(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, double phi, int ltaps,
+             int normalise, void* x_out, void* stream) {
+  if (int s = fir_check(p, phi, ltaps)) return s;
+  if (!spec || !x_out) return fail(IPFB_EINVAL, "spec and x_out must be non-NULL device pointers");
+  if (check_infmt(infmt, chan_scale)) return IPFB_EINVAL;
+  DeviceGuard g(p->dev);
+  if (!p->fir_g) {
+    if (int s2 = dev_alloc(p, &p->fir_g, (size_t)kFirMaxTaps * p->lblock * esize(p->prec))) return s2;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  const int nn = normalise ? 1 : 0;
+  if (!(phi == p->fir_phi) || ltaps != p->fir_taps || nn != p->fir_norm) {
+    ProfScope ps("fir_kernels", st);
+    e = fir_kernels_into(p, phi, ltaps, normalise, p->fir_g, st);
+    p->fir_phi = e == hipSuccess ? phi : NAN;
+    p->fir_taps = ltaps;
+    p->fir_norm = nn;
+  }
+  if (e == hipSuccess) e = rows_into(p, infmt, spec, chan_scale, p->work, st);
+  if (e == hipSuccess) {
+    ProfScope ps("fir_apply", st);
+    e = launch_fir(p->prec, p->work, p->fir_g, x_out, p->lblock, p->nblock, ltaps,
+                   p->ntap / 2 - (ltaps - 1) / 2, st);
+  }
+  return launched(e, "ipfb_fir");
+}
+
+}  // extern "C"
 
 // ---- linear boundary, streaming -------------------------------------------
 struct ipfb_splan_s {

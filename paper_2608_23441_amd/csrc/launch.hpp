@@ -89,6 +89,22 @@ hipError_t launch_col_iir(int stage, int prec, const IirStream& one, const IirSt
                           int64_t nsegt, int64_t max_nseg, int N, int ntap, const double* win64, double phi,
                           double gnorm, double* coef, double* scoef, void* zs, hipStream_t st);
 
+// Tikhonov-regularised solve of each path's linear sub-problem by banded
+// Cholesky: x (first b - ntap + 1 rows: d) overwritten with
+// cnorm (W^T W + phi^2 I)^{-1} W^T d; ws: (ntap + 1) * b * N doubles.
+// ntap in {2, 3, 4, 5, 8, 16}, else hipErrorNotSupported.
+hipError_t launch_tikhonov(int prec, void* x, int N, int ntap, int64_t b, const double* win64, double phi,
+                           double cnorm, double* ws, hipStream_t st);
+// FIR decorrelation: stage 0 fills frames [b][N] with a unit sample at frame
+// 0; stage 1 copies lags c0 .. c0 + L - 1 (mod b) of the frames (the kernels,
+// after the column stage) into g [L][N]. launch_fir: x[j][n] = sum_{l<L}
+// g[l][n] d[(j - c0 - l) mod b][n], L <= kFirMaxTaps.
+constexpr int kFirMaxTaps = 255;
+hipError_t launch_fir_setup(int prec, int stage, void* frames, void* g, int N, int64_t b, int L, int64_t c0,
+                            hipStream_t st);
+hipError_t launch_fir(int prec, const void* d, const void* g, void* x, int N, int64_t b, int L, int64_t c0,
+                      hipStream_t st);
+
 // Column stage on the transposed frame matrix: per column n (contiguous in
 // d_T[n][0..b)), x_T[n] = F^-1[ G_n F d_T[n] ] with the FP64 gain.
 // precond = 1 applies the real gain 1/(|W_n|^2 + phi^2) instead (the inverse

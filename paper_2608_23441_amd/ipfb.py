@@ -31,7 +31,7 @@ EXPORTS = (
     "ipfb_batched_set_shape", "ipfb_batched_tune", "ipfb_stream_plan_create", "ipfb_stream_plan_destroy",
     "ipfb_wiener_stream", "ipfb_delta_analytic", "ipfb_autospectrum_error", "ipfb_mask_structured",
     "ipfb_wiener_filter", "ipfb_mask_pack", "ipfb_ml_cg_noalloc", "ipfb_plan_set_column_method",
-    "ipfb_batched_set_column_method",
+    "ipfb_batched_set_column_method", "ipfb_tikhonov", "ipfb_fir_kernels", "ipfb_fir",
 )
 COLS_AUTO, COLS_FFT, COLS_RECURSIVE = 0, 1, 2
 FILTER_WIENER, FILTER_THRESHOLD, FILTER_NU = 0, 1, 2
@@ -65,6 +65,9 @@ def lib():
         L.ipfb_plan_set_workspace.argtypes = [vp, vp, ctypes.c_size_t]
         L.ipfb_plan_set_column_method.argtypes = [vp, i32]
         L.ipfb_batched_set_column_method.argtypes = [vp, i32]
+        L.ipfb_tikhonov.argtypes = [vp, i32, vp, vp, dbl, i32, vp, vp]
+        L.ipfb_fir_kernels.argtypes = [vp, dbl, i32, i32, vp, vp]
+        L.ipfb_fir.argtypes = [vp, i32, vp, vp, dbl, i32, i32, vp, vp]
         L.pfb_forward.argtypes = [vp, vp, vp, vp]
         L.pfb_adjoint.argtypes = [vp, vp, vp, vp]
         L.ipfb_wiener.argtypes = [vp, i32, vp, vp, dbl, vp, vp]
@@ -297,6 +300,40 @@ def _spec_fmt(plan, spec, chan_scale):
     if n != plan.nblock * plan.nchan:
         raise ValueError("spec must hold nblock * (lblock/2+1) values")
     return fmt
+
+
+def tikhonov(plan: Plan, spec, chan_scale=None, phi: float = 0.1, normalise: bool = True, x_out=None,
+             stream=None):
+    """Appendix C's Tikhonov solver of the linear sub-problems (banded
+    Cholesky). spec: [nblock - ntap + 1, nchan] spectra of a linear PFB."""
+    fmt, n = _spec_format(spec, plan.nchan, chan_scale)
+    if n != (plan.nblock - plan.ntap + 1) * plan.nchan:
+        raise ValueError("spec must hold (nblock - ntap + 1) * (lblock/2+1) values")
+    if x_out is None:
+        x_out = _empty((plan.nblock * plan.lblock,), plan.real_dtype)
+    _check(lib().ipfb_tikhonov(plan.handle, fmt, _ptr(spec, "spec"), _ptr(chan_scale, "chan_scale"), float(phi),
+                               int(bool(normalise)), plan._real(x_out, "x_out"), _stream(stream)))
+    return x_out
+
+
+def fir_kernels(plan: Plan, phi: float, ltaps: int, normalise: bool = True, out=None, stream=None):
+    """The truncated decorrelation kernels [ltaps, lblock] (plan precision)."""
+    if out is None:
+        out = _empty((int(ltaps), plan.lblock), plan.real_dtype)
+    _check(lib().ipfb_fir_kernels(plan.handle, float(phi), int(ltaps), int(bool(normalise)), _ptr(out, "kernels"),
+                                  _stream(stream)))
+    return out
+
+
+def fir(plan: Plan, spec, chan_scale=None, phi: float = 0.1, ltaps: int = 51, normalise: bool = True, x_out=None,
+        stream=None):
+    """The inverse with FIR decorrelation by truncated kernels (Appendix C)."""
+    fmt = _spec_fmt(plan, spec, chan_scale)
+    if x_out is None:
+        x_out = _empty((plan.nblock * plan.lblock,), plan.real_dtype)
+    _check(lib().ipfb_fir(plan.handle, fmt, _ptr(spec, "spec"), _ptr(chan_scale, "chan_scale"), float(phi),
+                          int(ltaps), int(bool(normalise)), plan._real(x_out, "x_out"), _stream(stream)))
+    return x_out
 
 
 def ml_cg(plan: Plan, spec, chan_scale, mask, prior, lam: float = 1.0, phi_x0: float = 0.1,
