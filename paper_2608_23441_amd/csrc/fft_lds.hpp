@@ -163,6 +163,36 @@ __host__ __device__ constexpr int lds_len(int L) { return L + (L >> 4) + 1; }
 // and the writes m R Ns + k + r Ns (k < Ns) never carry into another
 // 16-element block except through the r term, hence
 //   pidx(a + r S) = pidx(a) + r S + (r S >> 4)  for S = L/R and S = Ns.
+// Twiddles and the radix-R butterfly of one Stockham pass, in registers:
+// v[r] = element j + r L/R of a sequence, k = j mod Ns.
+template <typename T, int L, int R, int DIR, int Ns, bool FULLTW>
+__device__ __forceinline__ void stockham_bfly(cx<T>* v, int k, const cx<T>* __restrict__ tw, int twmul) {
+  if constexpr (Ns > 1) {
+    // w^{rk} for r = 1..R-1 from the table entries for r = 1, 2, 4, 8
+    // (power-of-two multiples of k): at most three products per twiddle
+    const int step = (L / (Ns * R)) * twmul;
+    cx<T> w[R];
+    if constexpr (FULLTW) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) w[r] = tw[r * k * step];  // r k step < (R-1)/R LT
+    } else {
+      w[1] = tw[k * step];
+      if constexpr (R > 2) w[2] = tw[2 * k * step];
+      if constexpr (R > 4) w[4] = tw[4 * k * step];
+      if constexpr (R > 8) w[8] = tw[8 * k * step];
+#pragma unroll
+      for (int r = 3; r < R; ++r) {
+        if ((r & (r - 1)) == 0) continue;
+        const int hi = 1 << (31 - __builtin_clz(r));  // highest power of two in r
+        w[r] = cmul(w[r - hi], w[hi]);
+      }
+    }
+#pragma unroll
+    for (int r = 1; r < R; ++r) v[r] = (DIR < 0) ? cmul(v[r], w[r]) : cmulc(v[r], w[r]);
+  }
+  dftR<R, DIR>(v);
+}
+
 template <typename T, int L, int R, int NT, int C, int DIR, int Ns, bool FULLTW = false>
 __device__ __forceinline__ void stockham_pass(cx<T>* s, int LS, const cx<T>* __restrict__ tw, int twmul) {
   constexpr int LR = L / R;
@@ -187,30 +217,7 @@ __device__ __forceinline__ void stockham_pass(cx<T>* s, int LS, const cx<T>* __r
     if ((NB % NT == 0) || g < NB) {
       const int c = g / LR, j = g % LR;
       const int k = j & (Ns - 1);
-      if constexpr (Ns > 1) {
-        // w^{rk} for r = 1..R-1 from the table entries for r = 1, 2, 4, 8
-        // (power-of-two multiples of k): at most three products per twiddle
-        const int step = (L / (Ns * R)) * twmul;
-        cx<T> w[R];
-        if constexpr (FULLTW) {
-#pragma unroll
-          for (int r = 1; r < R; ++r) w[r] = tw[r * k * step];  // r k step < (R-1)/R LT
-        } else {
-          w[1] = tw[k * step];
-          if constexpr (R > 2) w[2] = tw[2 * k * step];
-          if constexpr (R > 4) w[4] = tw[4 * k * step];
-          if constexpr (R > 8) w[8] = tw[8 * k * step];
-#pragma unroll
-          for (int r = 3; r < R; ++r) {
-            if ((r & (r - 1)) == 0) continue;
-            const int hi = 1 << (31 - __builtin_clz(r));  // highest power of two in r
-            w[r] = cmul(w[r - hi], w[hi]);
-          }
-        }
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[i][r] = (DIR < 0) ? cmul(v[i][r], w[r]) : cmulc(v[i][r], w[r]);
-      }
-      dftR<R, DIR>(v[i]);
+      stockham_bfly<T, L, R, DIR, Ns, FULLTW>(v[i], k, tw, twmul);
       cx<T>* dst = s + c * LS + pidx((j - k) * R + k);
 #pragma unroll
       for (int r = 0; r < R; ++r) dst[r * Ns + ((r * Ns) >> 4)] = v[i][r];
@@ -220,16 +227,30 @@ __device__ __forceinline__ void stockham_pass(cx<T>* s, int LS, const cx<T>* __r
 }
 
 // Radix schedule: P passes of at most RMAXLOG bits each, bits spread evenly.
+template <int L, int RMAXLOG>
+struct FftSched {
+  static constexpr int E = ilog2c(L);
+  static constexpr int P = (E + RMAXLOG - 1) / RMAXLOG;
+  static constexpr int bits(int pass) { return E / P + ((pass < E % P) ? 1 : 0); }
+  static constexpr int nslog(int pass) { return pass == 0 ? 0 : nslog(pass - 1) + bits(pass - 1); }
+};
+
+// Largest radix (log2) lds_fft uses for EPT elements per thread.
+__host__ __device__ constexpr int fft_rmaxlog(int ept) { return ept >= 16 ? 4 : (ept >= 8 ? 3 : (ept >= 4 ? 2 : 1)); }
+
+// Passes PASS .. PEND-1 of the schedule (NSLOG: log2 of Ns at PASS).
+template <typename T, int L, int NT, int C, int DIR, int RMAXLOG, int PASS, int PEND, int NSLOG, bool FULLTW>
+__device__ __forceinline__ void stockham_range(cx<T>* s, int LS, const cx<T>* __restrict__ tw, int twmul) {
+  if constexpr (PASS < PEND) {
+    constexpr int bits = FftSched<L, RMAXLOG>::bits(PASS);
+    stockham_pass<T, L, (1 << bits), NT, C, DIR, (1 << NSLOG), FULLTW>(s, LS, tw, twmul);
+    stockham_range<T, L, NT, C, DIR, RMAXLOG, PASS + 1, PEND, NSLOG + bits, FULLTW>(s, LS, tw, twmul);
+  }
+}
+
 template <typename T, int L, int NT, int C, int DIR, int RMAXLOG, int PASS, int NSLOG, bool FULLTW>
 __device__ __forceinline__ void stockham_rec(cx<T>* s, int LS, const cx<T>* __restrict__ tw, int twmul) {
-  constexpr int E = ilog2c(L);
-  constexpr int P = (E + RMAXLOG - 1) / RMAXLOG;
-  if constexpr (PASS < P) {
-    constexpr int bits = E / P + ((PASS < E % P) ? 1 : 0);
-    constexpr int R = 1 << bits;
-    stockham_pass<T, L, R, NT, C, DIR, (1 << NSLOG), FULLTW>(s, LS, tw, twmul);
-    stockham_rec<T, L, NT, C, DIR, RMAXLOG, PASS + 1, NSLOG + bits, FULLTW>(s, LS, tw, twmul);
-  }
+  stockham_range<T, L, NT, C, DIR, RMAXLOG, PASS, FftSched<L, RMAXLOG>::P, NSLOG, FULLTW>(s, LS, tw, twmul);
 }
 
 // Full unnormalised transform, exp(DIR * 2 pi i jk / L). Ends with a barrier.
@@ -237,8 +258,76 @@ template <typename T, int L, int NT, int C, int DIR, bool FULLTW = false>
 __device__ __forceinline__ void lds_fft(cx<T>* s, int LS, const cx<T>* __restrict__ tw, int twmul) {
   if constexpr (L > 1) {
     constexpr int EPT = (L * C) / NT;  // elements per thread
-    constexpr int RM = EPT >= 16 ? 4 : (EPT >= 8 ? 3 : (EPT >= 4 ? 2 : 1));
-    stockham_rec<T, L, NT, C, DIR, RM, 0, 0, FULLTW>(s, LS, tw, twmul);
+    stockham_rec<T, L, NT, C, DIR, fft_rmaxlog(EPT), 0, 0, FULLTW>(s, LS, tw, twmul);
+  }
+}
+
+// The same transform split for callers that hold the input in registers
+// and/or consume the output straight from the last pass (no LDS round trip
+// at either end). Schedule as lds_fft's for C sequences on NT threads:
+//   First::R inputs per butterfly; butterfly j of a sequence takes the
+//   elements j + r L/R (r < R), has no twiddles (Ns = 1), and its outputs go
+//   to LDS at pidx(j R + r): fft_first_from_regs;
+//   then, after a barrier, fft_middle (passes 1 .. P-2);
+//   then fft_last_to, which hands output element j + r L/R_last of sequence
+//   c to out(c, m, value) (consecutive j: consecutive m).
+// Requires P >= 2.
+template <typename T, int L, int NT, int C>
+struct FftSplit {
+  static constexpr int EPT = (L * C) / NT;
+  static constexpr int RM = fft_rmaxlog(EPT);
+  using S = FftSched<L, RM>;
+  static constexpr int P = S::P;
+  static constexpr int R0 = 1 << S::bits(0);
+  static constexpr int RL = 1 << S::bits(P - 1);
+  static constexpr bool ok = P >= 2;
+};
+
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void fft_first_from_regs(cx<T>* seq, int j, cx<T>* v) {
+  dftR<R, DIR>(v);
+  cx<T>* dst = seq + pidx(j * R);
+#pragma unroll
+  for (int r = 0; r < R; ++r) dst[r] = v[r];  // j R + r stays in one 16-element block (R <= 16)
+}
+
+template <typename T, int L, int NT, int C, int DIR, bool FULLTW = false>
+__device__ __forceinline__ void fft_middle(cx<T>* s, int LS, const cx<T>* __restrict__ tw, int twmul) {
+  using F = FftSplit<T, L, NT, C>;
+  stockham_range<T, L, NT, C, DIR, F::RM, 1, F::P - 1, F::S::nslog(1), FULLTW>(s, LS, tw, twmul);
+}
+
+// Passes 1 .. P-1 after fft_first_from_regs (and its barrier), results in
+// LDS. Ends with a barrier.
+template <typename T, int L, int NT, int C, int DIR, bool FULLTW = false>
+__device__ __forceinline__ void fft_rest(cx<T>* s, int LS, const cx<T>* __restrict__ tw, int twmul) {
+  using F = FftSplit<T, L, NT, C>;
+  stockham_range<T, L, NT, C, DIR, F::RM, 1, F::P, F::S::nslog(1), FULLTW>(s, LS, tw, twmul);
+}
+
+// No barrier at the end: LDS is only read. The caller waits before it
+// overwrites s.
+template <typename T, int L, int NT, int C, int DIR, bool FULLTW, class Out>
+__device__ __forceinline__ void fft_last_to(const cx<T>* s, int LS, const cx<T>* __restrict__ tw, int twmul,
+                                            Out out) {
+  using F = FftSplit<T, L, NT, C>;
+  constexpr int R = F::RL, LR = L / R, Ns = LR;
+  constexpr int NB = C * LR;
+  constexpr int BPT = (NB + NT - 1) / NT;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < BPT; ++i) {
+    const int g = tid + i * NT;
+    if ((NB % NT == 0) || g < NB) {
+      const int c = g / LR, j = g % LR;
+      const cx<T>* src = s + c * LS + pidx(j);
+      cx<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = src[r * LR + ((r * LR) >> 4)];
+      stockham_bfly<T, L, R, DIR, Ns, FULLTW>(v, j, tw, twmul);  // k = j mod Ns = j
+#pragma unroll
+      for (int r = 0; r < R; ++r) out(c, j + r * Ns, v[r]);
+    }
   }
 }
 

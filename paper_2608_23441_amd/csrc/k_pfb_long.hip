@@ -174,8 +174,14 @@ __global__ __launch_bounds__((Lf1rCfg<T, LOG2P1>::NT)) void k_lf1r(const cx<T>* 
       ring[r][i] = x[fo + off0 + i * ASTEP * P2];
     }
   }
+  // element i of this thread is row a = tid / MB + i NT / MB of column
+  // tid % MB: when a thread holds EPT = R0 elements these are exactly the
+  // inputs of first-pass butterfly tid / MB, which then runs in registers
+  using F = FftSplit<T, P1, NT, MB>;
+  constexpr bool FIRST_IN_REGS = F::ok && F::R0 == EPT;
   for (int64_t j = ja; j < jb; ++j) {
     cx<T>* s = sbuf + ((j - ja) & 1) * (MB * LS);
+    cx<T> v[EPT];
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       cx<T> acc = mk<T>(T(0), T(0));
@@ -184,8 +190,16 @@ __global__ __launch_bounds__((Lf1rCfg<T, LOG2P1>::NT)) void k_lf1r(const cx<T>* 
         acc.x += w[r][i].x * ring[r][i].x;
         acc.y += w[r][i].y * ring[r][i].y;
       }
-      const int e = tid + i * NT;
-      s[(e % MB) * LS + pidx(e / MB)] = acc;
+      v[i] = acc;
+    }
+    if constexpr (FIRST_IN_REGS) {
+      fft_first_from_regs<T, EPT, -1>(s + (tid % MB) * LS, tid / MB, v);
+    } else {
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NT;
+        s[(e % MB) * LS + pidx(e / MB)] = v[i];
+      }
     }
     // slide by one frame; frame j + NTAP loads while the FFT runs
 #pragma unroll
@@ -198,7 +212,8 @@ __global__ __launch_bounds__((Lf1rCfg<T, LOG2P1>::NT)) void k_lf1r(const cx<T>* 
       for (int i = 0; i < EPT; ++i) ring[NTAP - 1][i] = x[fo + off0 + i * ASTEP * P2];
     }
     __syncthreads();
-    lds_fft<T, P1, NT, MB, -1>(s, LS, tP1s, 1);
+    if constexpr (FIRST_IN_REGS) fft_rest<T, P1, NT, MB, -1>(s, LS, tP1s, 1);
+    else lds_fft<T, P1, NT, MB, -1>(s, LS, tP1s, 1);
     cx<T>* tj = tmp + j * (int64_t)M;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {

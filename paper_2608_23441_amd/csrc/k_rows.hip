@@ -201,13 +201,11 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
     if (j + gridDim.x < nrows) fetch(j + gridDim.x);  // in flight during the FFT
     const int64_t jl = MULTI ? j - tab[sj].f0 : j;
     const unsigned char* rb = reinterpret_cast<const unsigned char*>(raw) + (int)((jl * (int64_t)(H + 1)) & 3);
-    // one dequantised pair (Y_k, Y_{H-k}) gives Z_k = a + i t and, since
-    // e^{+2 pi i (H-k)/N} = -conj e^{+2 pi i k/N}, Z_{H-k} = conj(a) + i conj(t)
-    constexpr int HH = H / 2;
-#pragma unroll
-    for (int i = 0; i < (HH + NT) / NT; ++i) {
-      const int k = tid + i * NT;
-      if (k > HH) continue;
+    T* out = MULTI ? (T*)tab[sj].out : out1;
+    cx<T>* orow = reinterpret_cast<cx<T>*>(out + jl * (int64_t)N);
+    // Z_k = a + i t, a = Y_k + conj Y_{H-k}, t = e^{+2 pi i k/N} (Y_k - conj Y_{H-k});
+    // k = 0 pairs DC with Nyquist (index H)
+    auto zval = [&](int k) -> cx<T> {
       const signed char bk = (signed char)rb[k], bm = (signed char)rb[H - k];
       const T fk = facs[k], fm = facs[H - k];
       cx<T> yk = mk<T>(T(bk >> 4) * fk, T((signed char)(bk << 4) >> 4) * fk);
@@ -218,20 +216,23 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
       }
       const cx<T> a = yk + conj(ym);
       const cx<T> t = cmul(Cfg::WT_LDS ? wt[k] : conj(twN[k]), yk - conj(ym));
-      s[pidx(k)] = mk<T>(a.x - t.y, a.y + t.x);  // a + i t
-      if (k != 0 && k != HH) s[pidx(H - k)] = mk<T>(a.x + t.y, t.x - a.y);
-    }
-    __syncthreads();
+      return mk<T>(a.x - t.y, a.y + t.x);
+    };
     // the FFT's own twiddles stay in global memory (L2): an LDS copy would
     // cost a workgroup per CU, which costs more than their latency
-    lds_fft<T, H, NT, 1, +1, true>(s, LS, twN, 2);  // twN: all N entries
-    T* out = MULTI ? (T*)tab[sj].out : out1;
-    cx<T>* orow = reinterpret_cast<cx<T>*>(out + jl * (int64_t)N);
+    using F = FftSplit<T, H, NT, 1>;
+    static_assert(F::ok && F::R0 * NT == H, "one first-pass butterfly per thread");
+    // one first-pass butterfly per thread, its inputs formed in registers from
+    // the packed bytes; the last pass stores the frame (consecutive threads,
+    // consecutive samples)
+    constexpr int R0 = F::R0, LR0 = H / R0;
+    cx<T> v[R0];
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int m = tid + i * NT;
-      if (m < H) orow[m] = s[pidx(m)];
-    }
+    for (int r = 0; r < R0; ++r) v[r] = zval(tid + r * LR0);
+    fft_first_from_regs<T, R0, +1>(s, tid, v);
+    __syncthreads();
+    fft_middle<T, H, NT, 1, +1, true>(s, LS, twN, 2);
+    fft_last_to<T, H, NT, 1, +1, true>(s, LS, twN, 2, [&](int, int m, cx<T> val) { orow[m] = val; });
     __syncthreads();  // s and raw are rewritten for the next frame
   }
 }

@@ -196,6 +196,27 @@ def test_pfb_forward_long_frames(prec, log2n, b):
     assert np.abs(y[:, -1] - ref[:, -1]).max() < 1e-3 * np.abs(ref).max()
 
 
+# many long frames (an odd count, so the sliding first pass's frame ranges end
+# raggedly), taps wrapping at the end; 4 taps take the sliding first pass, 6
+# taps the one-frame form; every frame checked, and the power sums of pass 2
+@pytest.mark.parametrize("prec,p,b", [(ipfb.F64, 4, 19), (ipfb.F32, 4, 37), (ipfb.F64, 6, 17)])
+def test_pfb_forward_many_long_frames(prec, p, b):
+    N = 1 << 20
+    print(f"case pfb_forward many frames prec={prec} p={p} b={b}", flush=True)
+    w = O.window_sinc_hamming(p, N)
+    x = I.gaussian_timestream(N * b, 53)
+    ref = O.pfb_forward(x, w, N, p)
+    plan = ipfb.Plan(N, p, w, b, prec)
+    xd = _dev(x.astype(np.float32) if prec == ipfb.F32 else x)
+    y = _host(ipfb.pfb_forward(plan, xd))
+    assert _rel(y, ref) < TOL[prec]
+    fr = np.linalg.norm(y - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert fr.max() < 10 * TOL[prec], f"worst frame {fr.argmax()}: {fr.max():.3e}"
+    A = _host(ipfb.upchannelize(plan, xd)[1])
+    A_ref = O.autospectrum(ref)
+    assert np.abs(A - A_ref).max() < 10 * TOL[prec] * A_ref.max()
+
+
 @pytest.mark.parametrize("prec", [ipfb.F64, ipfb.F32])
 def test_upchannelize_and_autospectrum(prec):
     # config-1 shapes: N = 2048, b = 128, Wiener phi = 0.1, then x8 fine channels
