@@ -270,7 +270,15 @@ int upchannelize(ipfb_plan fine, const void* x, void* y_fine, double* autospec, 
  * [iters+1] receiving |r_k|_2 (FP64 sums). Vectors are FP32 for F32 plans,
  * dot products and norms FP64. The first call on a plan allocates the
  * workspace (7 vectors of S reals and the mask bits transposed to the
- * column layout); later calls allocate nothing. */
+ * column layout); later calls allocate nothing.
+ * Two layouts: for power-of-two nblock <= 2^15 (2^14 in FP64) the vectors
+ * are kept transposed and the preconditioner is an in-LDS column FFT; for
+ * any other nblock, or when the plan's column method is
+ * IPFB_COLS_RECURSIVE, they stay in the natural [nblock][lblock] layout, the
+ * stencils run down the columns and the preconditioner is the recursive
+ * column stage with numerator 1 (exact, periodic). That form needs ntap = 4,
+ * phi_precond >= 1e-3, and phi_x0 >= 1e-3 unless x_init is given
+ * (IPFB_EUNSUPPORTED otherwise); it iterates in x_out. */
 int ipfb_ml_cg(ipfb_plan plan, int infmt, const void* spec, const float* chan_scale, const uint32_t* mask,
                const void* prior, double lambda, double phi_x0, double phi_precond, int iters,
                const void* x_init, void* x_out, double* resid_norms, void* stream);

@@ -111,6 +111,10 @@ struct ipfb_plan_s {
   double* iir_scoef = nullptr;
   void* iir_zs = nullptr;
   double iir_phi = NAN;
+  // the same for the ML-CG preconditioner 1/(|W|^2 + phi^2) (natural layout)
+  double* iir_coef_pc = nullptr;
+  double* iir_scoef_pc = nullptr;
+  double iir_phi_pc = NAN;
   int col_method = IPFB_COLS_AUTO;
   // Appendix C's comparison solvers (allocated on first use): the banded
   // Cholesky workspace, and the truncated decorrelation kernels with the
@@ -173,7 +177,7 @@ void free_bplan(ipfb_bplan p);
 void free_plan(ipfb_plan p) {
   if (p->blu1) free_bplan(p->blu1);
   void* ptrs[] = {p->win64, p->winT, p->twN, p->twB, p->twB64, p->part, p->fac, p->twS,
-                  p->cg, p->diag, p->iir_coef, p->iir_scoef, p->iir_zs,
+                  p->cg, p->diag, p->iir_coef, p->iir_scoef, p->iir_zs, p->iir_coef_pc, p->iir_scoef_pc,
                   p->tik_ws, p->fir_g};
   for (void* q : ptrs)
     if (q) hipFree(q);
@@ -259,7 +263,7 @@ struct ProfScope {
       std::lock_guard<std::mutex> lk(g_pm);
       on = g_prof;
     }
-    if (on && (a = ev_get())) hipEventRecord(a, st);
+    if (n && on && (a = ev_get())) hipEventRecord(a, st);
   }
   ~ProfScope() {
     if (!a) return;
@@ -357,6 +361,8 @@ int ipfb_plan_create(ipfb_plan* out, int lblock, int ntap, const double* window,
     st = dev_alloc(p, (void**)&p->iir_coef, (size_t)lblock * iir_coef_stride(ntap) * sizeof(double));
     if (!st) st = dev_alloc(p, (void**)&p->iir_scoef, (size_t)lblock * iir_stream_stride(ntap) * sizeof(double));
     if (!st) st = dev_alloc(p, &p->iir_zs, (size_t)nseg * lblock * 2 * (ntap - 1) * esize(prec));
+    if (!st) st = dev_alloc(p, (void**)&p->iir_coef_pc, (size_t)lblock * iir_coef_stride(ntap) * sizeof(double));
+    if (!st) st = dev_alloc(p, (void**)&p->iir_scoef_pc, (size_t)lblock * iir_stream_stride(ntap) * sizeof(double));
   }
   if (!st && !p->row_lds) st = dev_alloc(p, &p->tmp, (size_t)nblock * lblock * esize(prec));
   if (!st && !p->row_lds) {
@@ -569,6 +575,29 @@ bool use_recursive(ipfb_plan p, double phi) {
   return !(p->col_lds && p->log2b <= 9);
 }
 
+// The recursive column stage in place on buf [b][N]: the Wiener filter
+// (precond = 0: coefficient set iir_coef, output scaled by gnorm) or the CG
+// preconditioner 1/(|W|^2 + phi^2) (precond = 1: set iir_coef_pc, gnorm 1).
+// Each set is made again only when phi changes. names: NULL, or the profile
+// names of the five stages.
+hipError_t rec_stage(ipfb_plan p, void* buf, double phi, int precond, double gnorm, hipStream_t st,
+                     const char* const* names) {
+  const int seg = p->prec == IPFB_F32 ? kIirSegF32 : kIirSegF64;
+  const int64_t nseg = (p->nblock + seg - 1) / seg;
+  const IirStream one = {buf, p->nblock, 0};
+  double* coef = precond ? p->iir_coef_pc : p->iir_coef;
+  double* scoef = precond ? p->iir_scoef_pc : p->iir_scoef;
+  double& cached = precond ? p->iir_phi_pc : p->iir_phi;
+  hipError_t e = hipSuccess;
+  for (int stage = (phi == cached) ? kIirPass1 : kIirSetup; stage <= kIirApply && e == hipSuccess; ++stage) {
+    ProfScope ps(names ? names[stage] : nullptr, st);
+    e = launch_col_iir(stage, p->prec, one, nullptr, 1, nseg, nseg, p->lblock, p->ntap, p->win64, phi, gnorm, coef,
+                       scoef, p->iir_zs, st, precond);
+    if (stage <= kIirSetupLen) cached = e == hipSuccess ? phi : NAN;
+  }
+  return e;
+}
+
 int wiener_recursive(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, double phi, int normalise,
                      void* x_out, void* stream) {
   DeviceGuard g(p->dev);
@@ -576,17 +605,7 @@ int wiener_recursive(ipfb_plan p, int infmt, const void* spec, const float* chan
   hipError_t e = rows_into(p, infmt, spec, chan_scale, x_out, st);
   static const char* const names[5] = {"ipfb_cols_rec_setup", "ipfb_cols_rec_setup", "ipfb_cols_rec_pass1",
                                        "ipfb_cols_rec_carry", "ipfb_cols_rec_pass2"};
-  const double gnorm = normalise ? 1.0 + phi * phi : 1.0;
-  const int seg = p->prec == IPFB_F32 ? kIirSegF32 : kIirSegF64;
-  const int64_t nseg = (p->nblock + seg - 1) / seg;
-  const IirStream one = {x_out, p->nblock, 0};
-  // the coefficients depend on phi only (and the plan): set up again only when it changes
-  for (int stage = (phi == p->iir_phi) ? kIirPass1 : kIirSetup; stage <= kIirApply && e == hipSuccess; ++stage) {
-    ProfScope ps(names[stage], st);
-    e = launch_col_iir(stage, p->prec, one, nullptr, 1, nseg, nseg, p->lblock, p->ntap, p->win64, phi, gnorm,
-                       p->iir_coef, p->iir_scoef, p->iir_zs, st);
-    if (stage <= kIirSetupLen) p->iir_phi = e == hipSuccess ? phi : NAN;
-  }
+  if (e == hipSuccess) e = rec_stage(p, x_out, phi, 0, normalise ? 1.0 + phi * phi : 1.0, st, names);
   return launched(e, "ipfb_wiener");
 }
 
@@ -656,18 +675,7 @@ namespace {
 // the recursive form where it applies, else the FFT form (power-of-two b).
 hipError_t cols_into(ipfb_plan p, void* buf, double phi, int normalise, hipStream_t st) {
   hipError_t e = hipSuccess;
-  if (use_recursive(p, phi)) {
-    const int seg = p->prec == IPFB_F32 ? kIirSegF32 : kIirSegF64;
-    const int64_t nseg = (p->nblock + seg - 1) / seg;
-    const IirStream one = {buf, p->nblock, 0};
-    const double gnorm = normalise ? 1.0 + phi * phi : 1.0;
-    for (int stage = (phi == p->iir_phi) ? kIirPass1 : kIirSetup; stage <= kIirApply && e == hipSuccess; ++stage) {
-      e = launch_col_iir(stage, p->prec, one, nullptr, 1, nseg, nseg, p->lblock, p->ntap, p->win64, phi, gnorm,
-                         p->iir_coef, p->iir_scoef, p->iir_zs, st);
-      if (stage <= kIirSetupLen) p->iir_phi = e == hipSuccess ? phi : NAN;
-    }
-    return e;
-  }
+  if (use_recursive(p, phi)) return rec_stage(p, buf, phi, 0, normalise ? 1.0 + phi * phi : 1.0, st, nullptr);
   for (int pass = 0; pass < 3 && e == hipSuccess; ++pass) {
     if (p->log2b <= 9 && pass != 1) continue;
     e = launch_col_wiener_nat(p->prec, p->log2b, pass, buf, p->lblock, p->ntap, p->win64, phi, normalise, p->twB,
@@ -939,8 +947,15 @@ size_t cg_layout(ipfb_plan p, char* base, CgBufs* o) {
   return off;
 }
 
+// ML-CG runs on the natural layout [b][N] (stencils down the columns, the
+// recursive preconditioner) where the transposed form's in-LDS column FFT
+// does not apply (nblock not a power of two, or above 2^15), or when the
+// plan asks for the recursive column method.
+bool cg_natural(ipfb_plan p) { return !p->col_lds || p->col_method == IPFB_COLS_RECURSIVE; }
+
 int ml_cg_check(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, const uint32_t* mask,
-                const void* prior, double lam, double phi_x0, double phi_precond, int iters, void* x_out) {
+                const void* prior, double lam, double phi_x0, double phi_precond, int iters, const void* x_init,
+                void* x_out) {
   if (check_plan(p)) return IPFB_EINVAL;
   if (!spec || !mask || !prior || !x_out) return fail(IPFB_EINVAL, "spec, mask, prior and x_out must be non-NULL");
   if (check_infmt(infmt, chan_scale)) return IPFB_EINVAL;
@@ -948,8 +963,18 @@ int ml_cg_check(ipfb_plan p, int infmt, const void* spec, const float* chan_scal
   if (!(phi_precond > 0.0) || !std::isfinite(phi_precond)) return fail(IPFB_EINVAL, "phi_precond must be > 0");
   if (!(phi_x0 >= 0.0) || !std::isfinite(phi_x0)) return fail(IPFB_EINVAL, "phi_x0 must be finite and >= 0");
   if (iters < 0) return fail(IPFB_EINVAL, "iters must be >= 0");
-  if (!p->row_lds || !p->col_lds)
-    return fail(IPFB_EUNSUPPORTED, "ipfb_ml_cg needs a plan that supports ipfb_wiener");
+  if (!p->row_lds)
+    return fail(IPFB_EUNSUPPORTED, "ipfb_ml_cg supports lblock <= 2^%d for this precision", max_log2_row(p->prec));
+  if (cg_natural(p)) {
+    if (!p->iir_coef_pc)
+      return fail(IPFB_EUNSUPPORTED, "ipfb_ml_cg with nblock = %lld needs ntap = 4 (got %d); other tap counts take "
+                                     "power-of-two nblock <= 2^%d",
+                  (long long)p->nblock, p->ntap, max_log2_col(p->prec));
+    if (!(phi_precond >= kIirMinPhi))
+      return fail(IPFB_EUNSUPPORTED, "the recursive preconditioner needs phi_precond >= %g", kIirMinPhi);
+    if (!x_init && !(phi_x0 >= kIirMinPhi))
+      return fail(IPFB_EUNSUPPORTED, "the recursive Wiener start needs phi_x0 >= %g (or an x_init)", kIirMinPhi);
+  }
   return IPFB_OK;
 }
 
@@ -1003,6 +1028,67 @@ hipError_t ml_cg_enqueue(ipfb_plan p, const CgBufs& c, int infmt, const void* sp
   return e;
 }
 
+// The same solve on the natural layout: the iterate lives in x_out, d in the
+// plan's frame buffer, the mask and prior are read as given; z = M^-1 r is r
+// through the recursive stage with numerator 1.
+hipError_t ml_cg_enqueue_nat(ipfb_plan p, const CgBufs& c, int infmt, const void* spec, const float* chan_scale,
+                             const uint32_t* mask, const void* prior, double lam, double phi_x0, double phi_precond,
+                             int iters, const void* x_init, void* x_out, double* resid_norms, hipStream_t st) {
+  const int64_t b = p->nblock, S = (int64_t)p->lblock * b;
+  const int N = p->lblock;
+  const size_t vb = (size_t)S * esize(p->prec);
+  void* x = x_out;
+  // z = M^-1 r with the partial sums of r . z
+  auto precond_dot_nat = [&]() -> hipError_t {
+    hipError_t e2 = hipMemcpyAsync(c.zT, c.rT, vb, hipMemcpyDeviceToDevice, st);
+    if (e2 == hipSuccess) e2 = rec_stage(p, c.zT, phi_precond, 1, 1.0, st, nullptr);
+    if (e2 == hipSuccess) e2 = launch_cg_dot(p->prec, c.rT, c.zT, S, c.part, st);
+    return e2;
+  };
+  hipError_t e;
+  {
+    ProfScope ps("cg_setup", st);
+    e = rows_into(p, infmt, spec, chan_scale, p->work, st);
+    if (e == hipSuccess) e = launch_cg_autocorr(p->win64, N, p->ntap, c.autoc, st);
+    if (e == hipSuccess) e = launch_cg_rhs_nat(p->prec, p->work, c.rhsT, p->win64, mask, prior, lam, N, p->ntap, b, st);
+    if (e == hipSuccess) {
+      if (x_init) {
+        if (x_init != x) e = hipMemcpyAsync(x, x_init, vb, hipMemcpyDeviceToDevice, st);
+      } else {
+        e = hipMemcpyAsync(x, p->work, vb, hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = rec_stage(p, x, phi_x0, 0, 1.0 + phi_x0 * phi_x0, st, nullptr);
+      }
+    }
+    if (e == hipSuccess) e = launch_cg_normal_nat(p->prec, x, c.qT, c.autoc, mask, lam, N, p->ntap, b, c.part, st);
+    if (e == hipSuccess) e = launch_cg_resid(p->prec, c.rhsT, c.qT, c.rT, S, c.part, st);
+    if (e == hipSuccess) e = launch_cg_scalar(c.part, 2, c.sc, resid_norms, 0, st);
+    if (e == hipSuccess) e = precond_dot_nat();
+    if (e == hipSuccess) e = launch_cg_p(p->prec, c.pT, c.zT, c.sc, 0, S, st);
+    if (e == hipSuccess) e = launch_cg_scalar(c.part, 0, c.sc, nullptr, 0, st);
+  }
+  for (int k = 1; k <= iters && e == hipSuccess; ++k) {
+    ProfScope ps("cg_iter", st);
+    e = launch_cg_normal_nat(p->prec, c.pT, c.qT, c.autoc, mask, lam, N, p->ntap, b, c.part, st);
+    if (e == hipSuccess) e = launch_cg_scalar(c.part, 1, c.sc, nullptr, 0, st);
+    if (e == hipSuccess) e = launch_cg_xr(p->prec, x, c.rT, c.pT, c.qT, c.sc, S, c.part, st);
+    if (e == hipSuccess) e = launch_cg_scalar(c.part, 2, c.sc, resid_norms, k, st);
+    if (e == hipSuccess) e = precond_dot_nat();
+    if (e == hipSuccess) e = launch_cg_scalar(c.part, 3, c.sc, nullptr, 0, st);
+    if (e == hipSuccess) e = launch_cg_p(p->prec, c.pT, c.zT, c.sc, 1, S, st);
+  }
+  return e;
+}
+
+hipError_t ml_cg_run(ipfb_plan p, const CgBufs& c, int infmt, const void* spec, const float* chan_scale,
+                     const uint32_t* mask, const void* prior, double lam, double phi_x0, double phi_precond, int iters,
+                     const void* x_init, void* x_out, double* resid_norms, hipStream_t st) {
+  if (cg_natural(p))
+    return ml_cg_enqueue_nat(p, c, infmt, spec, chan_scale, mask, prior, lam, phi_x0, phi_precond, iters, x_init,
+                             x_out, resid_norms, st);
+  return ml_cg_enqueue(p, c, infmt, spec, chan_scale, mask, prior, lam, phi_x0, phi_precond, iters, x_init, x_out,
+                       resid_norms, st);
+}
+
 // ---- the entry point for callers that cannot allocate ------------------------
 // One file-scope device array holds every buffer of ipfb_ml_cg_noalloc's
 // solve. Each device the library runs on has its own copy at its own address,
@@ -1040,7 +1126,7 @@ extern "C" {
 int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, const uint32_t* mask,
                const void* prior, double lam, double phi_x0, double phi_precond, int iters, const void* x_init,
                void* x_out, double* resid_norms, void* stream) {
-  if (int s = ml_cg_check(p, infmt, spec, chan_scale, mask, prior, lam, phi_x0, phi_precond, iters, x_out))
+  if (int s = ml_cg_check(p, infmt, spec, chan_scale, mask, prior, lam, phi_x0, phi_precond, iters, x_init, x_out))
     return s;
   DeviceGuard g(p->dev);
   if (!p->cg) {
@@ -1048,15 +1134,15 @@ int ipfb_ml_cg(ipfb_plan p, int infmt, const void* spec, const float* chan_scale
   }
   CgBufs c;
   cg_layout(p, (char*)p->cg, &c);
-  return launched(ml_cg_enqueue(p, c, infmt, spec, chan_scale, mask, prior, lam, phi_x0, phi_precond, iters, x_init,
-                                x_out, resid_norms, (hipStream_t)stream),
+  return launched(ml_cg_run(p, c, infmt, spec, chan_scale, mask, prior, lam, phi_x0, phi_precond, iters, x_init,
+                            x_out, resid_norms, (hipStream_t)stream),
                   "ipfb_ml_cg");
 }
 
 int ipfb_ml_cg_noalloc(ipfb_plan p, int infmt, const void* spec, const float* chan_scale, const uint32_t* mask,
                        const void* prior, double lam, double phi_x0, double phi_precond, int iters,
                        const void* x_init, void* x_out, double* resid_norms, void* stream) {
-  if (int s = ml_cg_check(p, infmt, spec, chan_scale, mask, prior, lam, phi_x0, phi_precond, iters, x_out))
+  if (int s = ml_cg_check(p, infmt, spec, chan_scale, mask, prior, lam, phi_x0, phi_precond, iters, x_init, x_out))
     return s;
   const size_t need = cg_layout(p, nullptr, nullptr);
   if (need > kNoAllocScratchBytes)
@@ -1070,8 +1156,8 @@ int ipfb_ml_cg_noalloc(ipfb_plan p, int infmt, const void* spec, const float* ch
   if (int s = scratch_ptr(p->dev, &base)) return s;
   CgBufs c;
   cg_layout(p, base, &c);
-  return launched(ml_cg_enqueue(p, c, infmt, spec, chan_scale, mask, prior, lam, phi_x0, phi_precond, iters, x_init,
-                                x_out, resid_norms, (hipStream_t)stream),
+  return launched(ml_cg_run(p, c, infmt, spec, chan_scale, mask, prior, lam, phi_x0, phi_precond, iters, x_init,
+                            x_out, resid_norms, (hipStream_t)stream),
                   "ipfb_ml_cg_noalloc");
 }
 

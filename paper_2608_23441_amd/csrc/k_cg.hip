@@ -327,6 +327,104 @@ __global__ __launch_bounds__(kCgNT) void k_maskbits_transpose(const uint32_t* __
   }
 }
 
+// ---- natural layout v[j][n] (frame j, sub-filter path n), 4 taps -----------
+// The same two stencils run down the columns. A work item is a tile of kCgNT
+// consecutive columns and a chunk of kCgFR frames; a thread walks its column
+// through the chunk with the stencil's window in registers, so every access
+// is a run of kCgNT consecutive samples of one frame and each sample is read
+// once per item. Workgroup g takes items g, g + G, ... (G = kCgNWG): the
+// partial sums are deterministic. The mask is the time-order bitmask itself
+// (bit j N + n), read where the stencil needs it.
+constexpr int kCgFR = 64;
+
+__device__ __forceinline__ unsigned nat_bit(const uint32_t* __restrict__ mb, int64_t s) {
+  return (mb[s >> 5] >> (s & 31)) & 1u;
+}
+
+__device__ __forceinline__ int64_t wrap_frame(int64_t k, int64_t b) {
+  if (k < 0 || k >= b) {
+    k %= b;
+    if (k < 0) k += b;
+  }
+  return k;
+}
+
+// q = (A^T A + lam D) p ; partial sums of p.q
+template <typename T, int NTAP>
+__global__ __launch_bounds__(kCgNT) void k_cg_normal_nat(const T* __restrict__ p, T* __restrict__ q,
+                                                         const double* __restrict__ autoc,
+                                                         const uint32_t* __restrict__ mbits, double lam, int N,
+                                                         int64_t b, double* __restrict__ part) {
+  constexpr int H = NTAP - 1, NC = 2 * NTAP - 1;
+  __shared__ double sh[kCgNT];
+  const int ntile = (N + kCgNT - 1) / kCgNT;
+  const int64_t nw = (int64_t)ntile * ((b + kCgFR - 1) / kCgFR);
+  double acc = 0.0;
+  for (int64_t w = blockIdx.x; w < nw; w += gridDim.x) {
+    const int n = (int)(w % ntile) * kCgNT + threadIdx.x;
+    const int64_t j0 = (w / ntile) * kCgFR;
+    if (n >= N) continue;
+    const int len = (int)(b - j0 < kCgFR ? b - j0 : kCgFR);
+    double c[NC], win[NC];  // win[t] = p[j - H + t]
+#pragma unroll
+    for (int t = 0; t < NC; ++t) c[t] = autoc[(int64_t)n * NC + t];
+#pragma unroll
+    for (int t = 0; t < NC - 1; ++t) win[t] = (double)p[wrap_frame(j0 - H + t, b) * N + n];
+    int64_t jn = wrap_frame(j0 + H, b);  // frame entering the window
+#pragma unroll 4
+    for (int k = 0; k < len; ++k) {
+      win[NC - 1] = (double)p[jn * N + n];
+      if (++jn == b) jn = 0;
+      double v = 0.0;
+#pragma unroll
+      for (int t = 0; t < NC; ++t) v += c[t] * win[t];
+      const double pe = win[H];
+      const int64_t s = (j0 + k) * N + n;
+      if (nat_bit(mbits, s)) v += lam * pe;
+      const T vt = T(v);
+      q[s] = vt;
+      acc += pe * (double)vt;
+#pragma unroll
+      for (int t = 0; t < NC - 1; ++t) win[t] = win[t + 1];
+    }
+  }
+  const double tot = block_sum<kCgNT>(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// rhs = A^T d + lam D prior : (A^T d)[j][n] = sum_r h[rN+n] d[(j-r) mod b][n]
+template <typename T, int NTAP>
+__global__ __launch_bounds__(kCgNT) void k_cg_rhs_nat(const T* __restrict__ d, T* __restrict__ rhs,
+                                                      const double* __restrict__ win,
+                                                      const uint32_t* __restrict__ mbits,
+                                                      const T* __restrict__ prior, double lam, int N, int64_t b) {
+  const int ntile = (N + kCgNT - 1) / kCgNT;
+  const int64_t nw = (int64_t)ntile * ((b + kCgFR - 1) / kCgFR);
+  for (int64_t w = blockIdx.x; w < nw; w += gridDim.x) {
+    const int n = (int)(w % ntile) * kCgNT + threadIdx.x;
+    const int64_t j0 = (w / ntile) * kCgFR;
+    if (n >= N) continue;
+    const int len = (int)(b - j0 < kCgFR ? b - j0 : kCgFR);
+    double h[NTAP], dv[NTAP];  // dv[r] = d[j - r]
+#pragma unroll
+    for (int r = 0; r < NTAP; ++r) h[r] = win[(int64_t)r * N + n];
+#pragma unroll
+    for (int r = 1; r < NTAP; ++r) dv[r] = (double)d[wrap_frame(j0 - r, b) * N + n];
+#pragma unroll 4
+    for (int k = 0; k < len; ++k) {
+      const int64_t s = (j0 + k) * N + n;
+      dv[0] = (double)d[s];
+      double v = 0.0;
+#pragma unroll
+      for (int r = 0; r < NTAP; ++r) v += h[r] * dv[r];
+      if (nat_bit(mbits, s)) v += lam * (double)prior[s];
+      rhs[s] = T(v);
+#pragma unroll
+      for (int r = NTAP - 1; r > 0; --r) dv[r] = dv[r - 1];
+    }
+  }
+}
+
 #define CG_DISPATCH(prec, call) \
   do {                          \
     if ((prec) == F32) {        \
@@ -392,6 +490,22 @@ hipError_t launch_cg_p(int prec, void* p, const void* z, const double* sc, int u
 
 hipError_t launch_cg_scalar(const double* part, int mode, double* sc, double* resid, int k, hipStream_t st) {
   k_cg_scalar<<<1, kCgNWG, 0, st>>>(part, mode, sc, resid, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_normal_nat(int prec, const void* p, void* q, const double* autoc, const uint32_t* mbits,
+                                double lam, int N, int ntap, int64_t b, double* part, hipStream_t st) {
+  if (ntap != 4) return hipErrorNotSupported;
+  CG_DISPATCH(prec, (k_cg_normal_nat<T, 4><<<kCgNWG, kCgNT, 0, st>>>((const T*)p, (T*)q, autoc, mbits, lam, N, b,
+                                                                     part)));
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_rhs_nat(int prec, const void* d, void* rhs, const double* win64, const uint32_t* mbits,
+                             const void* prior, double lam, int N, int ntap, int64_t b, hipStream_t st) {
+  if (ntap != 4) return hipErrorNotSupported;
+  CG_DISPATCH(prec, (k_cg_rhs_nat<T, 4><<<kCgNWG, kCgNT, 0, st>>>((const T*)d, (T*)rhs, win64, mbits,
+                                                                  (const T*)prior, lam, N, b)));
   return hipGetLastError();
 }
 

@@ -249,7 +249,7 @@ __device__ void iir_nmat(const double* a, const double* A, int len, double* Nm) 
 // for segments of L frames.
 template <int M>
 __global__ __launch_bounds__(64) void k_iir_setup(const double* __restrict__ win, int N, double phi, int L,
-                                                   double* __restrict__ coef) {
+                                                   double* __restrict__ coef, int precond) {
   using Ly = IirLayout<M>;
   const int n = blockIdx.x * 64 + threadIdx.x;
   if (n >= N) return;
@@ -306,7 +306,8 @@ __global__ __launch_bounds__(64) void k_iir_setup(const double* __restrict__ win
   const double P1 = hs * hs + phi * phi;
   const double Q1 = q1.x;  // real: the roots come in conjugate pairs
   const double invK = Q1 * Q1 / P1;
-  for (int r = 0; r <= M; ++r) cf[Ly::H + r] = h[r];
+  // numerator: the taps (Wiener), or 1 (the preconditioner 1/(|W|^2 + phi^2))
+  for (int r = 0; r <= M; ++r) cf[Ly::H + r] = precond ? (r == 0 ? 1.0 : 0.0) : h[r];
   for (int i = 0; i < M; ++i) cf[Ly::A + i] = a[i];
   cf[Ly::IK] = invK;
   double A[M * M], B[M * M];
@@ -698,13 +699,13 @@ __global__ __launch_bounds__(64) void k_iir_apply(int N, int ntiles, IirStream o
 template <int M>
 static hipError_t launch_iir_m(int stage, int prec, const IirStream& one, const IirStream* tab, int nstreams,
                                int64_t nsegt, int64_t max_nseg, int N, const double* win64, double phi,
-                               double gnorm, double* coef, double* scoef, void* zs, hipStream_t st) {
+                               double gnorm, double* coef, double* scoef, void* zs, hipStream_t st, int precond) {
   const int L = prec == F32 ? kIirSegF32 : kIirSegF64;
   const int t256 = (N + 255) / 256, t64 = (N + 63) / 64;
   if (nsegt * t64 > 0x7fffffffLL) return hipErrorNotSupported;  // one-dimensional grids
   switch (stage) {
     case kIirSetup:
-      k_iir_setup<M><<<dim3((unsigned)((N + 63) / 64)), 64, 0, st>>>(win64, N, phi, L, coef);
+      k_iir_setup<M><<<dim3((unsigned)((N + 63) / 64)), 64, 0, st>>>(win64, N, phi, L, coef, precond);
       break;
     case kIirSetupLen:
       k_iir_setup_len<M><<<dim3((unsigned)(((int64_t)nstreams * N + 63) / 64)), 64, 0, st>>>(N, L, one, tab,
@@ -747,12 +748,12 @@ static hipError_t launch_iir_m(int stage, int prec, const IirStream& one, const 
 
 hipError_t launch_col_iir(int stage, int prec, const IirStream& one, const IirStream* tab, int nstreams,
                           int64_t nsegt, int64_t max_nseg, int N, int ntap, const double* win64, double phi,
-                          double gnorm, double* coef, double* scoef, void* zs, hipStream_t st) {
+                          double gnorm, double* coef, double* scoef, void* zs, hipStream_t st, int precond) {
   if (N < 1 || nsegt < 1) return hipSuccess;
   switch (ntap) {
     case 4:
       return launch_iir_m<3>(stage, prec, one, tab, nstreams, nsegt, max_nseg, N, win64, phi, gnorm, coef, scoef, zs,
-                             st);
+                             st, precond);
     default: return hipErrorNotSupported;
   }
 }

@@ -75,6 +75,8 @@ hipError_t launch_row_c4(int prec, int log2n, const void* in, const float* chan_
 // zs), kIirApply the two recursions from those states, writing xhat over x.
 // One stream: `one` describes it and tab is unused; several: tab is a device
 // array of nstreams entries. max_nseg: the most segments of any stream.
+// precond = 1 (kIirSetup): the coefficients of 1/(|W_n|^2 + phi^2) instead
+// (numerator 1), the inverse of A^T A + phi^2 I; apply it with gnorm = 1.
 // hipErrorNotSupported (nothing launched) for tap counts without a kernel.
 constexpr int kIirSegF32 = 64, kIirSegF64 = 64;
 struct IirStream {
@@ -87,7 +89,7 @@ int iir_coef_stride(int ntap);
 int iir_stream_stride(int ntap);
 hipError_t launch_col_iir(int stage, int prec, const IirStream& one, const IirStream* tab, int nstreams,
                           int64_t nsegt, int64_t max_nseg, int N, int ntap, const double* win64, double phi,
-                          double gnorm, double* coef, double* scoef, void* zs, hipStream_t st);
+                          double gnorm, double* coef, double* scoef, void* zs, hipStream_t st, int precond = 0);
 
 // Tikhonov-regularised solve of each path's linear sub-problem by banded
 // Cholesky: x (first b - ntap + 1 rows: d) overwritten with
@@ -149,6 +151,12 @@ hipError_t launch_cg_xr(int prec, void* x, void* r, const void* p, const void* q
 hipError_t launch_cg_p(int prec, void* p, const void* z, const double* sc, int use_beta, int64_t S,
                        hipStream_t st);
 hipError_t launch_cg_scalar(const double* part, int mode, double* sc, double* resid, int k, hipStream_t st);
+// The same two stencils on the natural layout [b][N] (4 taps; else
+// hipErrorNotSupported), the mask being the time-order bitmask itself.
+hipError_t launch_cg_normal_nat(int prec, const void* p, void* q, const double* autoc, const uint32_t* mbits,
+                                double lam, int N, int ntap, int64_t b, double* part, hipStream_t st);
+hipError_t launch_cg_rhs_nat(int prec, const void* d, void* rhs, const double* win64, const uint32_t* mbits,
+                             const void* prior, double lam, int N, int ntap, int64_t b, hipStream_t st);
 // time-order bitmask (bit e = sample j N + n) -> transposed rows of ceil(b/32) words
 hipError_t launch_maskbits_transpose(const uint32_t* in, int N, int64_t b, uint32_t* out, hipStream_t st);
 constexpr int kCgParts = 1024;

@@ -1,7 +1,8 @@
 """The allocation-free CG entry point, called through the C ABI: its results
 equal ipfb_ml_cg's (same kernels on the same inputs, so bit for bit) on two
-calls in a row, the second on a smaller plan, and a plan whose solve does not
-fit its static scratch array is rejected before anything runs."""
+calls in a row, the second on a smaller plan, in both the transposed and the
+natural-layout form, and a plan whose solve does not fit its static scratch
+array is rejected before anything runs."""
 import ctypes
 
 import numpy as np
@@ -51,6 +52,22 @@ def test_noalloc_matches_ml_cg_twice_then_smaller(prec):
     for k, (N, b, iters) in enumerate(shapes):
         print(f"case ml_cg_noalloc prec={prec} N={N} b={b} iters={iters}", flush=True)
         w, packed, s, mask, prior = _case(N, 4, b, 600 + 7 * k + prec, prec)
+        plan = ipfb.Plan(N, 4, w, b, prec)
+        xr, nr = _call(L.ipfb_ml_cg, plan, packed, s, mask, prior, iters, dt)
+        xa, na = _call(L.ipfb_ml_cg_noalloc, plan, packed, s, mask, prior, iters, dt)
+        assert np.array_equal(xa, xr) and np.array_equal(na, nr)
+        assert nr[-1] < nr[0]
+
+
+@pytest.mark.parametrize("prec", [ipfb.F32, ipfb.F64])
+def test_noalloc_natural_layout_twice_then_smaller(prec):
+    # nblock not a power of two: the natural-layout solve (recursive
+    # preconditioner, whose coefficients the plan holds from its creation)
+    L = ipfb.lib()
+    dt = torch.float32 if prec == ipfb.F32 else torch.float64
+    for k, (N, b, iters) in enumerate([(512, 1500, 20), (64, 300, 30)]):
+        print(f"case ml_cg_noalloc natural prec={prec} N={N} b={b} iters={iters}", flush=True)
+        w, packed, s, mask, prior = _case(N, 4, b, 640 + 7 * k + prec, prec)
         plan = ipfb.Plan(N, 4, w, b, prec)
         xr, nr = _call(L.ipfb_ml_cg, plan, packed, s, mask, prior, iters, dt)
         xa, na = _call(L.ipfb_ml_cg_noalloc, plan, packed, s, mask, prior, iters, dt)
