@@ -43,11 +43,17 @@ namespace ipfb {
 // Per-(stream, column) block, for the stream's length b and its last
 // segment of L' = b - (nseg - 1) L frames:
 //   A^{L'}, B^{L'}, N_{L'}, (I - A^b)^-1, (I - B^b)^-1.
+// segments per lane at most in the uniform-power carry (nseg <= 64 kIirQMax)
+constexpr int kIirQMax = 8;
+
 template <int M>
 struct IirLayout {
   static constexpr int H = 0, A = M + 1, IK = 2 * M + 1, MAT = 2 * M + 2;
   static constexpr int AL = MAT, BL = MAT + M * M, NL = MAT + 2 * M * M;
-  static constexpr int STRIDE = MAT + 3 * M * M;
+  // A^{q L 2^k} and B^{q L 2^k} for q = 1..kIirQMax, k = 0..5 (the carry's
+  // lane-to-lane steps): PA + ((q-1) 6 + k) M^2, PB likewise
+  static constexpr int PA = MAT + 3 * M * M, PB = PA + kIirQMax * 6 * M * M;
+  static constexpr int STRIDE = PB + kIirQMax * 6 * M * M;
   // the per-stream block
   static constexpr int ALL = 0, BLL = M * M, NLL = 2 * M * M, IA = 3 * M * M, IB = 4 * M * M;
   static constexpr int SSTRIDE = 5 * M * M;
@@ -315,6 +321,16 @@ __global__ __launch_bounds__(64) void k_iir_setup(const double* __restrict__ win
   mat_pow<M>(A, L, cf + Ly::AL);
   mat_pow<M>(B, L, cf + Ly::BL);
   iir_nmat<M>(a, A, L, cf + Ly::NL);
+  for (int q = 1; q <= kIirQMax; ++q) {
+    double* pa = cf + Ly::PA + (q - 1) * 6 * M * M;
+    double* pb = cf + Ly::PB + (q - 1) * 6 * M * M;
+    mat_pow<M>(cf + Ly::AL, q, pa);
+    mat_pow<M>(cf + Ly::BL, q, pb);
+    for (int k = 1; k < 6; ++k) {
+      mat_mul<M>(pa + (k - 1) * M * M, pa + (k - 1) * M * M, pa + k * M * M);
+      mat_mul<M>(pb + (k - 1) * M * M, pb + (k - 1) * M * M, pb + k * M * M);
+    }
+  }
 }
 
 // One thread per (stream, column): the matrices that depend on the stream's
@@ -429,7 +445,6 @@ __device__ __forceinline__ void matvec_add(const double* m, const double* x, con
   for (int i = 0; i < M; ++i) out[i] = t[i];
 }
 
-constexpr int kIirCarryQ = 4;  // segments per lane held in registers by the carry scan
 
 // The carry scan moves 3x3 affine maps X -> P X + Y across the lanes of a
 // wavefront with cross-lane exchanges.
@@ -452,22 +467,21 @@ __device__ __forceinline__ void set_identity(double* P, double* Y) {
 
 // Per column (one wavefront): the periodic states entering every segment,
 // written over the pass-1 results: zs[s] = (causal state entering segment s,
-// anti-causal state entering it from the right). Lane l takes the
-// contiguous segments [l q, (l+1) q), q = ceil(nseg / 64): it composes its
-// segments' affine maps, an inclusive scan of the maps across the lanes
-// (Hillis-Steele) gives every lane its entering state, and the lanes then
-// walk their segments. Causal: S_{s+1} = A^{len_s} S_s + zc_s, periodic
-// S_0 = (I - A^b)^-1 (scan of all). Anti-causal, right to left:
+// anti-causal state entering it from the right), for streams of any length
+// (those of at most 64 kIirQMax segments take k_iir_carry_u below). Lane l
+// takes the contiguous segments [l q, (l+1) q), q = ceil(nseg / 64): it
+// composes its segments' affine maps, an inclusive scan of the maps across
+// the lanes (Hillis-Steele) gives every lane its entering state, and the
+// lanes then walk their segments. Causal: S_{s+1} = A^{len_s} S_s + zc_s,
+// periodic S_0 = (I - A^b)^-1 (scan of all). Anti-causal, right to left:
 // F_s = B^{len_s} F_{s+1} + c_s, c_s = za_s + N_{len_s} S_s, periodic
-// F_0 = (I - B^b)^-1 (scan of all); segment s receives V_s = F_{s+1}.
-// A lane's states (q <= QR segments) are loaded once into registers and
-// stored once; longer streams (QR = 0) re-read them for each phase.
-template <typename T, int M, int QR>
+// F_0 = (I - B^b)^-1 (scan of all); segment s receives V_s = F_{s+1}. A
+// lane reads its segments' states from global memory in each phase.
+template <typename T, int M>
 __global__ __launch_bounds__(256) void k_iir_carry(int N, int L, IirStream one, const IirStream* __restrict__ tab,
                                                    int nstreams, const double* __restrict__ coef,
                                                    const double* __restrict__ scoef, T* __restrict__ zs) {
   using Ly = IirLayout<M>;
-  constexpr int QA = QR > 0 ? QR : 1;
   constexpr int NMAT = 8 * M * M;
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -500,9 +514,8 @@ __global__ __launch_bounds__(256) void k_iir_carry(int N, int L, IirStream one, 
   }
   __syncthreads();
   if (n >= N) return;  // the whole wavefront
-  struct {
-    int AL, ALL, BL, BLL, NL, NLL, IA, IB;
-  } constexpr Lo = {0, MM, 2 * MM, 3 * MM, 4 * MM, 5 * MM, 6 * MM, 7 * MM};
+  constexpr int oAL = 0, oALL = MM, oBL = 2 * MM, oBLL = 3 * MM, oNL = 4 * MM, oNLL = 5 * MM, oIA = 6 * MM,
+                oIB = 7 * MM;
   const double* cf = smat[wv];
   IirStream sd = nstreams <= 1 ? one : tab[si];
   sd.b = uniform64(sd.b);
@@ -514,43 +527,19 @@ __global__ __launch_bounds__(256) void k_iir_carry(int N, int L, IirStream one, 
   const int64_t a0 = lane * q < nseg ? lane * q : nseg;
   const int64_t a1 = a0 + q < nseg ? a0 + q : nseg;
   const int cnt = (int)(a1 - a0);
-  // the lane's states in registers (QR > 0): zc then za of each segment
-  T r_zc[QA][M], r_za[QA][M];
-  if constexpr (QR > 0) {
-#pragma unroll
-    for (int k = 0; k < QR; ++k)
-#pragma unroll
-      for (int i = 0; i < M; ++i) {
-        r_zc[k][i] = k < cnt ? z[(a0 + k) * stride + i] : T(0);
-        r_za[k][i] = k < cnt ? z[(a0 + k) * stride + M + i] : T(0);
-      }
-  }
-  auto get = [&](int k, int i, bool za) -> double {
-    if constexpr (QR > 0) return (double)(za ? r_za[k][i] : r_zc[k][i]);
-    else return (double)z[(a0 + k) * stride + (za ? M : 0) + i];
-  };
-  auto put = [&](int k, int i, bool za, double v) {
-    if constexpr (QR > 0) {
-      if (za) r_za[k][i] = T(v);
-      else r_zc[k][i] = T(v);
-    } else {
-      z[(a0 + k) * stride + (za ? M : 0) + i] = T(v);
-    }
-  };
+  auto get = [&](int k, int i, bool za) -> double { return (double)z[(a0 + k) * stride + (za ? M : 0) + i]; };
+  auto put = [&](int k, int i, bool za, double v) { z[(a0 + k) * stride + (za ? M : 0) + i] = T(v); };
+  auto last_seg = [&](int k) { return a0 + k + 1 == nseg; };
   const double zero[M] = {};
   double P[M * M], Y[M], Po[M * M], Yo[M];
   // ---- causal: local composition, then the scan
   set_identity<M>(P, Y);
-#pragma unroll
-  for (int k = 0; k < (QR > 0 ? QR : 1); ++k) {
-    for (int kk = (QR > 0 ? k : 0); kk < (QR > 0 ? k + 1 : cnt); ++kk) {
-      if (kk >= cnt) break;
-      const double* As = cf + (a0 + kk + 1 < nseg ? Lo.AL : Lo.ALL);
-      double zc[M];
-      for (int i = 0; i < M; ++i) zc[i] = get(kk, i, false);
-      matvec_add<M>(As, Y, zc, Y);
-      mat_mul<M>(As, P, P);
-    }
+  for (int k = 0; k < cnt; ++k) {
+    const double* As = cf + (last_seg(k) ? oALL : oAL);
+    double zc[M];
+    for (int i = 0; i < M; ++i) zc[i] = get(k, i, false);
+    matvec_add<M>(As, Y, zc, Y);
+    mat_mul<M>(As, P, P);
   }
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -563,40 +552,32 @@ __global__ __launch_bounds__(256) void k_iir_carry(int N, int L, IirStream one, 
   double Tt[M], S0[M], S[M];
 #pragma unroll
   for (int i = 0; i < M; ++i) Tt[i] = __shfl(Y[i], 63, 64);
-  matvec_add<M>(cf + Lo.IA, Tt, zero, S0);
+  matvec_add<M>(cf + oIA, Tt, zero, S0);
   shfl_map<M>(P, Y, Po, Yo, 1, true);  // exclusive: the lanes to the left
   if (lane == 0) set_identity<M>(Po, Yo);
   matvec_add<M>(Po, S0, Yo, S);
-#pragma unroll
-  for (int k = 0; k < (QR > 0 ? QR : 1); ++k) {
-    for (int kk = (QR > 0 ? k : 0); kk < (QR > 0 ? k + 1 : cnt); ++kk) {
-      if (kk >= cnt) break;
-      const bool last = a0 + kk + 1 == nseg;
-      double zc[M], c[M];
-      for (int i = 0; i < M; ++i) {
-        zc[i] = get(kk, i, false);
-        c[i] = get(kk, i, true);
-      }
-      matvec_add<M>(cf + (last ? Lo.NLL : Lo.NL), S, c, c);
-      for (int i = 0; i < M; ++i) {
-        put(kk, i, false, S[i]);
-        put(kk, i, true, c[i]);
-      }
-      matvec_add<M>(cf + (last ? Lo.ALL : Lo.AL), S, zc, S);
+  for (int k = 0; k < cnt; ++k) {
+    const bool last = last_seg(k);
+    double zc[M], c[M];
+    for (int i = 0; i < M; ++i) {
+      zc[i] = get(k, i, false);
+      c[i] = get(k, i, true);
     }
+    matvec_add<M>(cf + (last ? oNLL : oNL), S, c, c);
+    for (int i = 0; i < M; ++i) {
+      put(k, i, false, S[i]);
+      put(k, i, true, c[i]);
+    }
+    matvec_add<M>(cf + (last ? oALL : oAL), S, zc, S);
   }
   // ---- anti-causal: local composition right to left, then the suffix scan
   set_identity<M>(P, Y);
-#pragma unroll
-  for (int k = (QR > 0 ? QR : 1) - 1; k >= 0; --k) {
-    for (int kk = (QR > 0 ? k : cnt - 1); kk >= (QR > 0 ? k : 0); --kk) {
-      if (kk >= cnt) continue;
-      const double* Bs = cf + (a0 + kk + 1 < nseg ? Lo.BL : Lo.BLL);
-      double c[M];
-      for (int i = 0; i < M; ++i) c[i] = get(kk, i, true);
-      matvec_add<M>(Bs, Y, c, Y);
-      mat_mul<M>(Bs, P, P);
-    }
+  for (int k = cnt - 1; k >= 0; --k) {
+    const double* Bs = cf + (last_seg(k) ? oBLL : oBL);
+    double c[M];
+    for (int i = 0; i < M; ++i) c[i] = get(k, i, true);
+    matvec_add<M>(Bs, Y, c, Y);
+    mat_mul<M>(Bs, P, P);
   }
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -609,29 +590,277 @@ __global__ __launch_bounds__(256) void k_iir_carry(int N, int L, IirStream one, 
   double Ut[M], F0[M], F[M];
 #pragma unroll
   for (int i = 0; i < M; ++i) Ut[i] = __shfl(Y[i], 0, 64);
-  matvec_add<M>(cf + Lo.IB, Ut, zero, F0);
+  matvec_add<M>(cf + oIB, Ut, zero, F0);
   shfl_map<M>(P, Y, Po, Yo, 1, false);  // the lanes to the right
   if (lane == 63) set_identity<M>(Po, Yo);
   matvec_add<M>(Po, F0, Yo, F);
-#pragma unroll
-  for (int k = (QR > 0 ? QR : 1) - 1; k >= 0; --k) {
-    for (int kk = (QR > 0 ? k : cnt - 1); kk >= (QR > 0 ? k : 0); --kk) {
-      if (kk >= cnt) continue;
-      double c[M];
-      for (int i = 0; i < M; ++i) c[i] = get(kk, i, true);
-      for (int i = 0; i < M; ++i) put(kk, i, true, F[i]);  // V_s = F_{s+1}
-      matvec_add<M>(cf + (a0 + kk + 1 < nseg ? Lo.BL : Lo.BLL), F, c, F);
-    }
+  for (int k = cnt - 1; k >= 0; --k) {
+    double c[M];
+    for (int i = 0; i < M; ++i) c[i] = get(k, i, true);
+    for (int i = 0; i < M; ++i) put(k, i, true, F[i]);  // V_s = F_{s+1}
+    matvec_add<M>(cf + (last_seg(k) ? oBLL : oBL), F, c, F);
   }
-  if constexpr (QR > 0) {
+}
+
+// The same periodic states for streams of at most 64 kIirQMax segments, with
+// lane-to-lane steps that are powers of one matrix. Lane l takes q =
+// ceil(nseg / 64) segments; every lane before the one holding the last
+// segment (lane_last) has q full segments, so composing lanes m..l of the
+// causal recursion is Y -> A^{qL (l-m+1)} Y + ..., the same matrix on every
+// lane. The scans therefore exchange only 3-vectors and apply the tabulated
+// A^{qL 2^k} (B^{qL 2^k}), instead of composing a matrix per lane:
+//   causal: local zero-start composition Y_l, inclusive scan
+//     E_l = sum_{m <= l} A^{qL(l-m)} Y_m (exact for l < lane_last), the
+//     lanes' zero-start entering states Ex_l = E_{l-1}; lane_last walks its
+//     segments from Ex to the zero-start total T; S_0 = (I - A^b)^-1 T; lane
+//     l enters with A^{qL l} S_0 + Ex_l (binary powers of the table);
+//   anti-causal (right to left, c_s = za_s + N_{len_s} S_s): local
+//     zero-start U_l, inclusive suffix scan G_l = sum_{m >= l} B^{qL(m-l)} U_m
+//     (lanes past lane_last hold 0, so windows that reach them add nothing),
+//     F_0 = (I - B^b)^-1 G_0; lane l < lane_last is entered from the right
+//     by B^{qL(lane_last-1-l)} W + G_{l+1}, W = B^{len(lane_last)} F_0, and
+//     lane_last by F_0.
+// One wavefront per (stream, column); the 20 matrices it uses staged in LDS.
+// With STAGE, the four columns' segment states also pass through LDS, loaded
+// and stored by the whole workgroup as runs of the four columns' states per
+// segment: a lane reading its own column's segments straight from global
+// memory touches a separate cache line for every 24 bytes, and that gather,
+// not the arithmetic, is what bounds the kernel at 4096 columns (with the
+// arithmetic removed it still takes 39.5 of its 46 us).
+template <typename T, int M, int QR>
+__global__ __launch_bounds__(256) void k_iir_carry_u(int N, int L, IirStream one, const IirStream* __restrict__ tab,
+                                                     int nstreams, const double* __restrict__ coef,
+                                                     const double* __restrict__ scoef, T* __restrict__ zs) {
+  using Ly = IirLayout<M>;
+  constexpr int MM = M * M;
+  constexpr int NMAT = 20;  // A^L, A^L', B^L, B^L', N_L, N_L', (I-A^b)^-1, (I-B^b)^-1, then the two power tables
+  constexpr int oAL = 0, oALL = MM, oBL = 2 * MM, oBLL = 3 * MM, oNL = 4 * MM, oNLL = 5 * MM, oIA = 6 * MM,
+                oIB = 7 * MM, oPA = 8 * MM, oPB = 14 * MM;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int groups = (N + 3) / 4;
+  const int si = __builtin_amdgcn_readfirstlane(blockIdx.x / groups);  // the stream
+  const int n = __builtin_amdgcn_readfirstlane((blockIdx.x % groups) * 4 + wv);
+  IirStream sd = nstreams <= 1 ? one : tab[si];
+  sd.b = uniform64(sd.b);
+  sd.seg0 = uniform64(sd.seg0);
+  const int64_t nseg = (sd.b + L - 1) / L;
+  const int q = (int)((nseg + 63) / 64);  // 1 .. QR (the launch checked max_nseg)
+  __shared__ double smat[4][NMAT * MM];
+  // staged states: [column][segment][2M], the column blocks padded by one
+  constexpr int SEGMAX = 64 * QR;
+  constexpr int CS = SEGMAX * 2 * M + 1;
+  // measured: staging pays in FP32 with up to 256 segments (QR = 4); with
+  // eight segments per lane, or in FP64, its LDS costs more occupancy than
+  // the gather it saves
+  constexpr bool STAGE = sizeof(T) == 4 && QR == 4;
+  __shared__ T zst[STAGE ? 4 * CS : 1];
+  const int nb = (int)(blockIdx.x % groups) * 4;  // the workgroup's first column
+  const int ncol = N - nb < 4 ? N - nb : 4;
+  const int64_t stride_g = (int64_t)N * 2 * M;
+  const int sgs = N * 2 * M;  // 32-bit: nseg * N * 2M < 2^31 (checked at launch)
+  T* zb = zs + (sd.seg0 * N + nb) * 2 * M;
+  // staging: thread t moves column t % 4's 2M values of segment
+  // pass * 64 + t / 4 (a wavefront: 16 segments, each a run of 4 columns)
+  const int sc = (int)(threadIdx.x & 3), ss = (int)(threadIdx.x >> 2);
+  if constexpr (STAGE) {
+    T buf[QR][2 * M];
 #pragma unroll
-    for (int k = 0; k < QR; ++k)
-      if (k < cnt)
+    for (int ps = 0; ps < QR; ++ps) {  // every load in flight at once
+      const int sg = ps * 64 + ss;
+      const bool ok = sg < nseg && sc < ncol;
 #pragma unroll
-        for (int i = 0; i < M; ++i) {
-          z[(a0 + k) * stride + i] = r_zc[k][i];
-          z[(a0 + k) * stride + M + i] = r_za[k][i];
-        }
+      for (int i = 0; i < 2 * M; ++i) buf[ps][i] = ok ? zb[sg * sgs + sc * 2 * M + i] : T(0);
+    }
+#pragma unroll
+    for (int ps = 0; ps < QR; ++ps)
+#pragma unroll
+      for (int i = 0; i < 2 * M; ++i) zst[sc * CS + (ps * 64 + ss) * 2 * M + i] = buf[ps][i];
+  }
+  for (int i = lane; i < NMAT * MM; i += 64) {
+    double v = 0.0;
+    if (n < N) {
+      const int m = i / MM, e = i - m * MM;
+      const double* cfm = coef + (int64_t)n * Ly::STRIDE;
+      const double* scm = scoef + ((int64_t)si * N + n) * Ly::SSTRIDE;
+      switch (m) {
+        case 0: v = cfm[Ly::AL + e]; break;
+        case 1: v = scm[Ly::ALL + e]; break;
+        case 2: v = cfm[Ly::BL + e]; break;
+        case 3: v = scm[Ly::BLL + e]; break;
+        case 4: v = cfm[Ly::NL + e]; break;
+        case 5: v = scm[Ly::NLL + e]; break;
+        case 6: v = scm[Ly::IA + e]; break;
+        case 7: v = scm[Ly::IB + e]; break;
+        default:
+          v = m < 14 ? cfm[Ly::PA + ((q - 1) * 6 + (m - 8)) * MM + e] : cfm[Ly::PB + ((q - 1) * 6 + (m - 14)) * MM + e];
+          break;
+      }
+    }
+    smat[wv][i] = v;
+  }
+  __syncthreads();
+  if (n < N) {  // the whole wavefront
+  const double* cf = smat[wv];
+  const int64_t stride = STAGE ? 2 * M : stride_g;
+  T* z = STAGE ? zst + wv * CS : zs + (sd.seg0 * N + n) * 2 * M;
+  const int64_t a0 = lane * (int64_t)q < nseg ? lane * (int64_t)q : nseg;
+  const int64_t a1 = a0 + q < nseg ? a0 + q : nseg;
+  const int cnt = (int)(a1 - a0);
+  const int lane_last = (int)((nseg - 1) / q);
+  // the lane's segment states: zc then za of each
+  T r_zc[QR][M], r_za[QR][M];
+#pragma unroll
+  for (int k = 0; k < QR; ++k)
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      r_zc[k][i] = k < cnt ? z[(a0 + k) * stride + i] : T(0);
+      r_za[k][i] = k < cnt ? z[(a0 + k) * stride + M + i] : T(0);
+    }
+  const double zero[M] = {};
+  auto last_seg = [&](int k) { return a0 + k + 1 == nseg; };
+  // ---- causal
+  double Y[M] = {};
+#pragma unroll
+  for (int k = 0; k < QR; ++k) {
+    if (k >= cnt) break;
+    double zc[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) zc[i] = (double)r_zc[k][i];
+    matvec_add<M>(cf + (last_seg(k) ? oALL : oAL), Y, zc, Y);
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int d = 1 << k;
+    double Yo[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) Yo[i] = __shfl_up(Y[i], d, 64);
+    if (lane >= d) matvec_add<M>(cf + oPA + k * MM, Yo, Y, Y);
+  }
+  double Ex[M], Tz[M], Tt[M], S0[M], S[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    Ex[i] = __shfl_up(Y[i], 1, 64);
+    if (lane == 0) Ex[i] = 0.0;
+    Tz[i] = Ex[i];
+  }
+#pragma unroll
+  for (int k = 0; k < QR; ++k) {  // lane_last: on to the zero-start total
+    if (k >= cnt) break;
+    double zc[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) zc[i] = (double)r_zc[k][i];
+    matvec_add<M>(cf + (last_seg(k) ? oALL : oAL), Tz, zc, Tz);
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) Tt[i] = __shfl(Tz[i], lane_last, 64);
+  matvec_add<M>(cf + oIA, Tt, zero, S0);
+#pragma unroll
+  for (int i = 0; i < M; ++i) S[i] = S0[i];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {  // A^{qL lane} S_0
+    double t[M];
+    matvec_add<M>(cf + oPA + k * MM, S, zero, t);
+    if ((lane >> k) & 1)
+#pragma unroll
+      for (int i = 0; i < M; ++i) S[i] = t[i];
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) S[i] += Ex[i];
+#pragma unroll
+  for (int k = 0; k < QR; ++k) {  // the segments' entering states; c_s = za_s + N S_s
+    if (k >= cnt) break;
+    const bool last = last_seg(k);
+    double zc[M], c[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      zc[i] = (double)r_zc[k][i];
+      c[i] = (double)r_za[k][i];
+    }
+    matvec_add<M>(cf + (last ? oNLL : oNL), S, c, c);
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      r_zc[k][i] = T(S[i]);
+      r_za[k][i] = T(c[i]);
+    }
+    matvec_add<M>(cf + (last ? oALL : oAL), S, zc, S);
+  }
+  // ---- anti-causal
+  double U[M] = {};
+#pragma unroll
+  for (int k = QR - 1; k >= 0; --k) {
+    if (k >= cnt) continue;
+    double c[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) c[i] = (double)r_za[k][i];
+    matvec_add<M>(cf + (last_seg(k) ? oBLL : oBL), U, c, U);
+  }
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int d = 1 << k;
+    double Uo[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) Uo[i] = __shfl_down(U[i], d, 64);
+    if (lane + d < 64) matvec_add<M>(cf + oPB + k * MM, Uo, U, U);
+  }
+  double Ut[M], F0[M], Wz[M], Wt[M], Gn[M], V[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    Ut[i] = __shfl(U[i], 0, 64);
+    Gn[i] = __shfl_down(U[i], 1, 64);
+  }
+  matvec_add<M>(cf + oIB, Ut, zero, F0);
+#pragma unroll
+  for (int i = 0; i < M; ++i) Wz[i] = F0[i];
+#pragma unroll
+  for (int k = QR - 1; k >= 0; --k) {  // lane_last: W = B^{len} F_0
+    if (k >= cnt) continue;
+    matvec_add<M>(cf + (last_seg(k) ? oBLL : oBL), Wz, zero, Wz);
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) Wt[i] = __shfl(Wz[i], lane_last, 64);
+  const int mpow = lane_last - 1 - lane;
+#pragma unroll
+  for (int i = 0; i < M; ++i) V[i] = Wt[i];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {  // B^{qL (lane_last - 1 - lane)} W
+    double t[M];
+    matvec_add<M>(cf + oPB + k * MM, V, zero, t);
+    if (mpow >= 0 && ((mpow >> k) & 1))
+#pragma unroll
+      for (int i = 0; i < M; ++i) V[i] = t[i];
+  }
+#pragma unroll
+  for (int i = 0; i < M; ++i) V[i] = lane < lane_last ? V[i] + Gn[i] : F0[i];
+#pragma unroll
+  for (int k = QR - 1; k >= 0; --k) {  // right to left: segment s receives F_{s+1}
+    if (k >= cnt) continue;
+    double c[M];
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+      c[i] = (double)r_za[k][i];
+      r_za[k][i] = T(V[i]);
+    }
+    matvec_add<M>(cf + (last_seg(k) ? oBLL : oBL), V, c, V);
+  }
+#pragma unroll
+  for (int k = 0; k < QR; ++k)
+    if (k < cnt)
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        z[(a0 + k) * stride + i] = r_zc[k][i];
+        z[(a0 + k) * stride + M + i] = r_za[k][i];
+      }
+  }  // n < N
+  if constexpr (STAGE) {
+    __syncthreads();
+#pragma unroll
+    for (int ps = 0; ps < QR; ++ps) {
+      const int sg = ps * 64 + ss;
+      if (sg < nseg && sc < ncol)
+#pragma unroll
+        for (int i = 0; i < 2 * M; ++i) zb[sg * sgs + sc * 2 * M + i] = zst[sc * CS + sg * 2 * M + i];
+    }
   }
 }
 
@@ -721,16 +950,21 @@ static hipError_t launch_iir_m(int stage, int prec, const IirStream& one, const 
       break;
     case kIirCarry: {
       const dim3 g4((unsigned)((int64_t)nstreams * ((N + 3) / 4)));  // one wavefront per (stream, column)
-#define CARRY(T, Q) k_iir_carry<T, M, Q><<<g4, 256, 0, st>>>(N, L, one, tab, nstreams, coef, scoef, (T*)zs)
+#define CARRY(T) k_iir_carry<T, M><<<g4, 256, 0, st>>>(N, L, one, tab, nstreams, coef, scoef, (T*)zs)
+      if (max_nseg * (int64_t)N * 2 * M >= (int64_t(1) << 31)) return hipErrorNotSupported;
+#define CARRY_U(T, Q) \
+  k_iir_carry_u<T, M, Q><<<g4, 256, 0, st>>>(N, L, one, tab, nstreams, coef, scoef, (T*)zs)
+      static_assert(kIirQMax == 8, "the uniform-power carry takes up to 8 segments per lane");
       if (prec == F32) {
-        if (max_nseg <= 64 * 4) CARRY(float, 4);
-        else if (max_nseg <= 64 * 8) CARRY(float, 8);
-        else CARRY(float, 0);
+        if (max_nseg <= 64 * 4) CARRY_U(float, 4);
+        else if (max_nseg <= 64 * 8) CARRY_U(float, 8);
+        else CARRY(float);
       } else {
-        if (max_nseg <= 64 * 4) CARRY(double, 4);
-        else if (max_nseg <= 64 * 8) CARRY(double, 8);
-        else CARRY(double, 0);
+        if (max_nseg <= 64 * 4) CARRY_U(double, 4);
+        else if (max_nseg <= 64 * 8) CARRY_U(double, 8);
+        else CARRY(double);
       }
+#undef CARRY_U
 #undef CARRY
       break;
     }

@@ -51,7 +51,11 @@ def _run(plan, packed, s, phi, method):
 @pytest.mark.parametrize("N,b,phi", [
     (16, 1, 0.1), (16, 3, 0.1), (64, 7, 0.1), (64, 64, 0.1), (64, 100, 0.1), (256, 257, 0.3),
     (32, 1000, 0.05), (128, 4096, 0.1), (2048, 128, 0.1), (4096, 512, 0.1), (8, 3000, 0.01),
-    (64, 1031, 0.001), (64, 20000, 0.1),  # 313 (F32) and 625 (F64) segments: the carry re-reads its states
+    (64, 1031, 0.001),
+    # segments of 64 frames, q = ceil(nseg / 64) per carry lane: 141 (q = 3, a
+    # 40-frame last segment), 256 (q = 4, all full), 313 (q = 5), 469 (q = 8,
+    # the largest of the uniform-power carry), 625 (q = 10: the general carry)
+    (16, 9000, 0.1), (16, 16384, 0.1), (64, 20000, 0.1), (16, 30000, 0.1), (16, 40000, 0.1),
 ])
 def test_recursive_matches_oracle(prec, N, b, phi):
     print(f"case recursive prec={prec} N={N} b={b} phi={phi}", flush=True)
