@@ -51,6 +51,11 @@ COLUMN_FIRST = ("ipfb_cols_fwd", "ipfb_cols_rec_pass1")
 COLUMN_LAST = ("ipfb_cols_inv", "ipfb_cols_rec_pass2")
 
 
+def progress(msg):
+    """One line per finished section on stderr (the JSON line stays alone on stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_bytes(name, N, b, Nf, bf, esz, kind="compulsory", one_pass=False):
     S = N * b
     K = Nf // 2 + 1
@@ -610,6 +615,7 @@ def main():
                 per_kernel[k] = {"avg_us": 1e3 * ms / n, "launches": n}
         ipfb.profile_reset()
         esz = 4 if tag == "f32" else 8
+        progress(f"{tag} form timed: {sec_plain * 1e3:.3f} ms per step")
         results[tag] = {"sec_per_step": sec, "sec_per_step_no_events": sec_plain, "per_kernel": per_kernel,
                         "esz": esz, "steps": steps}
         outputs[tag] = (xh, Y, A)
@@ -693,18 +699,25 @@ def main():
         out["roofline"]["frac_of_copy_peak"] = achieved / cp
     if not args.no_small:
         out["small_config_latency"] = small_config(torch, ipfb, inputs)
+        progress("small configuration done")
     if not args.no_ml:
         out["ml_form"] = ml_form(torch, ipfb, inputs)
+        progress("ML-CG form done")
     if not args.no_batched:
         out["batched_form"] = batched_form(torch, ipfb, inputs, args.batched_streams)
+        progress("batched form done")
     if not args.no_stream:
         out["streaming_form"] = streaming_form(torch, ipfb)
+        progress("streaming form done")
     if not args.no_sweep:
         out["structured_prior_sweep"] = structured_sweep(torch, ipfb)
+        progress("structured-prior sweep done")
     if not args.no_alt:
         out["alt_solvers"] = alt_solvers(torch, ipfb)
+        progress("comparison solvers done")
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(N, p, Nf, phi, args.cpu_frames, 2)
+        progress("CPU oracle baseline done")
     print(json.dumps(out), flush=True)
 
 
