@@ -8,7 +8,9 @@ inputs are regenerated here from the same seeds.
 
 FP32 and FP64 CG trajectories part once the FP32 residual reaches its
 rounding floor, so the residual histories are compared while the oracle's
-residual is above 1e-4 |r_0| and x_100 against the oracle's x_100."""
+residual is above 1e-4 |r_0| (CG amplifies rounding differences as the
+residual falls: measured 1.1e-4 here, bound 1e-3) and x_100 against the
+oracle's x_100."""
 import json
 import os
 
@@ -58,5 +60,6 @@ def test_ml_cg_workload_shape_against_stored_oracle():
           f"|r_100| gpu {ng[-1]:.3e} oracle {ref_n[-1]:.3e}", flush=True)
     assert int(k.sum()) >= 10
     assert e_hist < 1e-3
-    assert e_x < 1e-4 and e_norm < 1e-5
+    # measured: x_100 3.3e-7, |x_100| 2.6e-8 (FP32 vectors against the FP64 oracle)
+    assert e_x < 1e-5 and e_norm < 1e-6
     assert ng[-1] < 1e-5 * ng[0]
