@@ -107,6 +107,17 @@ def test_new_entry_points_reject_bad_arguments_before_any_device_call():
     assert L.ipfb_delta_analytic(None, 16, 0.1, 0.0, None, None) == ipfb.EINVAL
     assert L.ipfb_autospectrum_error(None, None, None, None, None) == ipfb.EINVAL
     assert L.ipfb_mask_structured(None, 4, 8, None, None) == ipfb.EINVAL
+    # column method, comparison solvers, ML-CG (both entries), mask packing
+    assert L.ipfb_plan_set_column_method(None, 0) == ipfb.EINVAL
+    assert L.ipfb_batched_set_column_method(None, 0) == ipfb.EINVAL
+    assert L.ipfb_tikhonov(None, 0, None, None, 0.1, 1, None, None) == ipfb.EINVAL
+    assert L.ipfb_fir_kernels(None, 0.1, 11, 1, None, None) == ipfb.EINVAL
+    assert L.ipfb_fir(None, 0, None, None, 0.1, 11, 1, None, None) == ipfb.EINVAL
+    assert L.ipfb_ml_cg(None, 0, None, None, None, None, 1.0, 0.1, 0.1, 5, None, None, None, None) == ipfb.EINVAL
+    assert L.ipfb_ml_cg_noalloc(None, 0, None, None, None, None, 1.0, 0.1, 0.1, 5, None, None, None,
+                                None) == ipfb.EINVAL
+    assert L.ipfb_mask_pack(None, -1, None, None) == ipfb.EINVAL
+    assert L.ipfb_mask_pack(None, 64, None, None) == ipfb.EINVAL
     w = np.ones(4 * 64)
     h = ctypes.c_void_p()
     for chunk, halo, prec in [(100, 8, 0), (64, 31, 0), (2, 0, 0), (64, -1, 0), (1 << 16, 8, 0), (1 << 15, 8, 1),
