@@ -91,9 +91,8 @@ __global__ __launch_bounds__((RowCfg<T, LOG2N>::NT)) void k_row_irfft(
 }
 
 // Persistent form for 4-bit spectra: each workgroup inverts frames j, j + G,
-// j + 2G, ... (G = grid size). The per-channel factors and (where they fit)
-// the pre-twiddles e^{+2 pi i k/N} sit in LDS for the workgroup's life; a
-// frame's packed bytes (an unaligned run of N/2+1 bytes) arrive as aligned
+// j + 2G, ... (G = grid size). The per-channel factors sit in LDS for the
+// workgroup's life; a frame's packed bytes (an unaligned run of N/2+1 bytes) arrive as aligned
 // 4-byte words staged through LDS, and the next frame's words are fetched
 // into registers while the current frame's FFT runs.
 template <typename T, int LOG2N>
@@ -105,12 +104,10 @@ struct RowPCfg {
   static constexpr int LS = lds_len(H);
   static constexpr int RAWW = (H + 1 + 3) / 4 + 2;  // words covering the run from its aligned start
   static constexpr int DPT = (RAWW + NT - 1) / NT;  // words fetched per thread
-  // the pre-twiddles sit in LDS where that still fits the LDS budget with
-  // them (FP32); otherwise (FP64, long frames) they are read from the global
-  // table, which stays in L2
-  static constexpr int LDSB0 = LS * (int)sizeof(cx<T>) + (H + 1) * (int)sizeof(T) + RAWW * 4;
-  static constexpr bool WT_LDS = LDSB0 + H * (int)sizeof(cx<T>) <= 81920;
-  static constexpr int LDSB = LDSB0 + (WT_LDS ? H * (int)sizeof(cx<T>) : 0);
+  // the pre-twiddles are read from the global table (it stays in L2): an
+  // LDS copy would cost a workgroup per CU, and measured slower (101 against
+  // 92 us at N = 4096, FP32)
+  static constexpr int LDSB = LS * (int)sizeof(cx<T>) + (H + 1) * (int)sizeof(T) + RAWW * 4;
 };
 
 // The stream of global frame j: the last s with f0[s] <= j.
@@ -138,7 +135,6 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
   static_assert(H % NT == 0 || NT == 64, "frame must split over the threads");
   __shared__ cx<T> s[LS];
   __shared__ T facs[H + 1];
-  __shared__ cx<T> wt[Cfg::WT_LDS ? H : 1];  // e^{+2 pi i k / N}: pre-twiddles
   __shared__ unsigned int raw[RAWW];
   const int tid = threadIdx.x;
   // dequantisation factor 1/(s_k N), formed in FP64 from the stored FP32 scale
@@ -146,8 +142,6 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
     for (int k = tid; k <= H; k += NT) facs[k] = T(1.0 / ((double)sc[k] * (double)N));
   };
   if (!MULTI) set_facs(scale1);
-  if constexpr (Cfg::WT_LDS)
-    for (int k = tid; k < H; k += NT) wt[k] = conj(twN[k]);
   unsigned int pf[DPT];
   int snext = 0;  // MULTI: the stream of the frame fetched last
   auto fetch = [&](int64_t j) {
@@ -215,7 +209,7 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
         ym.y = T(0);
       }
       const cx<T> a = yk + conj(ym);
-      const cx<T> t = cmul(Cfg::WT_LDS ? wt[k] : conj(twN[k]), yk - conj(ym));
+      const cx<T> t = cmul(conj(twN[k]), yk - conj(ym));  // e^{+2 pi i k/N}
       return mk<T>(a.x - t.y, a.y + t.x);
     };
     // the FFT's own twiddles stay in global memory (L2): an LDS copy would
