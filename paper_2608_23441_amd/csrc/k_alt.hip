@@ -183,24 +183,27 @@ hipError_t launch_fir_setup(int prec, int stage, void* frames, void* g, int N, i
 
 // x[j][n] = sum_{l<L} g[l][n] d[(j - c0 - l) mod b][n]. Workgroup: 64 columns
 // x 4 groups of kFirTJ consecutive output frames; the 64 columns' kernels sit
-// in LDS. A thread streams the inputs its outputs need, d[j0 - c0 - L + 1 ..
-// j0 + kFirTJ - 1 - c0], each once, and adds each into the outputs it feeds.
-constexpr int kFirTJ = 16;
+// in LDS, zero-padded to a multiple of kFirCH lags. A thread keeps its
+// kFirTJ outputs in registers and takes the taps kFirCH at a time: the chunk's
+// taps and the kFirTJ + kFirCH - 1 inputs they reach, then kFirTJ x kFirCH
+// multiply-adds from registers (FP64 sums).
+constexpr int kFirTJ = 16, kFirCH = 8;
 template <typename T>
 __global__ __launch_bounds__(256) void k_fir(const T* __restrict__ d, const T* __restrict__ g, T* __restrict__ x,
                                              int N, int64_t b, int L, int64_t c0) {
   extern __shared__ unsigned char fir_smem[];
-  T* gs = reinterpret_cast<T*>(fir_smem);  // [L][64]
+  T* gs = reinterpret_cast<T*>(fir_smem);  // [Lp][64]
   const int tid = threadIdx.x;
   const int col = tid & 63, rg = tid >> 6;
   const int ntile = (N + 63) / 64;
   const int tile = (int)(blockIdx.x % ntile);
   const int64_t fb = (int64_t)(blockIdx.x / ntile) * (4 * kFirTJ);
   const int n = tile * 64 + col;
-  for (int e = tid; e < L * 64; e += 256) {
+  const int Lp = (L + kFirCH - 1) / kFirCH * kFirCH;
+  for (int e = tid; e < Lp * 64; e += 256) {
     const int l = e >> 6, c = e & 63;
     const int nn = tile * 64 + c;
-    gs[e] = nn < N ? g[(int64_t)l * N + nn] : T(0);
+    gs[e] = (l < L && nn < N) ? g[(int64_t)l * N + nn] : T(0);
   }
   __syncthreads();
   if (n >= N) return;
@@ -209,20 +212,44 @@ __global__ __launch_bounds__(256) void k_fir(const T* __restrict__ d, const T* _
   double acc[kFirTJ];
 #pragma unroll
   for (int o = 0; o < kFirTJ; ++o) acc[o] = 0.0;
-  // input frame k = j0 + o - c0 - l feeds output o through kernel lag index l
-  const int nin = kFirTJ + L - 1;
-  int64_t k = j0 - c0 - (L - 1);
-  k %= b;
-  if (k < 0) k += b;
-  for (int q = 0; q < nin; ++q) {
-    const double dk = (double)d[k * N + n];
-    // this input is k = j0 + o - c0 - l, i.e. l = o - q + L - 1
+  // din[t] = d[j0 - c0 - l0 - (kFirCH - 1) + t]: output o, tap l0 + c reads
+  // t = o - c + kFirCH - 1. The next chunk's window is this one moved
+  // kFirCH frames back: kFirCH new inputs, fetched during this chunk's
+  // multiply-adds, and the rest shifted in registers.
+  constexpr int NIN = kFirTJ + kFirCH - 1;
+  auto wrap = [&](int64_t k) {
+    k %= b;
+    return k < 0 ? k + b : k;
+  };
+  double din[NIN], nx[kFirCH];
+  {
+    int64_t k = wrap(j0 - c0 - (kFirCH - 1));
 #pragma unroll
-    for (int o = 0; o < kFirTJ; ++o) {
-      const int l = o - q + L - 1;
-      if (l >= 0 && l < L) acc[o] += (double)gs[l * 64 + col] * dk;
+    for (int t = 0; t < NIN; ++t) {
+      din[t] = (double)d[k * N + n];
+      k = (k + 1 == b) ? 0 : k + 1;
     }
-    if (++k == b) k = 0;
+  }
+  for (int l0 = 0; l0 < Lp; l0 += kFirCH) {
+    if (l0 + kFirCH < Lp) {
+      int64_t k = wrap(j0 - c0 - (l0 + kFirCH) - (kFirCH - 1));
+#pragma unroll
+      for (int t = 0; t < kFirCH; ++t) {
+        nx[t] = (double)d[k * N + n];
+        k = (k + 1 == b) ? 0 : k + 1;
+      }
+    }
+    double tg[kFirCH];
+#pragma unroll
+    for (int c = 0; c < kFirCH; ++c) tg[c] = (double)gs[(l0 + c) * 64 + col];
+#pragma unroll
+    for (int o = 0; o < kFirTJ; ++o)
+#pragma unroll
+      for (int c = 0; c < kFirCH; ++c) acc[o] += tg[c] * din[o - c + kFirCH - 1];
+#pragma unroll
+    for (int t = NIN - 1; t >= kFirCH; --t) din[t] = din[t - kFirCH];
+#pragma unroll
+    for (int t = 0; t < kFirCH; ++t) din[t] = nx[t];
   }
 #pragma unroll
   for (int o = 0; o < kFirTJ; ++o)
@@ -235,7 +262,8 @@ hipError_t launch_fir(int prec, const void* d, const void* g, void* x, int N, in
   const int64_t nfb = (b + 4 * kFirTJ - 1) / (4 * kFirTJ);
   const int64_t grid = nfb * ((N + 63) / 64);
   if (grid > 0x7fffffffLL) return hipErrorNotSupported;
-  const size_t lds = (size_t)L * 64 * (prec == F32 ? sizeof(float) : sizeof(double));
+  const int Lp = (L + kFirCH - 1) / kFirCH * kFirCH;
+  const size_t lds = (size_t)Lp * 64 * (prec == F32 ? sizeof(float) : sizeof(double));
   if (prec == F32)
     k_fir<float><<<dim3((unsigned)grid), 256, lds, st>>>((const float*)d, (const float*)g, (float*)x, N, b, L, c0);
   else
