@@ -17,22 +17,40 @@ namespace ipfb {
 // forward y_i = ((W^T d)_i - sum_k L[i][k] y_k) / L[i][i]; backward
 // x_i = (y_i - sum_{t=1}^{P-1} L[i+t][i] x_{i+t}) / L[i][i].
 // One thread per column (the columns are the only independent work: each
-// sweep is sequential in i), FP64 throughout. The last P-1 rows of L, the
-// last P data values and the last P-1 results stay in registers; the rows of
-// L and y go to the workspace for the backward sweep (row i: P entries
-// L[i][i-t], t = 0..P-1, then y_i; laid out [i][P+1][N] for coalesced
-// access). d: the first nspec rows of x (the row stage's output), then x is
-// overwritten with the result.
+// sweep is sequential in i), FP64 throughout. Every thread works on the same
+// row at a time, so the rows whose Gram entries are the interior ones
+// (j >= P-1 and j < nspec: all P - t products present) take them from a table
+// made once, with no branch divergence. The diagonal is kept as its
+// reciprocal, so the sweeps multiply instead of divide. The last P-1 rows of
+// L, the last P data values and the last P-1 results stay in registers; the
+// rows of L and y go to the workspace for the backward sweep (row i: the
+// reciprocal diagonal, then L[i][i-t] for t = 1..P-1, then y_i; laid out
+// [i][P+1][N] for coalesced access). Both sweeps fetch their inputs a few
+// rows ahead (fewer for wide bands, whose P x P ring fills the registers), so
+// a row's step does not wait on memory. d: the first nspec rows of x (the row
+// stage's output), then x is overwritten with the result.
+template <int P>
+struct TikFetch {
+  static constexpr int CH = P <= 5 ? 8 : (P <= 8 ? 4 : 1);  // rows of d ahead (forward sweep)
+  static constexpr int CB = P <= 5 ? 4 : 1;                  // workspace rows ahead (backward sweep)
+};
 template <typename T, int P>
 __global__ __launch_bounds__(64) void k_tik(T* __restrict__ x, int N, int64_t b, const double* __restrict__ win,
                                             double phi2, double cnorm, double* __restrict__ ws) {
   const int n = blockIdx.x * 64 + threadIdx.x;
   if (n >= N) return;
   const int64_t nspec = b - P + 1;
-  double h[P];
+  double h[P], hint[P];
 #pragma unroll
   for (int r = 0; r < P; ++r) h[r] = win[(int64_t)r * N + n];
-  double lr[P][P];  // ring: lr[q] = row i - q (q = 1 .. P-1) as L[i-q][i-q-t], t = 0..P-1
+#pragma unroll
+  for (int t = 0; t < P; ++t) {  // interior Gram entries H[i][i-t]
+    double s = t == 0 ? phi2 : 0.0;
+#pragma unroll
+    for (int r = 0; r + t < P; ++r) s += h[r + t] * h[r];
+    hint[t] = s;
+  }
+  double lr[P][P];  // ring: lr[q] = row i - q (q = 1 .. P-1): [0] = 1/L[i-q][i-q], [t] = L[i-q][i-q-t]
   double yv[P], dv[P];
 #pragma unroll
   for (int q = 0; q < P; ++q) {
@@ -41,60 +59,81 @@ __global__ __launch_bounds__(64) void k_tik(T* __restrict__ x, int N, int64_t b,
     for (int t = 0; t < P; ++t) lr[q][t] = 0.0;
   }
   const int64_t rs = (int64_t)(P + 1) * N;  // workspace stride of one row
-  for (int64_t i = 0; i < b; ++i) {
-    // shift the rings: slot q holds row / value i - q
+  constexpr int kTikCh = TikFetch<P>::CH;
+  double dch[kTikCh], dnx[kTikCh];
+  auto load_d = [&](int64_t i0, double* v) {
 #pragma unroll
-    for (int q = P - 1; q > 0; --q) {
-      yv[q] = yv[q - 1];
-      dv[q] = dv[q - 1];
+    for (int u = 0; u < kTikCh; ++u) v[u] = (i0 + u < nspec) ? (double)x[(i0 + u) * N + n] : 0.0;
+  };
+  load_d(0, dch);
+  for (int64_t i0 = 0; i0 < b; i0 += kTikCh) {
+    if (i0 + kTikCh < b) load_d(i0 + kTikCh, dnx);
 #pragma unroll
-      for (int t = 0; t < P; ++t) lr[q][t] = lr[q - 1][t];
-    }
-    dv[0] = i < nspec ? (double)x[i * N + n] : 0.0;
-    // (W^T d)_i = sum_r h_r d_{i-r}, 0 <= i - r < nspec
-    double rhs = 0.0;
+    for (int u = 0; u < kTikCh; ++u) {
+      const int64_t i = i0 + u;
+      if (i >= b) break;
+      // shift the rings: slot q holds row / value i - q
 #pragma unroll
-    for (int r = 0; r < P; ++r)
-      if (i - r >= 0 && i - r < nspec) rhs += h[r] * dv[r];
-    // row i of L: entries for j = i - t, t = P-1 .. 1, then the diagonal
-    double row[P];
+      for (int q = P - 1; q > 0; --q) {
+        yv[q] = yv[q - 1];
+        dv[q] = dv[q - 1];
 #pragma unroll
-    for (int t = 0; t < P; ++t) row[t] = 0.0;
-#pragma unroll
-    for (int t = P - 1; t >= 0; --t) {
-      const int64_t j = i - t;
-      if (j < 0) continue;
-      // H[i][j] = sum over rows k = j - r, 0 <= r, r + t < P, 0 <= k < nspec of h_{r+t} h_r
-      double hij = t == 0 ? phi2 : 0.0;
-#pragma unroll
-      for (int r = 0; r + t < P; ++r) {
-        const int64_t k = j - r;
-        if (k >= 0 && k < nspec) hij += h[r + t] * h[r];
+        for (int t = 0; t < P; ++t) lr[q][t] = lr[q - 1][t];
       }
-      // minus sum over k in [max(0, i-P+1), j-1] of L[i][k] L[j][k]:
-      // L[i][k] = row[i-k], L[j][k] = lr[t][j-k] (row j is ring slot t)
+      dv[0] = dch[u];
+      // (W^T d)_i = sum_r h_r d_{i-r}, 0 <= i - r < nspec
+      double rhs = 0.0;
 #pragma unroll
-      for (int u = t + 1; u < P; ++u) {  // k = i - u
-        if (i - u < 0) continue;
-        hij -= row[u] * (t == 0 ? row[u] : lr[t][u - t]);
+      for (int r = 0; r < P; ++r)
+        if (i - r >= 0 && i - r < nspec) rhs += h[r] * dv[r];
+      // row i of L: entries for j = i - t, t = P-1 .. 1, then the diagonal
+      double row[P];
+#pragma unroll
+      for (int t = 0; t < P; ++t) row[t] = 0.0;
+#pragma unroll
+      for (int t = P - 1; t >= 0; --t) {
+        const int64_t j = i - t;
+        if (j < 0) continue;
+        double hij;
+        if (j >= P - 1 && j < nspec) {
+          hij = hint[t];
+        } else {  // H[i][j] = sum over rows k = j - r, 0 <= r, r + t < P, 0 <= k < nspec of h_{r+t} h_r
+          hij = t == 0 ? phi2 : 0.0;
+#pragma unroll
+          for (int r = 0; r + t < P; ++r) {
+            const int64_t k = j - r;
+            if (k >= 0 && k < nspec) hij += h[r + t] * h[r];
+          }
+        }
+        // minus sum over k in [max(0, i-P+1), j-1] of L[i][k] L[j][k]:
+        // L[i][k] = row[i-k], L[j][k] = lr[t][j-k] (row j is ring slot t)
+#pragma unroll
+        for (int v = t + 1; v < P; ++v) {  // k = i - v
+          if (i - v < 0) continue;
+          hij -= row[v] * (t == 0 ? row[v] : lr[t][v - t]);
+        }
+        if (t == 0) row[0] = 1.0 / sqrt(hij);  // the reciprocal diagonal
+        else row[t] = hij * lr[t][0];
       }
-      if (t == 0) row[0] = sqrt(hij);
-      else row[t] = hij / lr[t][0];
-    }
-    double yi = rhs;
+      double yi = rhs;
 #pragma unroll
-    for (int u = 1; u < P; ++u)
-      if (i - u >= 0) yi -= row[u] * yv[u];
-    yi /= row[0];
-    yv[0] = yi;
+      for (int v = 1; v < P; ++v)
+        if (i - v >= 0) yi -= row[v] * yv[v];
+      yi *= row[0];
+      yv[0] = yi;
 #pragma unroll
-    for (int t = 0; t < P; ++t) {
-      lr[0][t] = row[t];
-      ws[i * rs + (int64_t)t * N + n] = row[t];
+      for (int t = 0; t < P; ++t) {
+        lr[0][t] = row[t];
+        ws[i * rs + (int64_t)t * N + n] = row[t];
+      }
+      ws[i * rs + (int64_t)P * N + n] = yi;
     }
-    ws[i * rs + (int64_t)P * N + n] = yi;
+#pragma unroll
+    for (int u = 0; u < kTikCh; ++u) dch[u] = dnx[u];
   }
-  // backward: xs[q] = x_{i+q}; rows i+q of L in the ring again
+  // backward: xs[q] = x_{i+q}; rows i+q of L in the ring again, kTikCh rows
+  // of the workspace fetched ahead (fewer for wide bands: the register budget)
+  constexpr int CB = TikFetch<P>::CB;
   double xs[P];
 #pragma unroll
   for (int q = 0; q < P; ++q) {
@@ -102,22 +141,40 @@ __global__ __launch_bounds__(64) void k_tik(T* __restrict__ x, int N, int64_t b,
 #pragma unroll
     for (int t = 0; t < P; ++t) lr[q][t] = 0.0;
   }
-  for (int64_t i = b - 1; i >= 0; --i) {
+  double wch[CB][P + 1], wnx[CB][P + 1];
+  auto load_w = [&](int64_t itop, double (*v)[P + 1]) {  // rows itop, itop - 1, ..., itop - CB + 1
 #pragma unroll
-    for (int q = P - 1; q > 0; --q) {
-      xs[q] = xs[q - 1];
+    for (int u = 0; u < CB; ++u)
 #pragma unroll
-      for (int t = 0; t < P; ++t) lr[q][t] = lr[q - 1][t];
+      for (int t = 0; t <= P; ++t) v[u][t] = (itop - u >= 0) ? ws[(itop - u) * rs + (int64_t)t * N + n] : 0.0;
+  };
+  load_w(b - 1, wch);
+  for (int64_t itop = b - 1; itop >= 0; itop -= CB) {
+    if (itop - CB >= 0) load_w(itop - CB, wnx);
+#pragma unroll
+    for (int u = 0; u < CB; ++u) {
+      const int64_t i = itop - u;
+      if (i < 0) break;
+#pragma unroll
+      for (int q = P - 1; q > 0; --q) {
+        xs[q] = xs[q - 1];
+#pragma unroll
+        for (int t = 0; t < P; ++t) lr[q][t] = lr[q - 1][t];
+      }
+#pragma unroll
+      for (int t = 0; t < P; ++t) lr[0][t] = wch[u][t];
+      double xi = wch[u][P];
+#pragma unroll
+      for (int q = 1; q < P; ++q)
+        if (i + q < b) xi -= lr[q][q] * xs[q];  // L[i+q][i] = row i+q at offset q
+      xi *= lr[0][0];
+      xs[0] = xi;
+      x[i * N + n] = T(cnorm * xi);
     }
 #pragma unroll
-    for (int t = 0; t < P; ++t) lr[0][t] = ws[i * rs + (int64_t)t * N + n];
-    double xi = ws[i * rs + (int64_t)P * N + n];
+    for (int u = 0; u < CB; ++u)
 #pragma unroll
-    for (int q = 1; q < P; ++q)
-      if (i + q < b) xi -= lr[q][q] * xs[q];  // L[i+q][i] = row i+q at offset q
-    xi /= lr[0][0];
-    xs[0] = xi;
-    x[i * N + n] = T(cnorm * xi);
+      for (int t = 0; t <= P; ++t) wch[u][t] = wnx[u][t];
   }
 }
 
