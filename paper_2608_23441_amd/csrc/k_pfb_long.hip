@@ -7,7 +7,8 @@
 // output spectrum costs one M-point complex FFT:
 //   E[k] = (Z[k] + conj Z[M-k]) / 2,  O[k] = (Z[k] - conj Z[M-k]) / (2i),
 //   Y[k] = E[k] + t,  Y[M-k] = conj(E[k] - t),  t = e^{-2 pi i k/L} O[k].
-// The M-point FFT is four-step, M = P1 * P2, m = P2 a + c, k = k1 + P1 k2:
+// The M-point FFT is four-step, M = P1 * P2 (P1 = P2 / 2 for odd log2 M),
+// m = P2 a + c, k = k1 + P1 k2:
 //   pass 1, per block of MB consecutive c and one frame: the windowed sums
 //     for all a (each load a 128-byte run of one frame), the P1-point FFT
 //     over a, the twiddle e^{-2 pi i c k1 / M}; T[j][k1][c] written as
@@ -116,19 +117,20 @@ __global__ __launch_bounds__((Lf1Cfg<T, LOG2P1>::NT), 2) void k_lf1(
 }
 
 // Pass 1, sliding form (4 taps, P1 <= 512): one workgroup per column block
-// (64 bytes of columns: 8 in FP32, 4 in FP64) and a range of frames. The
+// (128 or 64 bytes of columns, see below) and a range of frames. The
 // window slice and the four frames of the sliding sum stay in registers (each
 // input sample is loaded once per workgroup, the window once), and the next
 // frame is fetched while the FFT of the current one runs.
 template <typename T, int LOG2P1>
 struct Lf1rCfg {
   static constexpr int P1 = 1 << LOG2P1;
-  static constexpr int MB = 64 / (int)sizeof(cx<T>);  // 64-byte runs: what the register budget allows
-  // FP32, P1 = 512: 512 threads of 8 elements, a 512-point FFT in three
-  // radix-8 passes and room (two waves per SIMD) for the ring and window slice
-  // in registers; shorter FP32 rows keep 1024 threads. FP64: 512 threads,
-  // the same register budget at half the elements
-  static constexpr int NT = (sizeof(T) == 8 || LOG2P1 == 9) ? 512 : 1024;
+  // 512 threads (two waves per SIMD, room for the ring and the window slice in
+  // registers). Columns per block: 128-byte runs for P1 <= 256 (FP32: 8
+  // elements per thread at P1 = 256), 64-byte runs at P1 = 512, where the
+  // four frames and four window taps of 16 columns would not fit the
+  // registers (FP32 then also holds 8 elements per thread)
+  static constexpr int MB = (LOG2P1 <= 8 ? 128 : 64) / (int)sizeof(cx<T>);
+  static constexpr int NT = 512;
   static constexpr int EPT = (P1 * MB) / NT;
   static constexpr int LS = lds_len(P1);
 };
@@ -147,8 +149,8 @@ __global__ __launch_bounds__((Lf1rCfg<T, LOG2P1>::NT)) void k_lf1r(const cx<T>* 
   __shared__ cx<T> sbuf[2 * MB * LS];
   // the twiddle tables live in LDS for the life of the workgroup: every FFT
   // pass and store then waits on LDS, not on global-memory latency
-  // M = P1 * P2 <= P1^2, so e^{-2 pi i 512 m / M} needs at most P1^2 / 512 entries
-  constexpr int NHI = (P1 * P1) / 512 > 0 ? (P1 * P1) / 512 : 1;
+  // M = P1 * P2 <= 2 P1^2, so e^{-2 pi i 512 m / M} needs at most 2 P1^2 / 512 entries
+  constexpr int NHI = (2 * P1 * P1) / 512 > 0 ? (2 * P1 * P1) / 512 : 1;
   __shared__ cx<T> tP1s[P1], tMlos[512], tMhis[NHI];
   const int tid = threadIdx.x;
   const int lg = xcd_remap(blockIdx.x, (int)gridDim.x);
@@ -386,7 +388,7 @@ template <typename T, int L1>
 static hipError_t launch_lf1_t(const void* x, void* tmp, int64_t nblock, int ntap, const void* winT,
                                const LfTw<T>& tw, int M, int P2, hipStream_t st) {
   if constexpr (L1 <= 9) {
-    if (ntap == 4 && nblock >= 4 && (M >> 9) <= ((1 << L1) * (1 << L1)) / 512) {
+    if (ntap == 4 && nblock >= 4 && (M >> 9) <= (2 * (1 << L1) * (1 << L1)) / 512) {
       using Cr = Lf1rCfg<T, L1>;
       const int ncb = P2 / Cr::MB;
       // about one workgroup per CU, each sliding over a range of frames
@@ -429,7 +431,7 @@ static hipError_t launch_long_t(int pass, int log2n, const void* x, void* y, int
                                 hipStream_t st) {
   if (nblock == 0) return hipSuccess;
   const int log2m = log2n - 1;
-  const int l1 = (log2m + 1) / 2, l2 = log2m / 2;
+  const int l2 = lf_log2p2(log2m), l1 = log2m - l2;
   const int M = 1 << log2m, P1 = 1 << l1, P2 = 1 << l2;
   const LfTw<T> tw = lf_tables<T>(twS, P1, P2, M);
   hipError_t e = hipSuccess;
@@ -462,7 +464,7 @@ static int lf_chunk_t(int P1, int64_t nblock) {
 int lf_frame_chunk(int prec, int log2n, int64_t nblock) {
   if (log2n < 15 || log2n > 20 || nblock < 1) return 1;
   const int log2m = log2n - 1;
-  const int l1 = (log2m + 1) / 2, l2 = log2m / 2;
+  const int l2 = lf_log2p2(log2m), l1 = log2m - l2;
   const int P1 = 1 << l1;
   if (prec == F32) {
     switch (l2) {
