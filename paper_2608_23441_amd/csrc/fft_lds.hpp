@@ -47,6 +47,33 @@ __device__ __forceinline__ cx<T> ld_once(const cx<T>* p) {
   const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
   return mk<T>(v.x, v.y);
 }
+// Buffer-resource access to a region of at most 2^31 bytes: a per-lane byte
+// offset in one VGPR plus a uniform byte offset in an SGPR, so a strided walk
+// over many rows keeps a single address register (flags word: gfx9 raw
+// buffer, 32-bit data format; accesses past `bytes` read 0 and are dropped).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  if constexpr (sizeof(T) == 4) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  } else {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return __hiloint2double((int)v.y, (int)v.x);
+  }
+}
+template <typename T>
+__device__ __forceinline__ void buf_st(T val, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  if constexpr (sizeof(T) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(val), r, voff, soff, 0);
+  } else {
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 v = {(unsigned)__double2loint(val), (unsigned)__double2hiint(val)};
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+  }
+}
 // multiply by DIR*i  (DIR = -1: forward transform kernel e^{-i...}; +1 inverse)
 template <int DIR, typename T>
 __device__ __forceinline__ cx<T> mul_i(cx<T> a) {

@@ -396,32 +396,55 @@ __global__ __launch_bounds__(256) void k_iir_zs(int N, int ntiles, int64_t nsegt
   const T* pd = (const T*)sd.x + j0 * (int64_t)N + n;
   double st[M], za[M], gr[M];
   for (int i = 0; i < M; ++i) st[i] = za[i] = gr[i] = 0.0;
-  T cur[kIirChunk], nxt[kIirChunk];
-  load_chunk(pd, N, 0, Ls, cur);
-  const int nch = (Ls + kIirChunk - 1) / kIirChunk;
-#pragma unroll 1
-  for (int c = 0; c < nch; ++c) {
-    if (c + 1 < nch) load_chunk(pd, N, (c + 1) * kIirChunk, Ls, nxt);
+  // one frame k of the segment: both recursions
+  auto frame = [&](T xv, int k) {
+    const double x = (double)xv;
+    const double y = fma(h[0], x, st[0]);
 #pragma unroll
-    for (int kk = 0; kk < kIirChunk; ++kk) {
-      const int k = c * kIirChunk + kk;
-      if (k < Ls) {
-        const double x = (double)cur[kk];
-        const double y = h[0] * x + st[0];
+    for (int i = 0; i + 1 < M; ++i) st[i] = fma(a[i], y, fma(h[i + 1], x, st[i + 1]));
+    st[M - 1] = fma(a[M - 1], y, h[M] * x);
+    double gk = a[0] * gr[0];
+    if (k == 0) gk = 1.0;  // gr = 0 at the first frame
 #pragma unroll
-        for (int i = 0; i < M; ++i) st[i] = h[i + 1] * x + a[i] * y + (i + 1 < M ? st[i + 1] : 0.0);
-        double gk = (k == 0) ? 1.0 : 0.0;
+    for (int i = 1; i < M; ++i) gk = fma(a[i], gr[i], gk);
 #pragma unroll
-        for (int i = 0; i < M; ++i) gk += a[i] * gr[i];
+    for (int i = M - 1; i > 0; --i) gr[i] = gr[i - 1];
+    gr[0] = gk;  // gr[t] = g_{k-t}
 #pragma unroll
-        for (int i = M - 1; i > 0; --i) gr[i] = gr[i - 1];
-        gr[0] = gk;  // gr[t] = g_{k-t}
+    for (int t = 0; t < M; ++t) za[t] += gr[t] * y;
+  };
+  if (Ls == L) {
+    // a full segment: straight-line code with no per-frame checks, its
+    // global loads issued a chunk ahead (FP32: the whole segment at once)
+    constexpr int CH = sizeof(T) == 4 ? L : 16;
+    typedef const __attribute__((address_space(1))) T GT;
+    GT* gp = (GT*)pd;
+    T v[2][CH];
 #pragma unroll
-        for (int t = 0; t < M; ++t) za[t] += gr[t] * y;
-      }
+    for (int kk = 0; kk < CH; ++kk) v[0][kk] = gp[(int64_t)kk * N];
+#pragma unroll
+    for (int c = 0; c < L / CH; ++c) {
+      if (c + 1 < L / CH)
+#pragma unroll
+        for (int kk = 0; kk < CH; ++kk) v[(c + 1) & 1][kk] = gp[(int64_t)((c + 1) * CH + kk) * N];
+#pragma unroll
+      for (int kk = 0; kk < CH; ++kk) frame(v[c & 1][kk], c * CH + kk);
     }
+  } else {
+    T cur[kIirChunk], nxt[kIirChunk];
+    load_chunk(pd, N, 0, Ls, cur);
+    const int nch = (Ls + kIirChunk - 1) / kIirChunk;
+#pragma unroll 1
+    for (int c = 0; c < nch; ++c) {
+      if (c + 1 < nch) load_chunk(pd, N, (c + 1) * kIirChunk, Ls, nxt);
 #pragma unroll
-    for (int kk = 0; kk < kIirChunk; ++kk) cur[kk] = nxt[kk];
+      for (int kk = 0; kk < kIirChunk; ++kk) {
+        const int k = c * kIirChunk + kk;
+        if (k < Ls) frame(cur[kk], k);
+      }
+#pragma unroll
+      for (int kk = 0; kk < kIirChunk; ++kk) cur[kk] = nxt[kk];
+    }
   }
   T* o = zs + (g * N + n) * (2 * M);
 #pragma unroll
@@ -874,7 +897,8 @@ __global__ __launch_bounds__(64) void k_iir_apply(int N, int ntiles, IirStream o
                                                    int nstreams, const double* __restrict__ coef,
                                                    const T* __restrict__ zs, double gnorm) {
   using Ly = IirLayout<M>;
-  __shared__ T ys[L * 64];
+  extern __shared__ __align__(16) unsigned char iir_lds[];  // L * 64 T, for partial segments only
+  T* ys = reinterpret_cast<T*>(iir_lds);
   const int tid = threadIdx.x;
   const int64_t g = __builtin_amdgcn_readfirstlane(blockIdx.x / ntiles);
   const int n = (int)__builtin_amdgcn_readfirstlane(blockIdx.x % ntiles) * 64 + tid;
@@ -893,6 +917,39 @@ __global__ __launch_bounds__(64) void k_iir_apply(int N, int ntiles, IirStream o
     v[i] = (double)zz[M + i];
   }
   T* px = (T*)sd.x + j0 * (int64_t)N + n;
+  // the causal ARMA: y_k from x_k, the state carried in st
+  auto causal = [&](double xin) -> double {
+    const double y = fma(h[0], xin, st[0]);
+#pragma unroll
+    for (int i = 0; i + 1 < M; ++i) st[i] = fma(a[i], y, fma(h[i + 1], xin, st[i + 1]));
+    st[M - 1] = fma(a[M - 1], y, h[M] * xin);
+    return y;
+  };
+  // the anti-causal all-pole step: w_k = y_k + sum_i a_i w_{k+1+i}
+  auto anti = [&](double y) -> double {
+    double w = y;
+#pragma unroll
+    for (int i = 0; i < M; ++i) w = fma(a[i], v[i], w);
+#pragma unroll
+    for (int i = M - 1; i > 0; --i) v[i] = v[i - 1];
+    v[0] = w;
+    return gn * w;
+  };
+  if (Ls == L && (int64_t)L * N * (int64_t)sizeof(T) < (int64_t(1) << 31)) {
+    // a full segment: its frames in registers (the launch then gives no LDS,
+    // so occupancy is set by registers alone), every load issued at once,
+    // straight-line code; one address register for the whole column walk
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(px - n, (uint32_t)((int64_t)L * N * sizeof(T)));
+    const int vo = n * (int)sizeof(T), rowb = N * (int)sizeof(T);
+    T yv[L];
+#pragma unroll
+    for (int k = 0; k < L; ++k) yv[k] = buf_ld<T>(rs, vo, k * rowb);
+#pragma unroll
+    for (int k = 0; k < L; ++k) yv[k] = T(causal((double)yv[k]));
+#pragma unroll
+    for (int k = L - 1; k >= 0; --k) buf_st<T>(T(anti((double)yv[k])), rs, vo, k * rowb);
+    return;
+  }
   T cur[kIirChunk], nxt[kIirChunk];
   load_chunk(px, N, 0, Ls, cur);
   const int nch = (Ls + kIirChunk - 1) / kIirChunk;
@@ -902,27 +959,13 @@ __global__ __launch_bounds__(64) void k_iir_apply(int N, int ntiles, IirStream o
 #pragma unroll
     for (int kk = 0; kk < kIirChunk; ++kk) {
       const int k = c * kIirChunk + kk;
-      if (k < Ls) {
-        const double xin = (double)cur[kk];
-        const double y = h[0] * xin + st[0];
-#pragma unroll
-        for (int i = 0; i < M; ++i) st[i] = h[i + 1] * xin + a[i] * y + (i + 1 < M ? st[i + 1] : 0.0);
-        ys[k * 64 + tid] = T(y);
-      }
+      if (k < Ls) ys[k * 64 + tid] = T(causal((double)cur[kk]));
     }
 #pragma unroll
     for (int kk = 0; kk < kIirChunk; ++kk) cur[kk] = nxt[kk];
   }
 #pragma unroll 4
-  for (int k = Ls - 1; k >= 0; --k) {
-    double w = (double)ys[k * 64 + tid];
-#pragma unroll
-    for (int i = 0; i < M; ++i) w += a[i] * v[i];
-#pragma unroll
-    for (int i = M - 1; i > 0; --i) v[i] = v[i - 1];
-    v[0] = w;
-    px[(int64_t)k * N] = T(gn * w);
-  }
+  for (int k = Ls - 1; k >= 0; --k) px[(int64_t)k * N] = T(anti((double)ys[k * 64 + tid]));
 }
 
 template <int M>
@@ -968,14 +1011,20 @@ static hipError_t launch_iir_m(int stage, int prec, const IirStream& one, const 
 #undef CARRY
       break;
     }
-    default:
+    default: {
+      // LDS for the partial segments' outputs, unless every segment is full
+      // (one stream of a multiple of L frames) and takes the register path
+      const size_t es = prec == F32 ? sizeof(float) : sizeof(double);
+      const bool all_full = nstreams <= 1 && one.b % L == 0 && (int64_t)L * N * (int64_t)es < (int64_t(1) << 31);
+      const size_t lds = all_full ? 0 : (size_t)L * 64 * es;
       if (prec == F32)
-        k_iir_apply<float, M, kIirSegF32><<<dim3((unsigned)(nsegt * t64)), 64, 0, st>>>(N, t64, one, tab, nstreams,
-                                                                                        coef, (const float*)zs, gnorm);
+        k_iir_apply<float, M, kIirSegF32><<<dim3((unsigned)(nsegt * t64)), 64, lds, st>>>(N, t64, one, tab, nstreams,
+                                                                                          coef, (const float*)zs, gnorm);
       else
-        k_iir_apply<double, M, kIirSegF64><<<dim3((unsigned)(nsegt * t64)), 64, 0, st>>>(N, t64, one, tab, nstreams,
-                                                                                         coef, (const double*)zs, gnorm);
+        k_iir_apply<double, M, kIirSegF64><<<dim3((unsigned)(nsegt * t64)), 64, lds, st>>>(N, t64, one, tab, nstreams,
+                                                                                           coef, (const double*)zs, gnorm);
       break;
+    }
   }
   return hipGetLastError();
 }
