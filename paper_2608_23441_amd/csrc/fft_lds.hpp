@@ -47,6 +47,22 @@ __device__ __forceinline__ cx<T> ld_once(const cx<T>* p) {
   const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(p));
   return mk<T>(v.x, v.y);
 }
+// Global-memory access through a pointer the compiler cannot place (one read
+// from a table in memory): without the cast it emits flat instructions, which
+// also count against the LDS wait counter, so every LDS wait would also wait
+// for them.
+template <typename T>
+__device__ __forceinline__ void st_global(cx<T>* p, cx<T> v) {
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  *(__attribute__((address_space(1))) v2*)p = v2{v.x, v.y};
+}
+__device__ __forceinline__ unsigned int ld_global_once(const unsigned char* p) {
+  return __builtin_nontemporal_load((const __attribute__((address_space(1))) unsigned int*)p);
+}
+__device__ __forceinline__ unsigned int ld_global_byte(const unsigned char* p) {
+  return *(const __attribute__((address_space(1))) unsigned char*)p;
+}
+
 // Buffer-resource access to a region of at most 2^31 bytes: a per-lane byte
 // offset in one VGPR plus a uniform byte offset in an SGPR, so a strided walk
 // over many rows keeps a single address register (flags word: gfx9 raw

@@ -365,10 +365,13 @@ __global__ __launch_bounds__(64) void k_iir_setup_len(int N, int L, IirStream on
 // fetched while the current one is used.
 constexpr int kIirChunk = 16;
 
+// (the frames come from a stream table, so the pointer is cast to global
+// memory: flat loads would also hold up every LDS wait)
 template <typename T>
 __device__ __forceinline__ void load_chunk(const T* __restrict__ p, int64_t N, int k0, int Ls, T* v) {
+  const __attribute__((address_space(1))) T* gp = (const __attribute__((address_space(1))) T*)p;
 #pragma unroll
-  for (int k = 0; k < kIirChunk; ++k) v[k] = (k0 + k < Ls) ? p[(int64_t)(k0 + k) * N] : T(0);
+  for (int k = 0; k < kIirChunk; ++k) v[k] = (k0 + k < Ls) ? gp[(int64_t)(k0 + k) * N] : T(0);
 }
 
 // Pass 1: per (column, segment), both recursions from zero state: the causal
@@ -965,7 +968,8 @@ __global__ __launch_bounds__(64) void k_iir_apply(int N, int ntiles, IirStream o
     for (int kk = 0; kk < kIirChunk; ++kk) cur[kk] = nxt[kk];
   }
 #pragma unroll 4
-  for (int k = Ls - 1; k >= 0; --k) px[(int64_t)k * N] = T(anti((double)ys[k * 64 + tid]));
+  for (int k = Ls - 1; k >= 0; --k)
+    ((__attribute__((address_space(1))) T*)px)[(int64_t)k * N] = T(anti((double)ys[k * 64 + tid]));
 }
 
 template <int M>

@@ -139,7 +139,8 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
   const int tid = threadIdx.x;
   // dequantisation factor 1/(s_k N), formed in FP64 from the stored FP32 scale
   auto set_facs = [&](const float* sc) {
-    for (int k = tid; k <= H; k += NT) facs[k] = T(1.0 / ((double)sc[k] * (double)N));
+    const __attribute__((address_space(1))) float* gsc = (const __attribute__((address_space(1))) float*)sc;
+    for (int k = tid; k <= H; k += NT) facs[k] = T(1.0 / ((double)gsc[k] * (double)N));
   };
   if (!MULTI) set_facs(scale1);
   unsigned int pf[DPT];
@@ -167,10 +168,10 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
           // read once: a non-temporal load, so that the input stream does not
           // push the frames this kernel writes out of the last-level cache
           // (the column pass that follows reads them back from there)
-          pf[d] = __builtin_nontemporal_load(reinterpret_cast<const unsigned int*>(in + byte));
+          pf[d] = ld_global_once(in + byte);
         } else {  // the array's last word may be partial: read its bytes one by one
           unsigned int w = 0u;
-          for (int q = 0; q < 4 && byte + q < total; ++q) w |= (unsigned int)in[byte + q] << (8 * q);
+          for (int q = 0; q < 4 && byte + q < total; ++q) w |= ld_global_byte(in + byte + q) << (8 * q);
           pf[d] = w;
         }
       }
@@ -226,7 +227,7 @@ __global__ __launch_bounds__((RowPCfg<T, LOG2N>::NT)) void k_row_c4p(
     fft_first_from_regs<T, R0, +1>(s, tid, v);
     __syncthreads();
     fft_middle<T, H, NT, 1, +1, true>(s, LS, twN, 2);
-    fft_last_to<T, H, NT, 1, +1, true>(s, LS, twN, 2, [&](int, int m, cx<T> val) { orow[m] = val; });
+    fft_last_to<T, H, NT, 1, +1, true>(s, LS, twN, 2, [&](int, int m, cx<T> val) { st_global(orow + m, val); });
     __syncthreads();  // s and raw are rewritten for the next frame
   }
 }
