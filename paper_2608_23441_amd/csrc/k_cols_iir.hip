@@ -653,8 +653,14 @@ __global__ __launch_bounds__(256) void k_iir_carry(int N, int L, IirStream one, 
 // memory touches a separate cache line for every 24 bytes, and that gather,
 // not the arithmetic, is what bounds the kernel at 4096 columns (with the
 // arithmetic removed it still takes 39.5 of its 46 us).
+// Columns per workgroup (one wavefront each): 16 when the states are staged,
+// so that the workgroup's states of one segment are a 128-byte-aligned run of
+// three lines (16 columns x 2M values x 4 bytes), else 4.
+template <typename T, int QR>
+constexpr int carry_u_cols() { return (sizeof(T) == 4 && QR == 4) ? 16 : 4; }
+
 template <typename T, int M, int QR>
-__global__ __launch_bounds__(256) void k_iir_carry_u(int N, int L, IirStream one, const IirStream* __restrict__ tab,
+__global__ __launch_bounds__((64 * carry_u_cols<T, QR>())) void k_iir_carry_u(int N, int L, IirStream one, const IirStream* __restrict__ tab,
                                                      int nstreams, const double* __restrict__ coef,
                                                      const double* __restrict__ scoef, T* __restrict__ zs) {
   using Ly = IirLayout<M>;
@@ -663,16 +669,17 @@ __global__ __launch_bounds__(256) void k_iir_carry_u(int N, int L, IirStream one
   constexpr int oAL = 0, oALL = MM, oBL = 2 * MM, oBLL = 3 * MM, oNL = 4 * MM, oNLL = 5 * MM, oIA = 6 * MM,
                 oIB = 7 * MM, oPA = 8 * MM, oPB = 14 * MM;
   const int lane = threadIdx.x & 63;
+  constexpr int COLS = carry_u_cols<T, QR>();
   const int wv = threadIdx.x >> 6;
-  const int groups = (N + 3) / 4;
+  const int groups = (N + COLS - 1) / COLS;
   const int si = __builtin_amdgcn_readfirstlane(blockIdx.x / groups);  // the stream
-  const int n = __builtin_amdgcn_readfirstlane((blockIdx.x % groups) * 4 + wv);
+  const int n = __builtin_amdgcn_readfirstlane((blockIdx.x % groups) * COLS + wv);
   IirStream sd = nstreams <= 1 ? one : tab[si];
   sd.b = uniform64(sd.b);
   sd.seg0 = uniform64(sd.seg0);
   const int64_t nseg = (sd.b + L - 1) / L;
   const int q = (int)((nseg + 63) / 64);  // 1 .. QR (the launch checked max_nseg)
-  __shared__ double smat[4][NMAT * MM];
+  __shared__ double smat[COLS][NMAT * MM];
   // staged states: [column][segment][2M], the column blocks padded by one
   constexpr int SEGMAX = 64 * QR;
   constexpr int CS = SEGMAX * 2 * M + 1;
@@ -680,15 +687,16 @@ __global__ __launch_bounds__(256) void k_iir_carry_u(int N, int L, IirStream one
   // eight segments per lane, or in FP64, its LDS costs more occupancy than
   // the gather it saves
   constexpr bool STAGE = sizeof(T) == 4 && QR == 4;
-  __shared__ T zst[STAGE ? 4 * CS : 1];
-  const int nb = (int)(blockIdx.x % groups) * 4;  // the workgroup's first column
-  const int ncol = N - nb < 4 ? N - nb : 4;
+  __shared__ T zst[STAGE ? COLS * CS : 1];
+  const int nb = (int)(blockIdx.x % groups) * COLS;  // the workgroup's first column
+  const int ncol = N - nb < COLS ? N - nb : COLS;
   const int64_t stride_g = (int64_t)N * 2 * M;
   const int sgs = N * 2 * M;  // 32-bit: nseg * N * 2M < 2^31 (checked at launch)
   T* zb = zs + (sd.seg0 * N + nb) * 2 * M;
-  // staging: thread t moves column t % 4's 2M values of segment
-  // pass * 64 + t / 4 (a wavefront: 16 segments, each a run of 4 columns)
-  const int sc = (int)(threadIdx.x & 3), ss = (int)(threadIdx.x >> 2);
+  // staging: thread t moves column t % COLS's 2M values of segment
+  // pass * 64 + t / COLS (a wavefront: 64 / COLS segments, each a run of
+  // COLS columns)
+  const int sc = (int)(threadIdx.x % COLS), ss = (int)(threadIdx.x / COLS);
   if constexpr (STAGE) {
     T buf[QR][2 * M];
 #pragma unroll
@@ -703,28 +711,37 @@ __global__ __launch_bounds__(256) void k_iir_carry_u(int N, int L, IirStream one
 #pragma unroll
       for (int i = 0; i < 2 * M; ++i) zst[sc * CS + (ps * 64 + ss) * 2 * M + i] = buf[ps][i];
   }
-  for (int i = lane; i < NMAT * MM; i += 64) {
-    double v = 0.0;
-    if (n < N) {
+  // the matrices: each lane's (at most three) elements located first, then
+  // all loads issued together
+  constexpr int NLD = (NMAT * MM + 63) / 64;
+  double mv[NLD];
+#pragma unroll
+  for (int it = 0; it < NLD; ++it) {
+    const int i = lane + it * 64;
+    mv[it] = 0.0;
+    if (n < N && i < NMAT * MM) {
       const int m = i / MM, e = i - m * MM;
       const double* cfm = coef + (int64_t)n * Ly::STRIDE;
       const double* scm = scoef + ((int64_t)si * N + n) * Ly::SSTRIDE;
-      switch (m) {
-        case 0: v = cfm[Ly::AL + e]; break;
-        case 1: v = scm[Ly::ALL + e]; break;
-        case 2: v = cfm[Ly::BL + e]; break;
-        case 3: v = scm[Ly::BLL + e]; break;
-        case 4: v = cfm[Ly::NL + e]; break;
-        case 5: v = scm[Ly::NLL + e]; break;
-        case 6: v = scm[Ly::IA + e]; break;
-        case 7: v = scm[Ly::IB + e]; break;
-        default:
-          v = m < 14 ? cfm[Ly::PA + ((q - 1) * 6 + (m - 8)) * MM + e] : cfm[Ly::PB + ((q - 1) * 6 + (m - 14)) * MM + e];
-          break;
+      int off = 0;
+      switch (m) {  // offsets only: the loads stay out of the branches
+        case 0: off = Ly::AL; break;
+        case 1: off = Ly::ALL; break;
+        case 2: off = Ly::BL; break;
+        case 3: off = Ly::BLL; break;
+        case 4: off = Ly::NL; break;
+        case 5: off = Ly::NLL; break;
+        case 6: off = Ly::IA; break;
+        case 7: off = Ly::IB; break;
+        default: off = m < 14 ? Ly::PA + ((q - 1) * 6 + (m - 8)) * MM : Ly::PB + ((q - 1) * 6 + (m - 14)) * MM;
       }
+      const bool from_s = m < 8 && ((m & 1) || m >= 6);  // the length-dependent ones
+      mv[it] = (from_s ? scm : cfm)[off + e];
     }
-    smat[wv][i] = v;
   }
+#pragma unroll
+  for (int it = 0; it < NLD; ++it)
+    if (lane + it * 64 < NMAT * MM) smat[wv][lane + it * 64] = mv[it];
   __syncthreads();
   if (n < N) {  // the whole wavefront
   const double* cf = smat[wv];
@@ -1000,7 +1017,8 @@ static hipError_t launch_iir_m(int stage, int prec, const IirStream& one, const 
 #define CARRY(T) k_iir_carry<T, M><<<g4, 256, 0, st>>>(N, L, one, tab, nstreams, coef, scoef, (T*)zs)
       if (max_nseg * (int64_t)N * 2 * M >= (int64_t(1) << 31)) return hipErrorNotSupported;
 #define CARRY_U(T, Q) \
-  k_iir_carry_u<T, M, Q><<<g4, 256, 0, st>>>(N, L, one, tab, nstreams, coef, scoef, (T*)zs)
+  k_iir_carry_u<T, M, Q><<<dim3((unsigned)((int64_t)nstreams * ((N + carry_u_cols<T, Q>() - 1) / carry_u_cols<T, Q>()))), \
+                           64 * carry_u_cols<T, Q>(), 0, st>>>(N, L, one, tab, nstreams, coef, scoef, (T*)zs)
       static_assert(kIirQMax == 8, "the uniform-power carry takes up to 8 segments per lane");
       if (prec == F32) {
         if (max_nseg <= 64 * 4) CARRY_U(float, 4);
