@@ -369,7 +369,8 @@ int ipfb_plan_create(ipfb_plan* out, int lblock, int ntap, const double* window,
     // long frames: M = lblock/2-point complex FFTs, M = P1 * P2
     const int log2m = p->log2n - 1;
     const int64_t M = int64_t(1) << log2m;
-    const int64_t P1 = int64_t(1) << (log2m - lf_log2p2(log2m)), P2 = int64_t(1) << lf_log2p2(log2m);
+    const int l2 = lf_log2p2(prec == IPFB_F32 ? F32 : F64, log2m);
+    const int64_t P1 = int64_t(1) << (log2m - l2), P2 = int64_t(1) << l2;
     std::vector<double> t1 = twiddles(P1), t2 = twiddles(P2), tm = twiddles(M), tl = twiddles(lblock);
     std::vector<double> all;
     all.insert(all.end(), t1.begin(), t1.end());

@@ -7,7 +7,7 @@
 // output spectrum costs one M-point complex FFT:
 //   E[k] = (Z[k] + conj Z[M-k]) / 2,  O[k] = (Z[k] - conj Z[M-k]) / (2i),
 //   Y[k] = E[k] + t,  Y[M-k] = conj(E[k] - t),  t = e^{-2 pi i k/L} O[k].
-// The M-point FFT is four-step, M = P1 * P2 (P1 = P2 / 2 for odd log2 M),
+// The M-point FFT is four-step, M = P1 * P2 (FP32: P1 = P2 / 2 for odd log2 M),
 // m = P2 a + c, k = k1 + P1 k2:
 //   pass 1, per block of MB consecutive c and one frame: the windowed sums
 //     for all a (each load a 128-byte run of one frame), the P1-point FFT
@@ -431,7 +431,7 @@ static hipError_t launch_long_t(int pass, int log2n, const void* x, void* y, int
                                 hipStream_t st) {
   if (nblock == 0) return hipSuccess;
   const int log2m = log2n - 1;
-  const int l2 = lf_log2p2(log2m), l1 = log2m - l2;
+  const int l2 = lf_log2p2(sizeof(T) == 8 ? F64 : F32, log2m), l1 = log2m - l2;
   const int M = 1 << log2m, P1 = 1 << l1, P2 = 1 << l2;
   const LfTw<T> tw = lf_tables<T>(twS, P1, P2, M);
   hipError_t e = hipSuccess;
@@ -464,7 +464,7 @@ static int lf_chunk_t(int P1, int64_t nblock) {
 int lf_frame_chunk(int prec, int log2n, int64_t nblock) {
   if (log2n < 15 || log2n > 20 || nblock < 1) return 1;
   const int log2m = log2n - 1;
-  const int l2 = lf_log2p2(log2m), l1 = log2m - l2;
+  const int l2 = lf_log2p2(prec, log2m), l1 = log2m - l2;
   const int P1 = 1 << l1;
   if (prec == F32) {
     switch (l2) {

@@ -199,7 +199,7 @@ hipError_t launch_pfb_fwd_small(int prec, int log2n, const void* x, void* y, int
 
 // Forward PFB for long frames (2^15 <= N <= 2^20): one frame per complex
 // M = N/2-point FFT (even and odd samples packed), M = P1 * P2 with
-// P2 = 2^lf_log2p2(log2 M), in two passes through tmp (nblock * M complex).
+// P2 = 2^lf_log2p2(prec, log2 M), in two passes through tmp (nblock * M complex).
 // part: NULL, or [ceil(nblock / fchunk)][N/2+1] doubles receiving per-chunk
 // sums of |Y_jk|^2. twS: tables [P1 | P2 | 512 | M/512 | 512 | M/512 + 1] of
 // e^{-2 pi i m/P1}, e^{-2 pi i m/P2}, e^{-2 pi i m/M} (m < 512),
@@ -207,10 +207,15 @@ hipError_t launch_pfb_fwd_small(int prec, int log2n, const void* x, void* y, int
 // Frames per power-sum chunk of the second pass: one workgroup per row group
 // and chunk, about as many workgroups as the device holds at once.
 int lf_frame_chunk(int prec, int log2n, int64_t nblock);
-// log2 P2 of the split M = P1 * P2: ceil(log2 M / 2), at most 9. For odd
-// log2 M the first pass thus takes the shorter FFT (P1 = P2 / 2), which
-// leaves room in its registers for 128-byte column blocks.
-__host__ __device__ constexpr int lf_log2p2(int log2m) { return (log2m + 1) / 2 < 9 ? (log2m + 1) / 2 : 9; }
+// log2 P2 of the split M = P1 * P2. FP32: ceil(log2 M / 2), at most 9, so for
+// odd log2 M the first pass takes the shorter FFT (P1 = P2 / 2), which leaves
+// room in its registers for 128-byte column blocks (measured at M = 2^17: first
+// pass 156 -> 121 us, second 120 -> 124 us). FP64: floor(log2 M / 2), the
+// other way round (there the second pass would lose more than the first gains:
+// 279 + 219 us against 262 + 253 us).
+__host__ __device__ constexpr int lf_log2p2(int prec, int log2m) {
+  return prec == F64 ? log2m / 2 : ((log2m + 1) / 2 < 9 ? (log2m + 1) / 2 : 9);
+}
 // pass 0 launches the first FFT pass only, 1 the second only, -1 both.
 hipError_t launch_pfb_fwd_long(int prec, int log2n, int pass, const void* x, void* y, int64_t nblock, int ntap,
                                const void* winT, const void* twS, void* tmp, int fchunk, double* part,

@@ -178,7 +178,7 @@ def test_pfb_forward_small(prec, N, p, b):
 
 # b >= 4 with 4 taps takes the sliding first pass (frames wrap at the end);
 # b < 4 the one-frame-per-workgroup form. P1 = 128, 256, 512 in both precisions
-# (even log2 N: P1 = P2 / 2; the sliding pass then takes 128-byte column blocks).
+# (FP32 at even log2 N: P1 = P2 / 2, and the sliding pass takes 128-byte column blocks).
 @pytest.mark.parametrize("prec,log2n,b", [(ipfb.F32, 16, 4), (ipfb.F32, 18, 3), (ipfb.F64, 15, 4),
                                           (ipfb.F64, 17, 2), (ipfb.F32, 20, 2), (ipfb.F64, 16, 5),
                                           (ipfb.F64, 19, 4), (ipfb.F32, 19, 5), (ipfb.F32, 18, 6),
