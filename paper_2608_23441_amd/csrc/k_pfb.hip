@@ -14,11 +14,15 @@
 
 namespace ipfb {
 
-template <typename T, int LOG2N>
+// WIDE: 8 elements per thread in FP32 as well (twice the threads), for
+// launches of fewer workgroups than the device has CUs, where each
+// workgroup's FFT latency, not occupancy, sets the time (16 frames of 2^14:
+// 32 against 25 us).
+template <typename T, int LOG2N, bool WIDE = false>
 struct FwdCfg {
   static constexpr int H = 1 << (LOG2N - 1);
   static constexpr int C = H >= 1024 ? 1 : 1024 / H;
-  static constexpr int EPT = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int EPT = (sizeof(T) == 4 && !WIDE) ? 16 : 8;
   static constexpr int NT0 = (H * C) / EPT;
   static constexpr int NT = NT0 < 64 ? 64 : (NT0 > 1024 ? 1024 : NT0);
 };
@@ -48,12 +52,12 @@ __device__ __forceinline__ cx<T> polyphase_pair(const T* __restrict__ x, const T
   return acc;
 }
 
-template <typename T, int LOG2N>
-__global__ __launch_bounds__((FwdCfg<T, LOG2N>::NT)) void k_pfb_fwd(const T* __restrict__ x,
-                                                                  cx<T>* __restrict__ y, int64_t nblock,
-                                                                  int ntap, const T* __restrict__ win,
-                                                                  const cx<T>* __restrict__ twN) {
-  using Cfg = FwdCfg<T, LOG2N>;
+template <typename T, int LOG2N, bool WIDE>
+__global__ __launch_bounds__((FwdCfg<T, LOG2N, WIDE>::NT)) void k_pfb_fwd(const T* __restrict__ x,
+                                                                        cx<T>* __restrict__ y, int64_t nblock,
+                                                                        int ntap, const T* __restrict__ win,
+                                                                        const cx<T>* __restrict__ twN) {
+  using Cfg = FwdCfg<T, LOG2N, WIDE>;
   constexpr int N = 1 << LOG2N, H = Cfg::H, C = Cfg::C, NT = Cfg::NT;
   constexpr int LS = lds_len(H);
   __shared__ cx<T> s[C * LS];
@@ -83,10 +87,15 @@ template <typename T, int LOG2N>
 static hipError_t launch_fwd_small_t(const void* x, void* y, int64_t nblock, int ntap, const void* winT,
                                      const void* twN, hipStream_t st) {
   using Cfg = FwdCfg<T, LOG2N>;
+  using Wide = FwdCfg<T, LOG2N, true>;
   const int64_t grid = (nblock + Cfg::C - 1) / Cfg::C;
   if (grid == 0) return hipSuccess;
-  k_pfb_fwd<T, LOG2N><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(
-      (const T*)x, (cx<T>*)y, nblock, ntap, (const T*)winT, (const cx<T>*)twN);
+  if (Wide::NT != Cfg::NT && grid < 256)
+    k_pfb_fwd<T, LOG2N, true><<<dim3((unsigned)grid), dim3(Wide::NT), 0, st>>>(
+        (const T*)x, (cx<T>*)y, nblock, ntap, (const T*)winT, (const cx<T>*)twN);
+  else
+    k_pfb_fwd<T, LOG2N, false><<<dim3((unsigned)grid), dim3(Cfg::NT), 0, st>>>(
+        (const T*)x, (cx<T>*)y, nblock, ntap, (const T*)winT, (const cx<T>*)twN);
   return hipGetLastError();
 }
 
