@@ -599,6 +599,7 @@ def main():
     import numpy as np
     import torch
 
+    from paper_2608_23441_amd import build as build_mod
     from paper_2608_23441_amd import inputs, ipfb
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -718,6 +719,7 @@ def main():
         "per_kernel_compulsory_GBps": {k: round(cb(k) / (v["avg_us"] * 1e-6) / 1e9, 1) for k, v in pk.items()},
         "per_kernel_moved_GBps": {k: round(mb(k) / (v["avg_us"] * 1e-6) / 1e9, 1) for k, v in pk.items()
                                   if mb(k)},
+        "library": {"source_digest": ipfb.library_source_digest(), "tree_source_digest": build_mod.source_digest()},
     }
     if "f64" in results:
         r64 = results["f64"]

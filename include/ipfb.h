@@ -69,7 +69,11 @@ typedef struct ipfb_plan_s* ipfb_plan;
 /* Message for the last failed call on this thread ("" if none). */
 const char* ipfb_last_error(void);
 
-/* Version string of the library. */
+/* Version string of the library: name, target and "sources <16 hex digits>",
+ * the first 16 hex digits of a SHA-256 over the sources it was built from
+ * (every .hip and .hpp file under csrc and this header, by name and content, as
+ * the package's build script computes it; "unknown" if built without it).
+ * Static storage; never NULL. */
 const char* ipfb_version(void);
 
 /* Host helper: the sinc x Hamming window of Section 2.2 (Hamming taper with

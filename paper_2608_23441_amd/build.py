@@ -5,6 +5,7 @@ objects are linked into paper_2608_23441_amd/libipfb.so. Always rebuilds.
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -32,9 +33,23 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src):
+def source_digest() -> str:
+    """SHA-256 (first 16 hex digits) of the library's sources: every csrc/*.hip
+    and *.hpp and include/ipfb.h, by name and content. Compiled into the
+    library (ipfb_version), so a loaded library can be matched to a tree."""
+    h = hashlib.sha256()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp")))
+    for f in files:
+        h.update(f.encode() + b"\0")
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    h.update(b"ipfb.h\0")
+    h.update(open(os.path.join(ROOT, "include", "ipfb.h"), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src, digest):
     obj = os.path.join(OBJ, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *CFLAGS, f"-DIPFB_SOURCE_DIGEST=\"{digest}\"", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
@@ -46,7 +61,8 @@ def build(verbose: bool = True) -> str:
     srcs = sources()
     jobs = int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))
     with ThreadPoolExecutor(max_workers=max(1, min(jobs, len(srcs)))) as ex:
-        objs = list(ex.map(_compile, srcs))
+        digest = source_digest()
+        objs = list(ex.map(lambda src: _compile(src, digest), srcs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)

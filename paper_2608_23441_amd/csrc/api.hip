@@ -289,7 +289,10 @@ extern "C" {
 
 const char* ipfb_last_error(void) { return g_err.c_str(); }
 
-const char* ipfb_version(void) { return "ipfb-mi355x 0.1 (gfx950)"; }
+#ifndef IPFB_SOURCE_DIGEST
+#define IPFB_SOURCE_DIGEST "unknown"
+#endif
+const char* ipfb_version(void) { return "ipfb-mi355x 0.1 (gfx950) sources " IPFB_SOURCE_DIGEST; }
 
 int ipfb_window_sinc_hamming(double* out, int ntap, int lblock) {
   if (!out) return fail(IPFB_EINVAL, "window output is NULL");

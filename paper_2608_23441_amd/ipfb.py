@@ -104,6 +104,12 @@ def lib():
     return _lib
 
 
+def library_source_digest() -> str:
+    """The source digest compiled into the loaded library (see ipfb_version)."""
+    v = lib().ipfb_version().decode()
+    return v.rsplit("sources ", 1)[-1] if "sources " in v else "unknown"
+
+
 def _check(status):
     if status != OK:
         raise IpfbError(status, lib().ipfb_last_error().decode())

@@ -44,6 +44,13 @@ def test_library_exports_every_header_symbol():
     assert b"gfx950" in L.ipfb_version()
 
 
+def test_library_built_from_these_sources():
+    # the digest compiled into libipfb.so is the one of the tree's sources:
+    # a source edited after the last build fails here
+    from paper_2608_23441_amd import build as B
+    assert ipfb.library_source_digest() == B.source_digest()
+
+
 def test_window_helper_matches_oracle():
     for ntap, lblock in [(4, 64), (4, 2048), (3, 32), (1, 16)]:
         w = ipfb.window_sinc_hamming(ntap, lblock)

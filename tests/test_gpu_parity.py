@@ -13,6 +13,14 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
+
+def test_library_on_this_machine_built_from_these_sources():
+    # the library these GPU tests load carries the digest of the tree's sources
+    from paper_2608_23441_amd import build as B
+    print(f"libipfb.so sources {ipfb.library_source_digest()}, tree {B.source_digest()}", flush=True)
+    assert ipfb.library_source_digest() == B.source_digest()
+
+
 TOL = {ipfb.F64: 1e-12, ipfb.F32: 1e-5}
 # worst single sub-filter path (column of the frame matrix)
 TOL_COL = {ipfb.F64: 1e-11, ipfb.F32: 1e-4}
