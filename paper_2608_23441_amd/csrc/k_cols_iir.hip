@@ -647,12 +647,13 @@ __global__ __launch_bounds__(256) void k_iir_carry(int N, int L, IirStream one, 
 //     by B^{qL(lane_last-1-l)} W + G_{l+1}, W = B^{len(lane_last)} F_0, and
 //     lane_last by F_0.
 // One wavefront per (stream, column); the 20 matrices it uses staged in LDS.
-// With STAGE, the four columns' segment states also pass through LDS, loaded
-// and stored by the whole workgroup as runs of the four columns' states per
+// With STAGE, the workgroup's segment states also pass through LDS, loaded
+// and stored by the whole workgroup as runs of its columns' states per
 // segment: a lane reading its own column's segments straight from global
-// memory touches a separate cache line for every 24 bytes, and that gather,
-// not the arithmetic, is what bounds the kernel at 4096 columns (with the
-// arithmetic removed it still takes 39.5 of its 46 us).
+// memory touches a separate cache line for every 24 bytes. (At 4096 columns
+// and 256 segments the loads and stores alone take 32 us with runs of four
+// columns, 16.5 us with runs of sixteen; the kernel takes about 40 us, the
+// rest being its dependent FP64 chains.)
 // Columns per workgroup (one wavefront each): 16 when the states are staged,
 // so that the workgroup's states of one segment are a 128-byte-aligned run of
 // three lines (16 columns x 2M values x 4 bytes), else 4.
