@@ -583,9 +583,10 @@ bool use_recursive(ipfb_plan p, double phi) {
 // (precond = 0: coefficient set iir_coef, output scaled by gnorm) or the CG
 // preconditioner 1/(|W|^2 + phi^2) (precond = 1: set iir_coef_pc, gnorm 1).
 // Each set is made again only when phi changes. names: NULL, or the profile
-// names of the five stages.
+// names of the five stages. dst: NULL, or where frames [doff, doff + dkeep)
+// of the result go (buf then keeps its input).
 hipError_t rec_stage(ipfb_plan p, void* buf, double phi, int precond, double gnorm, hipStream_t st,
-                     const char* const* names) {
+                     const char* const* names, void* dst = nullptr, int64_t doff = 0, int64_t dkeep = 0) {
   const int seg = p->prec == IPFB_F32 ? kIirSegF32 : kIirSegF64;
   const int64_t nseg = (p->nblock + seg - 1) / seg;
   const IirStream one = {buf, p->nblock, 0};
@@ -596,7 +597,7 @@ hipError_t rec_stage(ipfb_plan p, void* buf, double phi, int precond, double gno
   for (int stage = (phi == cached) ? kIirPass1 : kIirSetup; stage <= kIirApply && e == hipSuccess; ++stage) {
     ProfScope ps(names ? names[stage] : nullptr, st);
     e = launch_col_iir(stage, p->prec, one, nullptr, 1, nseg, nseg, p->lblock, p->ntap, p->win64, phi, gnorm, coef,
-                       scoef, p->iir_zs, st, precond);
+                       scoef, p->iir_zs, st, precond, dst, doff, dkeep);
     if (stage <= kIirSetupLen) cached = e == hipSuccess ? phi : NAN;
   }
   return e;
@@ -876,7 +877,10 @@ int ipfb_wiener_stream(ipfb_splan sp, int infmt, const void* spec, const float* 
       e = launch_row_irfft(p->prec, p->log2n, infmt, sp_in, p->fac, work, nvalid, p->twN, st);
     if (e == hipSuccess && nvalid < B) e = launch_zero(work + (size_t)nvalid * fb, (size_t)(B - nvalid) * fb, st);
     if (e != hipSuccess) break;
-    if (p->log2b > 9) {
+    if (use_recursive(p, phi)) {  // the recursive stage, its last pass writing the kept frames
+      e = rec_stage(p, work, phi, 0, normalise ? 1.0 + phi * phi : 1.0, st, nullptr, xo + (size_t)k0 * fb, off,
+                    nkeep);
+    } else if (p->log2b > 9) {
       for (int pass = 0; pass < 2 && e == hipSuccess; ++pass)
         e = launch_col_wiener_nat(p->prec, p->log2b, pass, work, N, p->ntap, p->win64, phi, normalise, p->twB,
                                   p->twB64, st);

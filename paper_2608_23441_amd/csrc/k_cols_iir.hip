@@ -916,7 +916,8 @@ __global__ __launch_bounds__((64 * carry_u_cols<T, QR>())) void k_iir_carry_u(in
 template <typename T, int M, int L>
 __global__ __launch_bounds__(64) void k_iir_apply(int N, int ntiles, IirStream one, const IirStream* __restrict__ tab,
                                                    int nstreams, const double* __restrict__ coef,
-                                                   const T* __restrict__ zs, double gnorm) {
+                                                   const T* __restrict__ zs, double gnorm, T* __restrict__ dst,
+                                                   int64_t doff, int64_t dkeep) {
   using Ly = IirLayout<M>;
   extern __shared__ __align__(16) unsigned char iir_lds[];  // L * 64 T, for partial segments only
   T* ys = reinterpret_cast<T*>(iir_lds);
@@ -967,8 +968,17 @@ __global__ __launch_bounds__(64) void k_iir_apply(int N, int ntiles, IirStream o
     for (int k = 0; k < L; ++k) yv[k] = buf_ld<T>(rs, vo, k * rowb);
 #pragma unroll
     for (int k = 0; k < L; ++k) yv[k] = T(causal((double)yv[k]));
+    if (!dst) {
 #pragma unroll
-    for (int k = L - 1; k >= 0; --k) buf_st<T>(T(anti((double)yv[k])), rs, vo, k * rowb);
+      for (int k = L - 1; k >= 0; --k) buf_st<T>(T(anti((double)yv[k])), rs, vo, k * rowb);
+    } else {
+#pragma unroll
+      for (int k = L - 1; k >= 0; --k) {
+        const T val = T(anti((double)yv[k]));
+        const int64_t o = j0 + k - doff;  // uniform: the output frame
+        if (o >= 0 && o < dkeep) dst[o * N + n] = val;
+      }
+    }
     return;
   }
   T cur[kIirChunk], nxt[kIirChunk];
@@ -986,14 +996,22 @@ __global__ __launch_bounds__(64) void k_iir_apply(int N, int ntiles, IirStream o
     for (int kk = 0; kk < kIirChunk; ++kk) cur[kk] = nxt[kk];
   }
 #pragma unroll 4
-  for (int k = Ls - 1; k >= 0; --k)
-    ((__attribute__((address_space(1))) T*)px)[(int64_t)k * N] = T(anti((double)ys[k * 64 + tid]));
+  for (int k = Ls - 1; k >= 0; --k) {
+    const T val = T(anti((double)ys[k * 64 + tid]));
+    if (!dst) {
+      ((__attribute__((address_space(1))) T*)px)[(int64_t)k * N] = val;
+    } else {
+      const int64_t o = j0 + k - doff;
+      if (o >= 0 && o < dkeep) dst[o * N + n] = val;
+    }
+  }
 }
 
 template <int M>
 static hipError_t launch_iir_m(int stage, int prec, const IirStream& one, const IirStream* tab, int nstreams,
                                int64_t nsegt, int64_t max_nseg, int N, const double* win64, double phi,
-                               double gnorm, double* coef, double* scoef, void* zs, hipStream_t st, int precond) {
+                               double gnorm, double* coef, double* scoef, void* zs, hipStream_t st, int precond,
+                               void* dst, int64_t doff, int64_t dkeep) {
   const int L = prec == F32 ? kIirSegF32 : kIirSegF64;
   const int t256 = (N + 255) / 256, t64 = (N + 63) / 64;
   if (nsegt * t64 > 0x7fffffffLL) return hipErrorNotSupported;  // one-dimensional grids
@@ -1041,11 +1059,11 @@ static hipError_t launch_iir_m(int stage, int prec, const IirStream& one, const 
       const bool all_full = nstreams <= 1 && one.b % L == 0 && (int64_t)L * N * (int64_t)es < (int64_t(1) << 31);
       const size_t lds = all_full ? 0 : (size_t)L * 64 * es;
       if (prec == F32)
-        k_iir_apply<float, M, kIirSegF32><<<dim3((unsigned)(nsegt * t64)), 64, lds, st>>>(N, t64, one, tab, nstreams,
-                                                                                          coef, (const float*)zs, gnorm);
+        k_iir_apply<float, M, kIirSegF32><<<dim3((unsigned)(nsegt * t64)), 64, lds, st>>>(
+            N, t64, one, tab, nstreams, coef, (const float*)zs, gnorm, (float*)dst, doff, dkeep);
       else
-        k_iir_apply<double, M, kIirSegF64><<<dim3((unsigned)(nsegt * t64)), 64, lds, st>>>(N, t64, one, tab, nstreams,
-                                                                                           coef, (const double*)zs, gnorm);
+        k_iir_apply<double, M, kIirSegF64><<<dim3((unsigned)(nsegt * t64)), 64, lds, st>>>(
+            N, t64, one, tab, nstreams, coef, (const double*)zs, gnorm, (double*)dst, doff, dkeep);
       break;
     }
   }
@@ -1054,12 +1072,14 @@ static hipError_t launch_iir_m(int stage, int prec, const IirStream& one, const 
 
 hipError_t launch_col_iir(int stage, int prec, const IirStream& one, const IirStream* tab, int nstreams,
                           int64_t nsegt, int64_t max_nseg, int N, int ntap, const double* win64, double phi,
-                          double gnorm, double* coef, double* scoef, void* zs, hipStream_t st, int precond) {
+                          double gnorm, double* coef, double* scoef, void* zs, hipStream_t st, int precond,
+                          void* dst, int64_t doff, int64_t dkeep) {
   if (N < 1 || nsegt < 1) return hipSuccess;
+  if (dst && nstreams > 1) return hipErrorInvalidValue;
   switch (ntap) {
     case 4:
       return launch_iir_m<3>(stage, prec, one, tab, nstreams, nsegt, max_nseg, N, win64, phi, gnorm, coef, scoef, zs,
-                             st, precond);
+                             st, precond, dst, doff, dkeep);
     default: return hipErrorNotSupported;
   }
 }

@@ -77,6 +77,9 @@ hipError_t launch_row_c4(int prec, int log2n, const void* in, const float* chan_
 // array of nstreams entries. max_nseg: the most segments of any stream.
 // precond = 1 (kIirSetup): the coefficients of 1/(|W_n|^2 + phi^2) instead
 // (numerator 1), the inverse of A^T A + phi^2 I; apply it with gnorm = 1.
+// dst (kIirApply, one stream): NULL to write xhat over x; else frame j of
+// xhat goes to dst frame j - doff if 0 <= j - doff < dkeep, and no other
+// frame is written (x keeps d).
 // hipErrorNotSupported (nothing launched) for tap counts without a kernel.
 constexpr int kIirSegF32 = 64, kIirSegF64 = 64;
 struct IirStream {
@@ -89,7 +92,8 @@ int iir_coef_stride(int ntap);
 int iir_stream_stride(int ntap);
 hipError_t launch_col_iir(int stage, int prec, const IirStream& one, const IirStream* tab, int nstreams,
                           int64_t nsegt, int64_t max_nseg, int N, int ntap, const double* win64, double phi,
-                          double gnorm, double* coef, double* scoef, void* zs, hipStream_t st, int precond = 0);
+                          double gnorm, double* coef, double* scoef, void* zs, hipStream_t st, int precond = 0,
+                          void* dst = nullptr, int64_t doff = 0, int64_t dkeep = 0);
 
 // Tikhonov-regularised solve of each path's linear sub-problem by banded
 // Cholesky: x (first b - ntap + 1 rows: d) overwritten with
