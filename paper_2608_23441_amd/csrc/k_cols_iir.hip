@@ -909,10 +909,11 @@ __global__ __launch_bounds__((64 * carry_u_cols<T, QR>())) void k_iir_carry_u(in
 }
 
 // Pass 2: per (column, segment), the causal ARMA from its entering state,
-// its outputs kept in LDS (each thread its own column: no barriers), then
-// the anti-causal recursion backwards from the right-hand state; xhat =
-// gain * v written over d. One wavefront of 64 columns per workgroup;
-// workgroup w takes global segment w / ntiles.
+// its outputs kept in registers (a full segment) or LDS (a partial one; each
+// thread its own column: no barriers), then the anti-causal recursion
+// backwards from the right-hand state; xhat = gain * v written over d, or
+// (dst) its frames [doff, doff + dkeep) to dst. One wavefront of 64 columns
+// per workgroup; workgroup w takes global segment w / ntiles.
 template <typename T, int M, int L>
 __global__ __launch_bounds__(64) void k_iir_apply(int N, int ntiles, IirStream one, const IirStream* __restrict__ tab,
                                                    int nstreams, const double* __restrict__ coef,
