@@ -640,6 +640,9 @@ int ipfb_wiener_ex(ipfb_plan p, int infmt, const void* spec, const float* chan_s
       int s2 = ipfb_batched_plan_create(&p->blu1, p->lblock, p->ntap, w.data(), 1, &p->nblock, p->prec);
       if (s2) return s2;
       ipfb_batched_use_graph(p->blu1, 0);
+      // the FFT form (this path is taken only when the recursive one is not)
+      s2 = ipfb_batched_set_column_method(p->blu1, IPFB_COLS_FFT);
+      if (s2) return s2;
     }
     const void* sp[1] = {spec};
     const float* scs[1] = {chan_scale};

@@ -86,7 +86,7 @@ __device__ __forceinline__ int64_t uniform64(int64_t v) {
 __device__ __forceinline__ IirStream iir_stream_of(int64_t g, const IirStream& one, const IirStream* __restrict__ tab,
                                                    int nstreams) {
   IirStream r = one;
-  if (nstreams > 1) {
+  if (tab && nstreams > 0) {  // a table (one entry or more) takes precedence
     int lo = 0, hi = nstreams - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(64) void k_iir_setup_len(int N, int L, IirStream on
   const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (t >= (int64_t)nstreams * N) return;
   const int si = (int)(t / N), n = (int)(t - (int64_t)si * N);
-  const IirStream sd = nstreams <= 1 ? one : tab[si];
+  const IirStream sd = tab ? tab[si] : one;
   const double* cf = coef + (int64_t)n * Ly::STRIDE;
   double* sc = scoef + t * Ly::SSTRIDE;
   double a[M], A[M * M], B[M * M], t1[M * M];
@@ -543,10 +543,11 @@ __global__ __launch_bounds__(256) void k_iir_carry(int N, int L, IirStream one, 
   constexpr int oAL = 0, oALL = MM, oBL = 2 * MM, oBLL = 3 * MM, oNL = 4 * MM, oNLL = 5 * MM, oIA = 6 * MM,
                 oIB = 7 * MM;
   const double* cf = smat[wv];
-  IirStream sd = nstreams <= 1 ? one : tab[si];
+  IirStream sd = tab ? tab[si] : one;
   sd.b = uniform64(sd.b);
   sd.seg0 = uniform64(sd.seg0);
   const int64_t nseg = (sd.b + L - 1) / L;
+  if (nseg == 0) return;  // a stream without frames: nothing to carry
   const int64_t stride = (int64_t)N * 2 * M;
   T* z = zs + (sd.seg0 * N + n) * 2 * M;
   const int64_t q = (nseg + 63) / 64;
@@ -675,10 +676,11 @@ __global__ __launch_bounds__((64 * carry_u_cols<T, QR>())) void k_iir_carry_u(in
   const int groups = (N + COLS - 1) / COLS;
   const int si = __builtin_amdgcn_readfirstlane(blockIdx.x / groups);  // the stream
   const int n = __builtin_amdgcn_readfirstlane((blockIdx.x % groups) * COLS + wv);
-  IirStream sd = nstreams <= 1 ? one : tab[si];
+  IirStream sd = tab ? tab[si] : one;
   sd.b = uniform64(sd.b);
   sd.seg0 = uniform64(sd.seg0);
   const int64_t nseg = (sd.b + L - 1) / L;
+  if (nseg == 0) return;  // a stream without frames (uniform over the workgroup: one stream)
   const int q = (int)((nseg + 63) / 64);  // 1 .. QR (the launch checked max_nseg)
   __shared__ double smat[COLS][NMAT * MM];
   // staged states: [column][segment][2M], the column blocks padded by one
@@ -1057,7 +1059,7 @@ static hipError_t launch_iir_m(int stage, int prec, const IirStream& one, const 
       // LDS for the partial segments' outputs, unless every segment is full
       // (one stream of a multiple of L frames) and takes the register path
       const size_t es = prec == F32 ? sizeof(float) : sizeof(double);
-      const bool all_full = nstreams <= 1 && one.b % L == 0 && (int64_t)L * N * (int64_t)es < (int64_t(1) << 31);
+      const bool all_full = !tab && one.b % L == 0 && (int64_t)L * N * (int64_t)es < (int64_t(1) << 31);
       const size_t lds = all_full ? 0 : (size_t)L * 64 * es;
       if (prec == F32)
         k_iir_apply<float, M, kIirSegF32><<<dim3((unsigned)(nsegt * t64)), 64, lds, st>>>(
@@ -1076,7 +1078,7 @@ hipError_t launch_col_iir(int stage, int prec, const IirStream& one, const IirSt
                           double gnorm, double* coef, double* scoef, void* zs, hipStream_t st, int precond,
                           void* dst, int64_t doff, int64_t dkeep) {
   if (N < 1 || nsegt < 1) return hipSuccess;
-  if (dst && nstreams > 1) return hipErrorInvalidValue;
+  if (dst && tab) return hipErrorInvalidValue;
   switch (ntap) {
     case 4:
       return launch_iir_m<3>(stage, prec, one, tab, nstreams, nsegt, max_nseg, N, win64, phi, gnorm, coef, scoef, zs,

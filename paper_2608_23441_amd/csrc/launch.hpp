@@ -73,11 +73,12 @@ hipError_t launch_row_c4(int prec, int log2n, const void* in, const float* chan_
 // zero-state end states into zs (nsegt * N * 2 (ntap - 1) values of the plan
 // precision), kIirCarry the periodic states entering each segment (over
 // zs), kIirApply the two recursions from those states, writing xhat over x.
-// One stream: `one` describes it and tab is unused; several: tab is a device
-// array of nstreams entries. max_nseg: the most segments of any stream.
+// tab NULL: `one` describes the single stream; else tab is a device array of
+// nstreams (>= 1) entries and `one` is unused. max_nseg: the most segments
+// of any stream.
 // precond = 1 (kIirSetup): the coefficients of 1/(|W_n|^2 + phi^2) instead
 // (numerator 1), the inverse of A^T A + phi^2 I; apply it with gnorm = 1.
-// dst (kIirApply, one stream): NULL to write xhat over x; else frame j of
+// dst (kIirApply, tab NULL): NULL to write xhat over x; else frame j of
 // xhat goes to dst frame j - doff if 0 <= j - doff < dkeep, and no other
 // frame is written (x keeps d).
 // hipErrorNotSupported (nothing launched) for tap counts without a kernel.

@@ -265,8 +265,58 @@ def test_batched_full_workload_sampled_columns(method):
         err = _rel(got, ref)
         print(f"stream {s_} b={b}: sampled columns rel RMS {err:.2e}", flush=True)
         assert err < 1e-5
+    if method == ipfb.COLS_AUTO:
+        # every column of 16 streams (the four above and 12 drawn at random)
+        # against the FFT form of the same inverse, an independent algorithm
+        # (Bluestein's identity for the lengths that are not powers of two)
+        rng = np.random.default_rng(7)
+        more = [int(v) for v in rng.choice(len(nbl), 16, replace=False) if int(v) not in pick][:12]
+        for s_ in pick + more:
+            plan = ipfb.Plan(N, p, w, nbl[s_], ipfb.F32)
+            plan.set_column_method(ipfb.COLS_FFT)
+            ref2 = ipfb.ipfb_wiener(plan, specs[s_], scales[s_], phi)
+            torch.cuda.synchronize()
+            err = float(torch.linalg.vector_norm(outs[s_] - ref2) / torch.linalg.vector_norm(ref2))
+            print(f"stream {s_} b={nbl[s_]}: every column, recursive vs FFT form rel RMS {err:.2e}", flush=True)
+            assert err < 2e-6
+            del plan, ref2
     del outs, specs, scales, bp
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("method", [ipfb.COLS_AUTO, ipfb.COLS_RECURSIVE, ipfb.COLS_FFT])
+@pytest.mark.parametrize("prec,tol", [(ipfb.F64, 1e-11), (ipfb.F32, 1e-5)])
+def test_batched_single_stream(prec, tol, method):
+    # a batched plan of exactly one stream: the multi-stream recursive launches
+    # read its table entry (regression: they once took the unused by-value
+    # stream, a zero-length one, for a table of one entry)
+    N, p, b = 64, 4, 100
+    print(f"case batched one stream prec={prec} method={method}", flush=True)
+    w, data = _streams(N, p, [b], 4300)
+    bp = ipfb.BatchedPlan(N, p, w, [b], prec)
+    bp.set_column_method(method)
+    (pk, sc), = data
+    for phi in (0.1, 0.3):
+        out, = ipfb.wiener_batched(bp, [torch.from_numpy(pk).cuda()], [torch.from_numpy(sc).cuda()], phi)
+        torch.cuda.synchronize()
+        assert _rel(out.cpu().numpy().astype(np.float64), O.ipfb_wiener(pk, sc, w, N, p, phi)) < tol, phi
+
+
+@pytest.mark.parametrize("prec,tol", [(ipfb.F64, 1e-11), (ipfb.F32, 1e-5)])
+def test_single_plan_fft_form_for_any_nblock(prec, tol):
+    # COLS_FFT on a plan whose nblock is not a power of two: the FFT form by
+    # Bluestein's identity (through a one-stream batched plan), phi > 0
+    N, p, b = 256, 4, 1031
+    print(f"case single plan FFT form nblock={b} prec={prec}", flush=True)
+    w, data = _streams(N, p, [b], 4400)
+    (pk, sc), = data
+    plan = ipfb.Plan(N, p, w, b, prec)
+    plan.set_column_method(ipfb.COLS_FFT)
+    for phi in (0.1, 0.0):
+        out = ipfb.ipfb_wiener(plan, torch.from_numpy(pk).cuda(), torch.from_numpy(sc).cuda(), phi)
+        torch.cuda.synchronize()
+        ref = O.ipfb_wiener(pk, sc, w, N, p, phi)
+        assert _rel(out.cpu().numpy().astype(np.float64), ref) < (tol if phi > 0 else 50 * tol), phi
 
 
 def test_batched_recursive_equals_single_stream_plans():
