@@ -23,11 +23,13 @@ def _linear_spectra(N, p, nspec, seed, window):
 
 
 # (N, p, chunk, halo, nspec): one-pass windows (chunk <= 512: copy of the kept
-# frames) and three-pass windows (kept frames written by the last pass);
+# frames) and larger windows (4 taps: the recursive column stage; else the
+# three FFT passes; either way the kept frames written by the last pass);
 # several windows with a ragged last one, a stream shorter than one window,
-# exactly one window, one spectrum
+# exactly one window, one spectrum, a few spectra in a large window
 CASES = [(64, 4, 64, 8, 300), (64, 4, 1024, 100, 3000), (128, 4, 2048, 256, 700), (64, 3, 64, 0, 62),
-         (64, 4, 64, 8, 1), (32, 5, 512, 30, 2000), (256, 4, 4096, 300, 9000)]
+         (64, 4, 64, 8, 1), (32, 5, 512, 30, 2000), (256, 4, 4096, 300, 9000), (64, 4, 1024, 100, 5),
+         (32, 5, 1024, 60, 2500)]
 
 
 @pytest.mark.parametrize("prec,tol", [(ipfb.F64, 1e-11), (ipfb.F32, 1e-5)])
